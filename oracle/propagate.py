@@ -1,0 +1,135 @@
+"""Density-matrix propagation (oracle; test infrastructure only).
+
+Paper passages:
+  * Magnus expansion, first term for a Hamiltonian linear over the step:
+    Omega_1 = -i dt (H_0 + H_1)/2 (Sec. Magnus expansion, eq. omega1a).
+  * Spectral propagator U = W exp(omega) W^dagger from the eigenpairs of Omega
+    (same section) and P(t) = U P(0) U^dagger (Sec. Density matrix propagation,
+    eq. UxP0xU).
+  * Commutator expansion P(t + dt) = P + sum_k dP^(k),
+    dP^(k) = (1/k)(-i dt)[Hbar, dP^(k-1)] for an orthonormal basis
+    (eq. commutator-expansion-ort), stopped when max|dP| <= dP_thrs (Algorithm 1).
+  * Self-consistent midpoint loop of Algorithm 1: predictor H_1 = 2 H_0 - H_-1,
+    repeat { Omega from (H_0 + H_1)/2; propagate; H_1 <- DFT(rho(P_1)) } until
+    the update of H_1 is below H_thrs; then shift H_-1 <- H_0, H_0 <- H_1,
+    P_0 <- P_1.
+  * Delta-kick perturbation (Sec. Numerical Results, kick equation).
+
+Readings where the paper is silent:
+  * The kick is an instantaneous unitary at t = 0+, P(0+) = e^{-i kappa M_q}
+    P_0 e^{+i kappa M_q}; afterwards the field is zero.  H_0 = H[P(0+)],
+    H_-1 = H_0.
+  * The self-consistency residual compares each new H_1 with the H_1 that built
+    Omega, so every step does at least one Hamiltonian update.
+  * The series is not stopped before k >= ceil(dt * w), w the Gershgorin width
+    of Hbar, so a term on the rising part of the series cannot end it.
+"""
+
+import math
+
+import numpy as np
+
+
+class NoConvergence(RuntimeError):
+    pass
+
+
+def expm_herm(Hbar: np.ndarray, dt: float) -> np.ndarray:
+    """U = exp(-i dt Hbar) for real symmetric Hbar, spectral form W e^{-i dt w} W^T."""
+    w, W = np.linalg.eigh(Hbar)
+    return (W * np.exp(-1j * dt * w)[None, :]) @ W.T
+
+
+def propagate_exact(Hbar: np.ndarray, P: np.ndarray, dt: float) -> np.ndarray:
+    """P -> U P U^dagger with the exact exponential of Omega_1 = -i dt Hbar."""
+    U = expm_herm(Hbar, dt)
+    return U @ P @ U.conj().T
+
+
+def gershgorin_width(A: np.ndarray) -> float:
+    """Width of the Gershgorin interval enclosing the spectrum of real symmetric A."""
+    d = np.diag(A)
+    r = np.sum(np.abs(A), axis=1) - np.abs(d)
+    return float(np.max(d + r) - np.min(d - r))
+
+
+def propagate_series(Hbar: np.ndarray, P: np.ndarray, dt: float, thrs: float, max_terms: int = 200):
+    """Commutator series for P(t + dt): dP^(0) = P,
+    dP^(k) = (1/k) (Omega dP^(k-1) + dP^(k-1) Omega^dagger) with Omega = -i dt Hbar,
+    i.e. (1/k)(-i dt)[Hbar, dP^(k-1)]; summed until max|dP^(k)| <= thrs.
+    Returns (P(t + dt), number of terms)."""
+    omega = -1j * dt * Hbar
+    k_min = math.ceil(dt * gershgorin_width(Hbar))
+    P1 = P.astype(np.complex128).copy()
+    dP = P1.copy()
+    k = 0
+    while True:
+        k += 1
+        if k > max_terms:
+            raise NoConvergence("commutator series exceeded max_terms")
+        dP = (omega @ dP + dP @ omega.conj().T) / k
+        P1 += dP
+        if k >= k_min and np.max(np.abs(dP)) <= thrs:
+            return P1, k
+
+
+def kick(P0: np.ndarray, M: np.ndarray, kappa: float) -> np.ndarray:
+    """Instantaneous delta kick: P(0+) = exp(-i kappa M) P_0 exp(+i kappa M)."""
+    return propagate_exact(M, P0.astype(np.complex128), kappa)
+
+
+def run(model, rp, method: str = "exact", predictor: str = "linear", record_p: bool = False,
+        P_start=None, H_start=None):
+    """Self-consistent midpoint time loop (Algorithm 1, time integration block).
+
+    method: "exact" (spectral exponential, the fixed point the method converges
+    to) or "series" (the commutator series of Algorithm 1).
+    Returns a dict with per-step dipole mu[j, 3], energy E[j], trace N[j],
+    update counts scf[j] and series terms.
+    """
+    N = model.N
+    if P_start is None:
+        P0 = np.diag(model.sys.occupations()[:N]).astype(np.complex128)
+        P = kick(P0, model.M[rp.axis], rp.kappa) if rp.kappa else P0
+    else:
+        P = P_start.astype(np.complex128)
+    H0, aux = model.h_of_p(P)
+    if H_start is not None:
+        Hm1 = H_start
+    else:
+        Hm1 = H0.copy()
+    mu = [model.dipole(P)]
+    E = [model.energy(P, aux)]
+    tr = [float(np.real(np.trace(P)))]
+    scf, terms = [0], [0]
+    Ps = [P.copy()] if record_p else None
+    for j in range(1, rp.n_steps + 1):
+        H1 = 2.0 * H0 - Hm1 if predictor == "linear" else H0.copy()
+        n_terms = 0
+        for m in range(1, rp.max_scf + 1):
+            Hbar = 0.5 * (H0 + H1)
+            if method == "exact":
+                P1 = propagate_exact(Hbar, P, rp.dt)
+            else:
+                P1, kk = propagate_series(Hbar, P, rp.dt, rp.dp_thrs, rp.max_terms)
+                n_terms += kk
+            Hn, aux = model.h_of_p(P1)
+            r = float(np.max(np.abs(Hn - H1)))
+            H1 = Hn
+            if r <= rp.h_thrs:
+                break
+        else:
+            raise NoConvergence(f"self-consistent loop did not converge at step {j}")
+        Hm1, H0, P = H0, H1, P1
+        mu.append(model.dipole(P))
+        E.append(model.energy(P, aux))
+        tr.append(float(np.real(np.trace(P))))
+        scf.append(m)
+        terms.append(n_terms)
+        if record_p:
+            Ps.append(P.copy())
+    out = dict(mu=np.array(mu), E=np.array(E), trace=np.array(tr), scf=np.array(scf),
+               terms=np.array(terms), P=P, H0=H0, Hm1=Hm1)
+    if record_p:
+        out["Ps"] = Ps
+    return out
