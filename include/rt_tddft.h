@@ -1,0 +1,242 @@
+/*
+ * rt_tddft.h -- C ABI of the MI355X real-time TDDFT time-step library.
+ *
+ * One time step of Kohn-Sham electron dynamics on a real-space grid, in the
+ * density-matrix form of arXiv:2410.09189 (Jakowski et al.): the Hamiltonian is
+ * applied to every active orbital on the grid and projected to the orbital
+ * basis, the density matrix is advanced by the first-order Magnus (midpoint)
+ * operator through the commutator series, and the density, Hartree and
+ * exchange potentials are rebuilt, all inside the self-consistent Hamiltonian
+ * loop of Algorithm 1.
+ *
+ * Conventions shared by every call
+ *   - Atomic units (hbar = m_e = e = 1).
+ *   - Grid arrays are C-order [nz][ny][nx] (x fastest); grid point (i,j,k) sits
+ *     at (i h, j h, k h) in a periodic cell of side n h per axis.
+ *   - Orbital arrays are orbital-major [N][nz][ny][nx]; orbitals are real
+ *     (Gamma point) and orthonormal under the quadrature <f,g> = h^3 sum f g.
+ *   - N x N matrices are row-major double.  The density matrix is carried as the
+ *     pair (S', A') of its real symmetric and imaginary antisymmetric parts.
+ *   - Host pointers are read during the call only; the library copies what it
+ *     keeps.  Device pointers are caller-owned and must stay valid for the call.
+ *   - All device work is enqueued on the stream given to rt_init.  rt_step with
+ *     stats == NULL and rt_apply_h are asynchronous; rt_dipole and the matrix
+ *     getters synchronise the stream.
+ *   - Every call returns an rt_status; no exception crosses the ABI.  On any
+ *     status other than RT_OK, rt_last_error(ctx) names the cause.  RT_EINVAL
+ *     leaves no side effects.  One context must not be used from two threads
+ *     at once.
+ */
+#ifndef RT_TDDFT_H
+#define RT_TDDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rt_ctx rt_ctx; /* opaque; created by rt_init, released by rt_free */
+
+typedef enum {
+  RT_OK = 0,
+  RT_EINVAL = -1,   /* inconsistent or out-of-range argument                     */
+  RT_ENOMEM = -2,   /* workspace smaller than rt_workspace_size reported          */
+  RT_EDEVICE = -3,  /* a HIP call failed                                          */
+  RT_ENOCONV = -4,  /* self-consistent loop or commutator series hit its cap      */
+  RT_ESTATE = -5    /* call not valid in the context's current state              */
+} rt_status;
+
+enum { RT_FP64 = 0, RT_MIXED = 1 };               /* arithmetic of the time step   */
+enum { RT_PRED_LINEAR = 0, RT_PRED_MLP = 1 };     /* first guess of H(t + dt)      */
+enum { RT_HUPDATE_FULL = 0, RT_HUPDATE_LOCAL = 1 };/* how H[P] is rebuilt, below    */
+
+/*
+ * One molecule: grid, synthetic electron-ion terms and the ground-state active
+ * space (Algorithm 1, ground-state and active-space blocks).
+ *
+ * Electron-ion terms (stand-ins for the norm-conserving pseudopotentials of
+ * Sec. Overview of RMG):
+ *   V_ion(r) = - sum_a depth[a] sum_{images |n_q| <= n_images}
+ *                exp(-|r - pos_a - n L|^2 / (2 width[a]^2))
+ *   V_nl     = sum_a sum_p |beta_ap> nl_D[a*nl_rank+p] <beta_ap| (h^3 quadrature),
+ *              beta_a1 ~ g(s), beta_a(1+q) ~ (s_q / nl_sigma) g(s), q = x,y,z,
+ *              g(s) = exp(-s^2/(2 nl_sigma^2)) (1 - s^2/nl_rcut^2)^2 for s < nl_rcut
+ *              (minimum-image displacement s), each column h^3-normalised.
+ * psi0: the N = n_occ + n_virt ground-state orbitals, FP64 [N][nz][ny][nx],
+ *   host memory unless psi0_on_device != 0.  If orthonormalize != 0 they are
+ *   first made h^3-orthonormal by S = h^3 Psi Psi^T = L L^T, Psi <- L^-1 Psi
+ *   (basis transform of the paper's non-orthogonal formulation, Appendix).
+ * occ: occupations f_i (nullable: 2 for the first n_occ, 0 for the rest).
+ */
+typedef struct {
+  int n[3];            /* nx, ny, nz; each in [8, 1024]                          */
+  double h;            /* grid spacing (bohr)                                    */
+  int n_atoms;
+  const double* pos;   /* [n_atoms][3] bohr                                      */
+  const double* depth; /* [n_atoms] Ha                                           */
+  const double* width; /* [n_atoms] bohr                                         */
+  int n_images;        /* periodic images summed per axis for V_ion (0..3)       */
+  int nl_rank;         /* 0 or 4                                                 */
+  double nl_rcut;      /* projector radius (bohr)                                */
+  double nl_sigma;     /* projector Gaussian width (bohr)                        */
+  const double* nl_D;  /* [n_atoms][nl_rank] Ha (nullable when nl_rank == 0)    */
+  int n_occ;
+  int n_virt;
+  const double* occ;   /* [N] or NULL                                            */
+  const double* psi0;  /* [N][nz][ny][nx]                                        */
+  int psi0_on_device;
+  int orthonormalize;
+} rt_system;
+
+/*
+ * Time loop and trajectories (Algorithm 1, parameter block).  Each trajectory
+ * starts from P_0 = diag(f) of its system, receives a delta kick
+ * P(0+) = exp(-i kappa M_q) P_0 exp(+i kappa M_q) along axis q (Sec. Numerical
+ * Results, kick perturbation; applied through the same commutator series with
+ * Omega = -i kappa M_q), and sets H_0 = H[P(0+)], H_-1 = H_0.
+ *
+ * hupdate selects how H[P] = h^3 Psi^T [T + V_ion + V_nl + V_H + v_x] Psi is
+ * rebuilt in the self-consistent loop:
+ *   RT_HUPDATE_FULL  -- the grid Hamiltonian is applied to every orbital (FD
+ *                       stencil + local + nonlocal) and projected, as in the
+ *                       paper's Hamiltonian update.
+ *   RT_HUPDATE_LOCAL -- the orbitals are fixed during propagation, so only the
+ *                       Hartree-exchange part changes: H[P] = H_gs +
+ *                       h^3 Psi^T diag(V_Hx[P] - V_Hx[P_gs]) Psi, with H_gs built
+ *                       once by the full apply.  Same fixed point.
+ * precision RT_MIXED computes that perturbation projection and the density
+ * change from the ground state in BF16x3 (split hi/lo, FP32 accumulate) and
+ * keeps H_gs, rho_gs, the series, energy and dipole in FP64; it implies
+ * RT_HUPDATE_LOCAL.
+ */
+typedef struct {
+  double dt;           /* time step (a.u.)                                       */
+  int n_steps_max;     /* capacity of the dipole/energy history                  */
+  double h_thrs;       /* max|H_1 - H_1_old| that ends the self-consistent loop  */
+  double dp_thrs;      /* max|dP^(k)| that ends the commutator series            */
+  int max_scf;         /* cap on Hamiltonian updates per step (>= 1)             */
+  int max_terms;       /* cap on series terms per propagation (>= 1)             */
+  int precision;       /* RT_FP64 | RT_MIXED                                     */
+  int predictor;       /* RT_PRED_LINEAR | RT_PRED_MLP                           */
+  int hupdate;         /* RT_HUPDATE_FULL | RT_HUPDATE_LOCAL                     */
+  int frozen_hxc;      /* test switch: V_H and v_x fixed at the ground state     */
+  int n_traj;
+  const int* traj_sys;       /* [n_traj] index into the system array             */
+  const double* traj_kappa;  /* [n_traj] kick strength                           */
+  const int* traj_axis;      /* [n_traj] 0 = x, 1 = y, 2 = z                     */
+} rt_run;
+
+/* Per-trajectory, per-step counters written by rt_step when stats != NULL. */
+typedef struct {
+  int32_t scf_iters;   /* Hamiltonian updates in this step                       */
+  int32_t series_terms;/* commutator-series terms summed over those updates      */
+  double residual;     /* final max|H_1 - H_1_old|                               */
+} rt_step_stats;
+
+/* Bytes of device workspace rt_init needs for this problem. */
+rt_status rt_workspace_size(const rt_system* sys, int n_sys, const rt_run* run, size_t* bytes);
+
+/*
+ * Builds the context: uploads (and optionally orthonormalises) the orbitals,
+ * builds V_ion, projector tables, H_core and the dipole matrices
+ * M_q = h^3 Psi^T diag(q) Psi (q: centred sawtooth coordinate, Sec. Algorithm),
+ * then applies each trajectory's kick and computes H_0.
+ * workspace_dev: device memory of at least rt_workspace_size bytes, owned by
+ * the caller, untouched by the caller until rt_free.  hip_stream: a
+ * hipStream_t (NULL = default stream).  The library never allocates device
+ * memory itself.
+ */
+rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* workspace_dev,
+                  size_t ws_bytes, void* hip_stream, rt_ctx** out);
+
+/*
+ * (H psi_j)(r) = -1/2 L_FD psi_j + V_loc psi_j + V_nl psi_j for j < n_orb
+ * (Eq. DFT with the kinetic sign read as -1/2 Laplacian; 8th-order central
+ * differences, Sec. Overview of RMG), V_loc = V_ion + V_H + v_x of the
+ * system's current density (after rt_init: that of the last Hamiltonian
+ * update).  psi_dev, hpsi_dev: caller-owned device arrays [n_orb][nz][ny][nx]
+ * of dtype 0 = double, 1 = float; they must not overlap.
+ */
+rt_status rt_apply_h(rt_ctx* ctx, int sys_index, const void* psi_dev, void* hpsi_dev, int n_orb,
+                     int dtype);
+
+/*
+ * Advances every trajectory by n_steps steps of Algorithm 1: predictor
+ * H_1 = 2 H_0 - H_-1; repeat { Omega = -i dt (H_0 + H_1)/2; P_1 by the
+ * commutator series dP^(k) = (1/k)(-i dt)[Hbar, dP^(k-1)] until
+ * max|dP^(k)| <= dp_thrs (eq. commutator-expansion-ort); H_new = H[P_1] } until
+ * max|H_new - H_1| <= h_thrs; then H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 and
+ * record mu_q = Tr(P M_q) and E.  stats: host [n_steps][n_traj] or NULL.
+ * Returns RT_ENOCONV if a cap is hit; the state then stays at the last
+ * completed step.  RT_ESTATE once n_steps_max steps have been taken.
+ */
+rt_status rt_step(rt_ctx* ctx, int n_steps, rt_step_stats* stats);
+
+/*
+ * Copies the history of trajectory traj, steps first_step .. first_step+count-1
+ * (step 0 = just after the kick): mu_host [count][3] (dipole, mu_0 = 0) and
+ * optionally energy_host [count] (E = Tr(Re P H_core) + E_H + E_x) and
+ * trace_host [count] (Tr P).  Synchronises the stream.
+ */
+rt_status rt_dipole(rt_ctx* ctx, int traj, int first_step, int count, double* mu_host,
+                    double* energy_host, double* trace_host);
+
+/*
+ * Matrix getters (synchronise the stream); out: host [N][N] double.
+ * which: 0 = H_0, 1 = H_-1, 2 = Re P_0 (S'), 3 = Im P_0 (A'), 4 = H_core,
+ * 5/6/7 = M_x/M_y/M_z (traj selects the system through traj_sys).
+ */
+rt_status rt_get_matrix(rt_ctx* ctx, int traj, int which, double* out);
+
+/*
+ * Overwrites the state of trajectory traj: P = S' + i A' (host [N][N] each),
+ * H_0 and H_-1 (host [N][N]); NULL keeps the current value.  For checkpoint
+ * restore and tests.
+ */
+rt_status rt_set_state(rt_ctx* ctx, int traj, const double* p_re, const double* p_im,
+                       const double* h0, const double* hm1);
+
+/*
+ * Component entry points over caller-owned device buffers (for validation of
+ * single stages; they run the same kernels as rt_step):
+ *   rt_eval_h:    H_out = H[P] for the density matrix with real part p_re_dev
+ *                 [N][N] (Algorithm 1, H_1 <- DFT(rho(P_1))), using the
+ *                 context's hupdate/precision; also leaves rho, V_H, v_x of that
+ *                 density in the system (rho/vh/vx getters below).
+ *   rt_propagate: (p_re, p_im) <- U (p_re + i p_im) U^dagger with
+ *                 U = exp(-i dt Hbar) by the commutator series
+ *                 (eq. commutator-expansion-ort), thresholds dp_thrs/max_terms
+ *                 of the run; *terms_out gets the number of terms (nullable).
+ *   rt_get_grid:  copies the system's current grid field: 0 = rho, 1 = V_H,
+ *                 2 = v_x, 3 = V_ion, 4 = V_loc (host [nz][ny][nx]).
+ */
+rt_status rt_eval_h(rt_ctx* ctx, int sys_index, const double* p_re_dev, double* h_out_dev);
+rt_status rt_propagate(rt_ctx* ctx, int sys_index, const double* hbar_dev, double dt,
+                       double* p_re_dev, double* p_im_dev, int* terms_out);
+rt_status rt_get_grid(rt_ctx* ctx, int sys_index, int which, double* out_host);
+
+/*
+ * Phase timers.  rt_profile(ctx, enable, reset): from now on record a pair of
+ * hipEvents around every launch of the tracked kernel classes on the context's
+ * stream (enable != 0) or stop (0); reset != 0 zeroes the totals.  Synchronises.
+ * rt_profile_read: accumulated device time in ms and launch count of one phase
+ * (0 <= phase < 10); *name (nullable) gets its static name:
+ * stencil_fd8, nonlocal, project_gemm, reduce_partials, density, poisson_dft,
+ * lda_vloc, series_gemm, series_update, small_matrix.
+ */
+rt_status rt_profile(rt_ctx* ctx, int enable, int reset);
+rt_status rt_profile_read(rt_ctx* ctx, int phase, double* total_ms, long* launches, const char** name);
+
+/* Releases host-side state; the caller then frees the workspace. */
+void rt_free(rt_ctx* ctx);
+
+/* Message for the last failing call on ctx (or of rt_init when ctx is NULL). */
+const char* rt_last_error(const rt_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT_TDDFT_H */

@@ -1,0 +1,90 @@
+// Internal launcher declarations for the RT-TDDFT kernels (gfx950).
+// Every launcher enqueues on the given stream and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rtk {
+
+constexpr int kRedBlocks = 512;  // fixed block count of deterministic grid reductions
+
+// ---- grid fields -----------------------------------------------------------
+hipError_t vion(hipStream_t s, double* v, int nx, int ny, int nz, double h, int n_atoms,
+                const double* pos, const double* depth, const double* width, int n_images);
+hipError_t coord(hipStream_t s, double* q, int nx, int ny, int nz, double h, int axis);
+hipError_t fill(hipStream_t s, double* p, long n, double v);
+hipError_t fill_u64(hipStream_t s, unsigned long long* p, long n, unsigned long long v);
+hipError_t copy_d(hipStream_t s, double* dst, const double* src, long n);
+hipError_t cast_d2f(hipStream_t s, float* dst, const double* src, long n);
+hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, long n);
+
+// ---- Hamiltonian on the grid -------------------------------------------------
+// hpsi[j] = -1/2 L psi[j] + v psi[j] (8th-order FD, periodic), j < n_orb.
+template <typename T>
+hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
+                   int nz, double h, const double* coef5);
+// c[j][p] = h^3 sum_s beta[s][p] psi_j[idx[s]] over atom spheres (rank 4 or 1..4).
+template <typename T>
+hipError_t nl_gather(hipStream_t s, const T* psi, long ng, int n_orb, int n_atoms, int rank,
+                     const int* atom_off, const int* sph_idx, const double* beta, double h3,
+                     double* c);
+// hpsi_j[u] += sum_{entries e of u} beta[ent[e]][p] D[a p] c[j][a p].
+template <typename T>
+hipError_t nl_scatter(hipStream_t s, T* hpsi, long ng, int n_orb, int n_union, const int* u_idx,
+                      const int* u_ptr, const int* ent_pt, const int* ent_atom, int rank,
+                      const double* beta, const double* D, const double* c, int n_proj);
+
+// ---- dense products -----------------------------------------------------------
+// part[s][m][n] = sum_{k in split s} A[m][k] w[k] B[n][k]   (w nullable)
+// tiles with tn < tm skipped when upper != 0 (M == N).  kps: k per split.
+hipError_t gemm_nt_f64(hipStream_t s, int M, int N, long K, const double* A, long lda,
+                       const double* B, long ldb, const double* w, double* part, long kps,
+                       int n_split, int upper, int big);
+// C[m][n] = alpha * sum_s part[s][m][n]; mirror: C[n][m] = C[m][n] for m < n (upper part kept)
+hipError_t reduce_parts(hipStream_t s, const double* part, int n_split, int M, int N, double alpha,
+                        double* C, int mirror);
+// out = W . Psi (mode 0) or rho[r] = sum_i Psi[i][r] (W Psi)[i][r] (mode 1);
+// tri: 0 full, 1 W upper triangular, 2 W lower triangular.
+hipError_t smalltall_f64(hipStream_t s, int N, long ng, const double* W, const double* psi,
+                         double* out, int mode, int tri);
+
+// ---- Poisson (spectral) ---------------------------------------------------------
+hipError_t twiddles(hipStream_t s, double2* tw, int n);
+hipError_t pack_real(hipStream_t s, double2* z, const double* r, long n);
+hipError_t dft_axis(hipStream_t s, double2* z, int nx, int ny, int nz, int axis, const double2* tw,
+                    int inverse);
+hipError_t poisson_scale(hipStream_t s, double2* z, int nx, int ny, int nz, double h);
+hipError_t real_part(hipStream_t s, double* r, const double2* z, long n);
+
+// ---- exchange, local potential, energies -------------------------------------------
+// vx = -(3 rho/pi)^(1/3), vloc = vion + vh + vx; part[b] = (sum e_x, sum rho vh) per block.
+hipError_t lda_vloc(hipStream_t s, const double* rho, const double* vh, const double* vion,
+                    double* vx, double* vloc, long n, double* part2);
+// out[0..ncol) = scale[c] * sum_b part[b][c]   (single block, fixed order)
+hipError_t reduce_cols(hipStream_t s, const double* part, int nblk, int ncol, const double* scale3,
+                       double* out);
+
+// ---- N x N kernels ---------------------------------------------------------------
+hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double b, const double* y,
+                   long n);
+hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
+                        unsigned long long* slot);
+hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out);
+// one series term k (1-based): reads C = Hbar . [S;A]^T (N x 2N), writes dP_k stacked [2N][N],
+// adds to P1 stacked, max |dP_k| -> slots[k].  Skips when the series has already stopped.
+hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1, int N, double dt,
+                         int k, unsigned long long* slots, const double* kmin, double thrs,
+                         int* done);
+hipError_t gemm_nt_f64_series(hipStream_t s, int N, const double* Hbar, const double* dP, double* C,
+                              int k, const unsigned long long* slots, const double* kmin,
+                              double thrs, const int* done);
+hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots,
+                         const double* kmin, double thrs, int* done);
+// hist[j] = (mu_x, mu_y, mu_z, E, TrP) from S' and energies.
+hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
+                       const double* eparts, double* hist_row);
+hipError_t cholesky(hipStream_t s, double* A, int N, int* info);
+hipError_t tri_inverse_lower(hipStream_t s, const double* L, double* Linv, int N);
+hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N);
+
+}  // namespace rtk

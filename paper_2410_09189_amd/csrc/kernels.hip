@@ -1,0 +1,1012 @@
+// RT-TDDFT time-step kernels for gfx950 (MI355X, CDNA4, 64-wide wavefronts).
+//
+// Grid fields are [nz][ny][nx] (x fastest), orbitals [N][nz][ny][nx], N x N
+// matrices row-major.  All reductions use a fixed partition and a fixed
+// combination order, so repeated runs are bitwise identical; the only atomics
+// are max-reductions of non-negative doubles (order independent).
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+namespace rtk {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Deterministic block sum over 256 threads (tree in LDS).
+__device__ double block_sum_256(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) sh[t] += sh[t + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max_256(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) sh[t] = fmax(sh[t], sh[t + o]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* slot, double v) {
+  atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+// ============================================================================
+// Grid fields
+// ============================================================================
+
+// V_ion(r) = - sum_a D_a sum_images exp(-|r - R_a - nL|^2 / (2 w_a^2)); atoms
+// outer, images (i, j, k) inner, accumulated in that order.
+__global__ void k_vion(double* __restrict__ v, int nx, int ny, int nz, double h, int n_atoms,
+                       const double* __restrict__ pos, const double* __restrict__ depth,
+                       const double* __restrict__ width, int nim) {
+  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long ng = (long)nx * ny * nz;
+  if (g >= ng) return;
+  int ix = (int)(g % nx);
+  int iy = (int)((g / nx) % ny);
+  int iz = (int)(g / ((long)nx * ny));
+  double x = ix * h, y = iy * h, z = iz * h;
+  double Lx = nx * h, Ly = ny * h, Lz = nz * h;
+  double acc = 0.0;
+  for (int a = 0; a < n_atoms; ++a) {
+    double inv = 1.0 / (2.0 * width[a] * width[a]);
+    double D = depth[a];
+    for (int i = -nim; i <= nim; ++i) {
+      double dx = x - pos[3 * a] - i * Lx;
+      for (int j = -nim; j <= nim; ++j) {
+        double dy = y - pos[3 * a + 1] - j * Ly;
+        for (int k = -nim; k <= nim; ++k) {
+          double dz = z - pos[3 * a + 2] - k * Lz;
+          acc -= D * exp(-((dx * dx + dy * dy) + dz * dz) * inv);
+        }
+      }
+    }
+  }
+  v[g] = acc;
+}
+
+hipError_t vion(hipStream_t s, double* v, int nx, int ny, int nz, double h, int n_atoms,
+                const double* pos, const double* depth, const double* width, int n_images) {
+  long ng = (long)nx * ny * nz;
+  hipLaunchKernelGGL(k_vion, dim3(cdiv(ng, 256)), dim3(256), 0, s, v, nx, ny, nz, h, n_atoms, pos,
+                     depth, width, n_images);
+  return hipGetLastError();
+}
+
+// Centred sawtooth coordinate q_i = (i - (n-1)/2) h along one axis.
+__global__ void k_coord(double* q, int nx, int ny, int nz, double h, int axis) {
+  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long ng = (long)nx * ny * nz;
+  if (g >= ng) return;
+  int i, n;
+  if (axis == 0) { i = (int)(g % nx); n = nx; }
+  else if (axis == 1) { i = (int)((g / nx) % ny); n = ny; }
+  else { i = (int)(g / ((long)nx * ny)); n = nz; }
+  q[g] = (i - 0.5 * (n - 1)) * h;
+}
+
+hipError_t coord(hipStream_t s, double* q, int nx, int ny, int nz, double h, int axis) {
+  long ng = (long)nx * ny * nz;
+  hipLaunchKernelGGL(k_coord, dim3(cdiv(ng, 256)), dim3(256), 0, s, q, nx, ny, nz, h, axis);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* p, long n, double v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, long n, unsigned long long v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_copy(double* d, const double* a, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    d[i] = a[i];
+}
+__global__ void k_cast_d2f(float* d, const double* a, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    d[i] = (float)a[i];
+}
+__global__ void k_sub(double* d, const double* a, const double* b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    d[i] = a[i] - b[i];
+}
+static int ew_blocks(long n) { long b = (n + 255) / 256; return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b)); }
+
+hipError_t fill(hipStream_t s, double* p, long n, double v) {
+  hipLaunchKernelGGL(k_fill, dim3(ew_blocks(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t fill_u64(hipStream_t s, unsigned long long* p, long n, unsigned long long v) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(ew_blocks(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t copy_d(hipStream_t s, double* dst, const double* src, long n) {
+  hipLaunchKernelGGL(k_copy, dim3(ew_blocks(n)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+hipError_t cast_d2f(hipStream_t s, float* dst, const double* src, long n) {
+  hipLaunchKernelGGL(k_cast_d2f, dim3(ew_blocks(n)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, long n) {
+  hipLaunchKernelGGL(k_sub, dim3(ew_blocks(n)), dim3(256), 0, s, dst, a, b, n);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// FD8 stencil + local potential
+// ============================================================================
+//
+// One block = one orbital, all x, a tile of TY rows in y, a chunk of z planes.
+// The block marches in z: each thread keeps the 9-plane window of its columns
+// in registers (z neighbours), and the current plane with a 4-row y halo is
+// staged in LDS (x and y neighbours, periodic wrap).  Global reads are whole
+// x rows (coalesced); the halo rows are the neighbouring tiles' interiors.
+struct StencilCoef {
+  double c[5];  // -1/2 a_k / h^2
+};
+
+template <typename T, int COLS>
+__global__ __launch_bounds__(256) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
+                                                 const T* __restrict__ v, int nx, int ny, int nz,
+                                                 int TY, int ZC, StencilCoef cf) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sp = reinterpret_cast<T*>(smem_raw);  // [(TY + 8)][nx]
+  const int tid = threadIdx.x;
+  const int y0 = blockIdx.x * TY;
+  const int rows = min(TY, ny - y0);
+  const long orb = blockIdx.y;
+  const int z0 = blockIdx.z * ZC;
+  const int z1 = min(nz, z0 + ZC);
+  const long plane = (long)nx * ny;
+  const T* __restrict__ f = psi + orb * plane * nz;
+  T* __restrict__ o = hpsi + orb * plane * nz;
+  const T c0 = (T)(3.0 * cf.c[0]);
+  const T c1 = (T)cf.c[1], c2 = (T)cf.c[2], c3 = (T)cf.c[3], c4 = (T)cf.c[4];
+
+  int cx[COLS], cy[COLS];
+  bool ok[COLS];
+  T q[COLS][9];
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    int p = tid + c * 256;
+    int yl = p / nx;
+    ok[c] = yl < rows;
+    cx[c] = p - yl * nx;
+    cy[c] = yl;
+    if (ok[c]) {
+      long base = (long)(y0 + yl) * nx + cx[c];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) q[c][d] = f[(long)wrapi(z0 - 4 + d, nz) * plane + base];
+    }
+  }
+  const int halo_n = 8 * nx;
+  for (int z = z0; z < z1; ++z) {
+    const long zoff = (long)z * plane;
+    const long zf = (long)wrapi(z + 4, nz) * plane;
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      if (ok[c]) {
+        q[c][8] = f[zf + (long)(y0 + cy[c]) * nx + cx[c]];
+        sp[(cy[c] + 4) * nx + cx[c]] = q[c][4];
+      }
+    }
+    for (int e = tid; e < halo_n; e += 256) {
+      int hr = e / nx, x = e - hr * nx;
+      int yl = hr < 4 ? hr - 4 : rows + (hr - 4);
+      int y = wrapi(y0 + yl, ny);
+      sp[(yl + 4) * nx + x] = f[zoff + (long)y * nx + x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      if (ok[c]) {
+        const int x = cx[c];
+        const T* row = sp + (cy[c] + 4) * nx;
+        const T ctr = q[c][4];
+        int xp1 = x + 1 >= nx ? x + 1 - nx : x + 1, xm1 = x - 1 < 0 ? x - 1 + nx : x - 1;
+        int xp2 = x + 2 >= nx ? x + 2 - nx : x + 2, xm2 = x - 2 < 0 ? x - 2 + nx : x - 2;
+        int xp3 = x + 3 >= nx ? x + 3 - nx : x + 3, xm3 = x - 3 < 0 ? x - 3 + nx : x - 3;
+        int xp4 = x + 4 >= nx ? x + 4 - nx : x + 4, xm4 = x - 4 < 0 ? x - 4 + nx : x - 4;
+        T sx1 = row[xp1] + row[xm1], sx2 = row[xp2] + row[xm2];
+        T sx3 = row[xp3] + row[xm3], sx4 = row[xp4] + row[xm4];
+        T sy1 = row[nx + x] + row[-nx + x], sy2 = row[2 * nx + x] + row[-2 * nx + x];
+        T sy3 = row[3 * nx + x] + row[-3 * nx + x], sy4 = row[4 * nx + x] + row[-4 * nx + x];
+        T sz1 = q[c][5] + q[c][3], sz2 = q[c][6] + q[c][2];
+        T sz3 = q[c][7] + q[c][1], sz4 = q[c][8] + q[c][0];
+        T acc = c0 * ctr;
+        acc += c1 * ((sx1 + sy1) + sz1);
+        acc += c2 * ((sx2 + sy2) + sz2);
+        acc += c3 * ((sx3 + sy3) + sz3);
+        acc += c4 * ((sx4 + sy4) + sz4);
+        const long gi = zoff + (long)(y0 + cy[c]) * nx + x;
+        o[gi] = acc + v[gi] * ctr;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) q[c][d] = q[c][d + 1];
+    }
+  }
+}
+
+template <typename T>
+hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
+                   int nz, double h, const double* a) {
+  StencilCoef cf;
+  for (int k = 0; k < 5; ++k) cf.c[k] = -0.5 * a[k] / (h * h);
+  int TY = 1;
+  const int cand[] = {16, 12, 10, 8, 6, 5, 4, 3, 2, 1};
+  for (int t : cand) {
+    if (t <= ny && ny % t == 0 && t * nx <= 2048) { TY = t; break; }
+  }
+  int cols = (TY * nx + 255) / 256;
+  int tiles = ny / TY;
+  int nzc = 1;
+  long blocks = (long)tiles * n_orb;
+  while (blocks * nzc < 2048 && nz / (nzc * 2) >= 16) nzc *= 2;
+  int ZC = (nz + nzc - 1) / nzc;
+  nzc = (nz + ZC - 1) / ZC;
+  size_t lds = (size_t)(TY + 8) * nx * sizeof(T);
+  dim3 grid(tiles, n_orb, nzc);
+  if (cols <= 1)
+    hipLaunchKernelGGL((k_stencil<T, 1>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
+  else if (cols <= 2)
+    hipLaunchKernelGGL((k_stencil<T, 2>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
+  else if (cols <= 4)
+    hipLaunchKernelGGL((k_stencil<T, 4>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
+  else
+    hipLaunchKernelGGL((k_stencil<T, 8>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
+  return hipGetLastError();
+}
+template hipError_t stencil<double>(hipStream_t, const double*, double*, const double*, int, int, int,
+                                    int, double, const double*);
+template hipError_t stencil<float>(hipStream_t, const float*, float*, const float*, int, int, int, int,
+                                   double, const double*);
+
+// ============================================================================
+// Separable nonlocal projectors
+// ============================================================================
+// gather: one block per (atom, group of 4 orbitals).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nl_gather(const T* __restrict__ psi, long ng, int n_orb,
+                                                   int rank, const int* __restrict__ atom_off,
+                                                   const int* __restrict__ sph_idx,
+                                                   const double* __restrict__ beta, double h3,
+                                                   double* __restrict__ c, int n_proj) {
+  __shared__ double sh[256];
+  const int a = blockIdx.x;
+  const int s0 = atom_off[a], s1 = atom_off[a + 1];
+  for (int jj = 0; jj < 4; ++jj) {
+    const int j = blockIdx.y * 4 + jj;
+    if (j >= n_orb) break;
+    const T* f = psi + (long)j * ng;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int sp = s0 + threadIdx.x; sp < s1; sp += 256) {
+      double val = (double)f[sph_idx[sp]];
+      for (int p = 0; p < rank; ++p) acc[p] += beta[(long)sp * rank + p] * val;
+    }
+    for (int p = 0; p < rank; ++p) {
+      double t = block_sum_256(acc[p], sh);
+      if (threadIdx.x == 0) c[(long)j * n_proj + a * rank + p] = h3 * t;
+    }
+  }
+}
+
+template <typename T>
+hipError_t nl_gather(hipStream_t s, const T* psi, long ng, int n_orb, int n_atoms, int rank,
+                     const int* atom_off, const int* sph_idx, const double* beta, double h3,
+                     double* c) {
+  dim3 grid(n_atoms, cdiv(n_orb, 4));
+  hipLaunchKernelGGL((k_nl_gather<T>), grid, dim3(256), 0, s, psi, ng, n_orb, rank, atom_off, sph_idx,
+                     beta, h3, c, n_atoms * rank);
+  return hipGetLastError();
+}
+template hipError_t nl_gather<double>(hipStream_t, const double*, long, int, int, int, const int*,
+                                      const int*, const double*, double, double*);
+template hipError_t nl_gather<float>(hipStream_t, const float*, long, int, int, int, const int*,
+                                     const int*, const double*, double, double*);
+
+template <typename T>
+__global__ void k_nl_scatter(T* __restrict__ hpsi, long ng, int n_union, const int* __restrict__ u_idx,
+                             const int* __restrict__ u_ptr, const int* __restrict__ ent_pt,
+                             const int* __restrict__ ent_atom, int rank, const double* __restrict__ beta,
+                             const double* __restrict__ D, const double* __restrict__ c, int n_proj) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n_union) return;
+  const long j = blockIdx.y;
+  const double* cj = c + j * n_proj;
+  double acc = 0.0;
+  for (int e = u_ptr[u]; e < u_ptr[u + 1]; ++e) {
+    const int a = ent_atom[e];
+    const long sp = ent_pt[e];
+    for (int p = 0; p < rank; ++p) acc += beta[sp * rank + p] * (D[a * rank + p] * cj[a * rank + p]);
+  }
+  T* o = hpsi + j * ng + u_idx[u];
+  *o = (T)((double)*o + acc);
+}
+
+template <typename T>
+hipError_t nl_scatter(hipStream_t s, T* hpsi, long ng, int n_orb, int n_union, const int* u_idx,
+                      const int* u_ptr, const int* ent_pt, const int* ent_atom, int rank,
+                      const double* beta, const double* D, const double* c, int n_proj) {
+  dim3 grid(cdiv(n_union, 256), n_orb);
+  hipLaunchKernelGGL((k_nl_scatter<T>), grid, dim3(256), 0, s, hpsi, ng, n_union, u_idx, u_ptr, ent_pt,
+                     ent_atom, rank, beta, D, c, n_proj);
+  return hipGetLastError();
+}
+template hipError_t nl_scatter<double>(hipStream_t, double*, long, int, int, const int*, const int*,
+                                       const int*, const int*, int, const double*, const double*,
+                                       const double*, int);
+template hipError_t nl_scatter<float>(hipStream_t, float*, long, int, int, const int*, const int*,
+                                      const int*, const int*, int, const double*, const double*,
+                                      const double*, int);
+
+// ============================================================================
+// FP64 MFMA GEMM, C = A . B^T with both operands K-contiguous (tall-skinny
+// projections over the grid and the N x N series products)
+// ============================================================================
+//
+// v_mfma_f64_16x16x4f64 fragment layout (64 lanes): A[m = lane%16][k = lane/16],
+// B^T[k = lane/16][n = lane%16]; the 16x16 result sits in 4 doubles per lane at
+// row 4*(lane/16) + r, column lane%16.  A block of 256 threads (2 x 2 waves)
+// computes a BM x BN tile; K is split across blockIdx.y into fixed ranges
+// whose partial tiles are summed afterwards in a fixed order.
+struct SeriesSkip {
+  const unsigned long long* slots;  // max |dP_k| per term (bits of a non-negative double)
+  const double* kmin;
+  const int* done;
+  double thrs;
+  int k;  // term this launch computes (1-based); 0 = not a series launch
+};
+
+__device__ __forceinline__ bool series_stopped(const SeriesSkip& sk) {
+  if (sk.k <= 1) return false;
+  if (*sk.done) return true;
+  double prev = __longlong_as_double((long long)sk.slots[sk.k - 1]);
+  return prev <= sk.thrs && (double)(sk.k - 1) >= *sk.kmin;
+}
+
+template <int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const double* __restrict__ A,
+                                                     long lda, const double* __restrict__ B, long ldb,
+                                                     const double* __restrict__ w,
+                                                     double* __restrict__ part, long kps, int upper,
+                                                     int n_tn, SeriesSkip sk) {
+  if (sk.k > 0 && series_stopped(sk)) return;
+  constexpr int PAD = 1;
+  __shared__ double As[BM][BK + PAD];
+  __shared__ double Bs[BN][BK + PAD];
+  int tm, tn;
+  {
+    int t = blockIdx.x;
+    if (upper) {
+      tm = 0;
+      int rowlen = n_tn;
+      while (t >= rowlen) { t -= rowlen; ++tm; --rowlen; }
+      tn = tm + t;
+    } else {
+      tm = t / n_tn;
+      tn = t - tm * n_tn;
+    }
+  }
+  const long k0 = (long)blockIdx.y * kps;
+  const long k1 = min(K, k0 + kps);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  dbl4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const long am0 = (long)tm * BM, bn0 = (long)tn * BN;
+  for (long kb = k0; kb < k1; kb += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      int r = e / BK, c = e - r * BK;
+      long gm = am0 + r, gk = kb + c;
+      double val = 0.0;
+      if (gm < M && gk < k1) {
+        val = A[gm * lda + gk];
+        if (w) val *= w[gk];
+      }
+      As[r][c] = val;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      int r = e / BK, c = e - r * BK;
+      long gn = bn0 + r, gk = kb + c;
+      Bs[r][c] = (gn < N && gk < k1) ? B[gn * ldb + gk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = As[wm * WM + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bf[j] = Bs[wn * WN + j * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* P = part + (long)blockIdx.y * M * N;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        long row = am0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        long col = bn0 + wn * WN + j * 16 + (lane & 15);
+        if (row < M && col < N) P[row * N + col] = acc[i][j][r];
+      }
+}
+
+static hipError_t gemm_launch(hipStream_t s, int M, int N, long K, const double* A, long lda,
+                              const double* B, long ldb, const double* w, double* part, long kps,
+                              int n_split, int upper, int big, SeriesSkip sk) {
+  if (big) {
+    int ntm = cdiv(M, 128), ntn = cdiv(N, 128);
+    int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
+    hipLaunchKernelGGL((k_gemm_nt_f64<128, 128, 16>), dim3(nt, n_split), dim3(256), 0, s, M, N, K, A,
+                       lda, B, ldb, w, part, kps, upper, ntn, sk);
+  } else {
+    int ntm = cdiv(M, 64), ntn = cdiv(N, 64);
+    int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
+    hipLaunchKernelGGL((k_gemm_nt_f64<64, 64, 32>), dim3(nt, n_split), dim3(256), 0, s, M, N, K, A,
+                       lda, B, ldb, w, part, kps, upper, ntn, sk);
+  }
+  return hipGetLastError();
+}
+
+hipError_t gemm_nt_f64(hipStream_t s, int M, int N, long K, const double* A, long lda,
+                       const double* B, long ldb, const double* w, double* part, long kps,
+                       int n_split, int upper, int big) {
+  SeriesSkip sk{nullptr, nullptr, nullptr, 0.0, 0};
+  return gemm_launch(s, M, N, K, A, lda, B, ldb, w, part, kps, n_split, upper, big, sk);
+}
+
+hipError_t gemm_nt_f64_series(hipStream_t s, int N, const double* Hbar, const double* dP, double* C,
+                              int k, const unsigned long long* slots, const double* kmin,
+                              double thrs, const int* done) {
+  SeriesSkip sk{slots, kmin, done, thrs, k};
+  return gemm_launch(s, N, 2 * N, N, Hbar, N, dP, N, nullptr, C, N, 1, 0, 0, sk);
+}
+
+__global__ void k_reduce_parts(const double* __restrict__ part, int n_split, int M, int N, double alpha,
+                               double* __restrict__ C, int mirror) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)M * N) return;
+  int m = (int)(e / N), n = (int)(e - (long)m * N);
+  if (mirror && m > n) return;
+  double acc = 0.0;
+  for (int sI = 0; sI < n_split; ++sI) acc += part[(long)sI * M * N + e];
+  acc *= alpha;
+  C[e] = acc;
+  if (mirror && m < n) C[(long)n * N + m] = acc;
+}
+
+hipError_t reduce_parts(hipStream_t s, const double* part, int n_split, int M, int N, double alpha,
+                        double* C, int mirror) {
+  long n = (long)M * N;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(cdiv(n, 256)), dim3(256), 0, s, part, n_split, M, N, alpha, C,
+                     mirror);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Small x tall FP64 MFMA product over grid columns: Phi = W . Psi with either
+// Phi stored (orthonormalisation) or rho[r] = sum_i Psi[i][r] Phi[i][r]
+// reduced in the epilogue (density from a density matrix), Phi never stored.
+// ============================================================================
+template <int MODE>
+__global__ __launch_bounds__(256) void k_smalltall_f64(int N, long ng, const double* __restrict__ W,
+                                                       const double* __restrict__ psi,
+                                                       double* __restrict__ out, int tri) {
+  constexpr int BM = 64, BN = 64, BK = 32;
+  __shared__ double Ws[BM][BK + 1];
+  __shared__ double Ps[BK][BN + 1];
+  __shared__ double red[2][4][BN];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long r0 = (long)blockIdx.x * BN;
+  double rho_part[2] = {0.0, 0.0};
+  const int nI = cdiv(N, BM);
+  for (int I = 0; I < nI; ++I) {
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = (dbl4){0.0, 0.0, 0.0, 0.0};
+    int jlo = 0, jhi = N;
+    if (tri == 1) jlo = I * BM;
+    if (tri == 2) jhi = min(N, (I + 1) * BM);
+    for (int jb = jlo; jb < jhi; jb += BK) {
+      for (int e = tid; e < BM * BK; e += 256) {
+        int r = e / BK, c = e - r * BK;
+        int gi = I * BM + r, gj = jb + c;
+        Ws[r][c] = (gi < N && gj < jhi) ? W[(long)gi * N + gj] : 0.0;
+      }
+      for (int e = tid; e < BK * BN; e += 256) {
+        int r = e / BN, c = e - r * BN;
+        int gj = jb + r;
+        long gr = r0 + c;
+        Ps[r][c] = (gj < jhi && gr < ng) ? psi[(long)gj * ng + gr] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = Ws[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bf[j] = Ps[kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int row = I * BM + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+          long col = r0 + wn * 32 + j * 16 + (lane & 15);
+          if (row < N && col < ng) {
+            if (MODE == 0) out[(long)row * ng + col] = acc[i][j][r];
+            else rho_part[j] += psi[(long)row * ng + col] * acc[i][j][r];
+          }
+        }
+  }
+  if (MODE == 1) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) red[wm][lane >> 4][wn * 32 + j * 16 + (lane & 15)] = rho_part[j];
+    __syncthreads();
+    if (tid < BN) {
+      double acc = 0.0;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 4; ++b) acc += red[a][b][tid];
+      if (r0 + tid < ng) out[r0 + tid] = acc;
+    }
+  }
+}
+
+hipError_t smalltall_f64(hipStream_t s, int N, long ng, const double* W, const double* psi,
+                         double* out, int mode, int tri) {
+  dim3 grid(cdiv(ng, 64));
+  if (mode == 0)
+    hipLaunchKernelGGL((k_smalltall_f64<0>), grid, dim3(256), 0, s, N, ng, W, psi, out, tri);
+  else
+    hipLaunchKernelGGL((k_smalltall_f64<1>), grid, dim3(256), 0, s, N, ng, W, psi, out, tri);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Spectral Poisson: discrete Fourier transforms along each axis in LDS
+// ============================================================================
+__global__ void k_twiddles(double2* tw, int n) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double sv, cv;
+  sincospi(2.0 * p / n, &sv, &cv);
+  tw[p] = make_double2(cv, sv);
+}
+hipError_t twiddles(hipStream_t s, double2* tw, int n) {
+  hipLaunchKernelGGL(k_twiddles, dim3(cdiv(n, 256)), dim3(256), 0, s, tw, n);
+  return hipGetLastError();
+}
+
+__global__ void k_pack_real(double2* z, const double* r, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    z[i] = make_double2(r[i], 0.0);
+}
+__global__ void k_real_part(double* r, const double2* z, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    r[i] = z[i].x;
+}
+hipError_t pack_real(hipStream_t s, double2* z, const double* r, long n) {
+  hipLaunchKernelGGL(k_pack_real, dim3(ew_blocks(n)), dim3(256), 0, s, z, r, n);
+  return hipGetLastError();
+}
+hipError_t real_part(hipStream_t s, double* r, const double2* z, long n) {
+  hipLaunchKernelGGL(k_real_part, dim3(ew_blocks(n)), dim3(256), 0, s, r, z, n);
+  return hipGetLastError();
+}
+
+// Lines of length n: element p of line (o, c) at o*os + p*st + c, c in [c0, c0+TC).
+// X[m] = sum_p x[p] exp(-+ 2 pi i m p / n).
+template <int TC>
+__global__ __launch_bounds__(256) void k_dft_lines(double2* __restrict__ z, int n, long st, long os,
+                                                   int C, const double2* __restrict__ tw, int inverse) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* tws = reinterpret_cast<double2*>(smem_raw);
+  double2* buf = tws + n;  // [n][TC]
+  const int c0 = blockIdx.x * TC;
+  const long base = (long)blockIdx.y * os;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) tws[p] = tw[p];
+  const int cw = min(TC, C - c0);
+  for (int e = threadIdx.x; e < n * TC; e += blockDim.x) {
+    int p = e / TC, c = e - p * TC;
+    buf[e] = c < cw ? z[base + p * st + c0 + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const double sgn = inverse ? 1.0 : -1.0;
+  for (int e = threadIdx.x; e < n * TC; e += blockDim.x) {
+    int m = e / TC, c = e - m * TC;
+    if (c >= cw) continue;
+    double re = 0.0, im = 0.0;
+    int idx = 0;
+    for (int p = 0; p < n; ++p) {
+      double2 x = buf[p * TC + c];
+      double2 t = tws[idx];
+      double ti = sgn * t.y;
+      re += x.x * t.x - x.y * ti;
+      im += x.x * ti + x.y * t.x;
+      idx += m;
+      if (idx >= n) idx -= n;
+    }
+    z[base + m * st + c0 + c] = make_double2(re, im);
+  }
+}
+
+// x lines are contiguous: treat each line as (o = line index, c = 0..0) with
+// TC = 1 would waste LDS bandwidth; instead lines of x are processed with the
+// line index as the inner "c" through a transposed view: element p of line l
+// at l*nx + p.
+__global__ __launch_bounds__(256) void k_dft_x(double2* __restrict__ z, int n, long n_lines,
+                                               const double2* __restrict__ tw, int inverse) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* tws = reinterpret_cast<double2*>(smem_raw);
+  const int lpb = max(1, 256 / n);
+  double2* buf = tws + n;  // [lpb][n]
+  const long l0 = (long)blockIdx.x * lpb;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) tws[p] = tw[p];
+  const int nl = (int)min((long)lpb, n_lines - l0);
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) buf[e] = z[l0 * n + e];
+  __syncthreads();
+  const double sgn = inverse ? 1.0 : -1.0;
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    int l = e / n, m = e - l * n;
+    double re = 0.0, im = 0.0;
+    int idx = 0;
+    const double2* x = buf + l * n;
+    for (int p = 0; p < n; ++p) {
+      double2 t = tws[idx];
+      double ti = sgn * t.y;
+      re += x[p].x * t.x - x[p].y * ti;
+      im += x[p].x * ti + x[p].y * t.x;
+      idx += m;
+      if (idx >= n) idx -= n;
+    }
+    z[l0 * n + e] = make_double2(re, im);
+  }
+}
+
+hipError_t dft_axis(hipStream_t s, double2* z, int nx, int ny, int nz, int axis, const double2* tw,
+                    int inverse) {
+  if (axis == 0) {
+    long n_lines = (long)ny * nz;
+    int lpb = nx >= 256 ? 1 : 256 / nx;
+    size_t lds = (size_t)(nx + lpb * nx) * sizeof(double2);
+    hipLaunchKernelGGL(k_dft_x, dim3(cdiv(n_lines, lpb)), dim3(256), lds, s, z, nx, n_lines, tw, inverse);
+  } else {
+    constexpr int TC = 16;
+    int n = axis == 1 ? ny : nz;
+    long st = axis == 1 ? nx : (long)nx * ny;
+    int C = axis == 1 ? nx : nx * ny;
+    int n_outer = axis == 1 ? nz : 1;
+    long os = axis == 1 ? (long)nx * ny : 0;
+    size_t lds = (size_t)(n + n * TC) * sizeof(double2);
+    hipLaunchKernelGGL((k_dft_lines<TC>), dim3(cdiv(C, TC), n_outer), dim3(256), lds, s, z, n, st, os, C,
+                       tw, inverse);
+  }
+  return hipGetLastError();
+}
+
+// V_H(G) = 4 pi rho(G) / |G|^2 / Ng (inverse-transform normalisation folded in), V_H(0) = 0.
+__global__ void k_poisson_scale(double2* z, int nx, int ny, int nz, double h) {
+  long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long ng = (long)nx * ny * nz;
+  if (g >= ng) return;
+  int ix = (int)(g % nx), iy = (int)((g / nx) % ny), iz = (int)(g / ((long)nx * ny));
+  int mx = ix < (nx + 1) / 2 ? ix : ix - nx;
+  int my = iy < (ny + 1) / 2 ? iy : iy - ny;
+  int mz = iz < (nz + 1) / 2 ? iz : iz - nz;
+  double gx = 2.0 * M_PI * mx / (nx * h), gy = 2.0 * M_PI * my / (ny * h), gz = 2.0 * M_PI * mz / (nz * h);
+  double g2 = (gz * gz + gy * gy) + gx * gx;
+  double f = g2 > 0.0 ? 4.0 * M_PI / (g2 * (double)ng) : 0.0;
+  double2 v = z[g];
+  z[g] = make_double2(v.x * f, v.y * f);
+}
+hipError_t poisson_scale(hipStream_t s, double2* z, int nx, int ny, int nz, double h) {
+  long ng = (long)nx * ny * nz;
+  hipLaunchKernelGGL(k_poisson_scale, dim3(cdiv(ng, 256)), dim3(256), 0, s, z, nx, ny, nz, h);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// LDA exchange, local potential and energy partial sums
+// ============================================================================
+__global__ __launch_bounds__(256) void k_lda_vloc(const double* __restrict__ rho,
+                                                  const double* __restrict__ vh,
+                                                  const double* __restrict__ vion, double* __restrict__ vx,
+                                                  double* __restrict__ vloc, long n, double* part2) {
+  __shared__ double sh[256];
+  const double cx = cbrt(3.0 / M_PI);
+  double ex_sum = 0.0, eh_sum = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double r = rho[i];
+    double rc = r > 0.0 ? r : 0.0;
+    double c = cbrt(rc);
+    double v = -cx * c;
+    vx[i] = v;
+    double h = vh[i];
+    vloc[i] = (vion[i] + h) + v;
+    ex_sum += -0.75 * cx * rc * c;
+    eh_sum += r * h;
+  }
+  double a = block_sum_256(ex_sum, sh);
+  double b = block_sum_256(eh_sum, sh);
+  if (threadIdx.x == 0) {
+    part2[2 * blockIdx.x] = a;
+    part2[2 * blockIdx.x + 1] = b;
+  }
+}
+hipError_t lda_vloc(hipStream_t s, const double* rho, const double* vh, const double* vion, double* vx,
+                    double* vloc, long n, double* part2) {
+  hipLaunchKernelGGL(k_lda_vloc, dim3(kRedBlocks), dim3(256), 0, s, rho, vh, vion, vx, vloc, n, part2);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_reduce_cols(const double* part, int nblk, int ncol,
+                                                     const double* scale, double* out) {
+  __shared__ double sh[256];
+  for (int c = 0; c < ncol; ++c) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += part[(long)b * ncol + c];
+    double t = block_sum_256(acc, sh);
+    if (threadIdx.x == 0) out[c] = t * scale[c];
+  }
+}
+hipError_t reduce_cols(hipStream_t s, const double* part, int nblk, int ncol, const double* scale,
+                       double* out) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, s, part, nblk, ncol, scale, out);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// N x N kernels
+// ============================================================================
+__global__ void k_lincomb(double* out, double a, const double* x, double b, const double* y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = a * x[i] + b * y[i];
+}
+hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double b, const double* y,
+                   long n) {
+  hipLaunchKernelGGL(k_lincomb, dim3(ew_blocks(n)), dim3(256), 0, s, out, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_max_abs_diff(const double* a, const double* b, long n,
+                                                      unsigned long long* slot) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(a[i] - b[i]));
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) atomic_max_nonneg(slot, m);
+}
+hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n, unsigned long long* slot) {
+  hipLaunchKernelGGL(k_max_abs_diff, dim3(ew_blocks(n) > 256 ? 256 : ew_blocks(n)), dim3(256), 0, s, a, b,
+                     n, slot);
+  return hipGetLastError();
+}
+
+// k_min = ceil(dt * (max_i (a_ii + r_i) - min_i (a_ii - r_i))), r_i = sum_{j != i} |a_ij|.
+__global__ __launch_bounds__(256) void k_gershgorin(const double* A, int N, double dt, double* kmin) {
+  __shared__ double sh[256];
+  double hi = -1e300, lo = 1e300;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    double r = 0.0;
+    for (int j = 0; j < N; ++j)
+      if (j != i) r += fabs(A[(long)i * N + j]);
+    double d = A[(long)i * N + i];
+    hi = fmax(hi, d + r);
+    lo = fmin(lo, d - r);
+  }
+  hi = block_max_256(hi, sh);
+  lo = -block_max_256(-lo, sh);
+  if (threadIdx.x == 0) *kmin = ceil(fabs(dt) * (hi - lo));
+}
+hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out) {
+  hipLaunchKernelGGL(k_gershgorin, dim3(1), dim3(256), 0, s, A, N, dt, kmin_out);
+  return hipGetLastError();
+}
+
+// dP_k = (1/k)(-i dt)[Hbar, S + iA]:  S_k = (dt/k)[Hbar, A],  A_k = -(dt/k)[Hbar, S].
+// C = Hbar . [S; A]^T, so C[:, :N] = Hbar S and C[:, N:] = -Hbar A (S symmetric, A antisymmetric).
+__global__ __launch_bounds__(256) void k_series_update(const double* __restrict__ C, double* __restrict__ dPn,
+                                                       double* __restrict__ P1, int N, double dt,
+                                                       SeriesSkip sk, int* done) {
+  __shared__ double sh[256];
+  if (series_stopped(sk)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && done[0] == 0) {
+      done[0] = 1;
+      done[1] = sk.k - 1;
+    }
+    return;
+  }
+  const double f = dt / sk.k;
+  const long NN = (long)N * N;
+  const long N2 = 2L * N;
+  double m = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += (long)gridDim.x * blockDim.x) {
+    int i = (int)(e / N), j = (int)(e - (long)i * N);
+    double gA_ij = C[(long)i * N2 + N + j], gA_ji = C[(long)j * N2 + N + i];
+    double gS_ij = C[(long)i * N2 + j], gS_ji = C[(long)j * N2 + i];
+    double s = -f * (gA_ij + gA_ji);
+    double a = -f * (gS_ij - gS_ji);
+    dPn[e] = s;
+    dPn[NN + e] = a;
+    P1[e] += s;
+    P1[NN + e] += a;
+    m = fmax(m, sqrt(s * s + a * a));
+  }
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) atomic_max_nonneg(const_cast<unsigned long long*>(sk.slots) + sk.k, m);
+}
+hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1, int N, double dt, int k,
+                         unsigned long long* slots, const double* kmin, double thrs, int* done) {
+  SeriesSkip sk{slots, kmin, done, thrs, k};
+  long NN = (long)N * N;
+  int nb = ew_blocks(NN);
+  if (nb > 256) nb = 256;
+  hipLaunchKernelGGL(k_series_update, dim3(nb), dim3(256), 0, s, C, dPn, P1, N, dt, sk, done);
+  return hipGetLastError();
+}
+
+__global__ void k_series_finish(SeriesSkip sk, int* done) {
+  if (threadIdx.x == 0 && done[0] == 0 && series_stopped(sk)) {
+    done[0] = 1;
+    done[1] = sk.k - 1;
+  }
+}
+hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, const double* kmin,
+                         double thrs, int* done) {
+  SeriesSkip sk{slots, kmin, done, thrs, kmax + 1};
+  hipLaunchKernelGGL(k_series_finish, dim3(1), dim3(64), 0, s, sk, done);
+  return hipGetLastError();
+}
+
+// mu_q = sum_ij S_ij M_q,ij ; E = sum_ij S_ij Hcore_ij + E_x + E_H ; TrP = sum_i S_ii.
+__global__ __launch_bounds__(256) void k_observables(const double* S, const double* M3, const double* hc,
+                                                     int N, const double* eparts, double* row) {
+  __shared__ double sh[256];
+  const long NN = (long)N * N;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+  for (long e = threadIdx.x; e < NN; e += 256) {
+    double s = S[e];
+    a0 += s * M3[e];
+    a1 += s * M3[NN + e];
+    a2 += s * M3[2 * NN + e];
+    a3 += s * hc[e];
+  }
+  for (int i = threadIdx.x; i < N; i += 256) a4 += S[(long)i * N + i];
+  a0 = block_sum_256(a0, sh);
+  a1 = block_sum_256(a1, sh);
+  a2 = block_sum_256(a2, sh);
+  a3 = block_sum_256(a3, sh);
+  a4 = block_sum_256(a4, sh);
+  if (threadIdx.x == 0) {
+    row[0] = a0;
+    row[1] = a1;
+    row[2] = a2;
+    row[3] = a3 + eparts[0] + eparts[1];
+    row[4] = a4;
+  }
+}
+hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
+                       const double* eparts, double* hist_row) {
+  hipLaunchKernelGGL(k_observables, dim3(1), dim3(256), 0, s, S, M3, hcore, N, eparts, hist_row);
+  return hipGetLastError();
+}
+
+// In-place Cholesky A = L L^T (lower part; upper part zeroed), one block, left-looking.
+__global__ __launch_bounds__(256) void k_cholesky(double* A, int N, int* info) {
+  __shared__ double sh[256];
+  __shared__ double djj;
+  if (threadIdx.x == 0) *info = 0;
+  for (int j = 0; j < N; ++j) {
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < j; k += 256) acc += A[(long)j * N + k] * A[(long)j * N + k];
+    acc = block_sum_256(acc, sh);
+    if (threadIdx.x == 0) {
+      double d = A[(long)j * N + j] - acc;
+      if (!(d > 0.0)) {
+        if (*info == 0) *info = j + 1;
+        d = 1.0;
+      }
+      djj = sqrt(d);
+      A[(long)j * N + j] = djj;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < N; i += 256) {
+      double t = A[(long)i * N + j];
+      for (int k = 0; k < j; ++k) t -= A[(long)i * N + k] * A[(long)j * N + k];
+      A[(long)i * N + j] = t / djj;
+    }
+    __syncthreads();
+  }
+  for (long e = threadIdx.x; e < (long)N * N; e += 256) {
+    int i = (int)(e / N), j = (int)(e - (long)i * N);
+    if (j > i) A[e] = 0.0;
+  }
+}
+hipError_t cholesky(hipStream_t s, double* A, int N, int* info) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, s, A, N, info);
+  return hipGetLastError();
+}
+
+// Linv = L^-1 for lower-triangular L: one column per thread by forward substitution.
+__global__ void k_tri_inverse_lower(const double* L, double* X, int N) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  for (int i = 0; i < c; ++i) X[(long)i * N + c] = 0.0;
+  for (int i = c; i < N; ++i) {
+    double t = (i == c) ? 1.0 : 0.0;
+    for (int k = c; k < i; ++k) t -= L[(long)i * N + k] * X[(long)k * N + c];
+    X[(long)i * N + c] = t / L[(long)i * N + i];
+  }
+}
+hipError_t tri_inverse_lower(hipStream_t s, const double* L, double* Linv, int N) {
+  hipLaunchKernelGGL(k_tri_inverse_lower, dim3(cdiv(N, 64)), dim3(64), 0, s, L, Linv, N);
+  return hipGetLastError();
+}
+
+// W_ij = S_ij * (2 if i < j, 1 if i == j, 0 if i > j): rho = sum_i psi_i sum_{j >= i} W_ij psi_j.
+__global__ void k_upper_weighted(const double* S, double* W, int N) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)N * N) return;
+  int i = (int)(e / N), j = (int)(e - (long)i * N);
+  W[e] = i < j ? 2.0 * S[e] : (i == j ? S[e] : 0.0);
+}
+hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N) {
+  long n = (long)N * N;
+  hipLaunchKernelGGL(k_upper_weighted, dim3(cdiv(n, 256)), dim3(256), 0, s, S, W, N);
+  return hipGetLastError();
+}
+
+}  // namespace rtk

@@ -1,0 +1,262 @@
+"""ctypes binding of include/rt_tddft.h (argument marshalling only).
+
+Every numerical step runs in the HIP library librt_tddft.so; this module only
+lays out the C structs, keeps host arrays alive for the duration of a call and
+turns status codes into exceptions.  PyTorch, when used, supplies the device
+workspace and the stream.  Importing this module loads the library and fails
+loudly if it has not been built.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt_tddft.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ENOCONV, RT_ESTATE = 0, -1, -2, -3, -4, -5
+RT_FP64, RT_MIXED = 0, 1
+RT_PRED_LINEAR, RT_PRED_MLP = 0, 1
+RT_HUPDATE_FULL, RT_HUPDATE_LOCAL = 0, 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class rt_system(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+        ("n_atoms", ctypes.c_int), ("pos", _dp), ("depth", _dp), ("width", _dp),
+        ("n_images", ctypes.c_int), ("nl_rank", ctypes.c_int), ("nl_rcut", ctypes.c_double),
+        ("nl_sigma", ctypes.c_double), ("nl_D", _dp), ("n_occ", ctypes.c_int),
+        ("n_virt", ctypes.c_int), ("occ", _dp), ("psi0", ctypes.c_void_p),
+        ("psi0_on_device", ctypes.c_int), ("orthonormalize", ctypes.c_int),
+    ]
+
+
+class rt_run(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double), ("n_steps_max", ctypes.c_int), ("h_thrs", ctypes.c_double),
+        ("dp_thrs", ctypes.c_double), ("max_scf", ctypes.c_int), ("max_terms", ctypes.c_int),
+        ("precision", ctypes.c_int), ("predictor", ctypes.c_int), ("hupdate", ctypes.c_int),
+        ("frozen_hxc", ctypes.c_int), ("n_traj", ctypes.c_int), ("traj_sys", _ip),
+        ("traj_kappa", _dp), ("traj_axis", _ip),
+    ]
+
+
+class rt_step_stats(ctypes.Structure):
+    _fields_ = [("scf_iters", ctypes.c_int32), ("series_terms", ctypes.c_int32),
+                ("residual", ctypes.c_double)]
+
+
+class RTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2410_09189_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    sig = {
+        "rt_workspace_size": ([ctypes.POINTER(rt_system), ctypes.c_int, ctypes.POINTER(rt_run),
+                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "rt_init": ([ctypes.POINTER(rt_system), ctypes.c_int, ctypes.POINTER(rt_run), vp, ctypes.c_size_t,
+                     vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "rt_apply_h": ([vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "rt_step": ([vp, ctypes.c_int, ctypes.POINTER(rt_step_stats)], ctypes.c_int),
+        "rt_dipole": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp], ctypes.c_int),
+        "rt_get_matrix": ([vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
+        "rt_set_state": ([vp, ctypes.c_int, _dp, _dp, _dp, _dp], ctypes.c_int),
+        "rt_eval_h": ([vp, ctypes.c_int, vp, vp], ctypes.c_int),
+        "rt_propagate": ([vp, ctypes.c_int, vp, ctypes.c_double, vp, vp, _ip], ctypes.c_int),
+        "rt_get_grid": ([vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
+        "rt_profile": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "rt_profile_read": ([vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_long),
+                             ctypes.POINTER(ctypes.c_char_p)], ctypes.c_int),
+        "rt_free": ([vp], None),
+        "rt_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _ptr(a, ctype=ctypes.c_double):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _check(status, ctx=None):
+    if status != RT_OK:
+        msg = lib.rt_last_error(ctx)
+        raise RTError(status, msg.decode() if msg else "")
+
+
+class SystemArgs:
+    """Holds the host arrays referenced by one rt_system struct."""
+
+    def __init__(self, n, h, pos, depth, width, n_occ, n_virt, psi0, nl_rank=0, nl_rcut=2.0,
+                 nl_sigma=0.6, nl_D=None, n_images=2, occ=None, orthonormalize=False):
+        self.pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        self.depth = np.ascontiguousarray(depth, dtype=np.float64)
+        self.width = np.ascontiguousarray(width, dtype=np.float64)
+        self.nl_D = None if nl_D is None else np.ascontiguousarray(nl_D, dtype=np.float64)
+        self.occ = None if occ is None else np.ascontiguousarray(occ, dtype=np.float64)
+        self.psi0 = psi0  # numpy float64 array (host) or torch CUDA tensor (device)
+        s = rt_system()
+        s.n[:] = list(n)
+        s.h = h
+        s.n_atoms = self.pos.shape[0]
+        s.pos, s.depth, s.width = _ptr(self.pos), _ptr(self.depth), _ptr(self.width)
+        s.n_images = n_images
+        s.nl_rank, s.nl_rcut, s.nl_sigma = nl_rank, nl_rcut, nl_sigma
+        s.nl_D = _ptr(self.nl_D)
+        s.n_occ, s.n_virt = n_occ, n_virt
+        s.occ = _ptr(self.occ)
+        if isinstance(psi0, np.ndarray):
+            assert psi0.dtype == np.float64 and psi0.flags.c_contiguous
+            s.psi0 = psi0.ctypes.data
+            s.psi0_on_device = 0
+        else:
+            s.psi0 = psi0.data_ptr()
+            s.psi0_on_device = 1
+        s.orthonormalize = int(orthonormalize)
+        self.struct = s
+
+
+class RunArgs:
+    def __init__(self, dt, n_steps_max, h_thrs, dp_thrs, max_scf, max_terms, traj_sys, traj_kappa,
+                 traj_axis, precision=RT_FP64, predictor=RT_PRED_LINEAR, hupdate=RT_HUPDATE_FULL,
+                 frozen_hxc=False):
+        self.traj_sys = np.ascontiguousarray(traj_sys, dtype=np.int32)
+        self.traj_kappa = np.ascontiguousarray(traj_kappa, dtype=np.float64)
+        self.traj_axis = np.ascontiguousarray(traj_axis, dtype=np.int32)
+        r = rt_run()
+        r.dt, r.n_steps_max, r.h_thrs, r.dp_thrs = dt, n_steps_max, h_thrs, dp_thrs
+        r.max_scf, r.max_terms = max_scf, max_terms
+        r.precision, r.predictor, r.hupdate, r.frozen_hxc = precision, predictor, hupdate, int(frozen_hxc)
+        r.n_traj = len(self.traj_sys)
+        r.traj_sys = _ptr(self.traj_sys, ctypes.c_int)
+        r.traj_kappa = _ptr(self.traj_kappa)
+        r.traj_axis = _ptr(self.traj_axis, ctypes.c_int)
+        self.struct = r
+
+
+def rt_workspace_size(systems, run) -> int:
+    arr = (rt_system * len(systems))(*[s.struct for s in systems])
+    out = ctypes.c_size_t(0)
+    _check(lib.rt_workspace_size(arr, len(systems), ctypes.byref(run.struct), ctypes.byref(out)))
+    return out.value
+
+
+def rt_init(systems, run, workspace_ptr: int, ws_bytes: int, stream_ptr: int):
+    arr = (rt_system * len(systems))(*[s.struct for s in systems])
+    ctx = ctypes.c_void_p(None)
+    _check(lib.rt_init(arr, len(systems), ctypes.byref(run.struct), ctypes.c_void_p(workspace_ptr),
+                       ws_bytes, ctypes.c_void_p(stream_ptr), ctypes.byref(ctx)))
+    return ctx
+
+
+def rt_apply_h(ctx, sys_index, psi_ptr, hpsi_ptr, n_orb, dtype):
+    _check(lib.rt_apply_h(ctx, sys_index, ctypes.c_void_p(psi_ptr), ctypes.c_void_p(hpsi_ptr), n_orb, dtype), ctx)
+
+
+def rt_step(ctx, n_steps, n_traj=None, stats=False):
+    buf = (rt_step_stats * (n_steps * n_traj))() if stats else None
+    _check(lib.rt_step(ctx, n_steps, buf), ctx)
+    if stats:
+        return [(b.scf_iters, b.series_terms, b.residual) for b in buf]
+    return None
+
+
+def rt_dipole(ctx, traj, first_step, count):
+    mu = np.zeros((count, 3))
+    e = np.zeros(count)
+    tr = np.zeros(count)
+    _check(lib.rt_dipole(ctx, traj, first_step, count, _ptr(mu), _ptr(e), _ptr(tr)), ctx)
+    return mu, e, tr
+
+
+def rt_get_matrix(ctx, traj, which, n):
+    out = np.zeros((n, n))
+    _check(lib.rt_get_matrix(ctx, traj, which, _ptr(out)), ctx)
+    return out
+
+
+def rt_set_state(ctx, traj, p_re=None, p_im=None, h0=None, hm1=None):
+    args = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (p_re, p_im, h0, hm1)]
+    _check(lib.rt_set_state(ctx, traj, *[_ptr(a) for a in args]), ctx)
+
+
+def rt_eval_h(ctx, sys_index, p_re_ptr, h_out_ptr):
+    _check(lib.rt_eval_h(ctx, sys_index, ctypes.c_void_p(p_re_ptr), ctypes.c_void_p(h_out_ptr)), ctx)
+
+
+def rt_propagate(ctx, sys_index, hbar_ptr, dt, p_re_ptr, p_im_ptr):
+    terms = ctypes.c_int(0)
+    _check(lib.rt_propagate(ctx, sys_index, ctypes.c_void_p(hbar_ptr), dt, ctypes.c_void_p(p_re_ptr),
+                            ctypes.c_void_p(p_im_ptr), ctypes.byref(terms)), ctx)
+    return terms.value
+
+
+def rt_get_grid(ctx, sys_index, which, shape):
+    out = np.zeros(shape)
+    _check(lib.rt_get_grid(ctx, sys_index, which, _ptr(out)), ctx)
+    return out
+
+
+def rt_profile(ctx, enable=True, reset=True):
+    _check(lib.rt_profile(ctx, int(enable), int(reset)), ctx)
+
+
+def rt_profile_read(ctx):
+    """{phase name: (total ms, launches)} for every phase."""
+    out = {}
+    for ph in range(10):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_long(0)
+        name = ctypes.c_char_p()
+        _check(lib.rt_profile_read(ctx, ph, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(name)), ctx)
+        out[name.value.decode()] = (ms.value, n.value)
+    return out
+
+
+def rt_free(ctx):
+    lib.rt_free(ctx)
+
+
+def rt_last_error(ctx=None) -> str:
+    m = lib.rt_last_error(ctx)
+    return m.decode() if m else ""
+
+
+class Session:
+    """Device workspace (a torch uint8 tensor) + context on torch's current stream."""
+
+    def __init__(self, systems, run, device="cuda"):
+        import torch
+
+        self.systems, self.run = systems, run
+        self.ws_bytes = rt_workspace_size(systems, run)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(device).cuda_stream
+        self.ctx = rt_init(systems, run, self.ws.data_ptr(), self.ws_bytes, self.stream)
+
+    def close(self):
+        if self.ctx is not None:
+            rt_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,204 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, element
+by element on the same seeded inputs.  Tolerances: FP64 stages within 1e-12
+relative of the oracle (rounding order only); whole trajectories within 1e-10
+a.u. on the dipole and energy."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import hamiltonian, propagate
+from conftest import c1_ground_state, c1_model, c1_oracle_run, c1_system
+from rt_helpers import orthonormalize_np, run_args, system_args
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _session(systems, run):
+    from paper_2410_09189_amd import rt
+
+    return rt.Session(systems, run)
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _ragged_system(seed=7, n=(36, 40, 32), n_orb=20, nl_rank=4):
+    s = synth.make_system(n, 0.3, 6, n_orb // 2, n_orb - n_orb // 2, seed=seed, nl_rank=nl_rank,
+                          region=(0.3, 0.7))
+    psi = synth.lowpass_orbitals(n, 0.3, n_orb, seed)
+    return s, psi
+
+
+def test_apply_h_fp64_matches_oracle_ragged_grid():
+    _say("apply_h fp64 36x40x32 N=20 nonlocal")
+    torch = _torch()
+    from paper_2410_09189_amd import rt
+
+    s, psi = _ragged_system()
+    rp = synth.RunParams(dt=0.05, n_steps=2)
+    ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp))
+    vloc = rt.rt_get_grid(ses.ctx, 0, 4, s.ng)
+    x = torch.from_numpy(psi.reshape(psi.shape[0], -1)).cuda()
+    y = torch.empty_like(x)
+    rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), psi.shape[0], 0)
+    torch.cuda.synchronize()
+    m = oracle.Model(s, orthonormalize_np(s, psi))
+    ref = m.apply_h(psi.reshape(psi.shape[0], -1), vloc)
+    got = y.cpu().numpy()
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))
+    ses.close()
+
+
+def test_apply_h_fp32_within_single_precision():
+    _say("apply_h fp32 36x40x32 N=20")
+    torch = _torch()
+    from paper_2410_09189_amd import rt
+
+    s, psi = _ragged_system(seed=8)
+    rp = synth.RunParams(dt=0.05, n_steps=2)
+    ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp))
+    vloc = rt.rt_get_grid(ses.ctx, 0, 4, s.ng)
+    x = torch.from_numpy(psi.reshape(psi.shape[0], -1)).float().cuda()
+    y = torch.empty_like(x)
+    rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), psi.shape[0], 1)
+    torch.cuda.synchronize()
+    m = oracle.Model(s, orthonormalize_np(s, psi))
+    ref = m.apply_h(psi.reshape(psi.shape[0], -1).astype(np.float32).astype(np.float64), vloc)
+    got = y.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) < 2e-5 * np.max(np.abs(ref))
+    ses.close()
+
+
+def test_static_matrices_match_oracle():
+    _say("H_core, M_q, H_gs 36x40x32 N=20 with GPU orthonormalisation")
+    from paper_2410_09189_amd import rt
+
+    s, psi = _ragged_system(seed=9)
+    rp = synth.RunParams(dt=0.05, n_steps=2)
+    ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp))
+    m = oracle.Model(s, orthonormalize_np(s, psi))
+    N = m.N
+    hc = rt.rt_get_matrix(ses.ctx, 0, 4, N)
+    assert np.max(np.abs(hc - m.hcore)) < 1e-11 * np.max(np.abs(m.hcore))
+    for q in range(3):
+        Mq = rt.rt_get_matrix(ses.ctx, 0, 5 + q, N)
+        assert np.max(np.abs(Mq - m.M[q])) < 1e-11 * np.max(np.abs(m.M[q]))
+    Hgs = rt.rt_get_matrix(ses.ctx, 0, 8, N)
+    ref, _ = m.h_of_p(np.diag(s.occupations()).astype(complex))
+    assert np.max(np.abs(Hgs - ref)) < 1e-11 * np.max(np.abs(ref))
+    ses.close()
+
+
+@pytest.mark.parametrize("hupdate", [0, 1])
+def test_eval_h_and_potentials_match_oracle(hupdate):
+    _say(f"eval_h hupdate={hupdate} 36x40x32 N=20")
+    torch = _torch()
+    from paper_2410_09189_amd import rt
+
+    s, psi = _ragged_system(seed=10)
+    rp = synth.RunParams(dt=0.05, n_steps=2)
+    ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp, hupdate=hupdate))
+    m = oracle.Model(s, orthonormalize_np(s, psi))
+    N = m.N
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((N, N))
+    S = np.diag(s.occupations()) + 0.1 * (A + A.T)
+    Sd = torch.from_numpy(S).cuda()
+    Hd = torch.empty_like(Sd)
+    rt.rt_eval_h(ses.ctx, 0, Sd.data_ptr(), Hd.data_ptr())
+    torch.cuda.synchronize()
+    ref, aux = m.h_of_p(S.astype(complex))
+    got = Hd.cpu().numpy()
+    assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref))
+    for which, key in ((0, "rho"), (1, "vh"), (2, "vx")):
+        g = rt.rt_get_grid(ses.ctx, 0, which, s.ng)
+        assert np.max(np.abs(g - aux[key])) < 1e-12 * max(1.0, np.max(np.abs(aux[key]))), key
+    ses.close()
+
+
+@pytest.mark.parametrize("dt,n", [(0.05, 16), (0.3, 70), (-0.2, 33)])
+def test_series_propagation_matches_exact(dt, n):
+    _say(f"rt_propagate dt={dt} N={n}")
+    torch = _torch()
+    from paper_2410_09189_amd import rt
+
+    s = synth.make_system(16, 0.4, 1, n // 2, n - n // 2, seed=2)
+    psi = synth.lowpass_orbitals(16, 0.4, n, 2)
+    rp = synth.RunParams(dt=0.05, n_steps=2)
+    ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp, kappas=[0.0]))
+    rng = np.random.default_rng(n)
+    H = rng.standard_normal((n, n))
+    H = 0.5 * (H + H.T)
+    B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    P = B @ B.conj().T / n
+    pr = torch.from_numpy(np.ascontiguousarray(P.real)).cuda()
+    pi = torch.from_numpy(np.ascontiguousarray(P.imag)).cuda()
+    hd = torch.from_numpy(H).cuda()
+    k = rt.rt_propagate(ses.ctx, 0, hd.data_ptr(), dt, pr.data_ptr(), pi.data_ptr())
+    torch.cuda.synchronize()
+    ref = propagate.propagate_exact(H, P, dt)
+    got = pr.cpu().numpy() + 1j * pi.cpu().numpy()
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(P))
+    _, kref = propagate.propagate_series(H, P, dt, rp.dp_thrs)
+    assert k == kref
+    ses.close()
+
+
+def _c1_gpu_run(n_steps, hupdate=0, frozen=False, axes=(0,)):
+    from paper_2410_09189_amd import rt
+
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    rp = synth.config_run("c1_parity_32", n_steps=n_steps)
+    ses = _session([system_args(s, psi)], run_args(rp, n_traj_axes=axes, hupdate=hupdate, frozen_hxc=frozen))
+    stats = rt.rt_step(ses.ctx, n_steps, n_traj=len(axes), stats=True)
+    res = [rt.rt_dipole(ses.ctx, t, 0, n_steps + 1) for t in range(len(axes))]
+    ses.close()
+    return res, stats
+
+
+@pytest.mark.parametrize("hupdate", [0, 1])
+def test_c1_trajectory_200_steps_matches_oracle(hupdate):
+    _say(f"C1 32^3 N=16 200 steps hupdate={hupdate}")
+    ref = c1_oracle_run()
+    (mu, E, tr), = _c1_gpu_run(200, hupdate=hupdate)[0]
+    assert np.max(np.abs(mu - ref["mu"])) < 1e-10
+    assert np.max(np.abs(E - ref["E"])) < 1e-10
+    assert np.max(np.abs(tr - 16.0)) < 1e-12
+
+
+def test_c1_frozen_hxc_matches_closed_form():
+    _say("C1 frozen Hxc 100 steps")
+    s = c1_system()
+    psi, eps = c1_ground_state()
+    m = c1_model()
+    (mu, E, tr), = _c1_gpu_run(100, frozen=True)[0]
+    P0 = np.diag(s.occupations()).astype(complex)
+    Pk = oracle.kick(P0, m.M[0], 1e-3)
+    e = eps[: m.N]
+    t = 0.05 * np.arange(101)
+    ph = np.exp(-1j * (e[:, None] - e[None, :])[None] * t[:, None, None])
+    ref = np.real(np.einsum("tij,ji->t", Pk[None] * ph, m.M[0]))
+    assert np.max(np.abs(mu[:, 0] - ref)) < 1e-9
+
+
+def test_c1_three_kicks_and_bitwise_determinism():
+    _say("C1 kicks x,y,z 20 steps twice")
+    a, sa = _c1_gpu_run(20, axes=(0, 1, 2))
+    b, sb = _c1_gpu_run(20, axes=(0, 1, 2))
+    for q in range(3):
+        assert np.array_equal(a[q][0], b[q][0])
+        assert np.array_equal(a[q][1], b[q][1])
+    ref = c1_oracle_run(n_steps=20, axis=1)
+    assert np.max(np.abs(a[1][0] - ref["mu"])) < 1e-10
+    assert sa == sb
