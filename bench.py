@@ -35,18 +35,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(phase, N, ng, n_proj):
-    """(bound, algorithmic units per launch): flops for contractions, bytes for
-    streaming kernels."""
+PEAK_BF16 = 2.5e15  # flop/s dense MFMA
+
+
+def roof(phase, N, ng, mixed):
+    """Algorithmic bytes and flops of one launch of a phase, and the matrix
+    peak that applies.  BF16x3 contractions execute three bf16 products per
+    FP product on the matrix cores."""
+    pairs = float(N) * (N + 1) / 2  # unique entries of a symmetric N x N result / pair products
     if phase == "project_gemm":
-        return "mfma", float(N) * (N + 1) * ng  # N(N+1)/2 unique entries x 2 ng flops
+        if mixed:
+            return 4.0 * N * ng + 4.0 * ng, 3 * 2 * pairs * ng, PEAK_BF16
+        return 16.0 * N * ng, 2 * pairs * ng, PEAK_FP64
     if phase == "density":
-        return "mfma", float(N) * (N + 1) * ng  # sum_{i<=j} W_ij psi_i psi_j per point
+        if mixed:
+            return 4.0 * N * ng + 16.0 * ng, 3 * 2 * pairs * ng, PEAK_BF16
+        return 8.0 * N * ng + 8.0 * ng, 2 * pairs * ng, PEAK_FP64
     if phase == "series_gemm":
-        return "mfma", 4.0 * N ** 3  # Hbar . [S'; A'] : N x 2N x N
+        return 3 * 16.0 * N * N, 4.0 * N ** 3, PEAK_FP64
     if phase == "stencil_fd8":
-        return "hbm", 16.0 * N * ng + 8.0 * ng  # read psi, write H psi (FP64), V once
-    return None, None
+        return 16.0 * N * ng + 8.0 * ng, 0.0, PEAK_FP64
+    return None
 
 
 def cpu_baseline(s, psi_host, m_mean, dt):
@@ -82,12 +91,48 @@ def cpu_baseline(s, psi_host, m_mean, dt):
     }
 
 
+def run_leg(rt, torch, sa, s, args, precision, hupdate, h_thrs, dp_thrs, profile):
+    total = args.warmup + args.steps
+    ra = rt.RunArgs(dt=0.05, n_steps_max=total, h_thrs=h_thrs, dp_thrs=dp_thrs, max_scf=50, max_terms=200,
+                    traj_sys=[0], traj_kappa=[1e-3], traj_axis=[0], hupdate=hupdate, precision=precision)
+    ses = rt.Session([sa], ra)
+    ctx = ses.ctx
+    rt.rt_step(ctx, args.warmup, n_traj=1, stats=False)
+    torch.cuda.synchronize()
+    if profile:
+        rt.rt_profile(ctx, enable=True, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = rt.rt_step(ctx, args.steps, n_traj=1, stats=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = rt.rt_profile_read(ctx) if profile else None
+    mu, E, tr = rt.rt_dipole(ctx, 0, 0, total + 1)
+    leg = dict(elapsed=elapsed, stats=stats, prof=prof, mu=mu, E=E, tr=tr, ses=ses)
+    return leg
+
+
+def roofline_of(prof, N, ng, mixed):
+    cands = [k for k in prof if prof[k][1] and roof(k, N, ng, mixed)]
+    dom = max(cands, key=lambda k: prof[k][0])
+    nbytes, flops, pk = roof(dom, N, ng, mixed)
+    ms, launches = prof[dom]
+    avg = ms / 1e3 / launches
+    t_hbm, t_mfma = nbytes / PEAK_HBM, (flops / pk if flops else 0.0)
+    if t_hbm >= t_mfma:
+        return {"bound": "hbm", "kernel": dom, "achieved": nbytes / avg / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": nbytes / avg / PEAK_HBM, "traffic": None, "avg_launch_us": avg * 1e6,
+                "algorithmic_bytes_per_launch": nbytes}
+    return {"bound": "mfma", "kernel": dom, "achieved": flops / avg / 1e12, "peak": pk / 1e12,
+            "unit": "TFLOP/s", "frac": flops / avg / pk, "traffic": None, "avg_launch_us": avg * 1e6,
+            "algorithmic_flops_per_launch": flops}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--hupdate", choices=["full", "local"], default="full")
     ap.add_argument("--h-thrs", type=float, default=1e-7)
     ap.add_argument("--dp-thrs", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -110,45 +155,20 @@ def main():
     sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
                        n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
                        nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images, orthonormalize=True)
-    total = args.warmup + args.steps
-    hup = rt.RT_HUPDATE_FULL if args.hupdate == "full" else rt.RT_HUPDATE_LOCAL
-    ra = rt.RunArgs(dt=0.05, n_steps_max=total, h_thrs=args.h_thrs, dp_thrs=args.dp_thrs, max_scf=50,
-                    max_terms=200, traj_sys=[0], traj_kappa=[1e-3], traj_axis=[0], hupdate=hup)
-    log("rt_init")
-    ses = rt.Session([sa], ra)
-    ctx = ses.ctx
-    rt.rt_step(ctx, args.warmup, n_traj=1, stats=False)
-    torch.cuda.synchronize()
-    rt.rt_profile(ctx, enable=True, reset=True)
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = rt.rt_step(ctx, args.steps, n_traj=1, stats=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = rt.rt_profile_read(ctx)
-    rt.rt_profile(ctx, enable=False, reset=False)
-    m_total = sum(x[0] for x in stats)
-    m_mean = m_total / len(stats)
-    terms_mean = sum(x[1] for x in stats) / max(1, m_total)
-    steps_per_s = args.steps / elapsed
+    log("leg 1/3: FP64 reference, tight thresholds (1e-12, 1e-15)")
+    ref = run_leg(rt, torch, sa, s, args, rt.RT_FP64, rt.RT_HUPDATE_FULL, 1e-12, 1e-15, False)
+    ref["ses"].close()
+    log("leg 2/3: plain FP64, full Hamiltonian apply, paper thresholds")
+    plain = run_leg(rt, torch, sa, s, args, rt.RT_FP64, rt.RT_HUPDATE_FULL, args.h_thrs, args.dp_thrs, True)
+    plain["ses"].close()
+    log("leg 3/3: mixed BF16x3 + FP64, paper thresholds")
+    mixed = run_leg(rt, torch, sa, s, args, rt.RT_MIXED, rt.RT_HUPDATE_LOCAL, args.h_thrs, args.dp_thrs, True)
+    ctx = mixed["ses"].ctx
 
-    # dominant kernel of the timed region
-    n_proj = s.n_atoms * s.nl_rank
-    dom = max((k for k in prof if algorithmic(k, N, s.ng, n_proj)[0]), key=lambda k: prof[k][0])
-    bound, units = algorithmic(dom, N, s.ng, n_proj)
-    ms, launches = prof[dom]
-    avg_s = ms / 1e3 / max(1, launches)
-    achieved = units / avg_s
-    peak = PEAK_FP64 if bound == "mfma" else PEAK_HBM
-    roofline = {
-        "bound": bound, "kernel": dom,
-        "achieved": achieved / (1e12 if bound == "mfma" else 1e9),
-        "peak": peak / (1e12 if bound == "mfma" else 1e9),
-        "unit": "TFLOP/s" if bound == "mfma" else "GB/s",
-        "frac": achieved / peak, "traffic": None, "avg_launch_us": avg_s * 1e6,
-    }
-    phases = {k: {"ms_total": round(v[0], 3), "launches": v[1]} for k, v in prof.items() if v[1]}
+    def dip_err(leg):
+        d = leg["mu"][:, 0] - leg["mu"][0, 0]
+        dr = ref["mu"][:, 0] - ref["mu"][0, 0]
+        return float(np.max(np.abs(d - dr)) / np.max(np.abs(dr)))
 
     # standalone H-apply rates (FP64 and FP32 stencil + nonlocal over all orbitals)
     x64 = torch.from_numpy(psi.reshape(N, -1)).cuda()
@@ -171,34 +191,51 @@ def main():
         rates["fp32" if dt_ else "fp64"] = {
             "orbital_gridpoints_per_s": N * s.ng / t_apply,
             "hbm_GBps_algorithmic": (2 * b * N * s.ng + b * s.ng) / t_apply / 1e9,
+            "hbm_frac": (2 * b * N * s.ng + b * s.ng) / t_apply / PEAK_HBM,
         }
-    mu, E, tr = rt.rt_dipole(ctx, 0, 0, total + 1)
-    ses.close()
+    mixed["ses"].close()
     del x64, y64, x32, y32
 
+    def summary(leg, mixed_mode):
+        m_total = sum(x[0] for x in leg["stats"])
+        return {
+            "steps_per_s": args.steps / leg["elapsed"], "ms_per_step": 1e3 * leg["elapsed"] / args.steps,
+            "mean_scf_updates_per_step": m_total / len(leg["stats"]),
+            "mean_series_terms_per_update": sum(x[1] for x in leg["stats"]) / max(1, m_total),
+            "h_updates_orbital_gridpoints_per_s": m_total * N * s.ng / leg["elapsed"],
+            "dipole_rel_err_vs_fp64_tight": dip_err(leg),
+            "energy_change_err_vs_fp64_tight": float(np.max(np.abs((leg["E"] - leg["E"][0]) - (ref["E"] - ref["E"][0])))),
+            "roofline": roofline_of(leg["prof"], N, s.ng, mixed_mode),
+            "phases_ms": {k: round(v[0], 3) for k, v in leg["prof"].items() if v[1]},
+        }
+
+    sm_plain = summary(plain, False)
+    sm_mixed = summary(mixed, True)
+    value = sm_mixed["steps_per_s"]
     out = {
-        "metric": METRIC, "value": steps_per_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{name}: 96^3 h=0.3, 40 wells + rank-4 projectors, N=240 (160 occ), "
-                               f"1 kick trajectory, dt=0.05, H_thrs={args.h_thrs:g}, dP_thrs={args.dp_thrs:g}, "
-                               f"hupdate={args.hupdate}, fp64",
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sm_mixed["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3+f64", "data": "synthetic",
+        "config": {"workload": f"{name}: 96^3 h=0.3, 40 Gaussian wells + rank-4 projectors (r_c=2), "
+                               f"N=240 (160 occ + 80 virt), 1 x-kick trajectory, dt=0.05, "
+                               f"H_thrs={args.h_thrs:g}, dP_thrs={args.dp_thrs:g}; mixed BF16x3 "
+                               f"perturbation contractions + FP64 series/Poisson/LDA/observables",
                    "grid": list(s.n), "n_orb": N, "trajectories": 1},
-        "h_applies_per_s": m_total * N * s.ng / elapsed,
-        "mean_scf_updates_per_step": m_mean, "mean_series_terms_per_update": terms_mean,
-        "apply_h_standalone": rates, "roofline": roofline, "phases": phases,
-        "energy_drift": float(E[-1] - E[1]), "trace_err": float(np.max(np.abs(tr - 2 * s.n_occ))),
+        "vs_plain_fp64": value / sm_plain["steps_per_s"],
+        "roofline": sm_mixed["roofline"],
+        "mixed": sm_mixed, "plain_fp64": sm_plain,
+        "fp64_tight_reference_steps_per_s": args.steps / ref["elapsed"],
+        "apply_h_standalone": rates,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        # the oracle works with orthonormal orbitals of the same recipe
         from scipy.linalg import solve_triangular
 
         P = psi.reshape(N, -1)
         L = np.linalg.cholesky(s.h ** 3 * (P @ P.T))
         psi_o = solve_triangular(L, P, lower=True)
         del P
-        out["cpu_baseline"] = cpu_baseline(s, psi_o, m_mean, 0.05)
+        out["cpu_baseline"] = cpu_baseline(s, psi_o, sm_plain["mean_scf_updates_per_step"], 0.05)
     print(json.dumps(out), flush=True)
 
 

@@ -8,6 +8,15 @@ namespace rtk {
 
 constexpr int kRedBlocks = 512;  // fixed block count of deterministic grid reductions
 
+// T independent problems in one launch (trajectory index fastest in blockIdx.x);
+// per-trajectory element strides of the operands A, B, the weight w and the output.
+struct Batch {
+  int T;
+  const int* active;  // [T] device flags, nullable = all active
+  long sa, sb, sw, sp;
+};
+inline Batch single() { return Batch{1, nullptr, 0, 0, 0, 0}; }
+
 // ---- grid fields -----------------------------------------------------------
 hipError_t vion(hipStream_t s, double* v, int nx, int ny, int nz, double h, int n_atoms,
                 const double* pos, const double* depth, const double* width, int n_images);
@@ -16,7 +25,8 @@ hipError_t fill(hipStream_t s, double* p, long n, double v);
 hipError_t fill_u64(hipStream_t s, unsigned long long* p, long n, unsigned long long v);
 hipError_t copy_d(hipStream_t s, double* dst, const double* src, long n);
 hipError_t cast_d2f(hipStream_t s, float* dst, const double* src, long n);
-hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, long n);
+// dst_t = a_t - b (b shared by the T stacked fields)
+hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, long n, int T, const int* active);
 
 // ---- Hamiltonian on the grid -------------------------------------------------
 // hpsi[j] = -1/2 L psi[j] + v psi[j] (8th-order FD, periodic), j < n_orb.
@@ -35,18 +45,19 @@ hipError_t nl_scatter(hipStream_t s, T* hpsi, long ng, int n_orb, int n_union, c
                       const double* beta, const double* D, const double* c, int n_proj);
 
 // ---- dense products -----------------------------------------------------------
-// part[s][m][n] = sum_{k in split s} A[m][k] w[k] B[n][k]   (w nullable)
+// part[s][m][n] = sum_{k in split s} A[m][k] w[k] B[n][k]   (w nullable), batched by bt;
 // tiles with tn < tm skipped when upper != 0 (M == N).  kps: k per split.
 hipError_t gemm_nt_f64(hipStream_t s, int M, int N, long K, const double* A, long lda,
                        const double* B, long ldb, const double* w, double* part, long kps,
-                       int n_split, int upper, int big);
-// C[m][n] = alpha * sum_s part[s][m][n]; mirror: C[n][m] = C[m][n] for m < n (upper part kept)
+                       int n_split, int upper, int big, Batch bt);
+// C_t = base_t + alpha * sum_s part_t[s] (base nullable); mirror keeps the upper part.
 hipError_t reduce_parts(hipStream_t s, const double* part, int n_split, int M, int N, double alpha,
-                        double* C, int mirror);
+                        double* C, int mirror, const double* base, int T, long sp, long sbase, long sc,
+                        const int* active);
 // out = W . Psi (mode 0) or rho[r] = sum_i Psi[i][r] (W Psi)[i][r] (mode 1);
-// tri: 0 full, 1 W upper triangular, 2 W lower triangular.
+// tri: 0 full, 1 W upper triangular, 2 W lower triangular; batched over T weight matrices.
 hipError_t smalltall_f64(hipStream_t s, int N, long ng, const double* W, const double* psi,
-                         double* out, int mode, int tri);
+                         double* out, int mode, int tri, int T, const int* active);
 
 // ---- Poisson (spectral) ---------------------------------------------------------
 hipError_t twiddles(hipStream_t s, double2* tw, int n);
@@ -64,27 +75,30 @@ hipError_t lda_vloc(hipStream_t s, const double* rho, const double* vh, const do
 hipError_t reduce_cols(hipStream_t s, const double* part, int nblk, int ncol, const double* scale3,
                        double* out);
 
-// ---- N x N kernels ---------------------------------------------------------------
+// ---- N x N kernels (batched over T trajectories with stacked buffers) ----------
 hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double b, const double* y,
                    long n);
+hipError_t copy_masked(hipStream_t s, double* dst, const double* src, long n, int T, const int* active);
 hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
-                        unsigned long long* slot);
-hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out);
-// one series term k (1-based): reads C = Hbar . [S;A]^T (N x 2N), writes dP_k stacked [2N][N],
-// adds to P1 stacked, max |dP_k| -> slots[k].  Skips when the series has already stopped.
-hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1, int N, double dt,
-                         int k, unsigned long long* slots, const double* kmin, double thrs,
-                         int* done);
-hipError_t gemm_nt_f64_series(hipStream_t s, int N, const double* Hbar, const double* dP, double* C,
-                              int k, const unsigned long long* slots, const double* kmin,
-                              double thrs, const int* done);
-hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots,
-                         const double* kmin, double thrs, int* done);
-// hist[j] = (mu_x, mu_y, mu_z, E, TrP) from S' and energies.
+                        unsigned long long* slot, int T, const int* active);
+hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, int T,
+                      const int* active);
+// series term k (1-based) for T trajectories: C_t = Hbar_t . [S;A]_t^T (N x 2N), dP_k -> dPn_t,
+// P1_t += dP_k, max |dP_k| -> slots[t][k]; skips trajectories whose series stopped.
+hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, const double* dP, double* C,
+                              int k, const unsigned long long* slots, int stride, const double* kmin,
+                              double thrs, const int* done, const int* active);
+hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1, int N, double dt, int k,
+                         unsigned long long* slots, int stride, const double* kmin, double thrs, int* done,
+                         int T, const int* active);
+hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, int stride,
+                         const double* kmin, double thrs, int* done, int T, const int* active);
+// rows_t = (mu_x, mu_y, mu_z, E, TrP) from S'_t (stride 2N^2) and eparts_t.
 hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
-                       const double* eparts, double* hist_row);
+                       const double* eparts, int estride, double* rows, long rstride, int T);
 hipError_t cholesky(hipStream_t s, double* A, int N, int* info);
 hipError_t tri_inverse_lower(hipStream_t s, const double* L, double* Linv, int N);
-hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N);
+hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N, long sstride, int T,
+                          const int* active);
 
 }  // namespace rtk

@@ -128,9 +128,12 @@ __global__ void k_cast_d2f(float* d, const double* a, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     d[i] = (float)a[i];
 }
-__global__ void k_sub(double* d, const double* a, const double* b, long n) {
+// d_t = a_t - b for T stacked fields (b shared); blockIdx.y = t.
+__global__ void k_sub(double* d, const double* a, const double* b, long n, const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    d[i] = a[i] - b[i];
+    d[t * n + i] = a[t * n + i] - b[i];
 }
 static int ew_blocks(long n) { long b = (n + 255) / 256; return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b)); }
 
@@ -150,8 +153,9 @@ hipError_t cast_d2f(hipStream_t s, float* dst, const double* src, long n) {
   hipLaunchKernelGGL(k_cast_d2f, dim3(ew_blocks(n)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
-hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, long n) {
-  hipLaunchKernelGGL(k_sub, dim3(ew_blocks(n)), dim3(256), 0, s, dst, a, b, n);
+hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, long n, int T, const int* active) {
+  int nb = ew_blocks(n) > 1024 ? 1024 : ew_blocks(n);
+  hipLaunchKernelGGL(k_sub, dim3(nb, T), dim3(256), 0, s, dst, a, b, n, active);
   return hipGetLastError();
 }
 
@@ -376,19 +380,24 @@ template hipError_t nl_scatter<float>(hipStream_t, float*, long, int, int, const
 // row 4*(lane/16) + r, column lane%16.  A block of 256 threads (2 x 2 waves)
 // computes a BM x BN tile; K is split across blockIdx.y into fixed ranges
 // whose partial tiles are summed afterwards in a fixed order.
+// Trajectory batching: T independent problems share one launch.  The
+// trajectory index is the fastest-varying part of blockIdx.x, so blocks of
+// different trajectories working on the same tile run together and share the
+// orbital reads through L2.
 struct SeriesSkip {
-  const unsigned long long* slots;  // max |dP_k| per term (bits of a non-negative double)
-  const double* kmin;
-  const int* done;
+  const unsigned long long* slots;  // [T][stride]: max |dP_k| per term (bits of a non-negative double)
+  const double* kmin;               // [T]
+  const int* done;                  // [T][2]
   double thrs;
-  int k;  // term this launch computes (1-based); 0 = not a series launch
+  int k;       // term this launch computes (1-based); 0 = not a series launch
+  int stride;  // slots per trajectory
 };
 
-__device__ __forceinline__ bool series_stopped(const SeriesSkip& sk) {
+__device__ __forceinline__ bool series_stopped(const SeriesSkip& sk, int t) {
   if (sk.k <= 1) return false;
-  if (*sk.done) return true;
-  double prev = __longlong_as_double((long long)sk.slots[sk.k - 1]);
-  return prev <= sk.thrs && (double)(sk.k - 1) >= *sk.kmin;
+  if (sk.done[2 * t]) return true;
+  double prev = __longlong_as_double((long long)sk.slots[(long)t * sk.stride + sk.k - 1]);
+  return prev <= sk.thrs && (double)(sk.k - 1) >= sk.kmin[t];
 }
 
 template <int BM, int BN, int BK>
@@ -396,14 +405,20 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
                                                      long lda, const double* __restrict__ B, long ldb,
                                                      const double* __restrict__ w,
                                                      double* __restrict__ part, long kps, int upper,
-                                                     int n_tn, SeriesSkip sk) {
-  if (sk.k > 0 && series_stopped(sk)) return;
+                                                     int n_tn, Batch bt, SeriesSkip sk) {
+  const int tb = blockIdx.x % bt.T;
+  if (bt.active && !bt.active[tb]) return;
+  if (sk.k > 0 && series_stopped(sk, tb)) return;
+  A += tb * bt.sa;
+  B += tb * bt.sb;
+  if (w) w += tb * bt.sw;
+  part += tb * bt.sp;
   constexpr int PAD = 1;
   __shared__ double As[BM][BK + PAD];
   __shared__ double Bs[BN][BK + PAD];
   int tm, tn;
   {
-    int t = blockIdx.x;
+    int t = blockIdx.x / bt.T;
     if (upper) {
       tm = 0;
       int rowlen = n_tn;
@@ -472,53 +487,67 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
 
 static hipError_t gemm_launch(hipStream_t s, int M, int N, long K, const double* A, long lda,
                               const double* B, long ldb, const double* w, double* part, long kps,
-                              int n_split, int upper, int big, SeriesSkip sk) {
+                              int n_split, int upper, int big, Batch bt, SeriesSkip sk) {
   if (big) {
     int ntm = cdiv(M, 128), ntn = cdiv(N, 128);
     int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
-    hipLaunchKernelGGL((k_gemm_nt_f64<128, 128, 16>), dim3(nt, n_split), dim3(256), 0, s, M, N, K, A,
-                       lda, B, ldb, w, part, kps, upper, ntn, sk);
+    hipLaunchKernelGGL((k_gemm_nt_f64<128, 128, 16>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K,
+                       A, lda, B, ldb, w, part, kps, upper, ntn, bt, sk);
   } else {
     int ntm = cdiv(M, 64), ntn = cdiv(N, 64);
     int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
-    hipLaunchKernelGGL((k_gemm_nt_f64<64, 64, 32>), dim3(nt, n_split), dim3(256), 0, s, M, N, K, A,
-                       lda, B, ldb, w, part, kps, upper, ntn, sk);
+    hipLaunchKernelGGL((k_gemm_nt_f64<64, 64, 32>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K, A,
+                       lda, B, ldb, w, part, kps, upper, ntn, bt, sk);
   }
   return hipGetLastError();
 }
 
 hipError_t gemm_nt_f64(hipStream_t s, int M, int N, long K, const double* A, long lda,
                        const double* B, long ldb, const double* w, double* part, long kps,
-                       int n_split, int upper, int big) {
-  SeriesSkip sk{nullptr, nullptr, nullptr, 0.0, 0};
-  return gemm_launch(s, M, N, K, A, lda, B, ldb, w, part, kps, n_split, upper, big, sk);
+                       int n_split, int upper, int big, Batch bt) {
+  SeriesSkip sk{nullptr, nullptr, nullptr, 0.0, 0, 0};
+  return gemm_launch(s, M, N, K, A, lda, B, ldb, w, part, kps, n_split, upper, big, bt, sk);
 }
 
-hipError_t gemm_nt_f64_series(hipStream_t s, int N, const double* Hbar, const double* dP, double* C,
-                              int k, const unsigned long long* slots, const double* kmin,
-                              double thrs, const int* done) {
-  SeriesSkip sk{slots, kmin, done, thrs, k};
-  return gemm_launch(s, N, 2 * N, N, Hbar, N, dP, N, nullptr, C, N, 1, 0, 0, sk);
+hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, const double* dP, double* C,
+                              int k, const unsigned long long* slots, int stride, const double* kmin,
+                              double thrs, const int* done, const int* active) {
+  SeriesSkip sk{slots, kmin, done, thrs, k, stride};
+  long NN = (long)N * N;
+  Batch bt{T, active, NN, 2 * NN, 0, 2 * NN};
+  return gemm_launch(s, N, 2 * N, N, Hbar, N, dP, N, nullptr, C, N, 1, 0, 0, bt, sk);
 }
 
+// C_t[m][n] = base_t[m][n] + alpha * sum_s part_t[s][m][n]; with mirror the upper
+// part is kept and copied to the lower one.  blockIdx.y = trajectory.
 __global__ void k_reduce_parts(const double* __restrict__ part, int n_split, int M, int N, double alpha,
-                               double* __restrict__ C, int mirror) {
+                               const double* __restrict__ base, double* __restrict__ C, int mirror,
+                               long sp, long sbase, long sc, const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)M * N) return;
   int m = (int)(e / N), n = (int)(e - (long)m * N);
   if (mirror && m > n) return;
+  part += t * sp;
+  C += t * sc;
+  if (base) base += t * sbase;
   double acc = 0.0;
   for (int sI = 0; sI < n_split; ++sI) acc += part[(long)sI * M * N + e];
   acc *= alpha;
-  C[e] = acc;
-  if (mirror && m < n) C[(long)n * N + m] = acc;
+  C[e] = base ? base[e] + acc : acc;
+  if (mirror && m < n) {
+    long f = (long)n * N + m;
+    C[f] = base ? base[f] + acc : acc;
+  }
 }
 
 hipError_t reduce_parts(hipStream_t s, const double* part, int n_split, int M, int N, double alpha,
-                        double* C, int mirror) {
+                        double* C, int mirror, const double* base, int T, long sp, long sbase, long sc,
+                        const int* active) {
   long n = (long)M * N;
-  hipLaunchKernelGGL(k_reduce_parts, dim3(cdiv(n, 256)), dim3(256), 0, s, part, n_split, M, N, alpha, C,
-                     mirror);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(cdiv(n, 256), T), dim3(256), 0, s, part, n_split, M, N, alpha, base,
+                     C, mirror, sp, sbase, sc, active);
   return hipGetLastError();
 }
 
@@ -526,18 +555,24 @@ hipError_t reduce_parts(hipStream_t s, const double* part, int n_split, int M, i
 // Small x tall FP64 MFMA product over grid columns: Phi = W . Psi with either
 // Phi stored (orthonormalisation) or rho[r] = sum_i Psi[i][r] Phi[i][r]
 // reduced in the epilogue (density from a density matrix), Phi never stored.
+// Batched over trajectories: W_t = W + t N^2, out_t = out + t * (N ng | ng).
 // ============================================================================
 template <int MODE>
 __global__ __launch_bounds__(256) void k_smalltall_f64(int N, long ng, const double* __restrict__ W,
                                                        const double* __restrict__ psi,
-                                                       double* __restrict__ out, int tri) {
+                                                       double* __restrict__ out, int tri, int T,
+                                                       const int* active) {
   constexpr int BM = 64, BN = 64, BK = 32;
   __shared__ double Ws[BM][BK + 1];
   __shared__ double Ps[BK][BN + 1];
   __shared__ double red[2][4][BN];
+  const int tb = blockIdx.x % T;
+  if (active && !active[tb]) return;
+  W += (long)tb * N * N;
+  out += MODE == 0 ? (long)tb * N * ng : (long)tb * ng;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
-  const long r0 = (long)blockIdx.x * BN;
+  const long r0 = (long)(blockIdx.x / T) * BN;
   double rho_part[2] = {0.0, 0.0};
   const int nI = cdiv(N, BM);
   for (int I = 0; I < nI; ++I) {
@@ -605,12 +640,12 @@ __global__ __launch_bounds__(256) void k_smalltall_f64(int N, long ng, const dou
 }
 
 hipError_t smalltall_f64(hipStream_t s, int N, long ng, const double* W, const double* psi,
-                         double* out, int mode, int tri) {
-  dim3 grid(cdiv(ng, 64));
+                         double* out, int mode, int tri, int T, const int* active) {
+  dim3 grid(cdiv(ng, 64) * T);
   if (mode == 0)
-    hipLaunchKernelGGL((k_smalltall_f64<0>), grid, dim3(256), 0, s, N, ng, W, psi, out, tri);
+    hipLaunchKernelGGL((k_smalltall_f64<0>), grid, dim3(256), 0, s, N, ng, W, psi, out, tri, T, active);
   else
-    hipLaunchKernelGGL((k_smalltall_f64<1>), grid, dim3(256), 0, s, N, ng, W, psi, out, tri);
+    hipLaunchKernelGGL((k_smalltall_f64<1>), grid, dim3(256), 0, s, N, ng, W, psi, out, tri, T, active);
   return hipGetLastError();
 }
 
@@ -820,24 +855,47 @@ hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double
   return hipGetLastError();
 }
 
+// dst_t = src_t for active trajectories (blockIdx.y = t), n elements each.
+__global__ void k_copy_masked(double* dst, const double* src, long n, const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[t * n + i] = src[t * n + i];
+}
+hipError_t copy_masked(hipStream_t s, double* dst, const double* src, long n, int T, const int* active) {
+  int nb = ew_blocks(n) > 256 ? 256 : ew_blocks(n);
+  hipLaunchKernelGGL(k_copy_masked, dim3(nb, T), dim3(256), 0, s, dst, src, n, active);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_max_abs_diff(const double* a, const double* b, long n,
-                                                      unsigned long long* slot) {
+                                                      unsigned long long* slot, const int* active) {
   __shared__ double sh[256];
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  a += t * n;
+  b += t * n;
   double m = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     m = fmax(m, fabs(a[i] - b[i]));
   m = block_max_256(m, sh);
-  if (threadIdx.x == 0) atomic_max_nonneg(slot, m);
+  if (threadIdx.x == 0) atomic_max_nonneg(slot + t, m);
 }
-hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n, unsigned long long* slot) {
-  hipLaunchKernelGGL(k_max_abs_diff, dim3(ew_blocks(n) > 256 ? 256 : ew_blocks(n)), dim3(256), 0, s, a, b,
-                     n, slot);
+hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n, unsigned long long* slot,
+                        int T, const int* active) {
+  int nb = ew_blocks(n) > 256 ? 256 : ew_blocks(n);
+  hipLaunchKernelGGL(k_max_abs_diff, dim3(nb, T), dim3(256), 0, s, a, b, n, slot, active);
   return hipGetLastError();
 }
 
-// k_min = ceil(dt * (max_i (a_ii + r_i) - min_i (a_ii - r_i))), r_i = sum_{j != i} |a_ij|.
-__global__ __launch_bounds__(256) void k_gershgorin(const double* A, int N, double dt, double* kmin) {
+// k_min = ceil(dt * (max_i (a_ii + r_i) - min_i (a_ii - r_i))), r_i = sum_{j != i} |a_ij|;
+// one block per trajectory (A_t = A + t N^2).
+__global__ __launch_bounds__(256) void k_gershgorin(const double* A, int N, double dt, double* kmin,
+                                                    const int* active) {
   __shared__ double sh[256];
+  const int t = blockIdx.x;
+  if (active && !active[t]) return;
+  A += (long)t * N * N;
   double hi = -1e300, lo = 1e300;
   for (int i = threadIdx.x; i < N; i += 256) {
     double r = 0.0;
@@ -849,80 +907,97 @@ __global__ __launch_bounds__(256) void k_gershgorin(const double* A, int N, doub
   }
   hi = block_max_256(hi, sh);
   lo = -block_max_256(-lo, sh);
-  if (threadIdx.x == 0) *kmin = ceil(fabs(dt) * (hi - lo));
+  if (threadIdx.x == 0) kmin[t] = ceil(fabs(dt) * (hi - lo));
 }
-hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out) {
-  hipLaunchKernelGGL(k_gershgorin, dim3(1), dim3(256), 0, s, A, N, dt, kmin_out);
+hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, int T,
+                      const int* active) {
+  hipLaunchKernelGGL(k_gershgorin, dim3(T), dim3(256), 0, s, A, N, dt, kmin_out, active);
   return hipGetLastError();
 }
 
 // dP_k = (1/k)(-i dt)[Hbar, S + iA]:  S_k = (dt/k)[Hbar, A],  A_k = -(dt/k)[Hbar, S].
 // C = Hbar . [S; A]^T, so C[:, :N] = Hbar S and C[:, N:] = -Hbar A (S symmetric, A antisymmetric).
+// blockIdx.y = trajectory; C, dPn, P1 have stride 2 N^2.
 __global__ __launch_bounds__(256) void k_series_update(const double* __restrict__ C, double* __restrict__ dPn,
                                                        double* __restrict__ P1, int N, double dt,
-                                                       SeriesSkip sk, int* done) {
+                                                       SeriesSkip sk, int* done, const int* active) {
   __shared__ double sh[256];
-  if (series_stopped(sk)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && done[0] == 0) {
-      done[0] = 1;
-      done[1] = sk.k - 1;
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  if (series_stopped(sk, t)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && done[2 * t] == 0) {
+      done[2 * t] = 1;
+      done[2 * t + 1] = sk.k - 1;
     }
     return;
   }
   const double f = dt / sk.k;
   const long NN = (long)N * N;
   const long N2 = 2L * N;
+  C += t * 2 * NN;
+  dPn += t * 2 * NN;
+  P1 += t * 2 * NN;
   double m = 0.0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += (long)gridDim.x * blockDim.x) {
     int i = (int)(e / N), j = (int)(e - (long)i * N);
     double gA_ij = C[(long)i * N2 + N + j], gA_ji = C[(long)j * N2 + N + i];
     double gS_ij = C[(long)i * N2 + j], gS_ji = C[(long)j * N2 + i];
-    double s = -f * (gA_ij + gA_ji);
-    double a = -f * (gS_ij - gS_ji);
-    dPn[e] = s;
-    dPn[NN + e] = a;
-    P1[e] += s;
-    P1[NN + e] += a;
-    m = fmax(m, sqrt(s * s + a * a));
+    double sv = -f * (gA_ij + gA_ji);
+    double av = -f * (gS_ij - gS_ji);
+    dPn[e] = sv;
+    dPn[NN + e] = av;
+    P1[e] += sv;
+    P1[NN + e] += av;
+    m = fmax(m, sqrt(sv * sv + av * av));
   }
   m = block_max_256(m, sh);
-  if (threadIdx.x == 0) atomic_max_nonneg(const_cast<unsigned long long*>(sk.slots) + sk.k, m);
+  if (threadIdx.x == 0)
+    atomic_max_nonneg(const_cast<unsigned long long*>(sk.slots) + (long)t * sk.stride + sk.k, m);
 }
 hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1, int N, double dt, int k,
-                         unsigned long long* slots, const double* kmin, double thrs, int* done) {
-  SeriesSkip sk{slots, kmin, done, thrs, k};
+                         unsigned long long* slots, int stride, const double* kmin, double thrs, int* done,
+                         int T, const int* active) {
+  SeriesSkip sk{slots, kmin, done, thrs, k, stride};
   long NN = (long)N * N;
   int nb = ew_blocks(NN);
   if (nb > 256) nb = 256;
-  hipLaunchKernelGGL(k_series_update, dim3(nb), dim3(256), 0, s, C, dPn, P1, N, dt, sk, done);
+  hipLaunchKernelGGL(k_series_update, dim3(nb, T), dim3(256), 0, s, C, dPn, P1, N, dt, sk, done, active);
   return hipGetLastError();
 }
 
-__global__ void k_series_finish(SeriesSkip sk, int* done) {
-  if (threadIdx.x == 0 && done[0] == 0 && series_stopped(sk)) {
-    done[0] = 1;
-    done[1] = sk.k - 1;
+__global__ void k_series_finish(SeriesSkip sk, int* done, int T, const int* active) {
+  int t = threadIdx.x;
+  if (t >= T || (active && !active[t])) return;
+  if (done[2 * t] == 0 && series_stopped(sk, t)) {
+    done[2 * t] = 1;
+    done[2 * t + 1] = sk.k - 1;
   }
 }
-hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, const double* kmin,
-                         double thrs, int* done) {
-  SeriesSkip sk{slots, kmin, done, thrs, kmax + 1};
-  hipLaunchKernelGGL(k_series_finish, dim3(1), dim3(64), 0, s, sk, done);
+hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, int stride,
+                         const double* kmin, double thrs, int* done, int T, const int* active) {
+  SeriesSkip sk{slots, kmin, done, thrs, kmax + 1, stride};
+  hipLaunchKernelGGL(k_series_finish, dim3(1), dim3(256), 0, s, sk, done, T, active);
   return hipGetLastError();
 }
 
 // mu_q = sum_ij S_ij M_q,ij ; E = sum_ij S_ij Hcore_ij + E_x + E_H ; TrP = sum_i S_ii.
+// One block per trajectory: S_t = S + t 2N^2, eparts_t = eparts + 2t, row_t = rows + t rstride.
 __global__ __launch_bounds__(256) void k_observables(const double* S, const double* M3, const double* hc,
-                                                     int N, const double* eparts, double* row) {
+                                                     int N, const double* eparts, int estride, double* rows,
+                                                     long rstride) {
   __shared__ double sh[256];
+  const int t = blockIdx.x;
   const long NN = (long)N * N;
+  S += t * 2 * NN;
+  eparts += (long)t * estride;
+  double* row = rows + t * rstride;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
   for (long e = threadIdx.x; e < NN; e += 256) {
-    double s = S[e];
-    a0 += s * M3[e];
-    a1 += s * M3[NN + e];
-    a2 += s * M3[2 * NN + e];
-    a3 += s * hc[e];
+    double sv = S[e];
+    a0 += sv * M3[e];
+    a1 += sv * M3[NN + e];
+    a2 += sv * M3[2 * NN + e];
+    a3 += sv * hc[e];
   }
   for (int i = threadIdx.x; i < N; i += 256) a4 += S[(long)i * N + i];
   a0 = block_sum_256(a0, sh);
@@ -939,8 +1014,8 @@ __global__ __launch_bounds__(256) void k_observables(const double* S, const doub
   }
 }
 hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
-                       const double* eparts, double* hist_row) {
-  hipLaunchKernelGGL(k_observables, dim3(1), dim3(256), 0, s, S, M3, hcore, N, eparts, hist_row);
+                       const double* eparts, int estride, double* rows, long rstride, int T) {
+  hipLaunchKernelGGL(k_observables, dim3(T), dim3(256), 0, s, S, M3, hcore, N, eparts, estride, rows, rstride);
   return hipGetLastError();
 }
 
@@ -997,15 +1072,21 @@ hipError_t tri_inverse_lower(hipStream_t s, const double* L, double* Linv, int N
 }
 
 // W_ij = S_ij * (2 if i < j, 1 if i == j, 0 if i > j): rho = sum_i psi_i sum_{j >= i} W_ij psi_j.
-__global__ void k_upper_weighted(const double* S, double* W, int N) {
+// blockIdx.y = trajectory; S_t = S + t sstride, W_t = W + t N^2.
+__global__ void k_upper_weighted(const double* S, double* W, int N, long sstride, const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)N * N) return;
+  S += t * sstride;
+  W += t * (long)N * N;
   int i = (int)(e / N), j = (int)(e - (long)i * N);
   W[e] = i < j ? 2.0 * S[e] : (i == j ? S[e] : 0.0);
 }
-hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N) {
+hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N, long sstride, int T,
+                          const int* active) {
   long n = (long)N * N;
-  hipLaunchKernelGGL(k_upper_weighted, dim3(cdiv(n, 256)), dim3(256), 0, s, S, W, N);
+  hipLaunchKernelGGL(k_upper_weighted, dim3(cdiv(n, 256), T), dim3(256), 0, s, S, W, N, sstride, active);
   return hipGetLastError();
 }
 

@@ -1,0 +1,24 @@
+// Launchers of the BF16x3 mixed-precision grid contractions (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rtk {
+
+// hi = bf16(x), lo = bf16(x - hi)
+hipError_t split_bf16(hipStream_t s, const double* x, unsigned short* hi, unsigned short* lo, long n);
+// upper-weighted (S - S0) split to bf16 hi/lo (density weights of the change)
+hipError_t upper_weighted_delta_bf16(hipStream_t s, const double* S, const double* S0, unsigned short* hi,
+                                     unsigned short* lo, int N, long sstride, int T, const int* active);
+// part[s] (FP32, N x N, upper tiles) = sum_k A[m][k] w[k] A[n][k]; requires ng % 8 == 0
+hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, const unsigned short* lo,
+                       const float* w, float* part, long kps, int n_split, int T, const int* active);
+// C = base + alpha * sum_s part[s] (upper kept, mirrored)
+hipError_t reduce_parts_f32(hipStream_t s, const float* part, int n_split, int N, double alpha,
+                            const double* base, double* C, int T, const int* active);
+// rho = rho0 + sum_i psi_i sum_{j>=i} W_ij psi_j
+hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* whi, const unsigned short* wlo,
+                          const unsigned short* phi, const unsigned short* plo, const double* rho0, double* rho,
+                          int T, const int* active);
+hipError_t delta_f32(hipStream_t s, float* d, const double* a, const double* b, long n, int T, const int* active);
+
+}  // namespace rtk

@@ -3,6 +3,7 @@
 // and the self-consistent time loop of Algorithm 1 driving the kernels.
 #include "../../include/rt_tddft.h"
 #include "kernels.h"
+#include "kernels_mixed.h"
 
 #include <hip/hip_runtime.h>
 
@@ -115,6 +116,9 @@ static NlTables build_nl(const rt_system& s) {
   return t;
 }
 
+// All trajectories of one system step in lockstep: their matrices are stacked
+// ([T][...]) so every stage is one launch over the active trajectories, and
+// the grid kernels of different trajectories share the orbital reads.
 struct SysDev {
   int nx, ny, nz, N, n_occ, n_atoms, n_images;
   long ng;
@@ -124,29 +128,42 @@ struct SysDev {
   int n_union = 0;
   int n_split = 1, big = 0;
   long kps = 0;
-  // device buffers
-  double *psi, *hpsi, *vion, *rho, *vh, *vx, *vloc, *vloc_gs, *dv;
-  float *psi32, *vloc32;
+  int n_split_x = 1;  // splits of the BF16x3 projection
+  long kps_x = 0;
+  bool mixed = false;
+  int T = 1;          // trajectory slots of this system (>= 1)
+  int step = 0;       // steps taken (lockstep)
+  std::vector<int> slot_traj;  // global trajectory index of each slot (-1: none)
+  std::vector<int> active_host;
+  std::vector<int> zeros2T;    // host zeros for the series flags
+  // orbitals and static fields
+  double *psi, *hpsi, *vion, *vloc_gs, *occ;
+  float* vloc32;
   double2* z;
   double2 *twx, *twy, *twz;
   double *pos, *depth, *width;
   int *atom_off, *sph_idx, *u_idx, *u_ptr, *ent_pt, *ent_atom;
   double *beta, *Dd, *cnl;
-  double *hcore, *M3, *Hgs, *W, *tmp, *part, *occ;
-  double *red2, *eparts, *escale, *ezero;
+  double *hcore, *M3, *Hgs, *tmp, *tmp2, *red2, *escale, *ezero;
   int* info;
+  // per-trajectory grid fields [T][ng] and weights
+  double *rho, *vh, *vx, *vloc, *dv, *eparts, *W, *part;
+  // mixed precision: orbitals and density weights as bf16 hi/lo, FP64 ground-state references
+  unsigned short *psi_hi, *psi_lo, *w_hi, *w_lo;
+  double *rho_gs, *S_gs;
+  float *dv32, *part32;
+  // per-trajectory state [T][...]
+  double *P0, *P1, *dP, *dPn, *C;          // stacked [S'; A'], 2 N^2 each
+  double *H0, *H1, *Hm1, *Hn, *Hbar;       // N^2 each
+  double* hist;                            // [T][cap + 1][5]
+  double* kmin;                            // [T]
+  unsigned long long *slots, *resid;       // [T][max_terms + 2], [T]
+  int *done, *active;                      // [T][2], [T]
 };
 
 struct TrajDev {
-  int sys, axis;
+  int sys, slot, axis;
   double kappa;
-  double *P0, *P1, *dP, *dPn, *C;
-  double *H0, *H1, *Hm1, *Hn, *Hbar;
-  double* hist;
-  double* kmin;
-  unsigned long long *slots, *resid;
-  int* done;
-  int step = 0;
 };
 
 }  // namespace
@@ -173,7 +190,6 @@ struct rt_ctx {
   std::vector<TrajDev> traj;
   std::string err;
   int hist_cap = 0;
-  double* coef_dev = nullptr;
 };
 
 namespace {
@@ -182,6 +198,11 @@ namespace {
   do {                                                                              \
     hipError_t e_ = (expr);                                                         \
     if (e_ != hipSuccess) return fail(c, RT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define RET(expr)                \
+  do {                           \
+    rt_status r_ = (expr);       \
+    if (r_ != RT_OK) return r_;  \
   } while (0)
 
 rt_status fail(rt_ctx* c, rt_status st, const std::string& msg) {
@@ -254,7 +275,12 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
   if (!(run->dt != 0.0) || run->n_steps_max < 0 || run->max_scf < 1 || run->max_terms < 1 ||
       !(run->h_thrs > 0) || !(run->dp_thrs > 0)) { why = "run parameters"; return RT_EINVAL; }
   if (run->precision != RT_FP64 && run->precision != RT_MIXED) { why = "precision"; return RT_EINVAL; }
-  if (run->precision == RT_MIXED) { why = "mixed precision is not available in this build"; return RT_EINVAL; }
+  if (run->precision == RT_MIXED) {
+    for (int i = 0; i < n_sys; ++i)
+      if (((long)sys[i].n[0] * sys[i].n[1] * sys[i].n[2]) % 8 != 0) {
+        why = "mixed precision needs a grid point count divisible by 8"; return RT_EINVAL;
+      }
+  }
   if (run->predictor != RT_PRED_LINEAR) { why = "only the linear predictor is available in this build"; return RT_EINVAL; }
   if (run->hupdate != RT_HUPDATE_FULL && run->hupdate != RT_HUPDATE_LOCAL) { why = "hupdate"; return RT_EINVAL; }
   if (run->n_traj < 0 || (run->n_traj > 0 && (!run->traj_sys || !run->traj_kappa || !run->traj_axis))) {
@@ -281,23 +307,26 @@ void choose_split(SysDev& d) {
   kps = (kps + bk - 1) / bk * bk;
   d.kps = kps;
   d.n_split = (int)((d.ng + kps - 1) / kps);
+  // BF16x3 projection: 128 x 128 upper tiles, K chunks of 64
+  int ntx = (d.N + 127) / 128;
+  int tx = ntx * (ntx + 1) / 2;
+  long nsx = std::min((1024L + tx - 1) / tx, std::max(1L, d.ng / 2048));
+  long kx = (d.ng + nsx - 1) / nsx;
+  kx = (kx + 63) / 64 * 64;
+  d.kps_x = kx;
+  d.n_split_x = (int)((d.ng + kx - 1) / kx);
 }
 
 // Places every buffer; with a.base == nullptr only sizes.
-void layout(Arena& a, std::vector<SysDev>& S, std::vector<TrajDev>& T, const rt_run& run, int hist_cap) {
+void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
   for (auto& d : S) {
-    long ng = d.ng, N = d.N;
+    const long ng = d.ng, N = d.N, T = d.T, NN = N * N;
     d.psi = a.take<double>(N * ng);
     d.hpsi = a.take<double>(N * ng);
     d.vion = a.take<double>(ng);
-    d.rho = a.take<double>(ng);
-    d.vh = a.take<double>(ng);
-    d.vx = a.take<double>(ng);
-    d.vloc = a.take<double>(ng);
     d.vloc_gs = a.take<double>(ng);
-    d.dv = a.take<double>(ng);
+    d.occ = a.take<double>(N);
     d.vloc32 = a.take<float>(ng);
-    d.psi32 = nullptr;
     d.z = a.take<double2>(ng);
     d.twx = a.take<double2>(d.nx);
     d.twy = a.take<double2>(d.ny);
@@ -314,42 +343,56 @@ void layout(Arena& a, std::vector<SysDev>& S, std::vector<TrajDev>& T, const rt_
     d.ent_pt = a.take<int>(d.nl.ent_pt.size() + 1);
     d.ent_atom = a.take<int>(d.nl.ent_atom.size() + 1);
     d.cnl = a.take<double>(N * std::max(1, d.nl.n_proj));
-    d.hcore = a.take<double>(N * N);
-    d.M3 = a.take<double>(3 * N * N);
-    d.Hgs = a.take<double>(N * N);
-    d.W = a.take<double>(N * N);
-    d.tmp = a.take<double>(N * N);
-    d.part = a.take<double>((long)d.n_split * N * N);
-    d.occ = a.take<double>(N);
+    d.hcore = a.take<double>(NN);
+    d.M3 = a.take<double>(3 * NN);
+    d.Hgs = a.take<double>(NN);
+    d.tmp = a.take<double>(NN);
+    d.tmp2 = a.take<double>(NN);
     d.red2 = a.take<double>(2 * rtk::kRedBlocks);
-    d.eparts = a.take<double>(2);
     d.escale = a.take<double>(2);
     d.ezero = a.take<double>(2);
     d.info = a.take<int>(4);
-  }
-  for (auto& t : T) {
-    long N = S[t.sys].N;
-    t.P0 = a.take<double>(2 * N * N);
-    t.P1 = a.take<double>(2 * N * N);
-    t.dP = a.take<double>(2 * N * N);
-    t.dPn = a.take<double>(2 * N * N);
-    t.C = a.take<double>(2 * N * N);
-    t.H0 = a.take<double>(N * N);
-    t.H1 = a.take<double>(N * N);
-    t.Hm1 = a.take<double>(N * N);
-    t.Hn = a.take<double>(N * N);
-    t.Hbar = a.take<double>(N * N);
-    t.hist = a.take<double>(5L * (hist_cap + 1));
-    t.kmin = a.take<double>(1);
-    t.slots = a.take<unsigned long long>(run.max_terms + 2);
-    t.resid = a.take<unsigned long long>(1);
-    t.done = a.take<int>(2);
+    d.rho = a.take<double>(T * ng);
+    d.vh = a.take<double>(T * ng);
+    d.vx = a.take<double>(T * ng);
+    d.vloc = a.take<double>(T * ng);
+    d.dv = a.take<double>(T * ng);
+    d.eparts = a.take<double>(2 * T);
+    d.W = a.take<double>(T * NN);
+    d.part = a.take<double>(T * d.n_split * NN);
+    if (d.mixed) {
+      d.psi_hi = a.take<unsigned short>(N * ng);
+      d.psi_lo = a.take<unsigned short>(N * ng);
+      d.w_hi = a.take<unsigned short>(T * NN);
+      d.w_lo = a.take<unsigned short>(T * NN);
+      d.rho_gs = a.take<double>(ng);
+      d.S_gs = a.take<double>(NN);
+      d.dv32 = a.take<float>(T * ng);
+      d.part32 = a.take<float>(T * d.n_split_x * NN);
+    }
+    d.P0 = a.take<double>(T * 2 * NN);
+    d.P1 = a.take<double>(T * 2 * NN);
+    d.dP = a.take<double>(T * 2 * NN);
+    d.dPn = a.take<double>(T * 2 * NN);
+    d.C = a.take<double>(T * 2 * NN);
+    d.H0 = a.take<double>(T * NN);
+    d.H1 = a.take<double>(T * NN);
+    d.Hm1 = a.take<double>(T * NN);
+    d.Hn = a.take<double>(T * NN);
+    d.Hbar = a.take<double>(T * NN);
+    d.hist = a.take<double>(T * 5L * (hist_cap + 1));
+    d.kmin = a.take<double>(T);
+    d.slots = a.take<unsigned long long>(T * (run.max_terms + 2));
+    d.resid = a.take<unsigned long long>(T);
+    d.done = a.take<int>(2 * T);
+    d.active = a.take<int>(T);
   }
 }
 
 void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<SysDev>& S,
               std::vector<TrajDev>& T) {
   S.resize(n_sys);
+  T.resize(run->n_traj);
   for (int i = 0; i < n_sys; ++i) {
     const rt_system& s = sys[i];
     SysDev& d = S[i];
@@ -366,13 +409,23 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
     d.coef[3] = 8.0 / 315.0; d.coef[4] = -1.0 / 560.0;
     d.nl = build_nl(s);
     d.n_union = (int)d.nl.u_idx.size();
+    d.mixed = run->precision == RT_MIXED;
+    d.slot_traj.clear();
     choose_split(d);
   }
-  T.resize(run->n_traj);
   for (int t = 0; t < run->n_traj; ++t) {
+    SysDev& d = S[run->traj_sys[t]];
     T[t].sys = run->traj_sys[t];
+    T[t].slot = (int)d.slot_traj.size();
     T[t].axis = run->traj_axis[t];
     T[t].kappa = run->traj_kappa[t];
+    d.slot_traj.push_back(t);
+  }
+  for (auto& d : S) {
+    if (d.slot_traj.empty()) d.slot_traj.push_back(-1);
+    d.T = (int)d.slot_traj.size();
+    d.active_host.assign(d.T, 1);
+    d.zeros2T.assign(2 * d.T, 0);
   }
 }
 
@@ -383,17 +436,23 @@ rt_status upload(rt_ctx* c, void* dst, const std::vector<V>& v) {
   return RT_OK;
 }
 
+rt_status push_active(rt_ctx* c, SysDev& d) {
+  CK(hipMemcpyAsync(d.active, d.active_host.data(), d.T * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  return RT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Stages
 // ---------------------------------------------------------------------------
-// Symmetric projection out = alpha * A diag(w) B^T over the grid (upper tiles, mirrored).
+// Symmetric projection out = h^3 A diag(w) B^T over the grid for one problem.
 rt_status project(rt_ctx* c, SysDev& d, const double* A, const double* B, const double* w, double* out) {
   {
     Timed tm(c, PH_PROJECT);
-    CK(rtk::gemm_nt_f64(c->stream, d.N, d.N, d.ng, A, d.ng, B, d.ng, w, d.part, d.kps, d.n_split, 1, d.big));
+    CK(rtk::gemm_nt_f64(c->stream, d.N, d.N, d.ng, A, d.ng, B, d.ng, w, d.part, d.kps, d.n_split, 1, d.big,
+                        rtk::single()));
   }
   Timed tm(c, PH_REDUCE);
-  CK(rtk::reduce_parts(c->stream, d.part, d.n_split, d.N, d.N, d.h3, out, 1));
+  CK(rtk::reduce_parts(c->stream, d.part, d.n_split, d.N, d.N, d.h3, out, 1, nullptr, 1, 0, 0, 0, nullptr));
   return RT_OK;
 }
 
@@ -428,106 +487,149 @@ rt_status apply_h32(rt_ctx* c, SysDev& d, const float* psi, float* hpsi, int n) 
   return RT_OK;
 }
 
-// rho = sum_ij S_ij psi_i psi_j; V_H by spectral Poisson; v_x, V_loc and energies.
-rt_status potentials(rt_ctx* c, SysDev& d, const double* S) {
+// Spectral Poisson + LDA for slot t (FP64): rho_t -> V_H, v_x, V_loc, energies.
+rt_status poisson_lda(rt_ctx* c, SysDev& d, int t) {
   hipStream_t s = c->stream;
+  const long o = (long)t * d.ng;
   {
-    Timed tm(c, PH_DENSITY);
-    CK(rtk::upper_weighted(s, S, d.W, d.N));
-    CK(rtk::smalltall_f64(s, d.N, d.ng, d.W, d.psi, d.rho, 1, 1));
-  }
-  {
-  Timed tp(c, PH_POISSON);
-  CK(rtk::pack_real(s, d.z, d.rho, d.ng));
-  CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 0, d.twx, 0));
-  CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 1, d.twy, 0));
-  CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 2, d.twz, 0));
-  CK(rtk::poisson_scale(s, d.z, d.nx, d.ny, d.nz, d.h));
-  CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 0, d.twx, 1));
-  CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 1, d.twy, 1));
-  CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 2, d.twz, 1));
-  CK(rtk::real_part(s, d.vh, d.z, d.ng));
+    Timed tp(c, PH_POISSON);
+    CK(rtk::pack_real(s, d.z, d.rho + o, d.ng));
+    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 0, d.twx, 0));
+    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 1, d.twy, 0));
+    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 2, d.twz, 0));
+    CK(rtk::poisson_scale(s, d.z, d.nx, d.ny, d.nz, d.h));
+    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 0, d.twx, 1));
+    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 1, d.twy, 1));
+    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 2, d.twz, 1));
+    CK(rtk::real_part(s, d.vh + o, d.z, d.ng));
   }
   Timed tl(c, PH_LDA);
-  CK(rtk::lda_vloc(s, d.rho, d.vh, d.vion, d.vx, d.vloc, d.ng, d.red2));
-  CK(rtk::reduce_cols(s, d.red2, rtk::kRedBlocks, 2, d.escale, d.eparts));
+  CK(rtk::lda_vloc(s, d.rho + o, d.vh + o, d.vion, d.vx + o, d.vloc + o, d.ng, d.red2));
+  CK(rtk::reduce_cols(s, d.red2, rtk::kRedBlocks, 2, d.escale, d.eparts + 2 * t));
   return RT_OK;
 }
 
-// H_out = H[P] for P with real part S (Algorithm 1: H_1 <- DFT(rho(P_1))).
-rt_status eval_h(rt_ctx* c, SysDev& d, const double* S, double* Hout, int force_full) {
+// Hout_t = H[P_t] for the T' slots (S_t real parts with stride sstride, Hout stride N^2).
+// act: device flags (nullable = all T); act_host mirrors them.  mode_full forces the
+// FP64 full apply (ground-state build).
+rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<int>& act_host,
+                 const double* S, long sstride, double* Hout, bool force_full) {
+  hipStream_t s = c->stream;
   const rt_run& r = c->run;
+  const long NN = nsq(d.N);
   if (r.frozen_hxc && !force_full) {
-    CK(rtk::copy_d(c->stream, Hout, d.Hgs, nsq(d.N)));
+    for (int t = 0; t < T; ++t)
+      if (act_host[t]) CK(rtk::copy_d(s, Hout + t * NN, d.Hgs, NN));
     return RT_OK;
   }
-  rt_status st = potentials(c, d, S);
-  if (st != RT_OK) return st;
-  if (r.hupdate == RT_HUPDATE_FULL || force_full) {
-    st = apply_h64(c, d, d.psi, d.hpsi, d.vloc, d.N);
-    if (st != RT_OK) return st;
-    return project(c, d, d.psi, d.hpsi, nullptr, Hout);
+  const bool mixed = d.mixed && !force_full;
+  {
+    Timed tm(c, PH_DENSITY);
+    if (mixed) {
+      CK(rtk::upper_weighted_delta_bf16(s, S, d.S_gs, d.w_hi, d.w_lo, d.N, sstride, T, act));
+      CK(rtk::density_bf16x3(s, d.N, d.ng, d.w_hi, d.w_lo, d.psi_hi, d.psi_lo, d.rho_gs, d.rho, T, act));
+    } else {
+      CK(rtk::upper_weighted(s, S, d.W, d.N, sstride, T, act));
+      CK(rtk::smalltall_f64(s, d.N, d.ng, d.W, d.psi, d.rho, 1, 1, T, act));
+    }
   }
-  // local update: H[P] = H_gs + h^3 Psi diag(V_loc - V_loc,gs) Psi^T
-  CK(rtk::sub_d(c->stream, d.dv, d.vloc, d.vloc_gs, d.ng));
-  st = project(c, d, d.psi, d.psi, d.dv, d.tmp);
-  if (st != RT_OK) return st;
-  CK(rtk::lincomb(c->stream, Hout, 1.0, d.Hgs, 1.0, d.tmp, nsq(d.N)));
+  for (int t = 0; t < T; ++t)
+    if (act_host[t]) RET(poisson_lda(c, d, t));
+  if (mixed) {
+    // H = H_gs + h^3 Psi diag(V_loc - V_loc,gs) Psi^T in BF16x3
+    CK(rtk::delta_f32(s, d.dv32, d.vloc, d.vloc_gs, d.ng, T, act));
+    {
+      Timed tm(c, PH_PROJECT);
+      CK(rtk::proj_bf16x3(s, d.N, d.ng, d.psi_hi, d.psi_lo, d.dv32, d.part32, d.kps_x, d.n_split_x, T, act));
+    }
+    Timed tr(c, PH_REDUCE);
+    CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.Hgs, Hout, T, act));
+    return RT_OK;
+  }
+  if (r.hupdate == RT_HUPDATE_FULL || force_full) {
+    for (int t = 0; t < T; ++t) {
+      if (!act_host[t]) continue;
+      RET(apply_h64(c, d, d.psi, d.hpsi, d.vloc + (long)t * d.ng, d.N));
+      RET(project(c, d, d.psi, d.hpsi, nullptr, Hout + t * NN));
+    }
+    return RT_OK;
+  }
+  // local update: H[P] = H_gs + h^3 Psi diag(V_loc - V_loc,gs) Psi^T (FP64)
+  CK(rtk::sub_d(s, d.dv, d.vloc, d.vloc_gs, d.ng, T, act));
+  const long sp = (long)d.n_split * NN;
+  {
+    Timed tm(c, PH_PROJECT);
+    CK(rtk::gemm_nt_f64(s, d.N, d.N, d.ng, d.psi, d.ng, d.psi, d.ng, d.dv, d.part, d.kps, d.n_split, 1, d.big,
+                        rtk::Batch{T, act, 0, 0, d.ng, sp}));
+  }
+  Timed tr(c, PH_REDUCE);
+  CK(rtk::reduce_parts(s, d.part, d.n_split, d.N, d.N, d.h3, Hout, 1, d.Hgs, T, sp, 0, NN, act));
   return RT_OK;
 }
 
-// P (stacked [S; A]) -> U P U^dagger, U = exp(-i dt Hbar), by the commutator series.
-rt_status series(rt_ctx* c, TrajDev& t, SysDev& d, const double* Hbar, double dt, const double* Pin,
-                 double* Pout, int* terms) {
+// P_t -> U_t P_t U_t^dagger, U_t = exp(-i dt Hbar_t), by the commutator series, for the
+// T slots starting at the given buffers (stacked [S; A], stride 2 N^2).  flags/scratch
+// (kmin, slots, done, dP, dPn, C) are the system's, offset by `first`.
+rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const std::vector<int>& act_host,
+                 const double* Hbar, double dt, const double* Pin, double* Pout, std::vector<int>& terms) {
   hipStream_t s = c->stream;
-  const long n2 = 2 * nsq(d.N);
+  const long NN = nsq(d.N), n2 = 2 * NN;
   const int max_terms = c->run.max_terms;
+  const int stride = max_terms + 2;
   const double thrs = c->run.dp_thrs;
-  CK(rtk::copy_d(s, Pout, Pin, n2));
-  CK(rtk::copy_d(s, t.dP, Pin, n2));
-  CK(rtk::gershgorin(s, Hbar, d.N, dt, t.kmin));
-  CK(rtk::fill_u64(s, t.slots, max_terms + 2, 0ULL));
-  int zero2[2] = {0, 0};
-  CK(hipMemcpyAsync(t.done, zero2, sizeof(zero2), hipMemcpyHostToDevice, s));
-  double* dP = t.dP;
-  double* dPn = t.dPn;
+  double* dP = d.dP + first * n2;
+  double* dPn = d.dPn + first * n2;
+  double* C = d.C + first * n2;
+  double* kmin = d.kmin + first;
+  unsigned long long* slots = d.slots + (long)first * stride;
+  int* done = d.done + 2 * first;
+  CK(rtk::copy_masked(s, Pout, Pin, n2, T, act));
+  CK(rtk::copy_masked(s, dP, Pin, n2, T, act));
+  CK(rtk::gershgorin(s, Hbar, d.N, dt, kmin, T, act));
+  CK(rtk::fill_u64(s, slots, (long)T * stride, 0ULL));
+  CK(hipMemcpyAsync(done, d.zeros2T.data(), 2 * T * sizeof(int), hipMemcpyHostToDevice, s));
   int k = 1;
   const int CH = 8;
+  std::vector<int> hd(2 * T);
   while (true) {
     int kend = std::min(max_terms, k + CH - 1);
     for (; k <= kend; ++k) {
       {
         Timed tm(c, PH_SERIES_GEMM);
-        CK(rtk::gemm_nt_f64_series(s, d.N, Hbar, dP, t.C, k, t.slots, t.kmin, thrs, t.done));
+        CK(rtk::gemm_nt_f64_series(s, d.N, T, Hbar, dP, C, k, slots, stride, kmin, thrs, done, act));
       }
       {
         Timed tm(c, PH_SERIES_UPDATE);
-        CK(rtk::series_update(s, t.C, dPn, Pout, d.N, dt, k, t.slots, t.kmin, thrs, t.done));
+        CK(rtk::series_update(s, C, dPn, Pout, d.N, dt, k, slots, stride, kmin, thrs, done, T, act));
       }
       std::swap(dP, dPn);
     }
-    CK(rtk::series_finish(s, kend, t.slots, t.kmin, thrs, t.done));
-    int hd[2];
-    CK(hipMemcpyAsync(hd, t.done, sizeof(hd), hipMemcpyDeviceToHost, s));
+    CK(rtk::series_finish(s, kend, slots, stride, kmin, thrs, done, T, act));
+    CK(hipMemcpyAsync(hd.data(), done, 2 * T * sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
-    if (hd[0]) {
-      if (terms) *terms = hd[1];
+    bool all = true;
+    for (int t = 0; t < T; ++t)
+      if (act_host[t] && !hd[2 * t]) all = false;
+    if (all) {
+      terms.assign(T, 0);
+      for (int t = 0; t < T; ++t) terms[t] = act_host[t] ? hd[2 * t + 1] : 0;
       return RT_OK;
     }
     if (kend >= max_terms) return fail(c, RT_ENOCONV, "commutator series reached max_terms");
   }
 }
 
-rt_status observe(rt_ctx* c, TrajDev& t, SysDev& d, int row) {
+rt_status observe(rt_ctx* c, SysDev& d, int row) {
   const double* Hc = c->run.frozen_hxc ? d.Hgs : d.hcore;
   const double* ep = c->run.frozen_hxc ? d.ezero : d.eparts;
-  CK(rtk::observables(c->stream, t.P0, d.M3, Hc, d.N, ep, t.hist + 5L * row));
+  const int es = c->run.frozen_hxc ? 0 : 2;
+  CK(rtk::observables(c->stream, d.P0, d.M3, Hc, d.N, ep, es, d.hist + 5L * row, 5L * (c->hist_cap + 1), d.T));
   return RT_OK;
 }
 
 rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   hipStream_t st = c->stream;
-  const long N = d.N, ng = d.ng;
+  const long N = d.N, ng = d.ng, NN = N * N;
   CK(hipMemcpyAsync(d.psi, s.psi0, N * ng * sizeof(double),
                     s.psi0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
   std::vector<double> occ(N);
@@ -541,113 +643,131 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
     CK(hipMemcpyAsync(d.depth, s.depth, d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(d.width, s.width, d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  rt_status r;
-  if ((r = upload(c, d.atom_off, d.nl.atom_off)) != RT_OK) return r;
-  if ((r = upload(c, d.sph_idx, d.nl.sph_idx)) != RT_OK) return r;
-  if ((r = upload(c, d.beta, d.nl.beta)) != RT_OK) return r;
-  if ((r = upload(c, d.Dd, d.nl.D)) != RT_OK) return r;
-  if ((r = upload(c, d.u_idx, d.nl.u_idx)) != RT_OK) return r;
-  if ((r = upload(c, d.u_ptr, d.nl.u_ptr)) != RT_OK) return r;
-  if ((r = upload(c, d.ent_pt, d.nl.ent_pt)) != RT_OK) return r;
-  if ((r = upload(c, d.ent_atom, d.nl.ent_atom)) != RT_OK) return r;
+  RET(upload(c, d.atom_off, d.nl.atom_off));
+  RET(upload(c, d.sph_idx, d.nl.sph_idx));
+  RET(upload(c, d.beta, d.nl.beta));
+  RET(upload(c, d.Dd, d.nl.D));
+  RET(upload(c, d.u_idx, d.nl.u_idx));
+  RET(upload(c, d.u_ptr, d.nl.u_ptr));
+  RET(upload(c, d.ent_pt, d.nl.ent_pt));
+  RET(upload(c, d.ent_atom, d.nl.ent_atom));
   CK(rtk::twiddles(st, d.twx, d.nx));
   CK(rtk::twiddles(st, d.twy, d.ny));
   CK(rtk::twiddles(st, d.twz, d.nz));
   if (s.orthonormalize) {
     // S = h^3 Psi Psi^T = L L^T;  Psi <- L^-1 Psi
-    if ((r = project(c, d, d.psi, d.psi, nullptr, d.tmp)) != RT_OK) return r;
+    RET(project(c, d, d.psi, d.psi, nullptr, d.tmp));
     CK(rtk::cholesky(st, d.tmp, d.N, d.info));
     int info = 0;
     CK(hipMemcpyAsync(&info, d.info, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     if (info) return fail(c, RT_EINVAL, "orbital overlap matrix is not positive definite");
-    CK(rtk::tri_inverse_lower(st, d.tmp, d.W, d.N));
-    CK(rtk::smalltall_f64(st, d.N, d.ng, d.W, d.psi, d.hpsi, 0, 2));
+    CK(rtk::tri_inverse_lower(st, d.tmp, d.tmp2, d.N));
+    CK(rtk::smalltall_f64(st, d.N, d.ng, d.tmp2, d.psi, d.hpsi, 0, 2, 1, nullptr));
     std::swap(d.psi, d.hpsi);
   }
   CK(rtk::vion(st, d.vion, d.nx, d.ny, d.nz, d.h, d.n_atoms, d.pos, d.depth, d.width, d.n_images));
   for (int q = 0; q < 3; ++q) {
     CK(rtk::coord(st, d.dv, d.nx, d.ny, d.nz, d.h, q));
-    if ((r = project(c, d, d.psi, d.psi, d.dv, d.M3 + q * N * N)) != RT_OK) return r;
+    RET(project(c, d, d.psi, d.psi, d.dv, d.M3 + q * NN));
   }
-  if ((r = apply_h64(c, d, d.psi, d.hpsi, d.vion, d.N)) != RT_OK) return r;
-  if ((r = project(c, d, d.psi, d.hpsi, nullptr, d.hcore)) != RT_OK) return r;
-  // ground-state Hamiltonian H_gs = H[diag(f)] with the full apply; V_loc of that density kept
-  std::vector<double> pgs(N * N, 0.0);
+  RET(apply_h64(c, d, d.psi, d.hpsi, d.vion, d.N));
+  RET(project(c, d, d.psi, d.hpsi, nullptr, d.hcore));
+  // ground-state Hamiltonian H_gs = H[diag(f)] with the full FP64 apply (slot 0 fields)
+  std::vector<double> pgs(NN, 0.0);
   for (long i = 0; i < N; ++i) pgs[i * N + i] = occ[i];
-  CK(hipMemcpyAsync(d.tmp, pgs.data(), N * N * sizeof(double), hipMemcpyHostToDevice, st));
-  if ((r = eval_h(c, d, d.tmp, d.Hgs, 1)) != RT_OK) return r;
+  CK(hipMemcpyAsync(d.tmp, pgs.data(), NN * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<int> one(1, 1);
+  RET(eval_h(c, d, 1, nullptr, one, d.tmp, NN, d.Hgs, true));
   CK(rtk::copy_d(st, d.vloc_gs, d.vloc, d.ng));
-  CK(hipStreamSynchronize(st));
-  return RT_OK;
-}
-
-rt_status init_traj(rt_ctx* c, TrajDev& t) {
-  SysDev& d = c->sys[t.sys];
-  hipStream_t st = c->stream;
-  const long N = d.N;
-  std::vector<double> p0(2 * N * N, 0.0);
-  std::vector<double> occ(N);
-  CK(hipMemcpyAsync(occ.data(), d.occ, N * sizeof(double), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  for (long i = 0; i < N; ++i) p0[i * N + i] = occ[i];
-  CK(hipMemcpyAsync(t.P1, p0.data(), 2 * N * N * sizeof(double), hipMemcpyHostToDevice, st));
-  rt_status r;
-  if (t.kappa != 0.0) {
-    // delta kick: exp(-i kappa M_q) P_0 exp(+i kappa M_q), same series with Hbar = M_q, dt = kappa
-    int terms = 0;
-    if ((r = series(c, t, d, d.M3 + t.axis * N * N, t.kappa, t.P1, t.P0, &terms)) != RT_OK) return r;
-  } else {
-    CK(rtk::copy_d(st, t.P0, t.P1, 2 * N * N));
+  if (d.mixed) {
+    CK(rtk::copy_d(st, d.rho_gs, d.rho, d.ng));
+    CK(rtk::copy_d(st, d.S_gs, d.tmp, NN));
+    CK(rtk::split_bf16(st, d.psi, d.psi_hi, d.psi_lo, N * ng));
   }
-  if ((r = eval_h(c, d, t.P0, t.H0, 0)) != RT_OK) return r;
-  CK(rtk::copy_d(st, t.Hm1, t.H0, N * N));
-  t.step = 0;
-  if ((r = observe(c, t, d, 0)) != RT_OK) return r;
-  CK(hipStreamSynchronize(st));  // p0 (host) must outlive its copy
+  // trajectories: P_0 = diag(f), then each slot's kick through the series
+  std::vector<double> p0((long)d.T * 2 * NN, 0.0);
+  for (int t = 0; t < d.T; ++t)
+    for (long i = 0; i < N; ++i) p0[(long)t * 2 * NN + i * N + i] = occ[i];
+  CK(hipMemcpyAsync(d.P1, p0.data(), p0.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  CK(rtk::copy_d(st, d.P0, d.P1, (long)d.T * 2 * NN));
+  for (int t = 0; t < d.T; ++t) {
+    int g = d.slot_traj[t];
+    if (g < 0) continue;
+    const TrajDev& tr = c->traj[g];
+    if (tr.kappa == 0.0) continue;
+    // delta kick: exp(-i kappa M_q) P_0 exp(+i kappa M_q), same series with Hbar = M_q, dt = kappa
+    CK(rtk::copy_d(st, d.Hbar + t * NN, d.M3 + tr.axis * NN, NN));
+    std::vector<int> terms, on(1, 1);
+    RET(series(c, d, t, 1, nullptr, on, d.Hbar + t * NN, tr.kappa, d.P1 + t * 2 * NN, d.P0 + t * 2 * NN, terms));
+  }
+  std::vector<int> all(d.T, 1);
+  RET(eval_h(c, d, d.T, nullptr, all, d.P0, 2 * NN, d.H0, false));
+  CK(rtk::copy_d(st, d.Hm1, d.H0, (long)d.T * NN));
+  d.step = 0;
+  RET(observe(c, d, 0));
+  CK(hipStreamSynchronize(st));  // host vectors above must outlive their copies
   return RT_OK;
 }
 
-rt_status step_traj(rt_ctx* c, TrajDev& t, rt_step_stats* stat) {
-  SysDev& d = c->sys[t.sys];
+// One lockstep time step of every trajectory of a system (Algorithm 1 time loop body).
+rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_total) {
   hipStream_t st = c->stream;
   const rt_run& run = c->run;
   const long NN = nsq(d.N);
-  CK(rtk::lincomb(st, t.H1, 2.0, t.H0, -1.0, t.Hm1, NN));
-  int terms_total = 0;
-  double res = 0.0;
-  int m = 0;
-  bool conv = false;
-  rt_status r;
-  for (m = 1; m <= run.max_scf; ++m) {
-    CK(rtk::lincomb(st, t.Hbar, 0.5, t.H0, 0.5, t.H1, NN));
-    int terms = 0;
-    if ((r = series(c, t, d, t.Hbar, run.dt, t.P0, t.P1, &terms)) != RT_OK) return r;
-    terms_total += terms;
-    if ((r = eval_h(c, d, t.P1, t.Hn, 0)) != RT_OK) return r;
-    CK(rtk::fill_u64(st, t.resid, 1, 0ULL));
-    CK(rtk::max_abs_diff(st, t.Hn, t.H1, NN, t.resid));
-    unsigned long long bits = 0;
-    CK(hipMemcpyAsync(&bits, t.resid, sizeof(bits), hipMemcpyDeviceToHost, st));
+  const int T = d.T;
+  CK(rtk::lincomb(st, d.H1, 2.0, d.H0, -1.0, d.Hm1, T * NN));
+  d.active_host.assign(T, 1);
+  RET(push_active(c, d));
+  std::vector<int> m_of(T, 0), terms_of(T, 0);
+  std::vector<double> res_of(T, 0.0);
+  std::vector<unsigned long long> bits(T);
+  int n_active = T;
+  for (int m = 1; m <= run.max_scf && n_active > 0; ++m) {
+    CK(rtk::lincomb(st, d.Hbar, 0.5, d.H0, 0.5, d.H1, T * NN));
+    std::vector<int> terms;
+    RET(series(c, d, 0, T, d.active, d.active_host, d.Hbar, run.dt, d.P0, d.P1, terms));
+    RET(eval_h(c, d, T, d.active, d.active_host, d.P1, 2 * NN, d.Hn, false));
+    CK(rtk::fill_u64(st, d.resid, T, 0ULL));
+    CK(rtk::max_abs_diff(st, d.Hn, d.H1, NN, d.resid, T, d.active));
+    CK(rtk::copy_masked(st, d.H1, d.Hn, NN, T, d.active));
+    CK(hipMemcpyAsync(bits.data(), d.resid, T * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    std::memcpy(&res, &bits, sizeof(res));
-    std::swap(t.H1, t.Hn);
-    if (res <= run.h_thrs) { conv = true; break; }
+    bool changed = false;
+    for (int t = 0; t < T; ++t) {
+      if (!d.active_host[t]) continue;
+      double r;
+      std::memcpy(&r, &bits[t], sizeof(r));
+      m_of[t] = m;
+      terms_of[t] += terms[t];
+      res_of[t] = r;
+      if (r <= run.h_thrs) {
+        d.active_host[t] = 0;
+        --n_active;
+        changed = true;
+      }
+    }
+    if (changed && n_active > 0) RET(push_active(c, d));
   }
-  if (!conv) return fail(c, RT_ENOCONV, "self-consistent Hamiltonian loop reached max_scf");
-  // H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1
-  double* old_m1 = t.Hm1;
-  t.Hm1 = t.H0;
-  t.H0 = t.H1;
-  t.H1 = old_m1;
-  std::swap(t.P0, t.P1);
-  t.step += 1;
-  if (stat) {
-    stat->scf_iters = m;
-    stat->series_terms = terms_total;
-    stat->residual = res;
+  if (n_active > 0) return fail(c, RT_ENOCONV, "self-consistent Hamiltonian loop reached max_scf");
+  // H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 (all slots together)
+  double* old_m1 = d.Hm1;
+  d.Hm1 = d.H0;
+  d.H0 = d.H1;
+  d.H1 = old_m1;
+  std::swap(d.P0, d.P1);
+  d.step += 1;
+  if (stats) {
+    for (int t = 0; t < T; ++t) {
+      int g = d.slot_traj[t];
+      if (g < 0) continue;
+      stats[g].scf_iters = m_of[t];
+      stats[g].series_terms = terms_of[t];
+      stats[g].residual = res_of[t];
+    }
   }
-  return observe(c, t, d, t.step);
+  (void)n_traj_total;
+  return observe(c, d, d.step);
 }
 
 }  // namespace
@@ -666,7 +786,7 @@ rt_status rt_workspace_size(const rt_system* sys, int n_sys, const rt_run* run, 
   std::vector<TrajDev> T;
   describe(sys, n_sys, run, S, T);
   Arena a;
-  layout(a, S, T, *run, run->n_steps_max);
+  layout(a, S, *run, run->n_steps_max);
   *bytes = a.used + 256;
   return RT_OK;
 }
@@ -688,7 +808,7 @@ rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* work
   c->hist_cap = run->n_steps_max;
   describe(sys, n_sys, run, c->sys, c->traj);
   Arena a;
-  layout(a, c->sys, c->traj, *run, c->hist_cap);
+  layout(a, c->sys, *run, c->hist_cap);
   size_t need = a.used + 256;
   if (ws_bytes < need) {
     g_init_error = "workspace too small: need " + std::to_string(need) + " bytes";
@@ -697,13 +817,9 @@ rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* work
   }
   Arena b;
   b.base = reinterpret_cast<char*>(((uintptr_t)workspace_dev + 255) & ~uintptr_t(255));
-  layout(b, c->sys, c->traj, *run, c->hist_cap);
+  layout(b, c->sys, *run, c->hist_cap);
   for (int i = 0; i < n_sys; ++i) {
     st = init_system(c, c->sys[i], sys[i]);
-    if (st != RT_OK) { g_init_error = c->err; delete c; return st; }
-  }
-  for (auto& t : c->traj) {
-    st = init_traj(c, t);
     if (st != RT_OK) { g_init_error = c->err; delete c; return st; }
   }
   hipError_t e = hipStreamSynchronize(c->stream);
@@ -721,20 +837,17 @@ rt_status rt_apply_h(rt_ctx* c, int si, const void* psi_dev, void* hpsi_dev, int
   if (si < 0 || si >= (int)c->sys.size()) return fail(c, RT_EINVAL, "sys_index out of range");
   if (!psi_dev || !hpsi_dev || n_orb < 0 || (dtype != 0 && dtype != 1))
     return fail(c, RT_EINVAL, "rt_apply_h arguments");
-  if (psi_dev == hpsi_dev) return fail(c, RT_EINVAL, "psi and hpsi must not overlap");
   SysDev& d = c->sys[si];
   size_t esz = dtype == 0 ? 8 : 4;
   uintptr_t p0 = (uintptr_t)psi_dev, p1 = (uintptr_t)hpsi_dev, len = (uintptr_t)n_orb * d.ng * esz;
-  if (p0 < p1 + len && p1 < p0 + len) return fail(c, RT_EINVAL, "psi and hpsi must not overlap");
+  if (n_orb > 0 && p0 < p1 + len && p1 < p0 + len) return fail(c, RT_EINVAL, "psi and hpsi must not overlap");
   if (dtype == 1) CK(rtk::cast_d2f(c->stream, d.vloc32, d.vloc, d.ng));
   for (int o = 0; o < n_orb; o += d.N) {
     int n = std::min(d.N, n_orb - o);
-    rt_status r;
     if (dtype == 0)
-      r = apply_h64(c, d, (const double*)psi_dev + (long)o * d.ng, (double*)hpsi_dev + (long)o * d.ng, d.vloc, n);
+      RET(apply_h64(c, d, (const double*)psi_dev + (long)o * d.ng, (double*)hpsi_dev + (long)o * d.ng, d.vloc, n));
     else
-      r = apply_h32(c, d, (const float*)psi_dev + (long)o * d.ng, (float*)hpsi_dev + (long)o * d.ng, n);
-    if (r != RT_OK) return r;
+      RET(apply_h32(c, d, (const float*)psi_dev + (long)o * d.ng, (float*)hpsi_dev + (long)o * d.ng, n));
   }
   return RT_OK;
 }
@@ -742,13 +855,13 @@ rt_status rt_apply_h(rt_ctx* c, int si, const void* psi_dev, void* hpsi_dev, int
 rt_status rt_step(rt_ctx* c, int n_steps, rt_step_stats* stats) {
   if (!c) return RT_EINVAL;
   if (n_steps < 0) return fail(c, RT_EINVAL, "n_steps < 0");
-  for (auto& t : c->traj)
-    if (t.step + n_steps > c->hist_cap) return fail(c, RT_ESTATE, "history capacity n_steps_max exhausted");
+  for (auto& d : c->sys)
+    if (d.step + n_steps > c->hist_cap) return fail(c, RT_ESTATE, "history capacity n_steps_max exhausted");
   const int nt = (int)c->traj.size();
   for (int k = 0; k < n_steps; ++k) {
-    for (int i = 0; i < nt; ++i) {
-      rt_status r = step_traj(c, c->traj[i], stats ? stats + (long)k * nt + i : nullptr);
-      if (r != RT_OK) return r;
+    for (auto& d : c->sys) {
+      if (d.slot_traj[0] < 0) continue;  // system without trajectories
+      RET(step_system(c, d, stats ? stats + (long)k * nt : nullptr, nt));
     }
   }
   if (c->prof) {
@@ -785,13 +898,12 @@ rt_status rt_dipole(rt_ctx* c, int traj, int first_step, int count, double* mu_h
   if (!c) return RT_EINVAL;
   if (traj < 0 || traj >= (int)c->traj.size()) return fail(c, RT_EINVAL, "traj out of range");
   TrajDev& t = c->traj[traj];
-  if (first_step < 0 || count < 0 || first_step + count > t.step + 1 || !mu_host)
+  SysDev& d = c->sys[t.sys];
+  if (first_step < 0 || count < 0 || first_step + count > d.step + 1 || !mu_host)
     return fail(c, RT_EINVAL, "requested steps outside the recorded history");
   std::vector<double> buf(5L * count);
-  if (count) {
-    CK(hipMemcpyAsync(buf.data(), t.hist + 5L * first_step, buf.size() * sizeof(double),
-                      hipMemcpyDeviceToHost, c->stream));
-  }
+  const double* src = d.hist + (long)t.slot * 5L * (c->hist_cap + 1) + 5L * first_step;
+  if (count) CK(hipMemcpyAsync(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   CK(hipStreamSynchronize(c->stream));
   for (int i = 0; i < count; ++i) {
     for (int q = 0; q < 3; ++q) mu_host[3 * i + q] = buf[5 * i + q];
@@ -809,10 +921,10 @@ rt_status rt_get_matrix(rt_ctx* c, int traj, int which, double* out) {
   const long NN = nsq(d.N);
   const double* src = nullptr;
   switch (which) {
-    case 0: src = t.H0; break;
-    case 1: src = t.Hm1; break;
-    case 2: src = t.P0; break;
-    case 3: src = t.P0 + NN; break;
+    case 0: src = d.H0 + t.slot * NN; break;
+    case 1: src = d.Hm1 + t.slot * NN; break;
+    case 2: src = d.P0 + t.slot * 2 * NN; break;
+    case 3: src = d.P0 + t.slot * 2 * NN + NN; break;
     case 4: src = d.hcore; break;
     case 5: case 6: case 7: src = d.M3 + (which - 5) * NN; break;
     case 8: src = d.Hgs; break;
@@ -831,10 +943,10 @@ rt_status rt_set_state(rt_ctx* c, int traj, const double* p_re, const double* p_
   SysDev& d = c->sys[t.sys];
   const long NN = nsq(d.N);
   hipStream_t s = c->stream;
-  if (p_re) CK(hipMemcpyAsync(t.P0, p_re, NN * 8, hipMemcpyHostToDevice, s));
-  if (p_im) CK(hipMemcpyAsync(t.P0 + NN, p_im, NN * 8, hipMemcpyHostToDevice, s));
-  if (h0) CK(hipMemcpyAsync(t.H0, h0, NN * 8, hipMemcpyHostToDevice, s));
-  if (hm1) CK(hipMemcpyAsync(t.Hm1, hm1, NN * 8, hipMemcpyHostToDevice, s));
+  if (p_re) CK(hipMemcpyAsync(d.P0 + t.slot * 2 * NN, p_re, NN * 8, hipMemcpyHostToDevice, s));
+  if (p_im) CK(hipMemcpyAsync(d.P0 + t.slot * 2 * NN + NN, p_im, NN * 8, hipMemcpyHostToDevice, s));
+  if (h0) CK(hipMemcpyAsync(d.H0 + t.slot * NN, h0, NN * 8, hipMemcpyHostToDevice, s));
+  if (hm1) CK(hipMemcpyAsync(d.Hm1 + t.slot * NN, hm1, NN * 8, hipMemcpyHostToDevice, s));
   CK(hipStreamSynchronize(s));
   return RT_OK;
 }
@@ -842,7 +954,8 @@ rt_status rt_set_state(rt_ctx* c, int traj, const double* p_re, const double* p_
 rt_status rt_eval_h(rt_ctx* c, int si, const double* p_re_dev, double* h_out_dev) {
   if (!c) return RT_EINVAL;
   if (si < 0 || si >= (int)c->sys.size() || !p_re_dev || !h_out_dev) return fail(c, RT_EINVAL, "rt_eval_h arguments");
-  return eval_h(c, c->sys[si], p_re_dev, h_out_dev, 0);
+  std::vector<int> one(1, 1);
+  return eval_h(c, c->sys[si], 1, nullptr, one, p_re_dev, 0, h_out_dev, false);
 }
 
 rt_status rt_propagate(rt_ctx* c, int si, const double* hbar_dev, double dt, double* p_re_dev, double* p_im_dev,
@@ -850,23 +963,20 @@ rt_status rt_propagate(rt_ctx* c, int si, const double* hbar_dev, double dt, dou
   if (!c) return RT_EINVAL;
   if (si < 0 || si >= (int)c->sys.size() || !hbar_dev || !p_re_dev || !p_im_dev)
     return fail(c, RT_EINVAL, "rt_propagate arguments");
-  int ti = -1;
-  for (int i = 0; i < (int)c->traj.size(); ++i)
-    if (c->traj[i].sys == si) { ti = i; break; }
-  if (ti < 0) return fail(c, RT_ESTATE, "rt_propagate needs a trajectory of this system for its work buffers");
-  TrajDev& t = c->traj[ti];
   SysDev& d = c->sys[si];
   const long NN = nsq(d.N);
   hipStream_t s = c->stream;
-  // work in the trajectory's P1/dP buffers, leaving its state P0 untouched
-  double* in = t.C;
+  // slot 0's work buffers: input in Hn/Hbar-free scratch (C), output in P1; the state P0 is untouched
+  double* in = d.C;
+  double* outp = d.P1;
   CK(hipMemcpyAsync(in, p_re_dev, NN * 8, hipMemcpyDeviceToDevice, s));
   CK(hipMemcpyAsync(in + NN, p_im_dev, NN * 8, hipMemcpyDeviceToDevice, s));
-  double* saved_P1 = t.P1;
-  rt_status r = series(c, t, d, hbar_dev, dt, in, saved_P1, terms_out);
-  if (r != RT_OK) return r;
-  CK(hipMemcpyAsync(p_re_dev, saved_P1, NN * 8, hipMemcpyDeviceToDevice, s));
-  CK(hipMemcpyAsync(p_im_dev, saved_P1 + NN, NN * 8, hipMemcpyDeviceToDevice, s));
+  std::vector<int> terms, one(1, 1);
+  RET(series(c, d, 0, 1, nullptr, one, hbar_dev, dt, in, outp, terms));
+  CK(hipMemcpyAsync(p_re_dev, outp, NN * 8, hipMemcpyDeviceToDevice, s));
+  CK(hipMemcpyAsync(p_im_dev, outp + NN, NN * 8, hipMemcpyDeviceToDevice, s));
+  CK(hipStreamSynchronize(s));
+  if (terms_out) *terms_out = terms.empty() ? 0 : terms[0];
   return RT_OK;
 }
 

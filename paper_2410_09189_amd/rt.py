@@ -59,6 +59,11 @@ class RTError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2410_09189_amd/build.py")
+    # One HIP runtime per process: PyTorch brings its own libamdhip64, and the
+    # library must bind to that one (same soname) rather than load a second
+    # runtime, which could not open the device.  So torch is loaded first.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     sig = {

@@ -202,3 +202,90 @@ def test_c1_three_kicks_and_bitwise_determinism():
     ref = c1_oracle_run(n_steps=20, axis=1)
     assert np.max(np.abs(a[1][0] - ref["mu"])) < 1e-10
     assert sa == sb
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision (BF16x3 perturbation contractions, FP64 references)
+# ---------------------------------------------------------------------------
+# Error model: hi/lo bf16 splitting keeps ~16 significant bits per factor and
+# the dropped lo*lo term is ~2^-16 relative, so each contraction of a
+# perturbation X carries a relative error of order 2^-15 ~ 3e-5 of the summed
+# magnitudes; FP32 accumulation over <= 4096-term chunks adds < 1e-6.  The
+# static ground-state parts are exact FP64, so the bound applies to the change
+# of H from the ground state only.
+MIXED_REL = 1e-4
+
+
+def test_mixed_eval_h_error_is_relative_to_the_perturbation():
+    _say("mixed eval_h 36x40x32 N=20")
+    torch = _torch()
+    from paper_2410_09189_amd import rt
+
+    s, psi = _ragged_system(seed=12)
+    rp = synth.RunParams(dt=0.05, n_steps=2)
+    ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp, precision=rt.RT_MIXED, hupdate=1))
+    m = oracle.Model(s, orthonormalize_np(s, psi))
+    N = m.N
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((N, N))
+    S = np.diag(s.occupations()) + 0.01 * (A + A.T)
+    Sd = torch.from_numpy(S).cuda()
+    Hd = torch.empty_like(Sd)
+    rt.rt_eval_h(ses.ctx, 0, Sd.data_ptr(), Hd.data_ptr())
+    torch.cuda.synchronize()
+    ref, aux = m.h_of_p(S.astype(complex))
+    Hgs, aux0 = m.h_of_p(np.diag(s.occupations()).astype(complex))
+    got = Hd.cpu().numpy()
+    dH = np.max(np.abs(ref - Hgs))
+    err = np.max(np.abs(got - ref))
+    print(f"mixed eval_h: max|dH| {dH:.3e}  max err {err:.3e}", flush=True)
+    assert err < MIXED_REL * dH + 1e-12 * np.max(np.abs(ref))
+    rho = rt.rt_get_grid(ses.ctx, 0, 0, s.ng)
+    drho = np.max(np.abs(aux["rho"] - aux0["rho"]))
+    assert np.max(np.abs(rho - aux["rho"])) < MIXED_REL * drho + 1e-14
+    ses.close()
+
+
+def test_mixed_c1_trajectory_relative_dipole_error():
+    _say("C1 mixed 200 steps")
+    from paper_2410_09189_amd import rt
+
+    ref = c1_oracle_run()
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    rp = synth.config_run("c1_parity_32", n_steps=200)
+    ses = _session([system_args(s, psi)], run_args(rp, precision=rt.RT_MIXED, hupdate=1))
+    rt.rt_step(ses.ctx, 200, n_traj=1)
+    mu, E, tr = rt.rt_dipole(ses.ctx, 0, 0, 201)
+    ses.close()
+    dmu_ref = ref["mu"][:, 0] - ref["mu"][0, 0]
+    dmu = mu[:, 0] - mu[0, 0]
+    e_mu = np.max(np.abs(dmu - dmu_ref)) / np.max(np.abs(dmu_ref))
+    e_E = np.max(np.abs((E - E[0]) - (ref["E"] - ref["E"][0])))
+    print(f"mixed C1: e_mu {e_mu:.3e}, energy-change err {e_E:.3e}", flush=True)
+    assert e_mu < 1e-5
+    assert np.max(np.abs(tr - 16.0)) < 1e-12
+    assert abs(mu[0, 0] - ref["mu"][0, 0]) < 1e-10
+
+
+@pytest.mark.parametrize("precision,hupdate", [(0, 0), (0, 1), (1, 1)])
+def test_batched_trajectories_equal_single_runs_bitwise(precision, hupdate):
+    _say(f"batched x,y,z kicks vs single runs precision={precision} hupdate={hupdate}")
+    from paper_2410_09189_amd import rt
+
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    rp = synth.config_run("c1_parity_32", n_steps=15)
+
+    def run(axes):
+        ses = _session([system_args(s, psi)], run_args(rp, n_traj_axes=axes, hupdate=hupdate, precision=precision))
+        st = rt.rt_step(ses.ctx, 15, n_traj=len(axes), stats=True)
+        out = [rt.rt_dipole(ses.ctx, t, 0, 16) for t in range(len(axes))]
+        ses.close()
+        return out, st
+
+    batch, st = run((0, 1, 2))
+    for q in range(3):
+        single, _ = run((q,))
+        assert np.array_equal(batch[q][0], single[0][0]), q
+        assert np.array_equal(batch[q][1], single[0][1]), q
