@@ -119,13 +119,15 @@ typedef struct {
   int max_scf;         /* cap on Hamiltonian updates per step (>= 1)             */
   int max_terms;       /* cap on series terms per propagation (>= 1)             */
   int precision;       /* RT_FP64 | RT_MIXED                                     */
-  int predictor;       /* RT_PRED_LINEAR | RT_PRED_MLP                           */
+  int predictor;       /* RT_PRED_LINEAR | RT_PRED_MLP (see Learned predictor)   */
   int hupdate;         /* RT_HUPDATE_FULL | RT_HUPDATE_LOCAL                     */
   int frozen_hxc;      /* test switch: V_H and v_x fixed at the ground state     */
   int n_traj;
   const int* traj_sys;       /* [n_traj] index into the system array             */
   const double* traj_kappa;  /* [n_traj] kick strength                           */
   const int* traj_axis;      /* [n_traj] 0 = x, 1 = y, 2 = z                     */
+  const float* mlp_params;   /* RT_PRED_MLP: packed network (host, rt_mlp_n_params of
+                                rt_mlp_dims floats, layout under "Learned predictor")   */
 } rt_run;
 
 /* Per-trajectory, per-step counters written by rt_step when stats != NULL. */
@@ -228,6 +230,53 @@ rt_status rt_get_grid(rt_ctx* ctx, int sys_index, int which, double* out_host);
  */
 rt_status rt_profile(rt_ctx* ctx, int enable, int reset);
 rt_status rt_profile_read(rt_ctx* ctx, int phase, double* total_ms, long* launches, const char** name);
+
+/*
+ * Learned predictor (the learned extension of Algorithm 1's first guess).
+ * With fixed orbitals H is affine in the Hartree-exchange potential V, so the
+ * linear extrapolation H_1 = 2 H_0 - H_-1 is the guess V = 2 V_j - V_(j-1) and
+ * its error is D_j = V_(j+1) - 2 V_j + V_(j-1).  RT_PRED_MLP adds
+ * h^3 Psi^T diag(P y) Psi to the linear guess, y = network(x_j) an estimate of
+ * R D_j on a coarse 16^3 grid (R: block average, P: periodic trilinear
+ * interpolation from cell centres).  x_j (8264 floats) = the 9 moments
+ * (h^3 sum drho q_a, h^3 sum drho q_a q_b) of the density change drho = rho - rho_gs
+ * at steps j-7..j (oldest first), then R drho_j, then R drho_(j-1).  The
+ * self-consistent loop then runs as usual, so the fixed point is unchanged;
+ * a trajectory falls back to the linear guess for good if its first residual
+ * exceeds 10x the median first residual of its linear-guess steps.  Needs
+ * grid edges divisible by 16; the first 8 steps use the linear guess.
+ *
+ * Network: tanh MLP n_in -> n_h -> n_h -> n_out on standardised data, FP32.
+ * Packed floats: x_mean[n_in] x_scale[n_in] y_mean[n_out] y_scale[n_out]
+ * W1[n_h][n_in] b1[n_h] W2[n_h][n_h] b2[n_h] W3[n_out][n_h] b3[n_out]
+ * (x_std = (x - x_mean) x_scale, y = y_mean + y_std / y_scale).  The
+ * trainable part starts at float offset 2 n_in + 2 n_out.
+ *
+ * rt_record: from the next step on, every step appends one training sample
+ * per trajectory, x_(j-1) into X_dev [capacity][8264] and the realised
+ * R D_(j-1) into Y_dev [capacity][4096] (device, caller-owned), until
+ * capacity rows are written; rt_record_count returns the rows written.
+ * The rt_mlp_* calls are context-free kernels on caller device buffers and
+ * the given stream: forward (work: rt_mlp_work_floats), mean-square loss of
+ * the standardised output (sum (y_std - t_std)^2 / (2 batch n_out)) with the
+ * gradients of the trainable part in its layout, one Adam step (Kingma & Ba,
+ * b1 0.9, b2 0.999, eps 1e-8, step t >= 1), and per-column mean and
+ * 1/max(std, floor) of a [rows][cols] matrix.
+ */
+void rt_mlp_dims(int* n_in, int* n_h, int* n_out);
+int64_t rt_mlp_n_params(int n_in, int n_h, int n_out);
+int64_t rt_mlp_work_floats(int n_in, int n_h, int n_out, int batch);
+rt_status rt_mlp_forward(void* hip_stream, int n_in, int n_h, int n_out, const float* params_dev,
+                         const float* x_dev, float* y_dev, int batch, float* work_dev);
+rt_status rt_mlp_loss_grad(void* hip_stream, int n_in, int n_h, int n_out, const float* params_dev,
+                           const float* x_dev, const float* target_dev, int batch, float* grads_dev,
+                           float* work_dev, float* loss_dev);
+rt_status rt_mlp_adam(void* hip_stream, float* train_params_dev, const float* grads_dev, float* m_dev,
+                      float* v_dev, int64_t n, int t, float lr);
+rt_status rt_mlp_colstats(void* hip_stream, const float* x_dev, int rows, int cols, float* mean_dev,
+                          float* scale_dev, float floor_std);
+rt_status rt_record(rt_ctx* ctx, float* x_dev, float* y_dev, int capacity);
+rt_status rt_record_count(rt_ctx* ctx, int* rows);
 
 /* Releases host-side state; the caller then frees the workspace. */
 void rt_free(rt_ctx* ctx);

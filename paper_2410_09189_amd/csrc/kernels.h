@@ -65,15 +65,19 @@ hipError_t pack_real(hipStream_t s, double2* z, const double* r, long n);
 hipError_t dft_axis(hipStream_t s, double2* z, int nx, int ny, int nz, int axis, const double2* tw,
                     int inverse);
 hipError_t poisson_scale(hipStream_t s, double2* z, int nx, int ny, int nz, double h);
+// V_H,t = IFFT[4 pi FFT[rho_t] / |G|^2] (G = 0 dropped) for T stacked fields; z: T x ng scratch
+hipError_t poisson_fft(hipStream_t s, const double* rho, double* vh, double2* z, int nx, int ny, int nz, double h,
+                       const double2* twx, const double2* twy, const double2* twz, int T);
 hipError_t real_part(hipStream_t s, double* r, const double2* z, long n);
 
 // ---- exchange, local potential, energies -------------------------------------------
 // vx = -(3 rho/pi)^(1/3), vloc = vion + vh + vx; part[b] = (sum e_x, sum rho vh) per block.
+// batched over T stacked fields (blockIdx.y), part2: [T][kRedBlocks][2]
 hipError_t lda_vloc(hipStream_t s, const double* rho, const double* vh, const double* vion,
-                    double* vx, double* vloc, long n, double* part2);
+                    double* vx, double* vloc, long n, double* part2, int T, const int* active);
 // out[0..ncol) = scale[c] * sum_b part[b][c]   (single block, fixed order)
 hipError_t reduce_cols(hipStream_t s, const double* part, int nblk, int ncol, const double* scale3,
-                       double* out);
+                       double* out, int T, const int* active);
 
 // ---- N x N kernels (batched over T trajectories with stacked buffers) ----------
 hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double b, const double* y,

@@ -11,7 +11,6 @@
 
 namespace rtk {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
@@ -371,15 +370,11 @@ template hipError_t nl_scatter<float>(hipStream_t, float*, long, int, int, const
                                       const double*, int);
 
 // ============================================================================
-// FP64 MFMA GEMM, C = A . B^T with both operands K-contiguous (tall-skinny
-// projections over the grid and the N x N series products)
+// FP64 GEMM, C = A . B^T with both operands K-contiguous (tall-skinny
+// projections over the grid and the N x N series products).  K is split across
+// blockIdx.y into fixed ranges whose partial tiles are summed afterwards in a
+// fixed order.
 // ============================================================================
-//
-// v_mfma_f64_16x16x4f64 fragment layout (64 lanes): A[m = lane%16][k = lane/16],
-// B^T[k = lane/16][n = lane%16]; the 16x16 result sits in 4 doubles per lane at
-// row 4*(lane/16) + r, column lane%16.  A block of 256 threads (2 x 2 waves)
-// computes a BM x BN tile; K is split across blockIdx.y into fixed ranges
-// whose partial tiles are summed afterwards in a fixed order.
 // Trajectory batching: T independent problems share one launch.  The
 // trajectory index is the fastest-varying part of blockIdx.x, so blocks of
 // different trajectories working on the same tile run together and share the
@@ -400,12 +395,18 @@ __device__ __forceinline__ bool series_stopped(const SeriesSkip& sk, int t) {
   return prev <= sk.thrs && (double)(sk.k - 1) >= sk.kmin[t];
 }
 
-template <int BM, int BN, int BK>
+// FP64 register-blocked GEMM on the vector units (MI355X: FP64 vector and
+// matrix peaks are equal).  Tile BM x BN = 128 x 128 (big) or 64 x 64, K chunk
+// 16, 256 threads each owning a TM x TN = BM/16 x BN/16 block of outputs.
+// Operands are staged k-major in LDS (As[k][m], Bs[k][n]) so each thread reads
+// contiguous runs of its rows/columns.
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const double* __restrict__ A,
                                                      long lda, const double* __restrict__ B, long ldb,
                                                      const double* __restrict__ w,
                                                      double* __restrict__ part, long kps, int upper,
                                                      int n_tn, Batch bt, SeriesSkip sk) {
+  constexpr int BK = 16, TM = BM / 16, TN = BN / 16;
   const int tb = blockIdx.x % bt.T;
   if (bt.active && !bt.active[tb]) return;
   if (sk.k > 0 && series_stopped(sk, tb)) return;
@@ -413,9 +414,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
   B += tb * bt.sb;
   if (w) w += tb * bt.sw;
   part += tb * bt.sp;
-  constexpr int PAD = 1;
-  __shared__ double As[BM][BK + PAD];
-  __shared__ double Bs[BN][BK + PAD];
+  __shared__ double As[BK][BM + 2];
+  __shared__ double Bs[BK][BN + 2];
   int tm, tn;
   {
     int t = blockIdx.x / bt.T;
@@ -431,58 +431,53 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
   }
   const long k0 = (long)blockIdx.y * kps;
   const long k1 = min(K, k0 + kps);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
-  dbl4 acc[FM][FN];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = (dbl4){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
   const long am0 = (long)tm * BM, bn0 = (long)tn * BN;
   for (long kb = k0; kb < k1; kb += BK) {
     for (int e = tid; e < BM * BK; e += 256) {
-      int r = e / BK, c = e - r * BK;
+      int r = e % BM, c = e / BM;
       long gm = am0 + r, gk = kb + c;
       double val = 0.0;
       if (gm < M && gk < k1) {
         val = A[gm * lda + gk];
         if (w) val *= w[gk];
       }
-      As[r][c] = val;
+      As[c][r] = val;
     }
     for (int e = tid; e < BN * BK; e += 256) {
-      int r = e / BK, c = e - r * BK;
+      int r = e % BN, c = e / BN;
       long gn = bn0 + r, gk = kb + c;
-      Bs[r][c] = (gn < N && gk < k1) ? B[gn * ldb + gk] : 0.0;
+      Bs[c][r] = (gn < N && gk < k1) ? B[gn * ldb + gk] : 0.0;
     }
     __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[TM], b[TN];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double af[FM], bf[FN];
+      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty * TM + i];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = As[wm * WM + i * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx * TN + j];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = Bs[wn * WN + j * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < TN; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
   double* P = part + (long)blockIdx.y * M * N;
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        long row = am0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
-        long col = bn0 + wn * WN + j * 16 + (lane & 15);
-        if (row < M && col < N) P[row * N + col] = acc[i][j][r];
-      }
+    for (int j = 0; j < TN; ++j) {
+      long row = am0 + ty * TM + i, col = bn0 + tx * TN + j;
+      if (row < M && col < N) P[row * N + col] = acc[i][j];
+    }
 }
 
 static hipError_t gemm_launch(hipStream_t s, int M, int N, long K, const double* A, long lda,
@@ -491,12 +486,12 @@ static hipError_t gemm_launch(hipStream_t s, int M, int N, long K, const double*
   if (big) {
     int ntm = cdiv(M, 128), ntn = cdiv(N, 128);
     int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
-    hipLaunchKernelGGL((k_gemm_nt_f64<128, 128, 16>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K,
+    hipLaunchKernelGGL((k_gemm_nt_f64<128, 128>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K,
                        A, lda, B, ldb, w, part, kps, upper, ntn, bt, sk);
   } else {
     int ntm = cdiv(M, 64), ntn = cdiv(N, 64);
     int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
-    hipLaunchKernelGGL((k_gemm_nt_f64<64, 64, 32>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K, A,
+    hipLaunchKernelGGL((k_gemm_nt_f64<64, 64>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K, A,
                        lda, B, ldb, w, part, kps, upper, ntn, bt, sk);
   }
   return hipGetLastError();
@@ -521,7 +516,7 @@ hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, c
 // C_t[m][n] = base_t[m][n] + alpha * sum_s part_t[s][m][n]; with mirror the upper
 // part is kept and copied to the lower one.  blockIdx.y = trajectory.
 __global__ void k_reduce_parts(const double* __restrict__ part, int n_split, int M, int N, double alpha,
-                               const double* __restrict__ base, double* __restrict__ C, int mirror,
+                               const double* base, double* C, int mirror,
                                long sp, long sbase, long sc, const int* active) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
@@ -562,86 +557,85 @@ __global__ __launch_bounds__(256) void k_smalltall_f64(int N, long ng, const dou
                                                        const double* __restrict__ psi,
                                                        double* __restrict__ out, int tri, int T,
                                                        const int* active) {
-  constexpr int BM = 64, BN = 64, BK = 32;
-  __shared__ double Ws[BM][BK + 1];
-  __shared__ double Ps[BK][BN + 1];
-  __shared__ double red[2][4][BN];
+  // Tile: 64 rows of W x 128 grid points; thread (ty, tx) owns rows ty*4..+3 and
+  // points tx*8..+7 (vector FP64 FMA), K chunk 16 over orbitals j.
+  constexpr int BM = 64, BN = 128, BK = 16;
+  __shared__ double Ws[BK][BM + 2];
+  __shared__ double Ps[BK][BN + 2];
+  __shared__ double red[16][BN];
   const int tb = blockIdx.x % T;
   if (active && !active[tb]) return;
   W += (long)tb * N * N;
   out += MODE == 0 ? (long)tb * N * ng : (long)tb * ng;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const long r0 = (long)(blockIdx.x / T) * BN;
-  double rho_part[2] = {0.0, 0.0};
+  double rho_part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int nI = cdiv(N, BM);
   for (int I = 0; I < nI; ++I) {
-    dbl4 acc[2][2];
+    double acc[4][8];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = (dbl4){0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
     int jlo = 0, jhi = N;
     if (tri == 1) jlo = I * BM;
     if (tri == 2) jhi = min(N, (I + 1) * BM);
     for (int jb = jlo; jb < jhi; jb += BK) {
       for (int e = tid; e < BM * BK; e += 256) {
-        int r = e / BK, c = e - r * BK;
+        int r = e % BM, c = e / BM;
         int gi = I * BM + r, gj = jb + c;
-        Ws[r][c] = (gi < N && gj < jhi) ? W[(long)gi * N + gj] : 0.0;
+        Ws[c][r] = (gi < N && gj < jhi) ? W[(long)gi * N + gj] : 0.0;
       }
       for (int e = tid; e < BK * BN; e += 256) {
-        int r = e / BN, c = e - r * BN;
-        int gj = jb + r;
-        long gr = r0 + c;
-        Ps[r][c] = (gj < jhi && gr < ng) ? psi[(long)gj * ng + gr] : 0.0;
+        int c = e / BN, r = e % BN;
+        int gj = jb + c;
+        long gr = r0 + r;
+        Ps[c][r] = (gj < jhi && gr < ng) ? psi[(long)gj * ng + gr] : 0.0;
       }
       __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < BK; ++kk) {
+        double a[4], b[8];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        double af[2], bf[2];
+        for (int i = 0; i < 4; ++i) a[i] = Ws[kk][ty * 4 + i];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = Ws[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+        for (int j = 0; j < 8; ++j) b[j] = Ps[kk][tx * 8 + j];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bf[j] = Ps[kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 8; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i) {
+      int row = I * BM + ty * 4 + i;
+      if (row >= N) continue;
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int row = I * BM + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-          long col = r0 + wn * 32 + j * 16 + (lane & 15);
-          if (row < N && col < ng) {
-            if (MODE == 0) out[(long)row * ng + col] = acc[i][j][r];
-            else rho_part[j] += psi[(long)row * ng + col] * acc[i][j][r];
-          }
+      for (int j = 0; j < 8; ++j) {
+        long col = r0 + tx * 8 + j;
+        if (col < ng) {
+          if (MODE == 0) out[(long)row * ng + col] = acc[i][j];
+          else rho_part[j] += psi[(long)row * ng + col] * acc[i][j];
         }
+      }
+    }
   }
   if (MODE == 1) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) red[wm][lane >> 4][wn * 32 + j * 16 + (lane & 15)] = rho_part[j];
+    for (int j = 0; j < 8; ++j) red[ty][tx * 8 + j] = rho_part[j];
     __syncthreads();
     if (tid < BN) {
-      double acc = 0.0;
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 4; ++b) acc += red[a][b][tid];
-      if (r0 + tid < ng) out[r0 + tid] = acc;
+      double a = 0.0;
+      for (int q = 0; q < 16; ++q) a += red[q][tid];
+      if (r0 + tid < ng) out[r0 + tid] = a;
     }
   }
 }
 
 hipError_t smalltall_f64(hipStream_t s, int N, long ng, const double* W, const double* psi,
                          double* out, int mode, int tri, int T, const int* active) {
-  dim3 grid(cdiv(ng, 64) * T);
+  dim3 grid(cdiv(ng, 128) * T);
   if (mode == 0)
     hipLaunchKernelGGL((k_smalltall_f64<0>), grid, dim3(256), 0, s, N, ng, W, psi, out, tri, T, active);
   else
@@ -681,94 +675,258 @@ hipError_t real_part(hipStream_t s, double* r, const double2* z, long n) {
   return hipGetLastError();
 }
 
-// Lines of length n: element p of line (o, c) at o*os + p*st + c, c in [c0, c0+TC).
-// X[m] = sum_p x[p] exp(-+ 2 pi i m p / n).
-template <int TC>
-__global__ __launch_bounds__(256) void k_dft_lines(double2* __restrict__ z, int n, long st, long os,
-                                                   int C, const double2* __restrict__ tw, int inverse) {
+// Mixed-radix (4, 2, 3, 5) self-sorting Stockham FFT of lines held in LDS
+// (ping-pong buffers).  Pass with radix R after passes whose radices multiply
+// to Ns: butterfly j reads x[j + r n/R], r < R, multiplies by the twiddle
+// w^(r (j mod Ns) n / (Ns R)), takes an R-point DFT and writes element
+// (j div Ns) Ns R + (j mod Ns) + r Ns.  After the last pass the line is in
+// natural order.  X[m] = sum_p x[p] exp(-+ 2 pi i m p / n).
+struct FftPlan {
+  int np;
+  int r[12];
+};
+
+static FftPlan fft_plan(int n) {
+  FftPlan pl{};
+  int m = n;
+  const int order[4] = {4, 2, 3, 5};
+  for (int q = 0; q < 4; ++q) {
+    int rr = order[q];
+    while (m % rr == 0 && !(rr == 2 && m % 4 == 0)) {
+      pl.r[pl.np++] = rr;
+      m /= rr;
+    }
+  }
+  if (m != 1) pl.np = -1;  // not 2,3,5-smooth
+  return pl;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// out[k] = sum_q v[q] exp(sgn 2 pi i q k / R), R in {2, 3, 4, 5}
+__device__ __forceinline__ void small_dft(double2* v, int R, double sgn) {
+  if (R == 2) {
+    double2 a = v[0], b = v[1];
+    v[0] = make_double2(a.x + b.x, a.y + b.y);
+    v[1] = make_double2(a.x - b.x, a.y - b.y);
+  } else if (R == 4) {
+    double2 a = v[0], b = v[1], c = v[2], d = v[3];
+    double2 s0 = make_double2(a.x + c.x, a.y + c.y), d0 = make_double2(a.x - c.x, a.y - c.y);
+    double2 s1 = make_double2(b.x + d.x, b.y + d.y), d1 = make_double2(b.x - d.x, b.y - d.y);
+    // w = exp(sgn i pi/2) = sgn i;  w * d1 = (-sgn d1.y, sgn d1.x)
+    double2 wd1 = make_double2(-sgn * d1.y, sgn * d1.x);
+    v[0] = make_double2(s0.x + s1.x, s0.y + s1.y);
+    v[1] = make_double2(d0.x + wd1.x, d0.y + wd1.y);
+    v[2] = make_double2(s0.x - s1.x, s0.y - s1.y);
+    v[3] = make_double2(d0.x - wd1.x, d0.y - wd1.y);
+  } else {
+    // R = 3 or 5: direct sum with exact-to-rounding cos/sin of 2 pi m / R
+    double c[5], sn[5];
+    c[0] = 1.0;
+    sn[0] = 0.0;
+    if (R == 3) {
+      c[1] = -0.5; sn[1] = 0.86602540378443864676;
+      c[2] = -0.5; sn[2] = -0.86602540378443864676;
+    } else {
+      c[1] = 0.30901699437494742410; sn[1] = 0.95105651629515357212;
+      c[2] = -0.80901699437494742410; sn[2] = 0.58778525229247312917;
+      c[3] = -0.80901699437494742410; sn[3] = -0.58778525229247312917;
+      c[4] = 0.30901699437494742410; sn[4] = -0.95105651629515357212;
+    }
+    double2 o[5];
+    for (int k = 0; k < R; ++k) {
+      double re = 0.0, im = 0.0;
+      for (int q = 0; q < R; ++q) {
+        int m = (q * k) % R;
+        double wr = c[m], wi = sgn * sn[m];
+        re += v[q].x * wr - v[q].y * wi;
+        im += v[q].x * wi + v[q].y * wr;
+      }
+      o[k] = make_double2(re, im);
+    }
+    for (int k = 0; k < R; ++k) v[k] = o[k];
+  }
+}
+
+// LAYOUT 0: element (line c, position p) at p * L + c (lines interleaved, L = lines);
+// LAYOUT 1: at c * n + p (lines contiguous).
+template <int LAYOUT>
+__device__ __forceinline__ int lidx(int c, int p, int n, int L) {
+  return LAYOUT == 0 ? p * L + c : c * n + p;
+}
+
+template <int LAYOUT>
+__device__ double2* fft_lds(double2* A, double2* B, const double2* tws, int n, int L, const FftPlan& pl,
+                            double sgn) {
+  int Ns = 1;
+  double2* src = A;
+  double2* dst = B;
+  for (int ps = 0; ps < pl.np; ++ps) {
+    const int R = pl.r[ps];
+    const int nb = n / R;
+    const int tstep = n / (Ns * R);
+    for (int e = threadIdx.x; e < nb * L; e += blockDim.x) {
+      int j = e / L, c = e - j * L;
+      double2 v[5];
+      int k = j % Ns;
+      for (int r = 0; r < R; ++r) {
+        double2 x = src[lidx<LAYOUT>(c, j + r * nb, n, L)];
+        if (r > 0) {
+          double2 t = tws[(k * r * tstep) % n];
+          t.y *= sgn;
+          x = cmul(x, t);
+        }
+        v[r] = x;
+      }
+      small_dft(v, R, sgn);
+      int base = (j / Ns) * Ns * R + k;
+      for (int r = 0; r < R; ++r) dst[lidx<LAYOUT>(c, base + r * Ns, n, L)] = v[r];
+    }
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// Lines along y or z: element p of line (o, c) at o*os + p*st + c, c in [c0, c0 + TC);
+// blockIdx.z = trajectory (field stride fs).  mode 0: one transform (sign by
+// inverse); mode 1: forward transform, multiply by the Poisson kernel
+// 4 pi / (|G|^2 Ng) (G = 0 dropped), inverse transform -- used on z lines,
+// the last forward and first inverse axis, so the k-space field never leaves LDS.
+struct PoissonGeom {
+  int nx, ny, nz;
+  double h;
+};
+
+__device__ __forceinline__ double poisson_factor(const PoissonGeom& g, long gidx) {
+  int ix = (int)(gidx % g.nx), iy = (int)((gidx / g.nx) % g.ny), iz = (int)(gidx / ((long)g.nx * g.ny));
+  int mx = ix < (g.nx + 1) / 2 ? ix : ix - g.nx;
+  int my = iy < (g.ny + 1) / 2 ? iy : iy - g.ny;
+  int mz = iz < (g.nz + 1) / 2 ? iz : iz - g.nz;
+  double gx = 2.0 * M_PI * mx / (g.nx * g.h), gy = 2.0 * M_PI * my / (g.ny * g.h), gz = 2.0 * M_PI * mz / (g.nz * g.h);
+  double g2 = (gz * gz + gy * gy) + gx * gx;
+  return g2 > 0.0 ? 4.0 * M_PI / (g2 * ((double)g.nx * g.ny * g.nz)) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_fft_strided(double2* __restrict__ z, int n, long st, long os, int C, int TC,
+                                                     const double2* __restrict__ tw, int inverse, FftPlan pl,
+                                                     long fs, int mode, PoissonGeom pg) {
   extern __shared__ unsigned char smem_raw[];
   double2* tws = reinterpret_cast<double2*>(smem_raw);
-  double2* buf = tws + n;  // [n][TC]
+  double2* A = tws + n;
+  double2* B = A + n * TC;
   const int c0 = blockIdx.x * TC;
   const long base = (long)blockIdx.y * os;
+  z += (long)blockIdx.z * fs;
   for (int p = threadIdx.x; p < n; p += blockDim.x) tws[p] = tw[p];
   const int cw = min(TC, C - c0);
   for (int e = threadIdx.x; e < n * TC; e += blockDim.x) {
     int p = e / TC, c = e - p * TC;
-    buf[e] = c < cw ? z[base + p * st + c0 + c] : make_double2(0.0, 0.0);
+    A[e] = c < cw ? z[base + p * st + c0 + c] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  const double sgn = inverse ? 1.0 : -1.0;
-  for (int e = threadIdx.x; e < n * TC; e += blockDim.x) {
-    int m = e / TC, c = e - m * TC;
-    if (c >= cw) continue;
-    double re = 0.0, im = 0.0;
-    int idx = 0;
-    for (int p = 0; p < n; ++p) {
-      double2 x = buf[p * TC + c];
-      double2 t = tws[idx];
-      double ti = sgn * t.y;
-      re += x.x * t.x - x.y * ti;
-      im += x.x * ti + x.y * t.x;
-      idx += m;
-      if (idx >= n) idx -= n;
+  double2* out;
+  if (mode == 0) {
+    out = fft_lds<0>(A, B, tws, n, TC, pl, inverse ? 1.0 : -1.0);
+  } else {
+    double2* k = fft_lds<0>(A, B, tws, n, TC, pl, -1.0);
+    for (int e = threadIdx.x; e < n * TC; e += blockDim.x) {
+      int p = e / TC, c = e - p * TC;
+      double f = c < cw ? poisson_factor(pg, base + p * st + c0 + c) : 0.0;
+      k[e] = make_double2(k[e].x * f, k[e].y * f);
     }
-    z[base + m * st + c0 + c] = make_double2(re, im);
+    __syncthreads();
+    double2* other = (k == A) ? B : A;
+    out = fft_lds<0>(k, other, tws, n, TC, pl, 1.0);
+  }
+  for (int e = threadIdx.x; e < n * TC; e += blockDim.x) {
+    int p = e / TC, c = e - p * TC;
+    if (c < cw) z[base + p * st + c0 + c] = out[e];
   }
 }
 
-// x lines are contiguous: treat each line as (o = line index, c = 0..0) with
-// TC = 1 would waste LDS bandwidth; instead lines of x are processed with the
-// line index as the inner "c" through a transposed view: element p of line l
-// at l*nx + p.
-__global__ __launch_bounds__(256) void k_dft_x(double2* __restrict__ z, int n, long n_lines,
-                                               const double2* __restrict__ tw, int inverse) {
+// Lines along x (contiguous), lpb lines per block, blockIdx.y = trajectory.
+// real_in: read the real field rin (stride rs) instead of z; real_out: write the
+// real part to rout (stride rs) instead of z.
+__global__ __launch_bounds__(256) void k_fft_x(double2* __restrict__ z, int n, long n_lines, int lpb,
+                                               const double2* __restrict__ tw, int inverse, FftPlan pl, long fs,
+                                               const double* __restrict__ rin, double* __restrict__ rout, long rs) {
   extern __shared__ unsigned char smem_raw[];
   double2* tws = reinterpret_cast<double2*>(smem_raw);
-  const int lpb = max(1, 256 / n);
-  double2* buf = tws + n;  // [lpb][n]
+  double2* A = tws + n;
+  double2* B = A + n * lpb;
   const long l0 = (long)blockIdx.x * lpb;
+  const int t = blockIdx.y;
+  z += (long)t * fs;
   for (int p = threadIdx.x; p < n; p += blockDim.x) tws[p] = tw[p];
   const int nl = (int)min((long)lpb, n_lines - l0);
-  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) buf[e] = z[l0 * n + e];
-  __syncthreads();
-  const double sgn = inverse ? 1.0 : -1.0;
-  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
-    int l = e / n, m = e - l * n;
-    double re = 0.0, im = 0.0;
-    int idx = 0;
-    const double2* x = buf + l * n;
-    for (int p = 0; p < n; ++p) {
-      double2 t = tws[idx];
-      double ti = sgn * t.y;
-      re += x[p].x * t.x - x[p].y * ti;
-      im += x[p].x * ti + x[p].y * t.x;
-      idx += m;
-      if (idx >= n) idx -= n;
-    }
-    z[l0 * n + e] = make_double2(re, im);
+  for (int e = threadIdx.x; e < lpb * n; e += blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    if (e < nl * n) v = rin ? make_double2(rin[t * rs + l0 * n + e], 0.0) : z[l0 * n + e];
+    A[e] = v;
   }
+  __syncthreads();
+  double2* out = fft_lds<1>(A, B, tws, n, lpb, pl, inverse ? 1.0 : -1.0);
+  for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+    if (rout) rout[t * rs + l0 * n + e] = out[e].x;
+    else z[l0 * n + e] = out[e];
+  }
+}
+
+static hipError_t fft_x_launch(hipStream_t s, double2* z, int nx, int ny, int nz, const double2* tw, int inverse,
+                               int T, const double* rin, double* rout) {
+  const int n = nx;
+  FftPlan pl = fft_plan(n);
+  if (pl.np < 0) return hipErrorInvalidValue;
+  long n_lines = (long)ny * nz;
+  int lpb = n >= 256 ? 1 : 256 / n;
+  if (lpb > 16) lpb = 16;
+  size_t lds = (size_t)(n + 2 * lpb * n) * sizeof(double2);
+  long ng = (long)nx * ny * nz;
+  hipLaunchKernelGGL(k_fft_x, dim3(cdiv(n_lines, lpb), T), dim3(256), lds, s, z, n, n_lines, lpb, tw, inverse, pl, ng,
+                     rin, rout, ng);
+  return hipGetLastError();
+}
+
+static hipError_t fft_strided_launch(hipStream_t s, double2* z, int nx, int ny, int nz, int axis, const double2* tw,
+                                     int inverse, int T, int mode, double h) {
+  const int n = axis == 1 ? ny : nz;
+  FftPlan pl = fft_plan(n);
+  if (pl.np < 0) return hipErrorInvalidValue;
+  int TC = n <= 96 ? 16 : (n <= 192 ? 8 : 4);
+  long st = axis == 1 ? nx : (long)nx * ny;
+  int C = axis == 1 ? nx : nx * ny;
+  int n_outer = axis == 1 ? nz : 1;
+  long os = axis == 1 ? (long)nx * ny : 0;
+  size_t lds = (size_t)(n + 2 * n * TC) * sizeof(double2);
+  PoissonGeom pg{nx, ny, nz, h};
+  long ng = (long)nx * ny * nz;
+  hipLaunchKernelGGL(k_fft_strided, dim3(cdiv(C, TC), n_outer, T), dim3(256), lds, s, z, n, st, os, C, TC, tw, inverse,
+                     pl, ng, mode, pg);
+  return hipGetLastError();
 }
 
 hipError_t dft_axis(hipStream_t s, double2* z, int nx, int ny, int nz, int axis, const double2* tw,
                     int inverse) {
-  if (axis == 0) {
-    long n_lines = (long)ny * nz;
-    int lpb = nx >= 256 ? 1 : 256 / nx;
-    size_t lds = (size_t)(nx + lpb * nx) * sizeof(double2);
-    hipLaunchKernelGGL(k_dft_x, dim3(cdiv(n_lines, lpb)), dim3(256), lds, s, z, nx, n_lines, tw, inverse);
-  } else {
-    constexpr int TC = 16;
-    int n = axis == 1 ? ny : nz;
-    long st = axis == 1 ? nx : (long)nx * ny;
-    int C = axis == 1 ? nx : nx * ny;
-    int n_outer = axis == 1 ? nz : 1;
-    long os = axis == 1 ? (long)nx * ny : 0;
-    size_t lds = (size_t)(n + n * TC) * sizeof(double2);
-    hipLaunchKernelGGL((k_dft_lines<TC>), dim3(cdiv(C, TC), n_outer), dim3(256), lds, s, z, n, st, os, C,
-                       tw, inverse);
-  }
-  return hipGetLastError();
+  if (axis == 0) return fft_x_launch(s, z, nx, ny, nz, tw, inverse, 1, nullptr, nullptr);
+  return fft_strided_launch(s, z, nx, ny, nz, axis, tw, inverse, 1, 0, 0.0);
+}
+
+// V_H,t = IFFT[4 pi FFT[rho_t] / |G|^2] for T stacked densities: five launches
+// (x fwd from the real field, y fwd, z fwd * kernel * z inv, y inv, x inv to the real field).
+hipError_t poisson_fft(hipStream_t s, const double* rho, double* vh, double2* z, int nx, int ny, int nz, double h,
+                       const double2* twx, const double2* twy, const double2* twz, int T) {
+  hipError_t e;
+  if ((e = fft_x_launch(s, z, nx, ny, nz, twx, 0, T, rho, nullptr)) != hipSuccess) return e;
+  if ((e = fft_strided_launch(s, z, nx, ny, nz, 1, twy, 0, T, 0, h)) != hipSuccess) return e;
+  if ((e = fft_strided_launch(s, z, nx, ny, nz, 2, twz, 0, T, 1, h)) != hipSuccess) return e;
+  if ((e = fft_strided_launch(s, z, nx, ny, nz, 1, twy, 1, T, 0, h)) != hipSuccess) return e;
+  return fft_x_launch(s, z, nx, ny, nz, twx, 1, T, nullptr, vh);
 }
 
 // V_H(G) = 4 pi rho(G) / |G|^2 / Ng (inverse-transform normalisation folded in), V_H(0) = 0.
@@ -798,8 +956,16 @@ hipError_t poisson_scale(hipStream_t s, double2* z, int nx, int ny, int nz, doub
 __global__ __launch_bounds__(256) void k_lda_vloc(const double* __restrict__ rho,
                                                   const double* __restrict__ vh,
                                                   const double* __restrict__ vion, double* __restrict__ vx,
-                                                  double* __restrict__ vloc, long n, double* part2) {
+                                                  double* __restrict__ vloc, long n, double* part2,
+                                                  const int* active) {
   __shared__ double sh[256];
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  rho += t * n;
+  vh += t * n;
+  vx += t * n;
+  vloc += t * n;
+  part2 += (long)t * 2 * gridDim.x;
   const double cx = cbrt(3.0 / M_PI);
   double ex_sum = 0.0, eh_sum = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -821,14 +987,19 @@ __global__ __launch_bounds__(256) void k_lda_vloc(const double* __restrict__ rho
   }
 }
 hipError_t lda_vloc(hipStream_t s, const double* rho, const double* vh, const double* vion, double* vx,
-                    double* vloc, long n, double* part2) {
-  hipLaunchKernelGGL(k_lda_vloc, dim3(kRedBlocks), dim3(256), 0, s, rho, vh, vion, vx, vloc, n, part2);
+                    double* vloc, long n, double* part2, int T, const int* active) {
+  hipLaunchKernelGGL(k_lda_vloc, dim3(kRedBlocks, T), dim3(256), 0, s, rho, vh, vion, vx, vloc, n, part2, active);
   return hipGetLastError();
 }
 
+// blockIdx.x = trajectory: part_t = part + t nblk ncol, out_t = out + t ncol
 __global__ __launch_bounds__(256) void k_reduce_cols(const double* part, int nblk, int ncol,
-                                                     const double* scale, double* out) {
+                                                     const double* scale, double* out, const int* active) {
   __shared__ double sh[256];
+  const int t = blockIdx.x;
+  if (active && !active[t]) return;
+  part += (long)t * nblk * ncol;
+  out += (long)t * ncol;
   for (int c = 0; c < ncol; ++c) {
     double acc = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) acc += part[(long)b * ncol + c];
@@ -837,8 +1008,8 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* part, int nbl
   }
 }
 hipError_t reduce_cols(hipStream_t s, const double* part, int nblk, int ncol, const double* scale,
-                       double* out) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, s, part, nblk, ncol, scale, out);
+                       double* out, int T, const int* active) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(T), dim3(256), 0, s, part, nblk, ncol, scale, out, active);
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, 
                        const float* w, float* part, long kps, int n_split, int T, const int* active);
 // C = base + alpha * sum_s part[s] (upper kept, mirrored)
 hipError_t reduce_parts_f32(hipStream_t s, const float* part, int n_split, int N, double alpha,
-                            const double* base, double* C, int T, const int* active);
+                            const double* base, double* C, int T, const int* active, long sbase);
 // rho = rho0 + sum_i psi_i sum_{j>=i} W_ij psi_j
 hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* whi, const unsigned short* wlo,
                           const unsigned short* phi, const unsigned short* plo, const double* rho0, double* rho,

@@ -204,11 +204,12 @@ hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, 
 
 // C[m][n] = alpha * sum_s part[s][m][n] (FP64 sum of FP32 partials), upper kept and mirrored, plus base.
 __global__ void k_reduce_parts_f32(const float* __restrict__ part, int n_split, int N, double alpha,
-                                   const double* __restrict__ base, double* __restrict__ C, const int* active) {
+                                   const double* base, double* C, const int* active, long sbase) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   part += (long)t * n_split * N * N;
   C += (long)t * N * N;
+  base += t * sbase;
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)N * N) return;
   int m = (int)(e / N), n = (int)(e - (long)m * N);
@@ -221,10 +222,10 @@ __global__ void k_reduce_parts_f32(const float* __restrict__ part, int n_split, 
 }
 
 hipError_t reduce_parts_f32(hipStream_t s, const float* part, int n_split, int N, double alpha,
-                            const double* base, double* C, int T, const int* active) {
+                            const double* base, double* C, int T, const int* active, long sbase) {
   long n = (long)N * N;
   hipLaunchKernelGGL(k_reduce_parts_f32, dim3(cdivm(n, 256), T), dim3(256), 0, s, part, n_split, N, alpha, base, C,
-                     active);
+                     active, sbase);
   return hipGetLastError();
 }
 

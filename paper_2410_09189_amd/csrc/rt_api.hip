@@ -4,6 +4,7 @@
 #include "../../include/rt_tddft.h"
 #include "kernels.h"
 #include "kernels_mixed.h"
+#include "kernels_mlp.h"
 
 #include <hip/hip_runtime.h>
 
@@ -159,7 +160,22 @@ struct SysDev {
   double* kmin;                            // [T]
   unsigned long long *slots, *resid;       // [T][max_terms + 2], [T]
   int *done, *active;                      // [T][2], [T]
+  // learned predictor / training-sample recording
+  bool feat = false;                       // grid edges divisible by 16: features available
+  bool mlp = false;                        // RT_PRED_MLP in use
+  int mom_head = -1, cd_cur = 1, cv_head = -1, n_hist = 0;
+  bool x_valid = false;
+  float *mom_ring, *cd_ring, *xbuf, *ybuf, *mlp_params, *mlp_work;
+  double* cv_ring;                         // [T][3][4096] coarse V_loc - V_loc,gs (FP64)
+  double* mom_part;
+  int* mlp_mask;
+  std::vector<int> mlp_on;                 // host copy of mlp_mask
+  std::vector<std::vector<double>> r1_linear;
+  double* rho_gs64;                        // ground-state density (all modes)
 };
+
+constexpr int kNIn = 8 * 9 + 2 * 4096, kNH = 256, kNOut = 4096;
+inline rtk::MlpDims pred_dims() { return rtk::MlpDims{kNIn, kNH, kNOut}; }
 
 struct TrajDev {
   int sys, slot, axis;
@@ -190,6 +206,8 @@ struct rt_ctx {
   std::vector<TrajDev> traj;
   std::string err;
   int hist_cap = 0;
+  float *rec_x = nullptr, *rec_y = nullptr;
+  int rec_cap = 0, rec_count = 0;
 };
 
 namespace {
@@ -260,6 +278,12 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
     for (int q = 0; q < 3; ++q)
       if (s.n[q] < 8 || s.n[q] > 1024) { why = "grid edge outside [8, 1024]"; return RT_EINVAL; }
     if ((s.n[1] > 256) || (s.n[2] > 256)) { why = "y and z grid edges above 256 are not supported"; return RT_EINVAL; }
+    for (int q = 0; q < 3; ++q) {
+      int m = s.n[q];
+      for (int f : {2, 3, 5})
+        while (m % f == 0) m /= f;
+      if (m != 1) { why = "grid edges must have no prime factor above 5 (FFT Poisson)"; return RT_EINVAL; }
+    }
     if (!(s.h > 0)) { why = "h must be positive"; return RT_EINVAL; }
     if (s.n_atoms < 0 || (s.n_atoms > 0 && (!s.pos || !s.depth || !s.width))) { why = "atom arrays"; return RT_EINVAL; }
     if (s.n_images < 0 || s.n_images > 3) { why = "n_images outside [0, 3]"; return RT_EINVAL; }
@@ -281,7 +305,14 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
         why = "mixed precision needs a grid point count divisible by 8"; return RT_EINVAL;
       }
   }
-  if (run->predictor != RT_PRED_LINEAR) { why = "only the linear predictor is available in this build"; return RT_EINVAL; }
+  if (run->predictor != RT_PRED_LINEAR && run->predictor != RT_PRED_MLP) { why = "predictor"; return RT_EINVAL; }
+  if (run->predictor == RT_PRED_MLP) {
+    if (!run->mlp_params) { why = "RT_PRED_MLP needs mlp_params"; return RT_EINVAL; }
+    for (int i = 0; i < n_sys; ++i)
+      if (sys[i].n[0] % 16 || sys[i].n[1] % 16 || sys[i].n[2] % 16) {
+        why = "the learned predictor needs grid edges divisible by 16"; return RT_EINVAL;
+      }
+  }
   if (run->hupdate != RT_HUPDATE_FULL && run->hupdate != RT_HUPDATE_LOCAL) { why = "hupdate"; return RT_EINVAL; }
   if (run->n_traj < 0 || (run->n_traj > 0 && (!run->traj_sys || !run->traj_kappa || !run->traj_axis))) {
     why = "trajectory arrays"; return RT_EINVAL;
@@ -327,7 +358,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.vloc_gs = a.take<double>(ng);
     d.occ = a.take<double>(N);
     d.vloc32 = a.take<float>(ng);
-    d.z = a.take<double2>(ng);
+    d.z = a.take<double2>(T * ng);
     d.twx = a.take<double2>(d.nx);
     d.twy = a.take<double2>(d.ny);
     d.twz = a.take<double2>(d.nz);
@@ -348,7 +379,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.Hgs = a.take<double>(NN);
     d.tmp = a.take<double>(NN);
     d.tmp2 = a.take<double>(NN);
-    d.red2 = a.take<double>(2 * rtk::kRedBlocks);
+    d.red2 = a.take<double>(T * 2 * rtk::kRedBlocks);
     d.escale = a.take<double>(2);
     d.ezero = a.take<double>(2);
     d.info = a.take<int>(4);
@@ -386,6 +417,20 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.resid = a.take<unsigned long long>(T);
     d.done = a.take<int>(2 * T);
     d.active = a.take<int>(T);
+    d.rho_gs64 = a.take<double>(ng);
+    if (d.feat) {
+      d.mom_ring = a.take<float>(T * 72);
+      d.cd_ring = a.take<float>(T * 2 * 4096);
+      d.cv_ring = a.take<double>(T * 3 * 4096);
+      d.xbuf = a.take<float>(T * kNIn);
+      d.ybuf = a.take<float>(T * kNOut);
+      d.mom_part = a.take<double>(T * 256 * 9);
+      d.mlp_mask = a.take<int>(T);
+    }
+    if (d.mlp) {
+      d.mlp_params = a.take<float>(rtk::mlp_n_params(pred_dims()));
+      d.mlp_work = a.take<float>(rtk::mlp_work_floats(pred_dims(), T));
+    }
   }
 }
 
@@ -410,6 +455,8 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
     d.nl = build_nl(s);
     d.n_union = (int)d.nl.u_idx.size();
     d.mixed = run->precision == RT_MIXED;
+    d.feat = d.nx % 16 == 0 && d.ny % 16 == 0 && d.nz % 16 == 0;
+    d.mlp = run->predictor == RT_PRED_MLP;
     d.slot_traj.clear();
     choose_split(d);
   }
@@ -426,6 +473,8 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
     d.T = (int)d.slot_traj.size();
     d.active_host.assign(d.T, 1);
     d.zeros2T.assign(2 * d.T, 0);
+    d.mlp_on.assign(d.T, d.mlp ? 1 : 0);
+    d.r1_linear.assign(d.T, std::vector<double>());
   }
 }
 
@@ -487,25 +536,16 @@ rt_status apply_h32(rt_ctx* c, SysDev& d, const float* psi, float* hpsi, int n) 
   return RT_OK;
 }
 
-// Spectral Poisson + LDA for slot t (FP64): rho_t -> V_H, v_x, V_loc, energies.
-rt_status poisson_lda(rt_ctx* c, SysDev& d, int t) {
+// Spectral Poisson + LDA for the active slots (FP64): rho_t -> V_H, v_x, V_loc, energies.
+rt_status poisson_lda(rt_ctx* c, SysDev& d, int T, const int* act) {
   hipStream_t s = c->stream;
-  const long o = (long)t * d.ng;
   {
     Timed tp(c, PH_POISSON);
-    CK(rtk::pack_real(s, d.z, d.rho + o, d.ng));
-    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 0, d.twx, 0));
-    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 1, d.twy, 0));
-    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 2, d.twz, 0));
-    CK(rtk::poisson_scale(s, d.z, d.nx, d.ny, d.nz, d.h));
-    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 0, d.twx, 1));
-    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 1, d.twy, 1));
-    CK(rtk::dft_axis(s, d.z, d.nx, d.ny, d.nz, 2, d.twz, 1));
-    CK(rtk::real_part(s, d.vh + o, d.z, d.ng));
+    CK(rtk::poisson_fft(s, d.rho, d.vh, d.z, d.nx, d.ny, d.nz, d.h, d.twx, d.twy, d.twz, T));
   }
   Timed tl(c, PH_LDA);
-  CK(rtk::lda_vloc(s, d.rho + o, d.vh + o, d.vion, d.vx + o, d.vloc + o, d.ng, d.red2));
-  CK(rtk::reduce_cols(s, d.red2, rtk::kRedBlocks, 2, d.escale, d.eparts + 2 * t));
+  CK(rtk::lda_vloc(s, d.rho, d.vh, d.vion, d.vx, d.vloc, d.ng, d.red2, T, act));
+  CK(rtk::reduce_cols(s, d.red2, rtk::kRedBlocks, 2, d.escale, d.eparts, T, act));
   return RT_OK;
 }
 
@@ -533,8 +573,7 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
       CK(rtk::smalltall_f64(s, d.N, d.ng, d.W, d.psi, d.rho, 1, 1, T, act));
     }
   }
-  for (int t = 0; t < T; ++t)
-    if (act_host[t]) RET(poisson_lda(c, d, t));
+  RET(poisson_lda(c, d, T, act));
   if (mixed) {
     // H = H_gs + h^3 Psi diag(V_loc - V_loc,gs) Psi^T in BF16x3
     CK(rtk::delta_f32(s, d.dv32, d.vloc, d.vloc_gs, d.ng, T, act));
@@ -543,7 +582,7 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
       CK(rtk::proj_bf16x3(s, d.N, d.ng, d.psi_hi, d.psi_lo, d.dv32, d.part32, d.kps_x, d.n_split_x, T, act));
     }
     Timed tr(c, PH_REDUCE);
-    CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.Hgs, Hout, T, act));
+    CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.Hgs, Hout, T, act, 0));
     return RT_OK;
   }
   if (r.hupdate == RT_HUPDATE_FULL || force_full) {
@@ -627,6 +666,54 @@ rt_status observe(rt_ctx* c, SysDev& d, int row) {
   return RT_OK;
 }
 
+// Appends the current (converged) state of every slot to the feature rings:
+// moments of drho, R drho, R (V_loc - V_loc,gs); writes a training sample when recording;
+// assembles x_j for the next prediction once 8 steps are known.
+rt_status update_features(rt_ctx* c, SysDev& d) {
+  if (!d.feat) return RT_OK;
+  hipStream_t s = c->stream;
+  const int T = d.T;
+  d.mom_head = (d.mom_head + 1) % 8;
+  d.cd_cur ^= 1;
+  d.cv_head = (d.cv_head + 1) % 3;
+  CK(rtk::moments9(s, d.rho, d.rho_gs64, d.nx, d.ny, d.nz, d.h, d.ng, d.mom_part, d.mom_ring + d.mom_head * 9, 72, T));
+  CK(rtk::restrict16(s, d.rho, d.rho_gs64, d.cd_ring + d.cd_cur * 4096, d.nx, d.ny, d.nz, d.ng, 2 * 4096, T));
+  CK(rtk::restrict16_f64(s, d.vloc, d.vloc_gs, d.cv_ring + d.cv_head * 4096, d.nx, d.ny, d.nz, d.ng, 3 * 4096, T));
+  d.n_hist += 1;
+  if (c->rec_x && d.x_valid && d.n_hist >= 3 && c->rec_count + T <= c->rec_cap) {
+    int inew = d.cv_head, imid = (d.cv_head + 2) % 3, iold = (d.cv_head + 1) % 3;
+    CK(rtk::second_diff(s, d.cv_ring, inew, imid, iold, c->rec_y + (long)c->rec_count * kNOut, 3 * 4096, kNOut, T));
+    CK(rtk::copy_rows_f(s, d.xbuf, c->rec_x + (long)c->rec_count * kNIn, kNIn, kNIn, kNIn, T));
+    c->rec_count += T;
+  }
+  if (d.n_hist >= 8) {
+    CK(rtk::assemble_features(s, d.mom_ring, d.mom_head, d.cd_ring, d.cd_cur, d.cd_cur ^ 1, d.xbuf, kNIn, 72,
+                              2 * 4096, T));
+    d.x_valid = true;
+  }
+  return RT_OK;
+}
+
+// H1_t += h^3 Psi^T diag(P network(x_t)) Psi for the slots whose network is on.
+rt_status predict_correction(rt_ctx* c, SysDev& d) {
+  hipStream_t s = c->stream;
+  const int T = d.T;
+  const long NN = nsq(d.N);
+  CK(rtk::mlp_forward(s, pred_dims(), d.mlp_params, d.xbuf, d.ybuf, T, d.mlp_work, false));
+  CK(rtk::prolong16(s, d.ybuf, d.dv, d.nx, d.ny, d.nz, kNOut, d.ng, T));
+  if (d.mixed) {
+    CK(rtk::cast_d2f(s, d.dv32, d.dv, (long)T * d.ng));
+    CK(rtk::proj_bf16x3(s, d.N, d.ng, d.psi_hi, d.psi_lo, d.dv32, d.part32, d.kps_x, d.n_split_x, T, d.mlp_mask));
+    CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.H1, d.H1, T, d.mlp_mask, NN));
+  } else {
+    const long sp = (long)d.n_split * NN;
+    CK(rtk::gemm_nt_f64(s, d.N, d.N, d.ng, d.psi, d.ng, d.psi, d.ng, d.dv, d.part, d.kps, d.n_split, 1, d.big,
+                        rtk::Batch{T, d.mlp_mask, 0, 0, d.ng, sp}));
+    CK(rtk::reduce_parts(s, d.part, d.n_split, d.N, d.N, d.h3, d.H1, 1, d.H1, T, sp, NN, NN, d.mlp_mask));
+  }
+  return RT_OK;
+}
+
 rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   hipStream_t st = c->stream;
   const long N = d.N, ng = d.ng, NN = N * N;
@@ -680,6 +767,12 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   std::vector<int> one(1, 1);
   RET(eval_h(c, d, 1, nullptr, one, d.tmp, NN, d.Hgs, true));
   CK(rtk::copy_d(st, d.vloc_gs, d.vloc, d.ng));
+  CK(rtk::copy_d(st, d.rho_gs64, d.rho, d.ng));
+  if (d.mlp) {
+    CK(hipMemcpyAsync(d.mlp_params, c->run.mlp_params, rtk::mlp_n_params(pred_dims()) * sizeof(float),
+                      hipMemcpyHostToDevice, st));
+  }
+  if (d.feat) CK(hipMemcpyAsync(d.mlp_mask, d.mlp_on.data(), d.T * sizeof(int), hipMemcpyHostToDevice, st));
   if (d.mixed) {
     CK(rtk::copy_d(st, d.rho_gs, d.rho, d.ng));
     CK(rtk::copy_d(st, d.S_gs, d.tmp, NN));
@@ -706,6 +799,7 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   CK(rtk::copy_d(st, d.Hm1, d.H0, (long)d.T * NN));
   d.step = 0;
   RET(observe(c, d, 0));
+  RET(update_features(c, d));
   CK(hipStreamSynchronize(st));  // host vectors above must outlive their copies
   return RT_OK;
 }
@@ -717,6 +811,15 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   const long NN = nsq(d.N);
   const int T = d.T;
   CK(rtk::lincomb(st, d.H1, 2.0, d.H0, -1.0, d.Hm1, T * NN));
+  bool predicted = false;
+  if (d.mlp && d.x_valid) {
+    bool any = false;
+    for (int t = 0; t < T; ++t) any = any || d.mlp_on[t];
+    if (any) {
+      RET(predict_correction(c, d));
+      predicted = true;
+    }
+  }
   d.active_host.assign(T, 1);
   RET(push_active(c, d));
   std::vector<int> m_of(T, 0), terms_of(T, 0);
@@ -734,10 +837,23 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
     CK(hipMemcpyAsync(bits.data(), d.resid, T * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     bool changed = false;
+    bool mask_changed = false;
     for (int t = 0; t < T; ++t) {
       if (!d.active_host[t]) continue;
       double r;
       std::memcpy(&r, &bits[t], sizeof(r));
+      if (m == 1 && d.mlp) {
+        if (predicted && d.mlp_on[t]) {
+          // fallback: the network's first residual against the median of linear first residuals
+          std::vector<double> v = d.r1_linear[t];
+          if (!v.empty()) {
+            std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+            if (r > 10.0 * v[v.size() / 2]) { d.mlp_on[t] = 0; mask_changed = true; }
+          }
+        } else {
+          d.r1_linear[t].push_back(r);
+        }
+      }
       m_of[t] = m;
       terms_of[t] += terms[t];
       res_of[t] = r;
@@ -748,6 +864,8 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
       }
     }
     if (changed && n_active > 0) RET(push_active(c, d));
+    if (mask_changed)
+      CK(hipMemcpyAsync(d.mlp_mask, d.mlp_on.data(), T * sizeof(int), hipMemcpyHostToDevice, st));
   }
   if (n_active > 0) return fail(c, RT_ENOCONV, "self-consistent Hamiltonian loop reached max_scf");
   // H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 (all slots together)
@@ -767,7 +885,10 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
     }
   }
   (void)n_traj_total;
-  return observe(c, d, d.step);
+  RET(observe(c, d, d.step));
+  RET(update_features(c, d));
+  if (d.mlp) CK(hipStreamSynchronize(st));  // mlp_on (host) feeds async copies
+  return RT_OK;
 }
 
 }  // namespace
@@ -995,6 +1116,76 @@ rt_status rt_get_grid(rt_ctx* c, int si, int which, double* out_host) {
   }
   CK(hipMemcpyAsync(out_host, src, d.ng * 8, hipMemcpyDeviceToHost, c->stream));
   CK(hipStreamSynchronize(c->stream));
+  return RT_OK;
+}
+
+void rt_mlp_dims(int* n_in, int* n_h, int* n_out) {
+  if (n_in) *n_in = kNIn;
+  if (n_h) *n_h = kNH;
+  if (n_out) *n_out = kNOut;
+}
+
+int64_t rt_mlp_n_params(int n_in, int n_h, int n_out) { return rtk::mlp_n_params(rtk::MlpDims{n_in, n_h, n_out}); }
+
+int64_t rt_mlp_work_floats(int n_in, int n_h, int n_out, int batch) {
+  return rtk::mlp_work_floats(rtk::MlpDims{n_in, n_h, n_out}, batch);
+}
+
+static rt_status mlp_check(int n_in, int n_h, int n_out, int batch) {
+  if (n_in < 1 || n_h < 1 || n_out < 1 || batch < 1) { g_init_error = "mlp dimensions"; return RT_EINVAL; }
+  return RT_OK;
+}
+#define CKS(expr)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) { g_init_error = hipGetErrorString(e_); return RT_EDEVICE; }     \
+  } while (0)
+
+rt_status rt_mlp_forward(void* stream, int n_in, int n_h, int n_out, const float* params, const float* x, float* y,
+                         int batch, float* work) {
+  RET(mlp_check(n_in, n_h, n_out, batch));
+  if (!params || !x || !y || !work) { g_init_error = "null buffer"; return RT_EINVAL; }
+  CKS(rtk::mlp_forward((hipStream_t)stream, rtk::MlpDims{n_in, n_h, n_out}, params, x, y, batch, work, false));
+  return RT_OK;
+}
+
+rt_status rt_mlp_loss_grad(void* stream, int n_in, int n_h, int n_out, const float* params, const float* x,
+                           const float* target, int batch, float* grads, float* work, float* loss) {
+  RET(mlp_check(n_in, n_h, n_out, batch));
+  if (!params || !x || !target || !grads || !work || !loss) { g_init_error = "null buffer"; return RT_EINVAL; }
+  CKS(rtk::mlp_loss_grad((hipStream_t)stream, rtk::MlpDims{n_in, n_h, n_out}, params, x, target, batch, grads, work,
+                         loss));
+  return RT_OK;
+}
+
+rt_status rt_mlp_adam(void* stream, float* p, const float* g, float* m, float* v, int64_t n, int t, float lr) {
+  if (!p || !g || !m || !v || n < 1 || t < 1) { g_init_error = "rt_mlp_adam arguments"; return RT_EINVAL; }
+  CKS(rtk::mlp_adam((hipStream_t)stream, p, g, m, v, n, t, lr));
+  return RT_OK;
+}
+
+rt_status rt_mlp_colstats(void* stream, const float* x, int rows, int cols, float* mean, float* scale,
+                          float floor_std) {
+  if (!x || !mean || !scale || rows < 1 || cols < 1) { g_init_error = "rt_mlp_colstats arguments"; return RT_EINVAL; }
+  CKS(rtk::mlp_colstats((hipStream_t)stream, x, rows, cols, mean, scale, floor_std));
+  return RT_OK;
+}
+
+rt_status rt_record(rt_ctx* c, float* x_dev, float* y_dev, int capacity) {
+  if (!c) return RT_EINVAL;
+  if (!x_dev || !y_dev || capacity < 0) return fail(c, RT_EINVAL, "rt_record arguments");
+  for (auto& d : c->sys)
+    if (!d.feat) return fail(c, RT_EINVAL, "recording needs grid edges divisible by 16");
+  c->rec_x = x_dev;
+  c->rec_y = y_dev;
+  c->rec_cap = capacity;
+  c->rec_count = 0;
+  return RT_OK;
+}
+
+rt_status rt_record_count(rt_ctx* c, int* rows) {
+  if (!c || !rows) return RT_EINVAL;
+  *rows = c->rec_count;
   return RT_OK;
 }
 

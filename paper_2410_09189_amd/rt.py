@@ -41,7 +41,7 @@ class rt_run(ctypes.Structure):
         ("dp_thrs", ctypes.c_double), ("max_scf", ctypes.c_int), ("max_terms", ctypes.c_int),
         ("precision", ctypes.c_int), ("predictor", ctypes.c_int), ("hupdate", ctypes.c_int),
         ("frozen_hxc", ctypes.c_int), ("n_traj", ctypes.c_int), ("traj_sys", _ip),
-        ("traj_kappa", _dp), ("traj_axis", _ip),
+        ("traj_kappa", _dp), ("traj_axis", _ip), ("mlp_params", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -82,6 +82,16 @@ def _load():
         "rt_profile": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "rt_profile_read": ([vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_long),
                              ctypes.POINTER(ctypes.c_char_p)], ctypes.c_int),
+        "rt_mlp_dims": ([_ip, _ip, _ip], None),
+        "rt_mlp_n_params": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int64),
+        "rt_mlp_work_floats": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int64),
+        "rt_mlp_forward": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
+        "rt_mlp_loss_grad": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp, vp, vp],
+                             ctypes.c_int),
+        "rt_mlp_adam": ([vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int, ctypes.c_float], ctypes.c_int),
+        "rt_mlp_colstats": ([vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_float], ctypes.c_int),
+        "rt_record": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "rt_record_count": ([vp, _ip], ctypes.c_int),
         "rt_free": ([vp], None),
         "rt_last_error": ([vp], ctypes.c_char_p),
     }
@@ -140,7 +150,7 @@ class SystemArgs:
 class RunArgs:
     def __init__(self, dt, n_steps_max, h_thrs, dp_thrs, max_scf, max_terms, traj_sys, traj_kappa,
                  traj_axis, precision=RT_FP64, predictor=RT_PRED_LINEAR, hupdate=RT_HUPDATE_FULL,
-                 frozen_hxc=False):
+                 frozen_hxc=False, mlp_params=None):
         self.traj_sys = np.ascontiguousarray(traj_sys, dtype=np.int32)
         self.traj_kappa = np.ascontiguousarray(traj_kappa, dtype=np.float64)
         self.traj_axis = np.ascontiguousarray(traj_axis, dtype=np.int32)
@@ -152,6 +162,8 @@ class RunArgs:
         r.traj_sys = _ptr(self.traj_sys, ctypes.c_int)
         r.traj_kappa = _ptr(self.traj_kappa)
         r.traj_axis = _ptr(self.traj_axis, ctypes.c_int)
+        self.mlp_params = None if mlp_params is None else np.ascontiguousarray(mlp_params, dtype=np.float32)
+        r.mlp_params = _ptr(self.mlp_params, ctypes.c_float)
         self.struct = r
 
 
@@ -232,6 +244,51 @@ def rt_profile_read(ctx):
         _check(lib.rt_profile_read(ctx, ph, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(name)), ctx)
         out[name.value.decode()] = (ms.value, n.value)
     return out
+
+
+def rt_mlp_dims():
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    lib.rt_mlp_dims(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
+
+
+def rt_mlp_n_params(n_in, n_h, n_out):
+    return int(lib.rt_mlp_n_params(n_in, n_h, n_out))
+
+
+def rt_mlp_work_floats(n_in, n_h, n_out, batch):
+    return int(lib.rt_mlp_work_floats(n_in, n_h, n_out, batch))
+
+
+def rt_mlp_forward(stream, dims, params_ptr, x_ptr, y_ptr, batch, work_ptr):
+    _check(lib.rt_mlp_forward(ctypes.c_void_p(stream), *dims, ctypes.c_void_p(params_ptr), ctypes.c_void_p(x_ptr),
+                              ctypes.c_void_p(y_ptr), batch, ctypes.c_void_p(work_ptr)))
+
+
+def rt_mlp_loss_grad(stream, dims, params_ptr, x_ptr, t_ptr, batch, grads_ptr, work_ptr, loss_ptr):
+    _check(lib.rt_mlp_loss_grad(ctypes.c_void_p(stream), *dims, ctypes.c_void_p(params_ptr), ctypes.c_void_p(x_ptr),
+                                ctypes.c_void_p(t_ptr), batch, ctypes.c_void_p(grads_ptr), ctypes.c_void_p(work_ptr),
+                                ctypes.c_void_p(loss_ptr)))
+
+
+def rt_mlp_adam(stream, p_ptr, g_ptr, m_ptr, v_ptr, n, t, lr):
+    _check(lib.rt_mlp_adam(ctypes.c_void_p(stream), ctypes.c_void_p(p_ptr), ctypes.c_void_p(g_ptr),
+                           ctypes.c_void_p(m_ptr), ctypes.c_void_p(v_ptr), n, t, lr))
+
+
+def rt_mlp_colstats(stream, x_ptr, rows, cols, mean_ptr, scale_ptr, floor_std):
+    _check(lib.rt_mlp_colstats(ctypes.c_void_p(stream), ctypes.c_void_p(x_ptr), rows, cols,
+                               ctypes.c_void_p(mean_ptr), ctypes.c_void_p(scale_ptr), floor_std))
+
+
+def rt_record(ctx, x_ptr, y_ptr, capacity):
+    _check(lib.rt_record(ctx, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), capacity), ctx)
+
+
+def rt_record_count(ctx):
+    n = ctypes.c_int(0)
+    _check(lib.rt_record_count(ctx, ctypes.byref(n)), ctx)
+    return n.value
 
 
 def rt_free(ctx):

@@ -253,7 +253,9 @@ def test_mixed_c1_trajectory_relative_dipole_error():
     ref = c1_oracle_run()
     s = c1_system()
     psi, _ = c1_ground_state()
-    rp = synth.config_run("c1_parity_32", n_steps=200)
+    # BF16x3 rounding leaves ~1e-5 of the Hamiltonian's perturbation (~1e-10 Ha
+    # here) in every update, so the self-consistency threshold sits above it.
+    rp = synth.config_run("c1_parity_32", n_steps=200, h_thrs=1e-9)
     ses = _session([system_args(s, psi)], run_args(rp, precision=rt.RT_MIXED, hupdate=1))
     rt.rt_step(ses.ctx, 200, n_traj=1)
     mu, E, tr = rt.rt_dipole(ses.ctx, 0, 0, 201)

@@ -1,0 +1,172 @@
+"""The learned first guess on the GPU: network forward/backward/Adam against
+the CPU oracle, device features against the oracle's definitions, and the
+fixed point's independence of the predictor."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import hamiltonian
+from oracle import predictor as opr
+from conftest import c1_ground_state, c1_model, c1_system
+from rt_helpers import run_args, system_args
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _oracle_params(p, dims):
+    n_in, n_h, n_out = dims
+    o = 2 * n_in + 2 * n_out
+    W1 = p[o:o + n_h * n_in].reshape(n_h, n_in); o += n_h * n_in
+    b1 = p[o:o + n_h]; o += n_h
+    W2 = p[o:o + n_h * n_h].reshape(n_h, n_h); o += n_h * n_h
+    b2 = p[o:o + n_h]; o += n_h
+    W3 = p[o:o + n_out * n_h].reshape(n_out, n_h); o += n_out * n_h
+    b3 = p[o:o + n_out]
+    return {k: v.astype(np.float64) for k, v in dict(W1=W1, b1=b1, W2=W2, b2=b2, W3=W3, b3=b3).items()}
+
+
+def test_network_forward_gradients_and_adam_match_oracle():
+    _say("mlp 37-19-11 batch 8 forward/backward/adam")
+    import torch
+    from paper_2410_09189_amd import predictor, rt
+
+    dims = (37, 19, 11)
+    rng = np.random.default_rng(7)
+    p = predictor.init_params(dims, seed=3)
+    off = predictor.train_offset(dims)
+    p[off:] += (0.2 * rng.standard_normal(p.size - off)).astype(np.float32)
+    X = rng.standard_normal((8, 37)).astype(np.float32)
+    Tg = rng.standard_normal((8, 11)).astype(np.float32)
+    stream = torch.cuda.current_stream().cuda_stream
+    pd, Xd, Td = (torch.from_numpy(a).cuda() for a in (p, X, Tg))
+    Yd = torch.empty((8, 11), dtype=torch.float32, device="cuda")
+    work = torch.empty(rt.rt_mlp_work_floats(*dims, 8), dtype=torch.float32, device="cuda")
+    rt.rt_mlp_forward(stream, dims, pd.data_ptr(), Xd.data_ptr(), Yd.data_ptr(), 8, work.data_ptr())
+    g = torch.empty(p.size - off, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    rt.rt_mlp_loss_grad(stream, dims, pd.data_ptr(), Xd.data_ptr(), Td.data_ptr(), 8, g.data_ptr(), work.data_ptr(),
+                        loss.data_ptr())
+    torch.cuda.synchronize()
+    po = _oracle_params(p, dims)
+    Yo, _ = opr.forward(po, X.astype(np.float64))
+    assert np.max(np.abs(Yd.cpu().numpy() - Yo)) < 1e-5 * max(1.0, np.max(np.abs(Yo)))
+    lo, go = opr.loss_and_grads(po, X.astype(np.float64), Tg.astype(np.float64))
+    assert abs(loss.item() - lo) < 1e-5 * lo
+    gflat = np.concatenate([go[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    assert np.max(np.abs(g.cpu().numpy() - gflat)) < 1e-5 * np.max(np.abs(gflat))
+    # one Adam step
+    m = torch.zeros_like(g)
+    v = torch.zeros_like(g)
+    rt.rt_mlp_adam(stream, pd[off:].data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), g.numel(), 1, 1e-2)
+    torch.cuda.synchronize()
+    st = {}
+    opr.adam(po, go, st, lr=1e-2)
+    pnew = _oracle_params(pd.cpu().numpy(), dims)
+    for k in po:
+        assert np.max(np.abs(pnew[k] - po[k])) < 1e-5, k
+
+
+def test_recorded_features_and_targets_match_oracle_definitions():
+    _say("C1 recording 14 steps, features vs oracle")
+    import torch
+    from paper_2410_09189_amd import rt
+
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    m = c1_model()
+    n_steps = 14
+    rp = synth.config_run("c1_parity_32", n_steps=n_steps)
+    ses = rt.Session([system_args(s, psi)], run_args(rp))
+    n_in, _, n_out = rt.rt_mlp_dims()
+    X = torch.zeros((32, n_in), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((32, n_out), dtype=torch.float32, device="cuda")
+    rt.rt_record(ses.ctx, X.data_ptr(), Y.data_ptr(), 32)
+    rt.rt_step(ses.ctx, n_steps)
+    rows = rt.rt_record_count(ses.ctx)
+    ses.close()
+    assert rows == n_steps - 7
+    ref = oracle.run(m, rp, record_p=True)
+    rho_gs = hamiltonian.density(np.diag(s.occupations()), m.psi)
+    vh_gs = hamiltonian.hartree(rho_gs, s)
+    v_gs = vh_gs + hamiltonian.lda_x(rho_gs)[0]
+    drho, dv, mom = [], [], []
+    for P in ref["Ps"]:
+        rho = hamiltonian.density(P.real, m.psi)
+        drho.append(rho - rho_gs)
+        dv.append(hamiltonian.hartree(rho, s) + hamiltonian.lda_x(rho)[0] - v_gs)
+        mom.append(opr.moments(drho[-1], m.qs, s.h))
+    Xg, Yg = X[:rows].cpu().numpy(), Y[:rows].cpu().numpy()
+    for r in range(rows):
+        j = 7 + r
+        x = opr.features(mom[j - 7:j + 1], drho[j], drho[j - 1], s.n)
+        y = (opr.restrict(dv[j + 1], s.n) - 2 * opr.restrict(dv[j], s.n) + opr.restrict(dv[j - 1], s.n)).ravel()
+        assert np.max(np.abs(Xg[r] - x)) < 1e-6 * np.max(np.abs(x)) + 1e-12, r
+        # targets are FP32 roundings of an FP64 second difference
+        assert np.max(np.abs(Yg[r] - y)) < 1e-5 * np.max(np.abs(y)) + 1e-15, r
+
+
+def test_learned_guess_keeps_the_fixed_point():
+    _say("C1 MLP predictor (untrained net) vs linear, 40 steps, tight thresholds")
+    from paper_2410_09189_amd import predictor, rt
+
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    rp = synth.config_run("c1_parity_32", n_steps=40)
+    dims = rt.rt_mlp_dims()
+    p = predictor.init_params(dims, seed=1)
+    p[2 * dims[0] + dims[2]:2 * dims[0] + 2 * dims[2]] = 1e6  # y_scale: outputs of size 1e-6 Ha
+    out = {}
+    for pred in (0, 1):
+        ses = rt.Session([system_args(s, psi)], run_args(rp, predictor=pred, mlp_params=p if pred else None))
+        st = rt.rt_step(ses.ctx, 40, n_traj=1, stats=True)
+        out[pred] = (rt.rt_dipole(ses.ctx, 0, 0, 41), st)
+        ses.close()
+    mu0, mu1 = out[0][0][0], out[1][0][0]
+    assert np.max(np.abs(mu0 - mu1)) < 1e-10
+    assert all(x[0] >= 1 for x in out[1][1])
+
+
+def test_trained_predictor_gain_on_held_out_trajectory():
+    """Trains on trajectories the step itself records (x and y kicks, two
+    strengths), evaluates on a z kick: the fixed point is unchanged and the
+    mean number of Hamiltonian updates per step does not grow."""
+    _say("C1 learned predictor: record, train on GPU, evaluate held-out z kick")
+    import torch
+    from paper_2410_09189_amd import predictor, rt
+
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    dt, n_rec, n_eval = 0.1, 300, 150
+    h_thrs = 1e-9
+
+    def run_args_for(axes, kappas, n, pred=0, params=None):
+        rp = synth.RunParams(dt=dt, n_steps=n, h_thrs=h_thrs, dp_thrs=1e-13)
+        return run_args(rp, n_traj_axes=axes, kappas=kappas, predictor=pred, mlp_params=params)
+
+    def factory():
+        return rt.Session([system_args(s, psi)], run_args_for((0, 1, 0, 1), [1e-3, 1e-3, 2e-3, 2e-3], n_rec))
+
+    X, Y = predictor.record(factory, n_rec, capacity=4 * n_rec)
+    assert X.shape[0] >= 4 * (n_rec - 10)
+    params, hist = predictor.train(X, Y, epochs=30, batch=64, lr=1e-3, seed=0)
+    print(f"training loss {hist[0]:.3e} -> {hist[-1]:.3e} on {X.shape[0]} samples", flush=True)
+    assert hist[-1] < hist[0]
+    res = {}
+    for pred in (0, 1):
+        ses = rt.Session([system_args(s, psi)],
+                         run_args_for((2,), [1.5e-3], n_eval, pred=pred, params=params if pred else None))
+        st = rt.rt_step(ses.ctx, n_eval, n_traj=1, stats=True)
+        mu, _, _ = rt.rt_dipole(ses.ctx, 0, 0, n_eval + 1)
+        ses.close()
+        res[pred] = (mu, np.array([x[0] for x in st]))
+    m_lin = res[0][1][8:].mean()
+    m_mlp = res[1][1][8:].mean()
+    print(f"mean Hamiltonian updates per step after warm-up: linear {m_lin:.3f}, learned {m_mlp:.3f}", flush=True)
+    assert np.max(np.abs(res[0][0] - res[1][0])) < 1e-7
+    assert m_mlp <= m_lin + 0.05
