@@ -87,6 +87,14 @@ hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
                         unsigned long long* slot, int T, const int* active);
 hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, int T,
                       const int* active);
+// series start: Pout = dP = Pin; Hbar = (H0 + H1)/2 when H0 != nullptr; slots, stop flags and
+// resid (nullable) zeroed; kmin from the Gershgorin width of Hbar
+hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
+                        const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
+                        int stride, int* done, unsigned long long* resid, int T, const int* active);
+// slot[t] = max |a_t - b_t| (atomic max; zeroed beforehand), then b_t = a_t
+hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, unsigned long long* slot, int T,
+                           const int* active);
 // series term k (1-based) for T trajectories: C_t = Hbar_t . [S;A]_t^T (N x 2N), dP_k -> dPn_t,
 // P1_t += dP_k, max |dP_k| -> slots[t][k]; skips trajectories whose series stopped.
 hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, const double* dP, double* C,

@@ -1086,6 +1086,90 @@ hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* 
   return hipGetLastError();
 }
 
+// Start of a series for T trajectories (blockIdx.y = t): Pout = dP = Pin (stacked,
+// 2 N^2 each); when H0 != nullptr also Hbar = (H0 + H1)/2; block 0 of each
+// trajectory zeroes its term slots, stop flags and residual slot and computes
+// kmin = ceil(|dt| (max_i (h_ii + r_i) - min_i (h_ii - r_i))) of Hbar (Gershgorin,
+// r_i = sum_{j != i} |h_ij|), reading (H0 + H1)/2 directly when given.
+__global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__ Pin, double* __restrict__ Pout,
+                                                      double* __restrict__ dP, const double* __restrict__ H0,
+                                                      const double* __restrict__ H1, double* Hbar, int N, double dt,
+                                                      double* kmin, unsigned long long* slots, int stride, int* done,
+                                                      unsigned long long* resid, const int* active) {
+  __shared__ double sh[256];
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  const long NN = (long)N * N;
+  Pin += t * 2 * NN;
+  Pout += t * 2 * NN;
+  dP += t * 2 * NN;
+  Hbar += t * NN;
+  if (H0) {
+    H0 += t * NN;
+    H1 += t * NN;
+  }
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * NN; e += (long)gridDim.x * blockDim.x) {
+    double v = Pin[e];
+    Pout[e] = v;
+    dP[e] = v;
+    if (H0 && e < NN) Hbar[e] = 0.5 * H0[e] + 0.5 * H1[e];
+  }
+  if (blockIdx.x != 0) return;
+  for (int q = threadIdx.x; q < stride; q += 256) slots[(long)t * stride + q] = 0ULL;
+  if (threadIdx.x == 0) {
+    done[2 * t] = 0;
+    done[2 * t + 1] = 0;
+    if (resid) resid[t] = 0ULL;
+  }
+  double hi = -1e300, lo = 1e300;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    double r = 0.0, dgn = 0.0;
+    for (int j = 0; j < N; ++j) {
+      long e = (long)i * N + j;
+      double hv = H0 ? 0.5 * H0[e] + 0.5 * H1[e] : Hbar[e];
+      if (j != i) r += fabs(hv); else dgn = hv;
+    }
+    hi = fmax(hi, dgn + r);
+    lo = fmin(lo, dgn - r);
+  }
+  hi = block_max_256(hi, sh);
+  lo = -block_max_256(-lo, sh);
+  if (threadIdx.x == 0) kmin[t] = ceil(fabs(dt) * (hi - lo));
+}
+hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
+                        const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
+                        int stride, int* done, unsigned long long* resid, int T, const int* active) {
+  long n2 = 2L * N * N;
+  int nb = ew_blocks(n2) > 256 ? 256 : ew_blocks(n2);
+  hipLaunchKernelGGL(k_series_begin, dim3(nb, T), dim3(256), 0, s, Pin, Pout, dP, H0, H1, Hbar, N, dt, kmin, slots,
+                     stride, done, resid, active);
+  return hipGetLastError();
+}
+
+// max_t |a_t - b_t| into slot[t] (zeroed beforehand), then b_t = a_t.
+__global__ __launch_bounds__(256) void k_max_diff_assign(const double* a, double* b, long n, unsigned long long* slot,
+                                                         const int* active) {
+  __shared__ double sh[256];
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  a += t * n;
+  b += t * n;
+  double m = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double x = a[i];
+    m = fmax(m, fabs(x - b[i]));
+    b[i] = x;
+  }
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0) atomic_max_nonneg(slot + t, m);
+}
+hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, unsigned long long* slot, int T,
+                           const int* active) {
+  int nb = ew_blocks(n) > 256 ? 256 : ew_blocks(n);
+  hipLaunchKernelGGL(k_max_diff_assign, dim3(nb, T), dim3(256), 0, s, a, b, n, slot, active);
+  return hipGetLastError();
+}
+
 // dP_k = (1/k)(-i dt)[Hbar, S + iA]:  S_k = (dt/k)[Hbar, A],  A_k = -(dt/k)[Hbar, S].
 // C = Hbar . [S; A]^T, so C[:, :N] = Hbar S and C[:, N:] = -Hbar A (S symmetric, A antisymmetric).
 // blockIdx.y = trajectory; C, dPn, P1 have stride 2 N^2.

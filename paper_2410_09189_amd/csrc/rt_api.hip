@@ -610,7 +610,8 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
 // T slots starting at the given buffers (stacked [S; A], stride 2 N^2).  flags/scratch
 // (kmin, slots, done, dP, dPn, C) are the system's, offset by `first`.
 rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const std::vector<int>& act_host,
-                 const double* Hbar, double dt, const double* Pin, double* Pout, std::vector<int>& terms) {
+                 const double* Hbar, double dt, const double* Pin, double* Pout, std::vector<int>& terms,
+                 const double* H0 = nullptr, const double* H1 = nullptr, unsigned long long* resid = nullptr) {
   hipStream_t s = c->stream;
   const long NN = nsq(d.N), n2 = 2 * NN;
   const int max_terms = c->run.max_terms;
@@ -622,11 +623,11 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
   double* kmin = d.kmin + first;
   unsigned long long* slots = d.slots + (long)first * stride;
   int* done = d.done + 2 * first;
-  CK(rtk::copy_masked(s, Pout, Pin, n2, T, act));
-  CK(rtk::copy_masked(s, dP, Pin, n2, T, act));
-  CK(rtk::gershgorin(s, Hbar, d.N, dt, kmin, T, act));
-  CK(rtk::fill_u64(s, slots, (long)T * stride, 0ULL));
-  CK(hipMemcpyAsync(done, d.zeros2T.data(), 2 * T * sizeof(int), hipMemcpyHostToDevice, s));
+  {
+    Timed tm(c, PH_SMALL);
+    CK(rtk::series_begin(s, Pin, Pout, dP, H0, H1, const_cast<double*>(Hbar), d.N, dt, kmin, slots, stride, done,
+                         resid, T, act));
+  }
   int k = 1;
   const int CH = 8;
   std::vector<int> hd(2 * T);
@@ -827,13 +828,13 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   std::vector<unsigned long long> bits(T);
   int n_active = T;
   for (int m = 1; m <= run.max_scf && n_active > 0; ++m) {
-    CK(rtk::lincomb(st, d.Hbar, 0.5, d.H0, 0.5, d.H1, T * NN));
     std::vector<int> terms;
-    RET(series(c, d, 0, T, d.active, d.active_host, d.Hbar, run.dt, d.P0, d.P1, terms));
+    RET(series(c, d, 0, T, d.active, d.active_host, d.Hbar, run.dt, d.P0, d.P1, terms, d.H0, d.H1, d.resid));
     RET(eval_h(c, d, T, d.active, d.active_host, d.P1, 2 * NN, d.Hn, false));
-    CK(rtk::fill_u64(st, d.resid, T, 0ULL));
-    CK(rtk::max_abs_diff(st, d.Hn, d.H1, NN, d.resid, T, d.active));
-    CK(rtk::copy_masked(st, d.H1, d.Hn, NN, T, d.active));
+    {
+      Timed tm(c, PH_SMALL);
+      CK(rtk::max_diff_assign(st, d.Hn, d.H1, NN, d.resid, T, d.active));
+    }
     CK(hipMemcpyAsync(bits.data(), d.resid, T * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     bool changed = false;
