@@ -50,29 +50,68 @@ hipError_t split_bf16(hipStream_t s, const double* x, unsigned short* hi, unsign
   return hipGetLastError();
 }
 
-// W_ij = (S_ij - S0_ij) * (2 if i < j, 1 if i == j, 0 if i > j), split to bf16 hi/lo.
-// blockIdx.y = trajectory: S_t = S + t sstride, hi/lo_t = + t N^2, S0 shared.
+// W_ij = (S_ij - S0_ij) * (2 if i < j, 1 if i == j, 0 if i > j), split to bf16 hi/lo,
+// stored with leading dimension ld >= N (rows and columns N..ld-1 zero).
+// blockIdx.y = trajectory: S_t = S + t sstride, hi/lo_t = + t ld^2, S0 shared.
 __global__ void k_upper_weighted_delta_bf16(const double* S, const double* S0, unsigned short* hi,
-                                            unsigned short* lo, int N, long sstride, const int* active) {
+                                            unsigned short* lo, int N, int ld, long sstride, const int* active) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)N * N) return;
+  if (e >= (long)ld * ld) return;
   S += t * sstride;
-  hi += t * (long)N * N;
-  lo += t * (long)N * N;
-  int i = (int)(e / N), j = (int)(e - (long)i * N);
-  double w = i < j ? 2.0 * (S[e] - S0[e]) : (i == j ? S[e] - S0[e] : 0.0);
+  hi += t * (long)ld * ld;
+  lo += t * (long)ld * ld;
+  int i = (int)(e / ld), j = (int)(e - (long)i * ld);
+  double w = 0.0;
+  if (i < N && j < N) {
+    long f = (long)i * N + j;
+    w = i < j ? 2.0 * (S[f] - S0[f]) : (i == j ? S[f] - S0[f] : 0.0);
+  }
   unsigned short h = f2bf((float)w);
   hi[e] = h;
   lo[e] = f2bf((float)(w - (double)bf2f(h)));
 }
 
 hipError_t upper_weighted_delta_bf16(hipStream_t s, const double* S, const double* S0, unsigned short* hi,
-                                     unsigned short* lo, int N, long sstride, int T, const int* active) {
-  long n = (long)N * N;
-  hipLaunchKernelGGL(k_upper_weighted_delta_bf16, dim3(cdivm(n, 256), T), dim3(256), 0, s, S, S0, hi, lo, N,
+                                     unsigned short* lo, int N, int ld, long sstride, int T, const int* active) {
+  long n = (long)ld * ld;
+  hipLaunchKernelGGL(k_upper_weighted_delta_bf16, dim3(cdivm(n, 256), T), dim3(256), 0, s, S, S0, hi, lo, N, ld,
                      sstride, active);
+  return hipGetLastError();
+}
+
+// Point-major split of the orbitals: hiT/loT[r][j] (pitch ld) = bf16 hi/lo of psi[j][r]
+// for j < N, zero for N <= j < ld.  64-point x 32-orbital tiles transposed through LDS.
+__global__ __launch_bounds__(256) void k_split_bf16_t(const double* __restrict__ psi, unsigned short* __restrict__ hiT,
+                                                      unsigned short* __restrict__ loT, int N, int ld, long ng) {
+  __shared__ unsigned short sh[32][66], sl[32][66];
+  const long p0 = (long)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 32, tid = threadIdx.x;
+  for (int e = tid; e < 32 * 64; e += 256) {
+    int jj = e >> 6, pp = e & 63;
+    int j = j0 + jj;
+    long r = p0 + pp;
+    double v = (j < N && r < ng) ? psi[(long)j * ng + r] : 0.0;
+    unsigned short h = f2bf((float)v);
+    sh[jj][pp] = h;
+    sl[jj][pp] = f2bf((float)(v - (double)bf2f(h)));
+  }
+  __syncthreads();
+  for (int e = tid; e < 32 * 64; e += 256) {
+    int pp = e >> 5, jj = e & 31;
+    long r = p0 + pp;
+    if (r < ng) {
+      hiT[r * ld + j0 + jj] = sh[jj][pp];
+      loT[r * ld + j0 + jj] = sl[jj][pp];
+    }
+  }
+}
+
+hipError_t split_bf16_t(hipStream_t s, const double* psi, unsigned short* hiT, unsigned short* loT, int N, int ld,
+                        long ng) {
+  if (ld % 32 || ld < N) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split_bf16_t, dim3(cdivm(ng, 64), ld / 32), dim3(256), 0, s, psi, hiT, loT, N, ld, ng);
   return hipGetLastError();
 }
 
@@ -241,12 +280,13 @@ __global__ __launch_bounds__(256) void k_density_bf16x3(int N, long ng, const un
                                                         const unsigned short* __restrict__ Phi_,
                                                         const unsigned short* __restrict__ Plo_,
                                                         const double* __restrict__ rho0,
-                                                        double* __restrict__ rho, int T, const int* active) {
+                                                        double* __restrict__ rho, int T, const int* active,
+                                                        int ld) {
   constexpr int BM = 64, BN = 64, BK = 32, PD = 8;
   const int tb = blockIdx.x % T;
   if (active && !active[tb]) return;
-  Whi += (long)tb * N * N;
-  Wlo += (long)tb * N * N;
+  Whi += (long)tb * ld * ld;
+  Wlo += (long)tb * ld * ld;
   rho += (long)tb * ng;
   __shared__ unsigned short sWh[BM][BK + PD], sWl[BM][BK + PD];
   __shared__ unsigned short sPh[BN][BK + PD], sPl[BN][BK + PD];
@@ -267,8 +307,8 @@ __global__ __launch_bounds__(256) void k_density_bf16x3(int N, long ng, const un
         int r = e / BK, c = e - r * BK;
         int gi = I * BM + r, gj = jb + c;
         bool ok = gi < N && gj < N;
-        sWh[r][c] = ok ? Whi[(long)gi * N + gj] : (unsigned short)0;
-        sWl[r][c] = ok ? Wlo[(long)gi * N + gj] : (unsigned short)0;
+        sWh[r][c] = ok ? Whi[(long)gi * ld + gj] : (unsigned short)0;
+        sWl[r][c] = ok ? Wlo[(long)gi * ld + gj] : (unsigned short)0;
       }
       for (int e = tid; e < BK * BN; e += 256) {
         int kj = e / BN, c = e - kj * BN;
@@ -328,11 +368,152 @@ __global__ __launch_bounds__(256) void k_density_bf16x3(int N, long ng, const un
   }
 }
 
+// Resident-tile density for N <= 256.  One block owns BN grid points and every
+// trajectory: the point-major hi/lo orbital tile [BN][NP] (NP = N rounded up to 32,
+// zero padded) is loaded into LDS once; for each trajectory Z = W Psi_tile is
+// accumulated on the matrix cores with W (upper triangular, leading dimension NP)
+// read as A fragments straight from L2, j-chunks of 32 outermost so each B fragment
+// read from LDS serves all of a wave's row blocks, triangular blocks skipped; then
+// rho_t = rho0 + sum_i psi_i Z_i with psi_i again from the LDS tile.
+// Waves: 4 row groups x WP point groups; row group g owns the 16-row blocks
+// g, 7-g, 8+g, 15-g, which balances the triangular work.
+template <int BN, int WP>
+__global__ __launch_bounds__(256 * WP) void k_density_tile(int NP, long ng, const unsigned short* __restrict__ whi,
+                                                           const unsigned short* __restrict__ wlo,
+                                                           const unsigned short* __restrict__ pth,
+                                                           const unsigned short* __restrict__ ptl,
+                                                           const double* __restrict__ rho0,
+                                                           double* __restrict__ rho, int T, const int* active) {
+  constexpr int LDP = 256 + 8;  // LDS row pitch (bf16)
+  constexpr int RB = 4, PC = BN / 16 / WP, NTH = 256 * WP;
+  __shared__ __attribute__((aligned(16))) unsigned short sT[2][BN][LDP];
+  __shared__ float red[4][BN];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 3, wp = wave >> 2;
+  const long p0 = (long)blockIdx.x * BN;
+  const int c8 = NP >> 3;
+  for (int e = tid; e < BN * c8; e += NTH) {
+    int row = e / c8, q = e - row * c8;
+    long r = p0 + row;
+    uint4 vh = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
+    if (r < ng) {
+      vh = *reinterpret_cast<const uint4*>(pth + r * NP + 8 * q);
+      vl = *reinterpret_cast<const uint4*>(ptl + r * NP + 8 * q);
+    }
+    *reinterpret_cast<uint4*>(&sT[0][row][8 * q]) = vh;
+    *reinterpret_cast<uint4*>(&sT[1][row][8 * q]) = vl;
+  }
+  __syncthreads();
+  const int NB = NP >> 4, NC = NP >> 5;
+  int Ib[RB] = {wr, 7 - wr, 8 + wr, 15 - wr};
+  const int kq = 8 * (lane >> 4), l16 = lane & 15;
+  const int pb = wp * (BN / WP);
+  for (int t = 0; t < T; ++t) {
+    if (active && !active[t]) continue;
+    const unsigned short* Wh = whi + (long)t * NP * NP;
+    const unsigned short* Wl = wlo + (long)t * NP * NP;
+    f32x4 acc[RB][PC];
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+#pragma unroll
+      for (int p = 0; p < PC; ++p) acc[k][p] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    bf16x8 ah[RB], al[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      ah[k] = (bf16x8){};
+      al[k] = (bf16x8){};
+      if (Ib[k] <= 1 && Ib[k] < NB) {
+        long off = (long)(16 * Ib[k] + l16) * NP + kq;
+        ah[k] = *reinterpret_cast<const bf16x8*>(Wh + off);
+        al[k] = *reinterpret_cast<const bf16x8*>(Wl + off);
+      }
+    }
+    for (int c = 0; c < NC; ++c) {
+      bf16x8 nh[RB], nl[RB];
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        nh[k] = (bf16x8){};
+        nl[k] = (bf16x8){};
+        if (c + 1 < NC && Ib[k] <= 2 * c + 3 && Ib[k] < NB) {
+          long off = (long)(16 * Ib[k] + l16) * NP + 32 * (c + 1) + kq;
+          nh[k] = *reinterpret_cast<const bf16x8*>(Wh + off);
+          nl[k] = *reinterpret_cast<const bf16x8*>(Wl + off);
+        }
+      }
+      bf16x8 bh[PC], bl[PC];
+#pragma unroll
+      for (int p = 0; p < PC; ++p) {
+        int pt = pb + 16 * p + l16;
+        bh[p] = *reinterpret_cast<const bf16x8*>(&sT[0][pt][32 * c + kq]);
+        bl[p] = *reinterpret_cast<const bf16x8*>(&sT[1][pt][32 * c + kq]);
+      }
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        if (Ib[k] > 2 * c + 1 || Ib[k] >= NB) continue;
+#pragma unroll
+        for (int p = 0; p < PC; ++p) {
+          acc[k][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[k], bh[p], acc[k][p], 0, 0, 0);
+          acc[k][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[k], bl[p], acc[k][p], 0, 0, 0);
+          acc[k][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[k], bh[p], acc[k][p], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        ah[k] = nh[k];
+        al[k] = nl[k];
+      }
+    }
+    float part[PC];
+#pragma unroll
+    for (int p = 0; p < PC; ++p) part[p] = 0.f;
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      if (Ib[k] >= NB) continue;
+      const int i0 = 16 * Ib[k] + 4 * (lane >> 4);
+#pragma unroll
+      for (int p = 0; p < PC; ++p) {
+        int pt = pb + 16 * p + l16;
+        uint2 hh = *reinterpret_cast<const uint2*>(&sT[0][pt][i0]);
+        uint2 ll = *reinterpret_cast<const uint2*>(&sT[1][pt][i0]);
+        float v0 = __uint_as_float(hh.x << 16) + __uint_as_float(ll.x << 16);
+        float v1 = __uint_as_float(hh.x & 0xFFFF0000u) + __uint_as_float(ll.x & 0xFFFF0000u);
+        float v2 = __uint_as_float(hh.y << 16) + __uint_as_float(ll.y << 16);
+        float v3 = __uint_as_float(hh.y & 0xFFFF0000u) + __uint_as_float(ll.y & 0xFFFF0000u);
+        part[p] += v0 * acc[k][p][0] + v1 * acc[k][p][1] + v2 * acc[k][p][2] + v3 * acc[k][p][3];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PC; ++p) {
+      part[p] += __shfl_xor(part[p], 16);
+      part[p] += __shfl_xor(part[p], 32);
+      if (lane < 16) red[wr][pb + 16 * p + lane] = part[p];
+    }
+    __syncthreads();
+    for (int x = tid; x < BN; x += NTH) {
+      long r = p0 + x;
+      if (r < ng) {
+        double a = (double)red[0][x] + (double)red[1][x] + (double)red[2][x] + (double)red[3][x];
+        rho[(long)t * ng + r] = rho0[r] + a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+int density_tile_ld(int N) { return N <= 256 ? (N + 31) / 32 * 32 : N; }
+
 hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* whi, const unsigned short* wlo,
-                          const unsigned short* phi, const unsigned short* plo, const double* rho0,
-                          double* rho, int T, const int* active) {
+                          const unsigned short* phi, const unsigned short* plo, const unsigned short* pthi,
+                          const unsigned short* ptlo, const double* rho0, double* rho, int T, const int* active) {
+  if (N <= 256) {
+    if (!pthi || !ptlo) return hipErrorInvalidValue;
+    const int NP = density_tile_ld(N);
+    hipLaunchKernelGGL((k_density_tile<128, 2>), dim3(cdivm(ng, 128)), dim3(512), 0, s, NP, ng, whi, wlo, pthi,
+                       ptlo, rho0, rho, T, active);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_density_bf16x3, dim3(cdivm(ng, 64) * T), dim3(256), 0, s, N, ng, whi, wlo, phi, plo, rho0,
-                     rho, T, active);
+                     rho, T, active, N);
   return hipGetLastError();
 }
 

@@ -151,6 +151,8 @@ struct SysDev {
   double *rho, *vh, *vx, *vloc, *dv, *eparts, *W, *part;
   // mixed precision: orbitals and density weights as bf16 hi/lo, FP64 ground-state references
   unsigned short *psi_hi, *psi_lo, *w_hi, *w_lo;
+  unsigned short *psiT_hi = nullptr, *psiT_lo = nullptr;  // point-major [ng][wld] (N <= 256)
+  int wld = 0;                                           // leading dimension of the W split
   double *rho_gs, *S_gs;
   float *dv32, *part32;
   // per-trajectory state [T][...]
@@ -394,8 +396,14 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     if (d.mixed) {
       d.psi_hi = a.take<unsigned short>(N * ng);
       d.psi_lo = a.take<unsigned short>(N * ng);
-      d.w_hi = a.take<unsigned short>(T * NN);
-      d.w_lo = a.take<unsigned short>(T * NN);
+      d.wld = rtk::density_tile_ld(d.N);
+      const long WW = (long)d.wld * d.wld;
+      d.w_hi = a.take<unsigned short>(T * WW);
+      d.w_lo = a.take<unsigned short>(T * WW);
+      if (d.N <= 256) {
+        d.psiT_hi = a.take<unsigned short>(ng * d.wld);
+        d.psiT_lo = a.take<unsigned short>(ng * d.wld);
+      }
       d.rho_gs = a.take<double>(ng);
       d.S_gs = a.take<double>(NN);
       d.dv32 = a.take<float>(T * ng);
@@ -566,8 +574,9 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
   {
     Timed tm(c, PH_DENSITY);
     if (mixed) {
-      CK(rtk::upper_weighted_delta_bf16(s, S, d.S_gs, d.w_hi, d.w_lo, d.N, sstride, T, act));
-      CK(rtk::density_bf16x3(s, d.N, d.ng, d.w_hi, d.w_lo, d.psi_hi, d.psi_lo, d.rho_gs, d.rho, T, act));
+      CK(rtk::upper_weighted_delta_bf16(s, S, d.S_gs, d.w_hi, d.w_lo, d.N, d.wld, sstride, T, act));
+      CK(rtk::density_bf16x3(s, d.N, d.ng, d.w_hi, d.w_lo, d.psi_hi, d.psi_lo, d.psiT_hi, d.psiT_lo, d.rho_gs,
+                             d.rho, T, act));
     } else {
       CK(rtk::upper_weighted(s, S, d.W, d.N, sstride, T, act));
       CK(rtk::smalltall_f64(s, d.N, d.ng, d.W, d.psi, d.rho, 1, 1, T, act));
@@ -778,6 +787,7 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
     CK(rtk::copy_d(st, d.rho_gs, d.rho, d.ng));
     CK(rtk::copy_d(st, d.S_gs, d.tmp, NN));
     CK(rtk::split_bf16(st, d.psi, d.psi_hi, d.psi_lo, N * ng));
+    if (d.psiT_hi) CK(rtk::split_bf16_t(st, d.psi, d.psiT_hi, d.psiT_lo, (int)N, d.wld, ng));
   }
   // trajectories: P_0 = diag(f), then each slot's kick through the series
   std::vector<double> p0((long)d.T * 2 * NN, 0.0);

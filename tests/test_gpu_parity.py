@@ -216,12 +216,16 @@ def test_c1_three_kicks_and_bitwise_determinism():
 MIXED_REL = 1e-4
 
 
-def test_mixed_eval_h_error_is_relative_to_the_perturbation():
-    _say("mixed eval_h 36x40x32 N=20")
+# N = 20, 100 and 250 cover one, several and all sixteen 16-row blocks of the
+# resident-tile density kernel (orbitals zero padded to 32, 128 and 256); the
+# 36 x 40 x 30 grid leaves a ragged last 128-point tile.
+@pytest.mark.parametrize("n,n_orb", [((36, 40, 32), 20), ((36, 40, 30), 100), ((36, 40, 30), 250)])
+def test_mixed_eval_h_error_is_relative_to_the_perturbation(n, n_orb):
+    _say(f"mixed eval_h {n} N={n_orb}")
     torch = _torch()
     from paper_2410_09189_amd import rt
 
-    s, psi = _ragged_system(seed=12)
+    s, psi = _ragged_system(seed=12, n=n, n_orb=n_orb)
     rp = synth.RunParams(dt=0.05, n_steps=2)
     ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp, precision=rt.RT_MIXED, hupdate=1))
     m = oracle.Model(s, orthonormalize_np(s, psi))
