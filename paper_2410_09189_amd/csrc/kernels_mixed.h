@@ -6,15 +6,18 @@ namespace rtk {
 
 // hi = bf16(x), lo = bf16(x - hi)
 hipError_t split_bf16(hipStream_t s, const double* x, unsigned short* hi, unsigned short* lo, long n);
-// upper-weighted (S - S0) split to bf16 hi/lo (density weights of the change), leading dimension ld
+// upper-weighted (S - S0) split to bf16 hi/lo (density weights of the change), padded to ld;
+// frag = 1 stores 32x32x16 A-fragment order (ld % 32 == 0), frag = 0 row-major
 hipError_t upper_weighted_delta_bf16(hipStream_t s, const double* S, const double* S0, unsigned short* hi,
-                                     unsigned short* lo, int N, int ld, long sstride, int T, const int* active);
+                                     unsigned short* lo, int N, int ld, long sstride, int T, const int* active,
+                                     int frag);
 // point-major split: hiT/loT[r][j] (pitch ld, multiple of 32, zero for j >= N) of psi[j][r]
 hipError_t split_bf16_t(hipStream_t s, const double* psi, unsigned short* hiT, unsigned short* loT, int N, int ld,
                         long ng);
 // leading dimension of the density weights and point-major orbitals for N orbitals
 int density_tile_ld(int N);
-// part[s] (FP32, N x N, upper tiles) = sum_k A[m][k] w[k] A[n][k]; requires ng % 8 == 0
+// part[s] (FP32, N x N, upper tiles) = sum_k A[m][k] w[k] A[n][k] over K split s of kps
+// points; requires ng % 8 == 0, kps % 64 == 0 and 256 ng < 2^31
 hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, const unsigned short* lo,
                        const float* w, float* part, long kps, int n_split, int T, const int* active);
 // C = base + alpha * sum_s part[s] (upper kept, mirrored)

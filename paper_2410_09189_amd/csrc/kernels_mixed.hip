@@ -51,10 +51,14 @@ hipError_t split_bf16(hipStream_t s, const double* x, unsigned short* hi, unsign
 }
 
 // W_ij = (S_ij - S0_ij) * (2 if i < j, 1 if i == j, 0 if i > j), split to bf16 hi/lo,
-// stored with leading dimension ld >= N (rows and columns N..ld-1 zero).
-// blockIdx.y = trajectory: S_t = S + t sstride, hi/lo_t = + t ld^2, S0 shared.
+// padded to ld >= N (rows and columns N..ld-1 zero).  blockIdx.y = trajectory:
+// S_t = S + t sstride, hi/lo_t = + t ld^2, S0 shared.
+// frag = 0: row-major [ld][ld].  frag = 1 (ld % 32 == 0): 32x32x16 A-fragment order,
+// one contiguous 64-lane x 8 block per (32-row block I, 16-column step c):
+//   offset = ((I (ld/16) + c) 64 + (i % 32) + 32 ((j % 16) / 8)) 8 + j % 8.
 __global__ void k_upper_weighted_delta_bf16(const double* S, const double* S0, unsigned short* hi,
-                                            unsigned short* lo, int N, int ld, long sstride, const int* active) {
+                                            unsigned short* lo, int N, int ld, long sstride, const int* active,
+                                            int frag) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -69,15 +73,19 @@ __global__ void k_upper_weighted_delta_bf16(const double* S, const double* S0, u
     w = i < j ? 2.0 * (S[f] - S0[f]) : (i == j ? S[f] - S0[f] : 0.0);
   }
   unsigned short h = f2bf((float)w);
-  hi[e] = h;
-  lo[e] = f2bf((float)(w - (double)bf2f(h)));
+  long o = e;
+  if (frag) o = (((long)(i >> 5) * (ld >> 4) + (j >> 4)) * 64 + (i & 31) + 32 * ((j & 15) >> 3)) * 8 + (j & 7);
+  hi[o] = h;
+  lo[o] = f2bf((float)(w - (double)bf2f(h)));
 }
 
 hipError_t upper_weighted_delta_bf16(hipStream_t s, const double* S, const double* S0, unsigned short* hi,
-                                     unsigned short* lo, int N, int ld, long sstride, int T, const int* active) {
+                                     unsigned short* lo, int N, int ld, long sstride, int T, const int* active,
+                                     int frag) {
+  if (frag && ld % 32) return hipErrorInvalidValue;
   long n = (long)ld * ld;
   hipLaunchKernelGGL(k_upper_weighted_delta_bf16, dim3(cdivm(n, 256), T), dim3(256), 0, s, S, S0, hi, lo, N, ld,
-                     sstride, active);
+                     sstride, active, frag);
   return hipGetLastError();
 }
 
@@ -126,72 +134,119 @@ hipError_t split_bf16_t(hipStream_t s, const double* psi, unsigned short* hiT, u
 // ---------------------------------------------------------------------------
 constexpr int XB = 128, XK = 64, XPAD = 8;
 
-__global__ __launch_bounds__(256) void k_proj_bf16x3(int N, long ng, const unsigned short* __restrict__ Ahi,
-                                                     const unsigned short* __restrict__ Alo,
-                                                     const float* __restrict__ w, float* __restrict__ part,
-                                                     long kps, int ntm, int T, const int* active) {
-  __shared__ unsigned short sAh[XB][XK + XPAD], sAl[XB][XK + XPAD];
-  __shared__ unsigned short sBh[XB][XK + XPAD], sBl[XB][XK + XPAD];
-  const int tb = blockIdx.x % T;
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2) in
+// linear-id order.  Logical id = position in a contiguous per-XCD range, so blocks
+// with neighbouring logical ids (here: the tile pairs and trajectories that read
+// the same chunk of grid points) run on one XCD and share its L2.
+__device__ __forceinline__ long xcd_logical(long h, long nblk) {
+  const long full = nblk / 8 * 8;
+  return h < full ? (h % 8) * (full / 8) + h / 8 : h;
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// (hi + lo) * w of two packed bf16 pairs, re-split to packed bf16 hi/lo (round to
+// nearest even on the hardware converter).
+__device__ __forceinline__ void split_scaled2(unsigned int h, unsigned int l, float w0, float w1, unsigned int& oh,
+                                              unsigned int& ol) {
+  float x0 = (__uint_as_float(h << 16) + __uint_as_float(l << 16)) * w0;
+  float x1 = (__uint_as_float(h & 0xFFFF0000u) + __uint_as_float(l & 0xFFFF0000u)) * w1;
+  bf16x2 hp = {(__bf16)x0, (__bf16)x1};
+  bf16x2 lp = {(__bf16)(x0 - (float)hp[0]), (__bf16)(x1 - (float)hp[1])};
+  oh = __builtin_bit_cast(unsigned int, hp);
+  ol = __builtin_bit_cast(unsigned int, lp);
+}
+
+// Raw buffer resource over [base, base + bytes): loads at offsets >= bytes return 0.
+// Word 3 is the gfx9 raw-buffer format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ uint4 buf_ld16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+// Projection kernel: per thread one 32-bit row offset for the whole loop (the K
+// position rides in the scalar offset of buffer loads), rows >= N read as zero
+// through the resource bound, the weights fetched once per K chunk (all four
+// vectors a thread stages share its K columns), the next chunk in flight in
+// registers during the MFMAs, XCD-aware block order.  Needs 256 ng < 2^31.
+__global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const unsigned short* __restrict__ Ahi,
+                                                        const unsigned short* __restrict__ Alo,
+                                                        const float* __restrict__ w, float* __restrict__ part,
+                                                        long kps, int ntm, int T, const int* active) {
+  __shared__ __attribute__((aligned(16))) unsigned short sAh[XB][XK + XPAD], sAl[XB][XK + XPAD];
+  __shared__ __attribute__((aligned(16))) unsigned short sBh[XB][XK + XPAD], sBl[XB][XK + XPAD];
+  const long h = blockIdx.x + (long)gridDim.x * blockIdx.y;
+  const long lid = xcd_logical(h, (long)gridDim.x * gridDim.y);
+  const int bx = (int)(lid % gridDim.x), by = (int)(lid / gridDim.x);
+  const int tb = bx % T;
   if (active && !active[tb]) return;
-  w += (long)tb * ng;
   part += (long)tb * gridDim.y * N * N;
   int tm = 0, tn;
   {
-    int t = blockIdx.x / T, rowlen = ntm;
+    int t = bx / T, rowlen = ntm;
     while (t >= rowlen) { t -= rowlen; ++tm; --rowlen; }
     tn = tm + t;
   }
-  const long k0 = (long)blockIdx.y * kps;
+  const long k0 = (long)by * kps;
   const long k1 = min(ng, k0 + kps);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
+  const long m0 = (long)tm * XB, n0 = (long)tn * XB;
+  const long va = min((long)XB, N - m0), vb = min((long)XB, N - n0);
+  const auto rAh = buf_rsrc(Ahi + m0 * ng + k0, (int)((va * ng - k0) * 2));
+  const auto rAl = buf_rsrc(Alo + m0 * ng + k0, (int)((va * ng - k0) * 2));
+  const auto rBh = buf_rsrc(Ahi + n0 * ng + k0, (int)((vb * ng - k0) * 2));
+  const auto rBl = buf_rsrc(Alo + n0 * ng + k0, (int)((vb * ng - k0) * 2));
+  const auto rW = buf_rsrc(w + (long)tb * ng + k0, (int)((ng - k0) * 4));
+  const int c8 = (tid & 7) * 8, r0 = tid >> 3;  // vector u covers row r0 + 32 u, columns c8..c8+7
+  int vo[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) vo[u] = (int)(((long)(r0 + 32 * u) * ng + c8) * 2);
+  uint4 rah[4], ral[4], rbh[4], rbl[4];
+  uint4 rw0, rw1;
+  auto fetch = [&](long kb) {
+    const int so = (int)((kb - k0) * 2);
+    int v[4];
+    const bool tail = kb + XK > k1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (tail && kb + c8 >= k1) ? (int)0x80000000 : vo[u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      rah[u] = buf_ld16(rAh, v[u], so);
+      ral[u] = buf_ld16(rAl, v[u], so);
+      rbh[u] = buf_ld16(rBh, v[u], so);
+      rbl[u] = buf_ld16(rBl, v[u], so);
+    }
+    rw0 = buf_ld16(rW, c8 * 4, 2 * so);
+    rw1 = buf_ld16(rW, c8 * 4 + 16, 2 * so);
+  };
   f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const long m0 = (long)tm * XB, n0 = (long)tn * XB;
+  fetch(k0);
   for (long kb = k0; kb < k1; kb += XK) {
-    // 128 rows x 64 k = 1024 vectors of 8 bf16 per array
-    for (int v = tid; v < XB * XK / 8; v += 256) {
-      int r = v >> 3, c8 = (v & 7) * 8;
-      long gk = kb + c8;
-      long ga = m0 + r, gb = n0 + r;
-      uint4 ah = make_uint4(0, 0, 0, 0), al = ah, bh = ah, bl = ah;
-      if (gk + 8 <= k1) {
-        if (ga < N) {
-          ah = *reinterpret_cast<const uint4*>(Ahi + ga * ng + gk);
-          al = *reinterpret_cast<const uint4*>(Alo + ga * ng + gk);
-        }
-        if (gb < N) {
-          uint4 xh = *reinterpret_cast<const uint4*>(Ahi + gb * ng + gk);
-          uint4 xl = *reinterpret_cast<const uint4*>(Alo + gb * ng + gk);
-          const unsigned short* ph = reinterpret_cast<const unsigned short*>(&xh);
-          const unsigned short* pl = reinterpret_cast<const unsigned short*>(&xl);
-          unsigned short oh[8], ol[8];
+    const float w0 = __uint_as_float(rw0.x), w1 = __uint_as_float(rw0.y), w2 = __uint_as_float(rw0.z),
+                w3 = __uint_as_float(rw0.w), w4 = __uint_as_float(rw1.x), w5 = __uint_as_float(rw1.y),
+                w6 = __uint_as_float(rw1.z), w7 = __uint_as_float(rw1.w);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) split2((bf2f(ph[q]) + bf2f(pl[q])) * w[gk + q], oh[q], ol[q]);
-          bh = *reinterpret_cast<uint4*>(oh);
-          bl = *reinterpret_cast<uint4*>(ol);
-        }
-      } else if (gk < k1) {
-        unsigned short th[8] = {0}, tl[8] = {0}, uh[8] = {0}, ul[8] = {0};
-        for (int q = 0; q < 8 && gk + q < k1; ++q) {
-          if (ga < N) { th[q] = Ahi[ga * ng + gk + q]; tl[q] = Alo[ga * ng + gk + q]; }
-          if (gb < N) split2((bf2f(Ahi[gb * ng + gk + q]) + bf2f(Alo[gb * ng + gk + q])) * w[gk + q], uh[q], ul[q]);
-        }
-        ah = *reinterpret_cast<uint4*>(th);
-        al = *reinterpret_cast<uint4*>(tl);
-        bh = *reinterpret_cast<uint4*>(uh);
-        bl = *reinterpret_cast<uint4*>(ul);
-      }
-      *reinterpret_cast<uint4*>(&sAh[r][c8]) = ah;
-      *reinterpret_cast<uint4*>(&sAl[r][c8]) = al;
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 32 * u;
+      *reinterpret_cast<uint4*>(&sAh[r][c8]) = rah[u];
+      *reinterpret_cast<uint4*>(&sAl[r][c8]) = ral[u];
+      uint4 bh, bl;
+      split_scaled2(rbh[u].x, rbl[u].x, w0, w1, bh.x, bl.x);
+      split_scaled2(rbh[u].y, rbl[u].y, w2, w3, bh.y, bl.y);
+      split_scaled2(rbh[u].z, rbl[u].z, w4, w5, bh.z, bl.z);
+      split_scaled2(rbh[u].w, rbl[u].w, w6, w7, bh.w, bl.w);
       *reinterpret_cast<uint4*>(&sBh[r][c8]) = bh;
       *reinterpret_cast<uint4*>(&sBl[r][c8]) = bl;
     }
     __syncthreads();
+    if (kb + XK < k1) fetch(kb + XK);
 #pragma unroll
     for (int kk = 0; kk < XK; kk += 32) {
       bf16x8 fah[4], fal[4], fbh[4], fbl[4];
@@ -219,7 +274,7 @@ __global__ __launch_bounds__(256) void k_proj_bf16x3(int N, long ng, const unsig
     }
     __syncthreads();
   }
-  float* P = part + (long)blockIdx.y * N * N;
+  float* P = part + (long)by * N * N;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -232,8 +287,19 @@ __global__ __launch_bounds__(256) void k_proj_bf16x3(int N, long ng, const unsig
       }
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Fragment layout of v_mfma_f32_32x32x16_bf16: lane l holds row (A) / column (B)
+// l & 31 and k = 8 (l >> 5) .. 8 (l >> 5) + 7; result register r of lane l is
+// row 8 (r >> 2) + 4 (l >> 5) + (r & 3), column l & 31.  It retires twice the
+// products of the 16x16x32 form per issue cycle.
+__device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
 hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, const unsigned short* lo,
                        const float* w, float* part, long kps, int n_split, int T, const int* active) {
+  if (ng % 8 || 256 * ng >= (1L << 31) || kps % XK) return hipErrorInvalidValue;
   int ntm = cdivm(N, XB);
   int nt = ntm * (ntm + 1) / 2;
   hipLaunchKernelGGL(k_proj_bf16x3, dim3(nt * T, n_split), dim3(256), 0, s, N, ng, hi, lo, w, part, kps, ntm, T,
@@ -371,96 +437,132 @@ __global__ __launch_bounds__(256) void k_density_bf16x3(int N, long ng, const un
 // Resident-tile density for N <= 256.  One block owns BN grid points and every
 // trajectory: the point-major hi/lo orbital tile [BN][NP] (NP = N rounded up to 32,
 // zero padded) is loaded into LDS once; for each trajectory Z = W Psi_tile is
-// accumulated on the matrix cores with W (upper triangular, leading dimension NP)
-// read as A fragments straight from L2, j-chunks of 32 outermost so each B fragment
-// read from LDS serves all of a wave's row blocks, triangular blocks skipped; then
-// rho_t = rho0 + sum_i psi_i Z_i with psi_i again from the LDS tile.
-// Waves: 4 row groups x WP point groups; row group g owns the 16-row blocks
-// g, 7-g, 8+g, 15-g, which balances the triangular work.
+// accumulated with 32x32x16 matrix instructions, W (upper triangular, stored in
+// A-fragment order) read straight from L2, j-chunks of 32 outermost so each B
+// fragment read from LDS serves all of a wave's row blocks, lower-triangle blocks
+// skipped; then rho_t = rho0 + sum_i psi_i Z_i with psi_i again from the LDS tile.
+// Waves: 4 row groups x WP point groups; row group g owns the 32-row blocks g and
+// 7 - g (equal triangular work), a point group owns BN / WP points.
 template <int BN, int WP>
-__global__ __launch_bounds__(256 * WP) void k_density_tile(int NP, long ng, const unsigned short* __restrict__ whi,
-                                                           const unsigned short* __restrict__ wlo,
-                                                           const unsigned short* __restrict__ pth,
-                                                           const unsigned short* __restrict__ ptl,
-                                                           const double* __restrict__ rho0,
-                                                           double* __restrict__ rho, int T, const int* active) {
+__global__ __launch_bounds__(256 * WP) void k_density_tile32(int NP, long ng, const unsigned short* __restrict__ whi,
+                                                             const unsigned short* __restrict__ wlo,
+                                                             const unsigned short* __restrict__ pth,
+                                                             const unsigned short* __restrict__ ptl,
+                                                             const double* __restrict__ rho0,
+                                                             double* __restrict__ rho, int T, const int* active) {
   constexpr int LDP = 256 + 8;  // LDS row pitch (bf16)
-  constexpr int RB = 4, PC = BN / 16 / WP, NTH = 256 * WP;
+  constexpr int RB = 2, PC = BN / 32 / WP, NTH = 256 * WP;
   __shared__ __attribute__((aligned(16))) unsigned short sT[2][BN][LDP];
   __shared__ float red[4][BN];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave & 3, wp = wave >> 2;
   const long p0 = (long)blockIdx.x * BN;
-  const int c8 = NP >> 3;
-  for (int e = tid; e < BN * c8; e += NTH) {
-    int row = e / c8, q = e - row * c8;
-    long r = p0 + row;
-    uint4 vh = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
-    if (r < ng) {
-      vh = *reinterpret_cast<const uint4*>(pth + r * NP + 8 * q);
-      vl = *reinterpret_cast<const uint4*>(ptl + r * NP + 8 * q);
+  {
+    constexpr int U = BN * 32 / NTH;
+    const int q = tid & 31, rb = tid >> 5;
+    const bool colok = q < (NP >> 3);
+    uint4 vh[U], vl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long r = p0 + rb + (NTH / 32) * u;
+      vh[u] = vl[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (colok && r < ng) {
+        vh[u] = *reinterpret_cast<const uint4*>(pth + r * NP + 8 * q);
+        vl[u] = *reinterpret_cast<const uint4*>(ptl + r * NP + 8 * q);
+      }
     }
-    *reinterpret_cast<uint4*>(&sT[0][row][8 * q]) = vh;
-    *reinterpret_cast<uint4*>(&sT[1][row][8 * q]) = vl;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int row = rb + (NTH / 32) * u;
+      if (colok) {
+        *reinterpret_cast<uint4*>(&sT[0][row][8 * q]) = vh[u];
+        *reinterpret_cast<uint4*>(&sT[1][row][8 * q]) = vl[u];
+      }
+    }
   }
   __syncthreads();
-  const int NB = NP >> 4, NC = NP >> 5;
-  int Ib[RB] = {wr, 7 - wr, 8 + wr, 15 - wr};
-  const int kq = 8 * (lane >> 4), l16 = lane & 15;
+  const int NB = NP >> 5, NC = NP >> 5;
+  const int Ib[RB] = {wr, 7 - wr};
+  const int kq = 8 * (lane >> 5), l32 = lane & 31;
   const int pb = wp * (BN / WP);
   for (int t = 0; t < T; ++t) {
     if (active && !active[t]) continue;
     const unsigned short* Wh = whi + (long)t * NP * NP;
     const unsigned short* Wl = wlo + (long)t * NP * NP;
-    f32x4 acc[RB][PC];
+    f32x16 acc[RB][PC];
 #pragma unroll
     for (int k = 0; k < RB; ++k)
 #pragma unroll
-      for (int p = 0; p < PC; ++p) acc[k][p] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    bf16x8 ah[RB], al[RB];
+      for (int p = 0; p < PC; ++p)
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      ah[k] = (bf16x8){};
-      al[k] = (bf16x8){};
-      if (Ib[k] <= 1 && Ib[k] < NB) {
-        long off = (long)(16 * Ib[k] + l16) * NP + kq;
-        ah[k] = *reinterpret_cast<const bf16x8*>(Wh + off);
-        al[k] = *reinterpret_cast<const bf16x8*>(Wl + off);
-      }
-    }
-    for (int c = 0; c < NC; ++c) {
-      bf16x8 nh[RB], nl[RB];
+        for (int r = 0; r < 16; ++r) acc[k][p][r] = 0.f;
+    // W fragments (A operand, stored in fragment order: one coalesced 1 KB block per
+    // load) through a buffer resource over W_t: the loads of the
+    // next PF chunks are always in flight (inactive lower-triangle blocks get an
+    // out-of-range offset and read zero without memory traffic), so their count
+    // is fixed and the wait for chunk c leaves the later ones outstanding.
+    const auto rWh = buf_rsrc(Wh, NP * NP * 2), rWl = buf_rsrc(Wl, NP * NP * 2);
+    constexpr int PF = 3;
+    auto wofs = [&](int k, int cc, int s2) -> int {  // W in 32x32x16 A-fragment order
+      return (cc < NC && Ib[k] <= cc && Ib[k] < NB) ? ((Ib[k] * (NP >> 4) + 2 * cc + s2) * 64 + lane) * 16
+                                                    : (int)0x80000000;
+    };
+    uint4 wh[PF][RB][2], wl[PF][RB][2];
 #pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        nh[k] = (bf16x8){};
-        nl[k] = (bf16x8){};
-        if (c + 1 < NC && Ib[k] <= 2 * c + 3 && Ib[k] < NB) {
-          long off = (long)(16 * Ib[k] + l16) * NP + 32 * (c + 1) + kq;
-          nh[k] = *reinterpret_cast<const bf16x8*>(Wh + off);
-          nl[k] = *reinterpret_cast<const bf16x8*>(Wl + off);
+    for (int d = 0; d < PF; ++d)
+#pragma unroll
+      for (int k = 0; k < RB; ++k)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int o = wofs(k, d, s2);
+          wh[d][k][s2] = buf_ld16(rWh, o, 0);
+          wl[d][k][s2] = buf_ld16(rWl, o, 0);
         }
-      }
-      bf16x8 bh[PC], bl[PC];
+    for (int c = 0; c < NC; ++c) {
+      bf16x8 ah[RB][2], al[RB][2];
 #pragma unroll
-      for (int p = 0; p < PC; ++p) {
-        int pt = pb + 16 * p + l16;
-        bh[p] = *reinterpret_cast<const bf16x8*>(&sT[0][pt][32 * c + kq]);
-        bl[p] = *reinterpret_cast<const bf16x8*>(&sT[1][pt][32 * c + kq]);
-      }
+      for (int k = 0; k < RB; ++k)
 #pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        if (Ib[k] > 2 * c + 1 || Ib[k] >= NB) continue;
+        for (int s2 = 0; s2 < 2; ++s2) {
+          ah[k][s2] = __builtin_bit_cast(bf16x8, wh[0][k][s2]);
+          al[k][s2] = __builtin_bit_cast(bf16x8, wl[0][k][s2]);
+        }
+#pragma unroll
+      for (int d = 0; d + 1 < PF; ++d)
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            wh[d][k][s2] = wh[d + 1][k][s2];
+            wl[d][k][s2] = wl[d + 1][k][s2];
+          }
+#pragma unroll
+      for (int k = 0; k < RB; ++k)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int o = wofs(k, c + PF, s2);
+          wh[PF - 1][k][s2] = buf_ld16(rWh, o, 0);
+          wl[PF - 1][k][s2] = buf_ld16(rWl, o, 0);
+        }
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        bf16x8 bh[PC], bl[PC];
 #pragma unroll
         for (int p = 0; p < PC; ++p) {
-          acc[k][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[k], bh[p], acc[k][p], 0, 0, 0);
-          acc[k][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[k], bl[p], acc[k][p], 0, 0, 0);
-          acc[k][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[k], bh[p], acc[k][p], 0, 0, 0);
+          int pt = pb + 32 * p + l32;
+          bh[p] = *reinterpret_cast<const bf16x8*>(&sT[0][pt][32 * c + 16 * s2 + kq]);
+          bl[p] = *reinterpret_cast<const bf16x8*>(&sT[1][pt][32 * c + 16 * s2 + kq]);
         }
-      }
 #pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        ah[k] = nh[k];
-        al[k] = nl[k];
+        for (int k = 0; k < RB; ++k) {
+          if (Ib[k] > c || Ib[k] >= NB) continue;
+#pragma unroll
+          for (int p = 0; p < PC; ++p) {
+            acc[k][p] = mfma32(al[k][s2], bh[p], acc[k][p]);
+            acc[k][p] = mfma32(ah[k][s2], bl[p], acc[k][p]);
+            acc[k][p] = mfma32(ah[k][s2], bh[p], acc[k][p]);
+          }
+        }
       }
     }
     float part[PC];
@@ -469,24 +571,27 @@ __global__ __launch_bounds__(256 * WP) void k_density_tile(int NP, long ng, cons
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
       if (Ib[k] >= NB) continue;
-      const int i0 = 16 * Ib[k] + 4 * (lane >> 4);
 #pragma unroll
       for (int p = 0; p < PC; ++p) {
-        int pt = pb + 16 * p + l16;
-        uint2 hh = *reinterpret_cast<const uint2*>(&sT[0][pt][i0]);
-        uint2 ll = *reinterpret_cast<const uint2*>(&sT[1][pt][i0]);
-        float v0 = __uint_as_float(hh.x << 16) + __uint_as_float(ll.x << 16);
-        float v1 = __uint_as_float(hh.x & 0xFFFF0000u) + __uint_as_float(ll.x & 0xFFFF0000u);
-        float v2 = __uint_as_float(hh.y << 16) + __uint_as_float(ll.y << 16);
-        float v3 = __uint_as_float(hh.y & 0xFFFF0000u) + __uint_as_float(ll.y & 0xFFFF0000u);
-        part[p] += v0 * acc[k][p][0] + v1 * acc[k][p][1] + v2 * acc[k][p][2] + v3 * acc[k][p][3];
+        const int pt = pb + 32 * p + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int i0 = 32 * Ib[k] + 8 * g + 4 * (lane >> 5);
+          uint2 hh = *reinterpret_cast<const uint2*>(&sT[0][pt][i0]);
+          uint2 ll = *reinterpret_cast<const uint2*>(&sT[1][pt][i0]);
+          float v0 = __uint_as_float(hh.x << 16) + __uint_as_float(ll.x << 16);
+          float v1 = __uint_as_float(hh.x & 0xFFFF0000u) + __uint_as_float(ll.x & 0xFFFF0000u);
+          float v2 = __uint_as_float(hh.y << 16) + __uint_as_float(ll.y << 16);
+          float v3 = __uint_as_float(hh.y & 0xFFFF0000u) + __uint_as_float(ll.y & 0xFFFF0000u);
+          part[p] += v0 * acc[k][p][4 * g] + v1 * acc[k][p][4 * g + 1] + v2 * acc[k][p][4 * g + 2] +
+                     v3 * acc[k][p][4 * g + 3];
+        }
       }
     }
 #pragma unroll
     for (int p = 0; p < PC; ++p) {
-      part[p] += __shfl_xor(part[p], 16);
       part[p] += __shfl_xor(part[p], 32);
-      if (lane < 16) red[wr][pb + 16 * p + lane] = part[p];
+      if (lane < 32) red[wr][pb + 32 * p + lane] = part[p];
     }
     __syncthreads();
     for (int x = tid; x < BN; x += NTH) {
@@ -508,7 +613,7 @@ hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* w
   if (N <= 256) {
     if (!pthi || !ptlo) return hipErrorInvalidValue;
     const int NP = density_tile_ld(N);
-    hipLaunchKernelGGL((k_density_tile<128, 2>), dim3(cdivm(ng, 128)), dim3(512), 0, s, NP, ng, whi, wlo, pthi,
+    hipLaunchKernelGGL((k_density_tile32<128, 2>), dim3(cdivm(ng, 128)), dim3(512), 0, s, NP, ng, whi, wlo, pthi,
                        ptlo, rho0, rho, T, active);
     return hipGetLastError();
   }

@@ -305,6 +305,8 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
     for (int i = 0; i < n_sys; ++i)
       if (((long)sys[i].n[0] * sys[i].n[1] * sys[i].n[2]) % 8 != 0) {
         why = "mixed precision needs a grid point count divisible by 8"; return RT_EINVAL;
+      } else if ((long)sys[i].n[0] * sys[i].n[1] * sys[i].n[2] >= (1L << 23)) {
+        why = "mixed precision supports below 2^23 grid points (32-bit buffer offsets)"; return RT_EINVAL;
       }
   }
   if (run->predictor != RT_PRED_LINEAR && run->predictor != RT_PRED_MLP) { why = "predictor"; return RT_EINVAL; }
@@ -574,7 +576,7 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
   {
     Timed tm(c, PH_DENSITY);
     if (mixed) {
-      CK(rtk::upper_weighted_delta_bf16(s, S, d.S_gs, d.w_hi, d.w_lo, d.N, d.wld, sstride, T, act));
+      CK(rtk::upper_weighted_delta_bf16(s, S, d.S_gs, d.w_hi, d.w_lo, d.N, d.wld, sstride, T, act, d.N <= 256));
       CK(rtk::density_bf16x3(s, d.N, d.ng, d.w_hi, d.w_lo, d.psi_hi, d.psi_lo, d.psiT_hi, d.psiT_lo, d.rho_gs,
                              d.rho, T, act));
     } else {

@@ -73,3 +73,16 @@ def test_projector_wider_than_cell_rejected():
     sa, ra = _args(nl_rcut=4.0)
     with pytest.raises(rt.RTError):
         rt.rt_workspace_size([sa], ra)
+
+
+def test_mixed_precision_grid_limit_rejected():
+    """BF16x3 kernels address a 128-row tile with 32-bit byte offsets: 2^23 points and
+    above are refused before any allocation."""
+    from paper_2410_09189_amd import rt
+
+    sa, ra = _args(precision=rt.RT_MIXED)
+    sa.struct.n[0], sa.struct.n[1], sa.struct.n[2] = 256, 256, 128
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_workspace_size([sa], ra)
+    assert e.value.status == rt.RT_EINVAL
+    assert "2^23" in rt.rt_last_error()

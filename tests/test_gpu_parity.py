@@ -216,10 +216,12 @@ def test_c1_three_kicks_and_bitwise_determinism():
 MIXED_REL = 1e-4
 
 
-# N = 20, 100 and 250 cover one, several and all sixteen 16-row blocks of the
+# N = 20, 100 and 250 cover one, several and all eight 32-row blocks of the
 # resident-tile density kernel (orbitals zero padded to 32, 128 and 256); the
-# 36 x 40 x 30 grid leaves a ragged last 128-point tile.
-@pytest.mark.parametrize("n,n_orb", [((36, 40, 32), 20), ((36, 40, 30), 100), ((36, 40, 30), 250)])
+# 36 x 40 x 30 grid leaves a ragged last 128-point tile; N = 300 takes the
+# row-major density kernel for N > 256 and three 128-row projection tiles.
+@pytest.mark.parametrize("n,n_orb", [((36, 40, 32), 20), ((36, 40, 30), 100), ((36, 40, 30), 250),
+                                     ((40, 36, 36), 300)])
 def test_mixed_eval_h_error_is_relative_to_the_perturbation(n, n_orb):
     _say(f"mixed eval_h {n} N={n_orb}")
     torch = _torch()
