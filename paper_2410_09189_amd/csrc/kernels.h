@@ -85,13 +85,14 @@ hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double
 hipError_t copy_masked(hipStream_t s, double* dst, const double* src, long n, int T, const int* active);
 hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
                         unsigned long long* slot, int T, const int* active);
-hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, int T,
+// kmin_t = ceil(|dt| Gershgorin width of A_t); rows: scratch [T][N][2]
+hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, double* rows, int T,
                       const int* active);
 // series start: Pout = dP = Pin; Hbar = (H0 + H1)/2 when H0 != nullptr; slots, stop flags and
-// resid (nullable) zeroed; kmin from the Gershgorin width of Hbar
+// resid (nullable) zeroed; kmin from the Gershgorin width of Hbar (rows: scratch [T][N][2])
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
-                        int stride, int* done, unsigned long long* resid, int T, const int* active);
+                        int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active);
 // slot[t] = max |a_t - b_t| (atomic max; zeroed beforehand), then b_t = a_t
 hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, unsigned long long* slot, int T,
                            const int* active);
@@ -105,9 +106,9 @@ hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1
                          int T, const int* active);
 hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, int stride,
                          const double* kmin, double thrs, int* done, int T, const int* active);
-// rows_t = (mu_x, mu_y, mu_z, E, TrP) from S'_t (stride 2N^2) and eparts_t.
+// rows_t = (mu_x, mu_y, mu_z, E, TrP) from S'_t (stride 2N^2) and eparts_t; work: [T][160]
 hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
-                       const double* eparts, int estride, double* rows, long rstride, int T);
+                       const double* eparts, int estride, double* rows, long rstride, double* work, int T);
 hipError_t cholesky(hipStream_t s, double* A, int N, int* info);
 hipError_t tri_inverse_lower(hipStream_t s, const double* L, double* Linv, int N);
 hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N, long sstride, int T,

@@ -705,13 +705,15 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// out[k] = sum_q v[q] exp(sgn 2 pi i q k / R), R in {2, 3, 4, 5}
-__device__ __forceinline__ void small_dft(double2* v, int R, double sgn) {
-  if (R == 2) {
+// out[k] = sum_q v[q] exp(sgn 2 pi i q k / R), R in {2, 3, 4, 5}; the radix is a
+// compile-time constant so v stays in registers.
+template <int R>
+__device__ __forceinline__ void small_dft(double2 (&v)[R], double sgn) {
+  if constexpr (R == 2) {
     double2 a = v[0], b = v[1];
     v[0] = make_double2(a.x + b.x, a.y + b.y);
     v[1] = make_double2(a.x - b.x, a.y - b.y);
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     double2 a = v[0], b = v[1], c = v[2], d = v[3];
     double2 s0 = make_double2(a.x + c.x, a.y + c.y), d0 = make_double2(a.x - c.x, a.y - c.y);
     double2 s1 = make_double2(b.x + d.x, b.y + d.y), d1 = make_double2(b.x - d.x, b.y - d.y);
@@ -722,30 +724,27 @@ __device__ __forceinline__ void small_dft(double2* v, int R, double sgn) {
     v[2] = make_double2(s0.x - s1.x, s0.y - s1.y);
     v[3] = make_double2(d0.x - wd1.x, d0.y - wd1.y);
   } else {
-    // R = 3 or 5: direct sum with exact-to-rounding cos/sin of 2 pi m / R
-    double c[5], sn[5];
-    c[0] = 1.0;
-    sn[0] = 0.0;
-    if (R == 3) {
-      c[1] = -0.5; sn[1] = 0.86602540378443864676;
-      c[2] = -0.5; sn[2] = -0.86602540378443864676;
-    } else {
-      c[1] = 0.30901699437494742410; sn[1] = 0.95105651629515357212;
-      c[2] = -0.80901699437494742410; sn[2] = 0.58778525229247312917;
-      c[3] = -0.80901699437494742410; sn[3] = -0.58778525229247312917;
-      c[4] = 0.30901699437494742410; sn[4] = -0.95105651629515357212;
-    }
-    double2 o[5];
+    // R = 3 or 5: direct sum with cos/sin of 2 pi m / R correctly rounded
+    constexpr double c3[3] = {1.0, -0.5, -0.5};
+    constexpr double s3[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
+    constexpr double c5[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410, -0.80901699437494742410,
+                              0.30901699437494742410};
+    constexpr double s5[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917, -0.58778525229247312917,
+                              -0.95105651629515357212};
+    double2 o[R];
+#pragma unroll
     for (int k = 0; k < R; ++k) {
       double re = 0.0, im = 0.0;
+#pragma unroll
       for (int q = 0; q < R; ++q) {
-        int m = (q * k) % R;
-        double wr = c[m], wi = sgn * sn[m];
+        const int m = (q * k) % R;
+        const double wr = R == 3 ? c3[m] : c5[m], wi = sgn * (R == 3 ? s3[m] : s5[m]);
         re += v[q].x * wr - v[q].y * wi;
         im += v[q].x * wi + v[q].y * wr;
       }
       o[k] = make_double2(re, im);
     }
+#pragma unroll
     for (int k = 0; k < R; ++k) v[k] = o[k];
   }
 }
@@ -757,6 +756,33 @@ __device__ __forceinline__ int lidx(int c, int p, int n, int L) {
   return LAYOUT == 0 ? p * L + c : c * n + p;
 }
 
+// One radix-R Stockham pass over L lines in LDS (twiddle index k r n / (Ns R) < n).
+template <int LAYOUT, int R>
+__device__ __forceinline__ void fft_pass(const double2* src, double2* dst, const double2* tws, int n, int L, int Ns,
+                                         double sgn) {
+  const int nb = n / R;
+  const int tstep = n / (Ns * R);
+  for (int e = threadIdx.x; e < nb * L; e += blockDim.x) {
+    const int j = e / L, c = e - j * L;
+    const int k = j % Ns;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double2 x = src[lidx<LAYOUT>(c, j + r * nb, n, L)];
+      if (r > 0) {
+        double2 t = tws[k * r * tstep];
+        t.y *= sgn;
+        x = cmul(x, t);
+      }
+      v[r] = x;
+    }
+    small_dft<R>(v, sgn);
+    const int base = (j - k) * R + k;  // (j / Ns) Ns R + k
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[lidx<LAYOUT>(c, base + r * Ns, n, L)] = v[r];
+  }
+}
+
 template <int LAYOUT>
 __device__ double2* fft_lds(double2* A, double2* B, const double2* tws, int n, int L, const FftPlan& pl,
                             double sgn) {
@@ -765,24 +791,11 @@ __device__ double2* fft_lds(double2* A, double2* B, const double2* tws, int n, i
   double2* dst = B;
   for (int ps = 0; ps < pl.np; ++ps) {
     const int R = pl.r[ps];
-    const int nb = n / R;
-    const int tstep = n / (Ns * R);
-    for (int e = threadIdx.x; e < nb * L; e += blockDim.x) {
-      int j = e / L, c = e - j * L;
-      double2 v[5];
-      int k = j % Ns;
-      for (int r = 0; r < R; ++r) {
-        double2 x = src[lidx<LAYOUT>(c, j + r * nb, n, L)];
-        if (r > 0) {
-          double2 t = tws[(k * r * tstep) % n];
-          t.y *= sgn;
-          x = cmul(x, t);
-        }
-        v[r] = x;
-      }
-      small_dft(v, R, sgn);
-      int base = (j / Ns) * Ns * R + k;
-      for (int r = 0; r < R; ++r) dst[lidx<LAYOUT>(c, base + r * Ns, n, L)] = v[r];
+    switch (R) {
+      case 2: fft_pass<LAYOUT, 2>(src, dst, tws, n, L, Ns, sgn); break;
+      case 3: fft_pass<LAYOUT, 3>(src, dst, tws, n, L, Ns, sgn); break;
+      case 4: fft_pass<LAYOUT, 4>(src, dst, tws, n, L, Ns, sgn); break;
+      default: fft_pass<LAYOUT, 5>(src, dst, tws, n, L, Ns, sgn); break;
     }
     __syncthreads();
     double2* t = src;
@@ -1061,42 +1074,72 @@ hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
 
 // k_min = ceil(dt * (max_i (a_ii + r_i) - min_i (a_ii - r_i))), r_i = sum_{j != i} |a_ij|;
 // one block per trajectory (A_t = A + t N^2).
-__global__ __launch_bounds__(256) void k_gershgorin(const double* A, int N, double dt, double* kmin,
-                                                    const int* active) {
+// Gershgorin rows of A_t (or of (A_t + A2_t)/2 when A2 != nullptr, the value the
+// series uses for Hbar): rows[t][i] = (a_ii + r_i, a_ii - r_i), r_i = sum_{j != i} |a_ij|.
+// One wave per row (lanes stride the row, fixed shuffle tree), blockIdx.y = t.
+__global__ __launch_bounds__(256) void k_gersh_rows(const double* __restrict__ A, const double* __restrict__ A2,
+                                                    int N, double* __restrict__ rows, const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= N) return;
+  const long NN = (long)N * N;
+  const double* a = A + t * NN + (long)i * N;
+  const double* a2 = A2 ? A2 + t * NN + (long)i * N : nullptr;
+  double r = 0.0, dg = 0.0;
+  for (int j = lane; j < N; j += 64) {
+    const double v = a2 ? 0.5 * a[j] + 0.5 * a2[j] : a[j];
+    if (j != i) r += fabs(v); else dg = v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    r += __shfl_xor(r, o);
+    dg += __shfl_xor(dg, o);
+  }
+  if (lane == 0) {
+    rows[(t * (long)N + i) * 2] = dg + r;
+    rows[(t * (long)N + i) * 2 + 1] = dg - r;
+  }
+}
+
+// kmin_t = ceil(|dt| (max_i rows[t][i][0] - min_i rows[t][i][1])), one block per t.
+__global__ __launch_bounds__(256) void k_gersh_final(const double* __restrict__ rows, int N, double dt, double* kmin,
+                                                     const int* active) {
   __shared__ double sh[256];
   const int t = blockIdx.x;
   if (active && !active[t]) return;
-  A += (long)t * N * N;
   double hi = -1e300, lo = 1e300;
   for (int i = threadIdx.x; i < N; i += 256) {
-    double r = 0.0;
-    for (int j = 0; j < N; ++j)
-      if (j != i) r += fabs(A[(long)i * N + j]);
-    double d = A[(long)i * N + i];
-    hi = fmax(hi, d + r);
-    lo = fmin(lo, d - r);
+    hi = fmax(hi, rows[(t * (long)N + i) * 2]);
+    lo = fmin(lo, rows[(t * (long)N + i) * 2 + 1]);
   }
   hi = block_max_256(hi, sh);
   lo = -block_max_256(-lo, sh);
   if (threadIdx.x == 0) kmin[t] = ceil(fabs(dt) * (hi - lo));
 }
-hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, int T,
-                      const int* active) {
-  hipLaunchKernelGGL(k_gershgorin, dim3(T), dim3(256), 0, s, A, N, dt, kmin_out, active);
+
+static hipError_t gersh_launch(hipStream_t s, const double* A, const double* A2, int N, double dt, double* kmin,
+                               double* rows, int T, const int* active) {
+  hipLaunchKernelGGL(k_gersh_rows, dim3(cdiv(N, 4), T), dim3(256), 0, s, A, A2, N, rows, active);
+  hipLaunchKernelGGL(k_gersh_final, dim3(T), dim3(256), 0, s, rows, N, dt, kmin, active);
   return hipGetLastError();
+}
+
+hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, double* rows, int T,
+                      const int* active) {
+  return gersh_launch(s, A, nullptr, N, dt, kmin_out, rows, T, active);
 }
 
 // Start of a series for T trajectories (blockIdx.y = t): Pout = dP = Pin (stacked,
 // 2 N^2 each); when H0 != nullptr also Hbar = (H0 + H1)/2; block 0 of each
-// trajectory zeroes its term slots, stop flags and residual slot and computes
-// kmin = ceil(|dt| (max_i (h_ii + r_i) - min_i (h_ii - r_i))) of Hbar (Gershgorin,
-// r_i = sum_{j != i} |h_ij|), reading (H0 + H1)/2 directly when given.
+// trajectory zeroes its term slots, stop flags and residual slot.  kmin =
+// ceil(|dt| (max_i (h_ii + r_i) - min_i (h_ii - r_i))) of Hbar (Gershgorin) follows
+// from the row kernels, reading (H0 + H1)/2 directly when given.
 __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__ Pin, double* __restrict__ Pout,
                                                       double* __restrict__ dP, const double* __restrict__ H0,
-                                                      const double* __restrict__ H1, double* Hbar, int N, double dt,
-                                                      double* kmin, unsigned long long* slots, int stride, int* done,
+                                                      const double* __restrict__ H1, double* Hbar, int N,
+                                                      unsigned long long* slots, int stride, int* done,
                                                       unsigned long long* resid, const int* active) {
-  __shared__ double sh[256];
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   const long NN = (long)N * N;
@@ -1121,29 +1164,15 @@ __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__
     done[2 * t + 1] = 0;
     if (resid) resid[t] = 0ULL;
   }
-  double hi = -1e300, lo = 1e300;
-  for (int i = threadIdx.x; i < N; i += 256) {
-    double r = 0.0, dgn = 0.0;
-    for (int j = 0; j < N; ++j) {
-      long e = (long)i * N + j;
-      double hv = H0 ? 0.5 * H0[e] + 0.5 * H1[e] : Hbar[e];
-      if (j != i) r += fabs(hv); else dgn = hv;
-    }
-    hi = fmax(hi, dgn + r);
-    lo = fmin(lo, dgn - r);
-  }
-  hi = block_max_256(hi, sh);
-  lo = -block_max_256(-lo, sh);
-  if (threadIdx.x == 0) kmin[t] = ceil(fabs(dt) * (hi - lo));
 }
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
-                        int stride, int* done, unsigned long long* resid, int T, const int* active) {
+                        int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active) {
   long n2 = 2L * N * N;
   int nb = ew_blocks(n2) > 256 ? 256 : ew_blocks(n2);
-  hipLaunchKernelGGL(k_series_begin, dim3(nb, T), dim3(256), 0, s, Pin, Pout, dP, H0, H1, Hbar, N, dt, kmin, slots,
-                     stride, done, resid, active);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_series_begin, dim3(nb, T), dim3(256), 0, s, Pin, Pout, dP, H0, H1, Hbar, N, slots, stride,
+                     done, resid, active);
+  return gersh_launch(s, H0 ? H0 : Hbar, H0 ? H1 : nullptr, N, dt, kmin, rows, T, active);
 }
 
 // max_t |a_t - b_t| into slot[t] (zeroed beforehand), then b_t = a_t.
@@ -1236,41 +1265,52 @@ hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slot
 }
 
 // mu_q = sum_ij S_ij M_q,ij ; E = sum_ij S_ij Hcore_ij + E_x + E_H ; TrP = sum_i S_ii.
-// One block per trajectory: S_t = S + t 2N^2, eparts_t = eparts + 2t, row_t = rows + t rstride.
-__global__ __launch_bounds__(256) void k_observables(const double* S, const double* M3, const double* hc,
-                                                     int N, const double* eparts, int estride, double* rows,
-                                                     long rstride) {
+// S_t = S + t 2N^2, eparts_t = eparts + t estride, row_t = rows + t rstride.  Stage 1:
+// kObsBlocks blocks per trajectory write partial sums part[t][b][5]; stage 2 adds
+// them in block order (deterministic, independent of T).
+constexpr int kObsBlocks = 32;
+__global__ __launch_bounds__(256) void k_observables_part(const double* S, const double* M3, const double* hc, int N,
+                                                          double* part) {
   __shared__ double sh[256];
-  const int t = blockIdx.x;
+  const int t = blockIdx.y;
   const long NN = (long)N * N;
   S += t * 2 * NN;
-  eparts += (long)t * estride;
-  double* row = rows + t * rstride;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
-  for (long e = threadIdx.x; e < NN; e += 256) {
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < NN; e += (long)kObsBlocks * 256) {
     double sv = S[e];
     a0 += sv * M3[e];
     a1 += sv * M3[NN + e];
     a2 += sv * M3[2 * NN + e];
     a3 += sv * hc[e];
   }
-  for (int i = threadIdx.x; i < N; i += 256) a4 += S[(long)i * N + i];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += kObsBlocks * 256) a4 += S[(long)i * N + i];
   a0 = block_sum_256(a0, sh);
   a1 = block_sum_256(a1, sh);
   a2 = block_sum_256(a2, sh);
   a3 = block_sum_256(a3, sh);
   a4 = block_sum_256(a4, sh);
   if (threadIdx.x == 0) {
-    row[0] = a0;
-    row[1] = a1;
-    row[2] = a2;
-    row[3] = a3 + eparts[0] + eparts[1];
-    row[4] = a4;
+    double* p = part + ((long)t * kObsBlocks + blockIdx.x) * 5;
+    p[0] = a0;
+    p[1] = a1;
+    p[2] = a2;
+    p[3] = a3;
+    p[4] = a4;
   }
 }
+__global__ void k_observables_final(const double* part, const double* eparts, int estride, double* rows,
+                                    long rstride) {
+  const int t = blockIdx.x, q = threadIdx.x;
+  if (q >= 5) return;
+  double a = 0.0;
+  for (int b = 0; b < kObsBlocks; ++b) a += part[((long)t * kObsBlocks + b) * 5 + q];
+  if (q == 3) a += eparts[(long)t * estride] + eparts[(long)t * estride + 1];
+  rows[t * rstride + q] = a;
+}
 hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
-                       const double* eparts, int estride, double* rows, long rstride, int T) {
-  hipLaunchKernelGGL(k_observables, dim3(T), dim3(256), 0, s, S, M3, hcore, N, eparts, estride, rows, rstride);
+                       const double* eparts, int estride, double* rows, long rstride, double* work, int T) {
+  hipLaunchKernelGGL(k_observables_part, dim3(kObsBlocks, T), dim3(256), 0, s, S, M3, hcore, N, work);
+  hipLaunchKernelGGL(k_observables_final, dim3(T), dim3(64), 0, s, work, eparts, estride, rows, rstride);
   return hipGetLastError();
 }
 

@@ -308,28 +308,37 @@ hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, 
 }
 
 // C[m][n] = alpha * sum_s part[s][m][n] (FP64 sum of FP32 partials), upper kept and mirrored, plus base.
-__global__ void k_reduce_parts_f32(const float* __restrict__ part, int n_split, int N, double alpha,
-                                   const double* base, double* C, const int* active, long sbase) {
+// Block = 64 consecutive elements x 4 wave groups; group g adds splits g, g + 4, ... in
+// order, the four group sums are combined in group order (deterministic).
+__global__ __launch_bounds__(256) void k_reduce_parts_f32(const float* __restrict__ part, int n_split, int N,
+                                                          double alpha, const double* base, double* C,
+                                                          const int* active, long sbase) {
+  __shared__ double sh[4][64];
   const int t = blockIdx.y;
   if (active && !active[t]) return;
-  part += (long)t * n_split * N * N;
-  C += (long)t * N * N;
+  const long NN = (long)N * N;
+  part += (long)t * n_split * NN;
+  C += t * NN;
   base += t * sbase;
-  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)N * N) return;
-  int m = (int)(e / N), n = (int)(e - (long)m * N);
-  if (m > n) return;
+  const int x = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const long e = (long)blockIdx.x * 64 + x;
   double acc = 0.0;
-  for (int sI = 0; sI < n_split; ++sI) acc += (double)part[(long)sI * N * N + e];
-  acc *= alpha;
-  C[e] = base[e] + acc;
-  if (m < n) C[(long)n * N + m] = base[(long)n * N + m] + acc;
+  if (e < NN)
+    for (int q = g; q < n_split; q += 4) acc += (double)part[(long)q * NN + e];
+  sh[g][x] = acc;
+  __syncthreads();
+  if (g != 0 || e >= NN) return;
+  const int m = (int)(e / N), n = (int)(e - (long)m * N);
+  if (m > n) return;
+  const double v = alpha * (((sh[0][x] + sh[1][x]) + sh[2][x]) + sh[3][x]);
+  C[e] = base[e] + v;
+  if (m < n) C[(long)n * N + m] = base[(long)n * N + m] + v;
 }
 
 hipError_t reduce_parts_f32(hipStream_t s, const float* part, int n_split, int N, double alpha,
                             const double* base, double* C, int T, const int* active, long sbase) {
   long n = (long)N * N;
-  hipLaunchKernelGGL(k_reduce_parts_f32, dim3(cdivm(n, 256), T), dim3(256), 0, s, part, n_split, N, alpha, base, C,
+  hipLaunchKernelGGL(k_reduce_parts_f32, dim3(cdivm(n, 64), T), dim3(256), 0, s, part, n_split, N, alpha, base, C,
                      active, sbase);
   return hipGetLastError();
 }

@@ -157,6 +157,7 @@ struct SysDev {
   float *dv32, *part32;
   // per-trajectory state [T][...]
   double *P0, *P1, *dP, *dPn, *C;          // stacked [S'; A'], 2 N^2 each
+  double* gwork = nullptr;                 // Gershgorin rows [T][N][2] / observable partials [T][160]
   double *H0, *H1, *Hm1, *Hn, *Hbar;       // N^2 each
   double* hist;                            // [T][cap + 1][5]
   double* kmin;                            // [T]
@@ -384,6 +385,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.tmp = a.take<double>(NN);
     d.tmp2 = a.take<double>(NN);
     d.red2 = a.take<double>(T * 2 * rtk::kRedBlocks);
+    d.gwork = a.take<double>(T * std::max(2L * N, 160L));
     d.escale = a.take<double>(2);
     d.ezero = a.take<double>(2);
     d.info = a.take<int>(4);
@@ -637,7 +639,7 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
   {
     Timed tm(c, PH_SMALL);
     CK(rtk::series_begin(s, Pin, Pout, dP, H0, H1, const_cast<double*>(Hbar), d.N, dt, kmin, slots, stride, done,
-                         resid, T, act));
+                         resid, d.gwork, T, act));
   }
   int k = 1;
   const int CH = 8;
@@ -674,7 +676,8 @@ rt_status observe(rt_ctx* c, SysDev& d, int row) {
   const double* Hc = c->run.frozen_hxc ? d.Hgs : d.hcore;
   const double* ep = c->run.frozen_hxc ? d.ezero : d.eparts;
   const int es = c->run.frozen_hxc ? 0 : 2;
-  CK(rtk::observables(c->stream, d.P0, d.M3, Hc, d.N, ep, es, d.hist + 5L * row, 5L * (c->hist_cap + 1), d.T));
+  CK(rtk::observables(c->stream, d.P0, d.M3, Hc, d.N, ep, es, d.hist + 5L * row, 5L * (c->hist_cap + 1), d.gwork,
+                      d.T));
   return RT_OK;
 }
 
