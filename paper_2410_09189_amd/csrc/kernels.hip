@@ -162,22 +162,47 @@ hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, l
 // FD8 stencil + local potential
 // ============================================================================
 //
-// One block = one orbital, all x, a tile of TY rows in y, a chunk of z planes.
-// The block marches in z: each thread keeps the 9-plane window of its columns
-// in registers (z neighbours), and the current plane with a 4-row y halo is
-// staged in LDS (x and y neighbours, periodic wrap).  Global reads are whole
-// x rows (coalesced); the halo rows are the neighbouring tiles' interiors.
+// One block = one orbital, all x (nx <= 256), a tile of TY rows in y, a chunk of z
+// planes, blockDim = the tile's strips rounded up to whole waves.  A thread owns
+// COLS strips of V consecutive x points (V = 16 bytes / element size when nx
+// allows, else 1) and marches in z: the 9-plane window of its strips
+// sits in registers (z neighbours) with the next two planes' loads in flight.  The
+// current plane with a 4-row y halo is staged in one of two LDS buffers whose rows
+// carry 4 periodic copies on each side, so the x and y neighbours of a strip are
+// whole 16-byte LDS reads at fixed offsets (no wrap arithmetic); one barrier per
+// plane.  The next plane's halo rows and potential load while this plane computes.
+// Global traffic is whole x rows in 16-byte vectors; halo rows are the neighbouring
+// tiles' interiors (L2).
 struct StencilCoef {
   double c[5];  // -1/2 a_k / h^2
 };
 
-template <typename T, int COLS>
-__global__ __launch_bounds__(256) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
+template <typename T, int V>
+struct SVec {
+  T e[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ SVec<T, V> sv_ld(const T* p) {
+  return *reinterpret_cast<const SVec<T, V>*>(p);
+}
+template <typename T, int V>
+__device__ __forceinline__ void sv_st(T* p, const SVec<T, V>& x) {
+  *reinterpret_cast<SVec<T, V>*>(p) = x;
+}
+
+// Four waves per SIMD for latency hiding where the halo takes at most two strips per
+// thread (the register bound then costs at most a couple of spilled words).
+template <typename T, int V, int COLS, int HS>
+__global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
                                                  const T* __restrict__ v, int nx, int ny, int nz,
                                                  int TY, int ZC, StencilCoef cf) {
+  typedef SVec<T, V> Vec;
   extern __shared__ unsigned char smem_raw[];
-  T* sp = reinterpret_cast<T*>(smem_raw);  // [(TY + 8)][nx]
-  const int tid = threadIdx.x;
+  T* const sp0 = reinterpret_cast<T*>(smem_raw);  // [2][TY + 8][nx + 8], x = 0 at column 4
+  const int P = nx + 8;
+  const int pln = (TY + 8) * P;
+  const int tid = threadIdx.x, NT = blockDim.x;
   const int y0 = blockIdx.x * TY;
   const int rows = min(TY, ny - y0);
   const long orb = blockIdx.y;
@@ -188,103 +213,167 @@ __global__ __launch_bounds__(256) void k_stencil(const T* __restrict__ psi, T* _
   T* __restrict__ o = hpsi + orb * plane * nz;
   const T c0 = (T)(3.0 * cf.c[0]);
   const T c1 = (T)cf.c[1], c2 = (T)cf.c[2], c3 = (T)cf.c[3], c4 = (T)cf.c[4];
+  const int spr = nx / V;  // strips per row
 
-  int cx[COLS], cy[COLS];
+  int cb[COLS], ls[COLS], pw[COLS];  // plane offset, LDS offset, LDS offset of the wrap copy (-1: none)
   bool ok[COLS];
-  T q[COLS][9];
+  Vec q[COLS][9], n1[COLS], n2[COLS], vv[COLS];
 #pragma unroll
   for (int c = 0; c < COLS; ++c) {
-    int p = tid + c * 256;
-    int yl = p / nx;
+    const int sidx = tid + c * NT;
+    const int yl = sidx / spr, x = (sidx - yl * spr) * V;
     ok[c] = yl < rows;
-    cx[c] = p - yl * nx;
-    cy[c] = yl;
+    cb[c] = (y0 + yl) * nx + x;
+    ls[c] = (yl + 4) * P + 4 + x;
+    pw[c] = x < 4 ? ls[c] + nx : (x >= nx - 4 ? ls[c] - nx : -1);
     if (ok[c]) {
-      long base = (long)(y0 + yl) * nx + cx[c];
 #pragma unroll
-      for (int d = 0; d < 8; ++d) q[c][d] = f[(long)wrapi(z0 - 4 + d, nz) * plane + base];
+      for (int d = 0; d < 9; ++d) q[c][d] = sv_ld<T, V>(f + (long)wrapi(z0 - 4 + d, nz) * plane + cb[c]);
+      n1[c] = sv_ld<T, V>(f + (long)wrapi(z0 + 5, nz) * plane + cb[c]);
+      n2[c] = sv_ld<T, V>(f + (long)wrapi(z0 + 6, nz) * plane + cb[c]);
+      vv[c] = sv_ld<T, V>(v + (long)z0 * plane + cb[c]);
     }
   }
-  const int halo_n = 8 * nx;
+  // y halo: 8 rows (4 below, 4 above the tile) of plane z, 8 spr <= NT HS strips
+  int hoff[HS], hl[HS], hw[HS];
+  Vec hv[HS];
+#pragma unroll
+  for (int i = 0; i < HS; ++i) {
+    const int e = tid + NT * i;
+    hoff[i] = -1;
+    if (e < 8 * spr) {
+      const int hr = e / spr, x = (e - hr * spr) * V;
+      const int yl = hr < 4 ? hr - 4 : rows + (hr - 4);
+      hoff[i] = wrapi(y0 + yl, ny) * nx + x;
+      hl[i] = (yl + 4) * P + 4 + x;
+      hw[i] = x < 4 ? hl[i] + nx : (x >= nx - 4 ? hl[i] - nx : -1);
+      hv[i] = sv_ld<T, V>(f + (long)z0 * plane + hoff[i]);
+    }
+  }
   for (int z = z0; z < z1; ++z) {
-    const long zoff = (long)z * plane;
-    const long zf = (long)wrapi(z + 4, nz) * plane;
+    T* const sp = sp0 + ((z - z0) & 1) * pln;
 #pragma unroll
-    for (int c = 0; c < COLS; ++c) {
+    for (int c = 0; c < COLS; ++c)
       if (ok[c]) {
-        q[c][8] = f[zf + (long)(y0 + cy[c]) * nx + cx[c]];
-        sp[(cy[c] + 4) * nx + cx[c]] = q[c][4];
+        sv_st<T, V>(sp + ls[c], q[c][4]);
+        if (pw[c] >= 0) sv_st<T, V>(sp + pw[c], q[c][4]);
       }
-    }
-    for (int e = tid; e < halo_n; e += 256) {
-      int hr = e / nx, x = e - hr * nx;
-      int yl = hr < 4 ? hr - 4 : rows + (hr - 4);
-      int y = wrapi(y0 + yl, ny);
-      sp[(yl + 4) * nx + x] = f[zoff + (long)y * nx + x];
-    }
+#pragma unroll
+    for (int i = 0; i < HS; ++i)
+      if (hoff[i] >= 0) {
+        sv_st<T, V>(sp + hl[i], hv[i]);
+        if (hw[i] >= 0) sv_st<T, V>(sp + hw[i], hv[i]);
+      }
     __syncthreads();
+    // next plane's halo and potential, and plane z + 7 of the window, in flight
+    Vec vn[COLS], n3[COLS];
+    const bool more = z + 1 < z1;
+    if (more) {
+      const long zn = (long)(z + 1) * plane;
+#pragma unroll
+      for (int i = 0; i < HS; ++i)
+        if (hoff[i] >= 0) hv[i] = sv_ld<T, V>(f + zn + hoff[i]);
+      const long z7 = (long)wrapi(z + 7, nz) * plane;
+#pragma unroll
+      for (int c = 0; c < COLS; ++c)
+        if (ok[c]) {
+          vn[c] = sv_ld<T, V>(v + zn + cb[c]);
+          n3[c] = sv_ld<T, V>(f + z7 + cb[c]);
+        }
+    }
+    const long zoff = (long)z * plane;
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
-      if (ok[c]) {
-        const int x = cx[c];
-        const T* row = sp + (cy[c] + 4) * nx;
-        const T ctr = q[c][4];
-        int xp1 = x + 1 >= nx ? x + 1 - nx : x + 1, xm1 = x - 1 < 0 ? x - 1 + nx : x - 1;
-        int xp2 = x + 2 >= nx ? x + 2 - nx : x + 2, xm2 = x - 2 < 0 ? x - 2 + nx : x - 2;
-        int xp3 = x + 3 >= nx ? x + 3 - nx : x + 3, xm3 = x - 3 < 0 ? x - 3 + nx : x - 3;
-        int xp4 = x + 4 >= nx ? x + 4 - nx : x + 4, xm4 = x - 4 < 0 ? x - 4 + nx : x - 4;
-        T sx1 = row[xp1] + row[xm1], sx2 = row[xp2] + row[xm2];
-        T sx3 = row[xp3] + row[xm3], sx4 = row[xp4] + row[xm4];
-        T sy1 = row[nx + x] + row[-nx + x], sy2 = row[2 * nx + x] + row[-2 * nx + x];
-        T sy3 = row[3 * nx + x] + row[-3 * nx + x], sy4 = row[4 * nx + x] + row[-4 * nx + x];
-        T sz1 = q[c][5] + q[c][3], sz2 = q[c][6] + q[c][2];
-        T sz3 = q[c][7] + q[c][1], sz4 = q[c][8] + q[c][0];
+      if (!ok[c]) continue;
+      const T* r0 = sp + ls[c];
+      T w[V + 8];  // x window x - 4 .. x + V + 3
+#pragma unroll
+      for (int g = 0; g < (V + 8) / V; ++g) {
+        Vec t = sv_ld<T, V>(r0 - 4 + g * V);
+#pragma unroll
+        for (int u = 0; u < V; ++u) w[g * V + u] = t.e[u];
+      }
+      Vec ym[4], yp[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ym[k] = sv_ld<T, V>(r0 - (k + 1) * P);
+        yp[k] = sv_ld<T, V>(r0 + (k + 1) * P);
+      }
+      Vec out;
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const T ctr = q[c][4].e[u];
+        T sx1 = w[u + 5] + w[u + 3], sx2 = w[u + 6] + w[u + 2];
+        T sx3 = w[u + 7] + w[u + 1], sx4 = w[u + 8] + w[u + 0];
+        T sy1 = yp[0].e[u] + ym[0].e[u], sy2 = yp[1].e[u] + ym[1].e[u];
+        T sy3 = yp[2].e[u] + ym[2].e[u], sy4 = yp[3].e[u] + ym[3].e[u];
+        T sz1 = q[c][5].e[u] + q[c][3].e[u], sz2 = q[c][6].e[u] + q[c][2].e[u];
+        T sz3 = q[c][7].e[u] + q[c][1].e[u], sz4 = q[c][8].e[u] + q[c][0].e[u];
         T acc = c0 * ctr;
         acc += c1 * ((sx1 + sy1) + sz1);
         acc += c2 * ((sx2 + sy2) + sz2);
         acc += c3 * ((sx3 + sy3) + sz3);
         acc += c4 * ((sx4 + sy4) + sz4);
-        const long gi = zoff + (long)(y0 + cy[c]) * nx + x;
-        o[gi] = acc + v[gi] * ctr;
+        out.e[u] = acc + vv[c].e[u] * ctr;
       }
+      sv_st<T, V>(o + zoff + cb[c], out);
     }
-    __syncthreads();
+    if (more) {
 #pragma unroll
-    for (int c = 0; c < COLS; ++c) {
+      for (int c = 0; c < COLS; ++c) {
 #pragma unroll
-      for (int d = 0; d < 8; ++d) q[c][d] = q[c][d + 1];
+        for (int d = 0; d < 8; ++d) q[c][d] = q[c][d + 1];
+        q[c][8] = n1[c];
+        n1[c] = n2[c];
+        n2[c] = n3[c];
+        vv[c] = vn[c];
+      }
     }
   }
 }
 
-template <typename T>
-hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
-                   int nz, double h, const double* a) {
-  StencilCoef cf;
-  for (int k = 0; k < 5; ++k) cf.c[k] = -0.5 * a[k] / (h * h);
+template <typename T, int V>
+static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
+                                 int nz, const StencilCoef& cf) {
+  const int spr = nx / V;
+  // y tile: the largest divisor of ny whose strips fit one 256-thread block (one strip
+  // per thread, registers for occupancy), block = strips rounded up to whole waves
   int TY = 1;
-  const int cand[] = {16, 12, 10, 8, 6, 5, 4, 3, 2, 1};
-  for (int t : cand) {
-    if (t <= ny && ny % t == 0 && t * nx <= 2048) { TY = t; break; }
-  }
-  int cols = (TY * nx + 255) / 256;
+  for (int t = 64; t >= 1; --t)
+    if (t <= ny && ny % t == 0 && t * spr <= 256) { TY = t; break; }
+  const int cols = (TY * spr + 255) / 256;
+  const int nt = cols > 1 ? 256 : (TY * spr + 63) / 64 * 64;
+  const int hs = (8 * spr + nt - 1) / nt;
   int tiles = ny / TY;
   int nzc = 1;
   long blocks = (long)tiles * n_orb;
   while (blocks * nzc < 2048 && nz / (nzc * 2) >= 16) nzc *= 2;
   int ZC = (nz + nzc - 1) / nzc;
   nzc = (nz + ZC - 1) / ZC;
-  size_t lds = (size_t)(TY + 8) * nx * sizeof(T);
+  size_t lds = 2 * (size_t)(TY + 8) * (nx + 8) * sizeof(T);
   dim3 grid(tiles, n_orb, nzc);
-  if (cols <= 1)
-    hipLaunchKernelGGL((k_stencil<T, 1>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
-  else if (cols <= 2)
-    hipLaunchKernelGGL((k_stencil<T, 2>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
-  else if (cols <= 4)
-    hipLaunchKernelGGL((k_stencil<T, 4>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
-  else
-    hipLaunchKernelGGL((k_stencil<T, 8>), grid, dim3(256), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf);
+#define RT_STENCIL(C, H) \
+  hipLaunchKernelGGL((k_stencil<T, V, C, H>), grid, dim3(nt), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf)
+  // nx <= 256 gives spr <= 256, so one strip per thread always fits (cols == 1), and
+  // nt >= spr bounds the halo at 8 strips per thread
+  if (cols != 1 || hs > 8) return hipErrorInvalidValue;
+  if (hs <= 1) RT_STENCIL(1, 1);
+  else if (hs <= 2) RT_STENCIL(1, 2);
+  else if (hs <= 4) RT_STENCIL(1, 4);
+  else RT_STENCIL(1, 8);
+#undef RT_STENCIL
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
+                   int nz, double h, const double* a) {
+  if (nx > 256 || ny > 256 || nz > 256) return hipErrorInvalidValue;
+  StencilCoef cf;
+  for (int k = 0; k < 5; ++k) cf.c[k] = -0.5 * a[k] / (h * h);
+  constexpr int VV = 16 / sizeof(T);
+  if (nx % VV == 0) return stencil_launch<T, VV>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf);
+  return stencil_launch<T, 1>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf);
 }
 template hipError_t stencil<double>(hipStream_t, const double*, double*, const double*, int, int, int,
                                     int, double, const double*);

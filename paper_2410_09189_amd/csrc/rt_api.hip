@@ -279,8 +279,7 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
   for (int i = 0; i < n_sys; ++i) {
     const rt_system& s = sys[i];
     for (int q = 0; q < 3; ++q)
-      if (s.n[q] < 8 || s.n[q] > 1024) { why = "grid edge outside [8, 1024]"; return RT_EINVAL; }
-    if ((s.n[1] > 256) || (s.n[2] > 256)) { why = "y and z grid edges above 256 are not supported"; return RT_EINVAL; }
+      if (s.n[q] < 8 || s.n[q] > 256) { why = "grid edge outside [8, 256]"; return RT_EINVAL; }
     for (int q = 0; q < 3; ++q) {
       int m = s.n[q];
       for (int f : {2, 3, 5})

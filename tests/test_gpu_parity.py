@@ -39,12 +39,18 @@ def _ragged_system(seed=7, n=(36, 40, 32), n_orb=20, nl_rank=4):
     return s, psi
 
 
-def test_apply_h_fp64_matches_oracle_ragged_grid():
-    _say("apply_h fp64 36x40x32 N=20 nonlocal")
+# x edge 36 takes the 16-byte strip path (2 doubles / 4 floats per thread), 45 the
+# one-point strips; both wrap periodically through the padded LDS rows.
+STENCIL_GRIDS = [(36, 40, 32), (45, 32, 30)]
+
+
+@pytest.mark.parametrize("n", STENCIL_GRIDS)
+def test_apply_h_fp64_matches_oracle_ragged_grid(n):
+    _say(f"apply_h fp64 {n} N=20 nonlocal")
     torch = _torch()
     from paper_2410_09189_amd import rt
 
-    s, psi = _ragged_system()
+    s, psi = _ragged_system(n=n)
     rp = synth.RunParams(dt=0.05, n_steps=2)
     ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp))
     vloc = rt.rt_get_grid(ses.ctx, 0, 4, s.ng)
@@ -59,12 +65,13 @@ def test_apply_h_fp64_matches_oracle_ragged_grid():
     ses.close()
 
 
-def test_apply_h_fp32_within_single_precision():
-    _say("apply_h fp32 36x40x32 N=20")
+@pytest.mark.parametrize("n", STENCIL_GRIDS)
+def test_apply_h_fp32_within_single_precision(n):
+    _say(f"apply_h fp32 {n} N=20")
     torch = _torch()
     from paper_2410_09189_amd import rt
 
-    s, psi = _ragged_system(seed=8)
+    s, psi = _ragged_system(seed=8, n=n)
     rp = synth.RunParams(dt=0.05, n_steps=2)
     ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp))
     vloc = rt.rt_get_grid(ses.ctx, 0, 4, s.ng)
