@@ -229,6 +229,8 @@ def main():
     for dt_, (x, y) in ((0, (x64, y64)), (1, (x32, y32))):
         for _ in range(2):
             rt.rt_apply_h(ctx, 0, x.data_ptr(), y.data_ptr(), N, dt_)
+        torch.cuda.synchronize()
+        rt.rt_profile(ctx, enable=True, reset=True)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = 10
         ev0.record()
@@ -236,12 +238,19 @@ def main():
             rt.rt_apply_h(ctx, 0, x.data_ptr(), y.data_ptr(), N, dt_)
         ev1.record()
         torch.cuda.synchronize()
+        ph = rt.rt_profile_read(ctx)
+        rt.rt_profile(ctx, enable=False, reset=True)
         t_apply = ev0.elapsed_time(ev1) / 1e3 / reps
         b = 4 if dt_ else 8
+        st_ms, st_n = ph["stencil_fd8"]
+        t_st = st_ms / 1e3 / st_n  # one stencil launch covers all N orbitals
+        st_bytes = 2 * b * N * s.ng + b * s.ng  # psi in, H psi out, V once
         rates["fp32" if dt_ else "fp64"] = {
             "orbital_gridpoints_per_s": N * s.ng / t_apply,
             "hbm_GBps_algorithmic": (2 * b * N * s.ng + b * s.ng) / t_apply / 1e9,
             "hbm_frac": (2 * b * N * s.ng + b * s.ng) / t_apply / PEAK_HBM,
+            "stencil_only": {"avg_launch_us": t_st * 1e6, "algorithmic_bytes_per_launch": st_bytes,
+                             "achieved_GBps": st_bytes / t_st / 1e9, "frac": st_bytes / t_st / PEAK_HBM},
         }
     mixed["ses"].close()
     del x64, y64, x32, y32

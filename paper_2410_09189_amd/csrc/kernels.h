@@ -8,6 +8,14 @@ namespace rtk {
 
 constexpr int kRedBlocks = 512;  // fixed block count of deterministic grid reductions
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2) in
+// linear-id order.  The logical id is the position in a contiguous per-XCD range, so
+// blocks with neighbouring logical ids run on one XCD and share its L2.
+__device__ __forceinline__ long xcd_logical(long h, long nblk) {
+  const long full = nblk / 8 * 8;
+  return h < full ? (h % 8) * (full / 8) + h / 8 : h;
+}
+
 // T independent problems in one launch (trajectory index fastest in blockIdx.x);
 // per-trajectory element strides of the operands A, B, the weight w and the output.
 struct Batch {

@@ -172,7 +172,9 @@ hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, l
 // whole 16-byte LDS reads at fixed offsets (no wrap arithmetic); one barrier per
 // plane.  The next plane's halo rows and potential load while this plane computes.
 // Global traffic is whole x rows in 16-byte vectors; halo rows are the neighbouring
-// tiles' interiors (L2).
+// tiles' interiors, read from L2: blocks are ordered (tile, z chunk, orbital) with
+// the tile fastest and mapped XCD-aware, so the tiles of one orbital run together
+// on one XCD.
 struct StencilCoef {
   double c[5];  // -1/2 a_k / h^2
 };
@@ -192,8 +194,9 @@ __device__ __forceinline__ void sv_st(T* p, const SVec<T, V>& x) {
 }
 
 // Four waves per SIMD for latency hiding where the halo takes at most two strips per
-// thread (the register bound then costs at most a couple of spilled words).
-template <typename T, int V, int COLS, int HS>
+// thread (the register bound then costs at most a couple of spilled words).  PD planes
+// beyond the window are in flight (two measured best for both element types).
+template <typename T, int V, int COLS, int HS, int PD>
 __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
                                                  const T* __restrict__ v, int nx, int ny, int nz,
                                                  int TY, int ZC, StencilCoef cf) {
@@ -203,10 +206,13 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
   const int P = nx + 8;
   const int pln = (TY + 8) * P;
   const int tid = threadIdx.x, NT = blockDim.x;
-  const int y0 = blockIdx.x * TY;
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int tiles = ny / TY, nzc = (nz + ZC - 1) / ZC;
+  const int tile = (int)(lid % tiles), zc = (int)((lid / tiles) % nzc);
+  const long orb = lid / ((long)tiles * nzc);
+  const int y0 = tile * TY;
   const int rows = min(TY, ny - y0);
-  const long orb = blockIdx.y;
-  const int z0 = blockIdx.z * ZC;
+  const int z0 = zc * ZC;
   const int z1 = min(nz, z0 + ZC);
   const long plane = (long)nx * ny;
   const T* __restrict__ f = psi + orb * plane * nz;
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
 
   int cb[COLS], ls[COLS], pw[COLS];  // plane offset, LDS offset, LDS offset of the wrap copy (-1: none)
   bool ok[COLS];
-  Vec q[COLS][9], n1[COLS], n2[COLS], vv[COLS];
+  Vec q[COLS][9], nq[COLS][PD], vv[COLS];
 #pragma unroll
   for (int c = 0; c < COLS; ++c) {
     const int sidx = tid + c * NT;
@@ -229,8 +235,8 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
     if (ok[c]) {
 #pragma unroll
       for (int d = 0; d < 9; ++d) q[c][d] = sv_ld<T, V>(f + (long)wrapi(z0 - 4 + d, nz) * plane + cb[c]);
-      n1[c] = sv_ld<T, V>(f + (long)wrapi(z0 + 5, nz) * plane + cb[c]);
-      n2[c] = sv_ld<T, V>(f + (long)wrapi(z0 + 6, nz) * plane + cb[c]);
+#pragma unroll
+      for (int k = 0; k < PD; ++k) nq[c][k] = sv_ld<T, V>(f + (long)wrapi(z0 + 5 + k, nz) * plane + cb[c]);
       vv[c] = sv_ld<T, V>(v + (long)z0 * plane + cb[c]);
     }
   }
@@ -265,7 +271,7 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
         if (hw[i] >= 0) sv_st<T, V>(sp + hw[i], hv[i]);
       }
     __syncthreads();
-    // next plane's halo and potential, and plane z + 7 of the window, in flight
+    // next plane's halo and potential, and plane z + 5 + PD of the window, in flight
     Vec vn[COLS], n3[COLS];
     const bool more = z + 1 < z1;
     if (more) {
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
 #pragma unroll
       for (int i = 0; i < HS; ++i)
         if (hoff[i] >= 0) hv[i] = sv_ld<T, V>(f + zn + hoff[i]);
-      const long z7 = (long)wrapi(z + 7, nz) * plane;
+      const long z7 = (long)wrapi(z + 5 + PD, nz) * plane;
 #pragma unroll
       for (int c = 0; c < COLS; ++c)
         if (ok[c]) {
@@ -323,9 +329,10 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
       for (int c = 0; c < COLS; ++c) {
 #pragma unroll
         for (int d = 0; d < 8; ++d) q[c][d] = q[c][d + 1];
-        q[c][8] = n1[c];
-        n1[c] = n2[c];
-        n2[c] = n3[c];
+        q[c][8] = nq[c][0];
+#pragma unroll
+        for (int k = 0; k + 1 < PD; ++k) nq[c][k] = nq[c][k + 1];
+        nq[c][PD - 1] = n3[c];
         vv[c] = vn[c];
       }
     }
@@ -351,9 +358,10 @@ static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* 
   int ZC = (nz + nzc - 1) / nzc;
   nzc = (nz + ZC - 1) / ZC;
   size_t lds = 2 * (size_t)(TY + 8) * (nx + 8) * sizeof(T);
-  dim3 grid(tiles, n_orb, nzc);
+  dim3 grid((unsigned)((long)tiles * nzc * n_orb));
 #define RT_STENCIL(C, H) \
-  hipLaunchKernelGGL((k_stencil<T, V, C, H>), grid, dim3(nt), lds, s, psi, hpsi, v, nx, ny, nz, TY, ZC, cf)
+  hipLaunchKernelGGL((k_stencil<T, V, C, H, 2>), grid, dim3(nt), lds, s, psi, hpsi, v, nx, \
+                     ny, nz, TY, ZC, cf)
   // nx <= 256 gives spr <= 256, so one strip per thread always fits (cols == 1), and
   // nt >= spr bounds the halo at 8 strips per thread
   if (cols != 1 || hs > 8) return hipErrorInvalidValue;

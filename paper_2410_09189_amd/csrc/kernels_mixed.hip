@@ -134,15 +134,6 @@ hipError_t split_bf16_t(hipStream_t s, const double* psi, unsigned short* hiT, u
 // ---------------------------------------------------------------------------
 constexpr int XB = 128, XK = 64, XPAD = 8;
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2) in
-// linear-id order.  Logical id = position in a contiguous per-XCD range, so blocks
-// with neighbouring logical ids (here: the tile pairs and trajectories that read
-// the same chunk of grid points) run on one XCD and share its L2.
-__device__ __forceinline__ long xcd_logical(long h, long nblk) {
-  const long full = nblk / 8 * 8;
-  return h < full ? (h % 8) * (full / 8) + h / 8 : h;
-}
-
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // (hi + lo) * w of two packed bf16 pairs, re-split to packed bf16 hi/lo (round to
