@@ -497,13 +497,23 @@ __device__ __forceinline__ bool series_stopped(const SeriesSkip& sk, int t) {
 // 16, 256 threads each owning a TM x TN = BM/16 x BN/16 block of outputs.
 // Operands are staged k-major in LDS (As[k][m], Bs[k][n]) so each thread reads
 // contiguous runs of its rows/columns.
+// FP64 matrix instructions: v_mfma_f64_16x16x4f64, lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16] (one double each), result register r is D[l / 16 + 4 r][l % 16]
+// (lane layout probed on the device).  Block = 2 x 2 waves, each owning a
+// (BM/2) x (BN/2) sub-tile of (BM/32) x (BN/32) 16 x 16 blocks; K in chunks of 16
+// staged row-major in LDS (pitch 17: the fragment reads hit distinct banks) from
+// coalesced loads (consecutive threads walk k along a row), the next chunk held in
+// registers during the MFMAs.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const double* __restrict__ A,
                                                      long lda, const double* __restrict__ B, long ldb,
                                                      const double* __restrict__ w,
                                                      double* __restrict__ part, long kps, int upper,
                                                      int n_tn, Batch bt, SeriesSkip sk) {
-  constexpr int BK = 16, TM = BM / 16, TN = BN / 16;
+  constexpr int BK = 16, PK = BK + 1, UA = BM * BK / 256, UB = BN * BK / 256;
+  constexpr int WM = BM / 2, WN = BN / 2, FI = WM / 16, FJ = WN / 16;
   const int tb = blockIdx.x % bt.T;
   if (bt.active && !bt.active[tb]) return;
   if (sk.k > 0 && series_stopped(sk, tb)) return;
@@ -511,8 +521,8 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
   B += tb * bt.sb;
   if (w) w += tb * bt.sw;
   part += tb * bt.sp;
-  __shared__ double As[BK][BM + 2];
-  __shared__ double Bs[BK][BN + 2];
+  __shared__ double As[BM][PK];
+  __shared__ double Bs[BN][PK];
   int tm, tn;
   {
     int t = blockIdx.x / bt.T;
@@ -528,69 +538,76 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
   }
   const long k0 = (long)blockIdx.y * kps;
   const long k1 = min(K, k0 + kps);
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  double acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lc = tid & 15, lr = tid >> 4;  // loader: column k, row (of 16 per pass)
   const long am0 = (long)tm * BM, bn0 = (long)tn * BN;
+  double ra[UA], rb[UB];
+  auto fetch = [&](long kb) {
+    const long gk = kb + lc;
+    const bool kok = gk < k1;
+    const double wk = (w && kok) ? w[gk] : 1.0;
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const long gm = am0 + lr + 16 * u;
+      ra[u] = (kok && gm < M) ? A[gm * lda + gk] * wk : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const long gn = bn0 + lr + 16 * u;
+      rb[u] = (kok && gn < N) ? B[gn * ldb + gk] : 0.0;
+    }
+  };
+  f64x4 acc[FI][FJ];
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  fetch(k0);
   for (long kb = k0; kb < k1; kb += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      int r = e % BM, c = e / BM;
-      long gm = am0 + r, gk = kb + c;
-      double val = 0.0;
-      if (gm < M && gk < k1) {
-        val = A[gm * lda + gk];
-        if (w) val *= w[gk];
-      }
-      As[c][r] = val;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int r = e % BN, c = e / BN;
-      long gn = bn0 + r, gk = kb + c;
-      Bs[c][r] = (gn < N && gk < k1) ? B[gn * ldb + gk] : 0.0;
-    }
+#pragma unroll
+    for (int u = 0; u < UA; ++u) As[lr + 16 * u][lc] = ra[u];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) Bs[lr + 16 * u][lc] = rb[u];
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < BK; ++kk) {
-      double a[TM], b[TN];
+    if (kb + BK < k1) fetch(kb + BK);
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty * TM + i];
+    for (int kk = 0; kk < BK; kk += 4) {
+      double fa[FI], fb[FJ];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx * TN + j];
+      for (int i = 0; i < FI; ++i) fa[i] = As[wm * WM + 16 * i + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int j = 0; j < FJ; ++j) fb[j] = Bs[wn * WN + 16 * j + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   double* P = part + (long)blockIdx.y * M * N;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      long row = am0 + ty * TM + i, col = bn0 + tx * TN + j;
-      if (row < M && col < N) P[row * N + col] = acc[i][j];
-    }
+    for (int j = 0; j < FJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = am0 + wm * WM + 16 * i + (lane >> 4) + 4 * r;
+        const long col = bn0 + wn * WN + 16 * j + (lane & 15);
+        if (row < M && col < N) P[row * N + col] = acc[i][j][r];
+      }
 }
 
 static hipError_t gemm_launch(hipStream_t s, int M, int N, long K, const double* A, long lda,
                               const double* B, long ldb, const double* w, double* part, long kps,
                               int n_split, int upper, int big, Batch bt, SeriesSkip sk) {
-  if (big) {
-    int ntm = cdiv(M, 128), ntn = cdiv(N, 128);
-    int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
-    hipLaunchKernelGGL((k_gemm_nt_f64<128, 128>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K,
-                       A, lda, B, ldb, w, part, kps, upper, ntn, bt, sk);
-  } else {
-    int ntm = cdiv(M, 64), ntn = cdiv(N, 64);
-    int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
-    hipLaunchKernelGGL((k_gemm_nt_f64<64, 64>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K, A,
-                       lda, B, ldb, w, part, kps, upper, ntn, bt, sk);
-  }
+  // 64 x 64 tiles for every shape: 4 waves per SIMD hide the load latency that the
+  // 128 x 128 tile (one wave per SIMD, 275 registers) leaves exposed.
+  (void)big;
+  int ntm = cdiv(M, 64), ntn = cdiv(N, 64);
+  int nt = upper ? ntm * (ntm + 1) / 2 : ntm * ntn;
+  hipLaunchKernelGGL((k_gemm_nt_f64<64, 64>), dim3(nt * bt.T, n_split), dim3(256), 0, s, M, N, K, A, lda, B, ldb,
+                     w, part, kps, upper, ntn, bt, sk);
   return hipGetLastError();
 }
 
@@ -654,82 +671,93 @@ __global__ __launch_bounds__(256) void k_smalltall_f64(int N, long ng, const dou
                                                        const double* __restrict__ psi,
                                                        double* __restrict__ out, int tri, int T,
                                                        const int* active) {
-  // Tile: 64 rows of W x 128 grid points; thread (ty, tx) owns rows ty*4..+3 and
-  // points tx*8..+7 (vector FP64 FMA), K chunk 16 over orbitals j.
+  // Tile: 64 rows of W x 128 grid points on FP64 matrix instructions (layout as in
+  // k_gemm_nt_f64); 2 x 2 waves, wave (wm, wn) owns rows 32 wm.. and points 64 wn..
+  // as 2 x 4 blocks of 16 x 16; K chunk 16 over orbitals j, loaded coalesced (W along
+  // its rows, psi along the grid) and prefetched one chunk ahead.
   constexpr int BM = 64, BN = 128, BK = 16;
-  __shared__ double Ws[BK][BM + 2];
+  __shared__ double Ws[BM][BK + 1];
   __shared__ double Ps[BK][BN + 2];
-  __shared__ double red[16][BN];
+  __shared__ double red[2][BN];
   const int tb = blockIdx.x % T;
   if (active && !active[tb]) return;
   W += (long)tb * N * N;
   out += MODE == 0 ? (long)tb * N * ng : (long)tb * ng;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
   const long r0 = (long)(blockIdx.x / T) * BN;
-  double rho_part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double rho_part[4] = {0.0, 0.0, 0.0, 0.0};
   const int nI = cdiv(N, BM);
   for (int I = 0; I < nI; ++I) {
-    double acc[4][8];
+    f64x4 acc[2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+      for (int j = 0; j < 4; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
     int jlo = 0, jhi = N;
     if (tri == 1) jlo = I * BM;
     if (tri == 2) jhi = min(N, (I + 1) * BM);
+    double rw[4], rp[8];
+    auto fetch = [&](int jb) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {  // W rows (tid >> 4) + 16 u, column jb + (tid & 15)
+        const int gi = I * BM + (tid >> 4) + 16 * u, gj = jb + (tid & 15);
+        rw[u] = (gi < N && gj < jhi) ? W[(long)gi * N + gj] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {  // psi row jb + (tid >> 7) + 2 u, point r0 + (tid & 127)
+        const int gj = jb + (tid >> 7) + 2 * u;
+        const long gr = r0 + (tid & 127);
+        rp[u] = (gj < jhi && gr < ng) ? psi[(long)gj * ng + gr] : 0.0;
+      }
+    };
+    if (jlo < jhi) fetch(jlo);
     for (int jb = jlo; jb < jhi; jb += BK) {
-      for (int e = tid; e < BM * BK; e += 256) {
-        int r = e % BM, c = e / BM;
-        int gi = I * BM + r, gj = jb + c;
-        Ws[c][r] = (gi < N && gj < jhi) ? W[(long)gi * N + gj] : 0.0;
-      }
-      for (int e = tid; e < BK * BN; e += 256) {
-        int c = e / BN, r = e % BN;
-        int gj = jb + c;
-        long gr = r0 + r;
-        Ps[c][r] = (gj < jhi && gr < ng) ? psi[(long)gj * ng + gr] : 0.0;
-      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Ws[(tid >> 4) + 16 * u][tid & 15] = rw[u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Ps[(tid >> 7) + 2 * u][tid & 127] = rp[u];
       __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < BK; ++kk) {
-        double a[4], b[8];
+      if (jb + BK < jhi) fetch(jb + BK);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = Ws[kk][ty * 4 + i];
+      for (int kk = 0; kk < BK; kk += 4) {
+        double fa[2], fb[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) b[j] = Ps[kk][tx * 8 + j];
+        for (int i = 0; i < 2; ++i) fa[i] = Ws[wm * 32 + 16 * i + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) fb[j] = Ps[kk + (lane >> 4)][wn * 64 + 16 * j + (lane & 15)];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int row = I * BM + ty * 4 + i;
-      if (row >= N) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        long col = r0 + tx * 8 + j;
-        if (col < ng) {
-          if (MODE == 0) out[(long)row * ng + col] = acc[i][j];
-          else rho_part[j] += psi[(long)row * ng + col] * acc[i][j];
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = I * BM + wm * 32 + 16 * i + (lane >> 4) + 4 * r;
+          const long col = r0 + wn * 64 + 16 * j + (lane & 15);
+          if (row < N && col < ng) {
+            if (MODE == 0) out[(long)row * ng + col] = acc[i][j][r];
+            else rho_part[j] += psi[(long)row * ng + col] * acc[i][j][r];
+          }
         }
-      }
-    }
   }
   if (MODE == 1) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) red[ty][tx * 8 + j] = rho_part[j];
-    __syncthreads();
-    if (tid < BN) {
-      double a = 0.0;
-      for (int q = 0; q < 16; ++q) a += red[q][tid];
-      if (r0 + tid < ng) out[r0 + tid] = a;
+    for (int j = 0; j < 4; ++j) {
+      rho_part[j] += __shfl_xor(rho_part[j], 16);
+      rho_part[j] += __shfl_xor(rho_part[j], 32);
+      if (lane < 16) red[wm][wn * 64 + 16 * j + lane] = rho_part[j];
     }
+    __syncthreads();
+    if (tid < BN && r0 + tid < ng) out[r0 + tid] = red[0][tid] + red[1][tid];
   }
 }
-
 hipError_t smalltall_f64(hipStream_t s, int N, long ng, const double* W, const double* psi,
                          double* out, int mode, int tri, int T, const int* active) {
   dim3 grid(cdiv(ng, 128) * T);

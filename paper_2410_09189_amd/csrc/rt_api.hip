@@ -329,15 +329,15 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
 }
 
 void choose_split(SysDev& d) {
-  d.big = d.N >= 128 ? 1 : 0;
-  int tile = d.big ? 128 : 64;
-  int ntm = (d.N + tile - 1) / tile;
+  // FP64 projection: 64 x 64 upper tiles, K chunks of 16, ~2048 blocks
+  d.big = 0;
+  int ntm = (d.N + 63) / 64;
   int tiles = ntm * (ntm + 1) / 2;
-  long target = 1024;
+  long target = 2048;
   long ns = (target + tiles - 1) / tiles;
   long maxs = std::max(1L, d.ng / 1024);
   ns = std::min(ns, maxs);
-  int bk = d.big ? 16 : 32;
+  const int bk = 16;
   long kps = (d.ng + ns - 1) / ns;
   kps = (kps + bk - 1) / bk * bk;
   d.kps = kps;
