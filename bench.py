@@ -158,6 +158,25 @@ def run_leg(rt, torch, sa, s, args, precision, hupdate, h_thrs, dp_thrs, profile
     return leg
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel's source file
+    has changed since the counters were taken."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC_FILE))["kernels"][key]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def roofline_of(prof, N, ng, mixed, full):
     T = len(AXES)
     cands = [k for k in prof if prof[k][1] and roof(k, N, ng, mixed, T, full)]
@@ -166,13 +185,14 @@ def roofline_of(prof, N, ng, mixed, full):
     ms, launches = prof[dom]
     avg = ms / 1e3 / launches
     t_hbm, t_mfma = nbytes / PEAK_HBM, (flops / pk if flops else 0.0)
+    traffic = measured_traffic(dom if mixed else dom + "_fp64")
     if t_hbm >= t_mfma:
         return {"bound": "hbm", "kernel": dom, "achieved": nbytes / avg / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": nbytes / avg / PEAK_HBM, "traffic": None, "avg_launch_us": avg * 1e6,
+                "unit": "GB/s", "frac": nbytes / avg / PEAK_HBM, "traffic": traffic, "avg_launch_us": avg * 1e6,
                 "algorithmic_bytes_per_launch": nbytes}
     return {"bound": "mfma", "kernel": dom, "achieved": flops / avg / 1e12, "peak": pk / 1e12,
-            "unit": "TFLOP/s", "frac": flops / avg / pk, "traffic": None, "avg_launch_us": avg * 1e6,
-            "algorithmic_flops_per_launch": flops}
+            "unit": "TFLOP/s", "frac": flops / avg / pk, "traffic": traffic, "avg_launch_us": avg * 1e6,
+            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes}
 
 
 def main():
@@ -250,7 +270,8 @@ def main():
             "hbm_GBps_algorithmic": (2 * b * N * s.ng + b * s.ng) / t_apply / 1e9,
             "hbm_frac": (2 * b * N * s.ng + b * s.ng) / t_apply / PEAK_HBM,
             "stencil_only": {"avg_launch_us": t_st * 1e6, "algorithmic_bytes_per_launch": st_bytes,
-                             "achieved_GBps": st_bytes / t_st / 1e9, "frac": st_bytes / t_st / PEAK_HBM},
+                             "achieved_GBps": st_bytes / t_st / 1e9, "frac": st_bytes / t_st / PEAK_HBM,
+                             "traffic": measured_traffic("stencil_fd8_fp32" if dt_ else "stencil_fd8_fp64")},
         }
     mixed["ses"].close()
     del x64, y64, x32, y32
