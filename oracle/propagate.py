@@ -14,6 +14,8 @@ Paper passages:
     the update of H_1 is below H_thrs; then shift H_-1 <- H_0, H_0 <- H_1,
     P_0 <- P_1.
   * Delta-kick perturbation (Sec. Numerical Results, kick equation).
+  * External field (Algorithm 1 inputs and Magnus line): V_j = sum_q E_q(t_j) M_q
+    enters the midpoint as Omega = -i dt (H_0 + H_1 + V_(j-1) + V_j)/2, t_j = j dt.
 
 Readings where the paper is silent:
   * The kick is an instantaneous unitary at t = 0+, P(0+) = e^{-i kappa M_q}
@@ -23,6 +25,10 @@ Readings where the paper is silent:
     Omega, so every step does at least one Hamiltonian update.
   * The series is not stopped before k >= ceil(dt * w), w the Gershgorin width
     of Hbar, so a term on the rising part of the series cannot end it.
+  * The field's time origin is the kick (t_0 = 0); the self-consistency residual
+    compares Kohn-Sham Hamiltonians only (the field matrix is known exactly).
+  * Pulse shape (the paper names no shape): E(t) = a sin^2(pi t / tau)
+    sin(omega t + phase) along a fixed direction for 0 <= t <= tau, zero after.
 """
 
 import math
@@ -78,12 +84,26 @@ def kick(P0: np.ndarray, M: np.ndarray, kappa: float) -> np.ndarray:
     return propagate_exact(M, P0.astype(np.complex128), kappa)
 
 
+def pulse(t: float, amp: float, omega: float, tau: float, phase: float = 0.0, direction=(1.0, 0.0, 0.0)):
+    """Field vector (E_x, E_y, E_z) of a sin^2-envelope pulse at time t."""
+    if t < 0.0 or t > tau:
+        return np.zeros(3)
+    return amp * math.sin(math.pi * t / tau) ** 2 * math.sin(omega * t + phase) * np.asarray(direction, float)
+
+
+def field_matrix(model, e3) -> np.ndarray:
+    """V = E_x M_x + E_y M_y + E_z M_z (Algorithm 1, perturbation matrix)."""
+    return e3[0] * model.M[0] + e3[1] * model.M[1] + e3[2] * model.M[2]
+
+
 def run(model, rp, method: str = "exact", predictor: str = "linear", record_p: bool = False,
-        P_start=None, H_start=None):
+        P_start=None, H_start=None, field=None):
     """Self-consistent midpoint time loop (Algorithm 1, time integration block).
 
     method: "exact" (spectral exponential, the fixed point the method converges
     to) or "series" (the commutator series of Algorithm 1).
+    field: optional callable t -> (E_x, E_y, E_z); V(t) = sum_q E_q(t) M_q is
+    added to the midpoint Hamiltonian as (V(t_(j-1)) + V(t_j))/2.
     Returns a dict with per-step dipole mu[j, 3], energy E[j], trace N[j],
     update counts scf[j] and series terms.
     """
@@ -106,8 +126,11 @@ def run(model, rp, method: str = "exact", predictor: str = "linear", record_p: b
     for j in range(1, rp.n_steps + 1):
         H1 = 2.0 * H0 - Hm1 if predictor == "linear" else H0.copy()
         n_terms = 0
+        Vbar = 0.0
+        if field is not None:
+            Vbar = 0.5 * (field_matrix(model, field((j - 1) * rp.dt)) + field_matrix(model, field(j * rp.dt)))
         for m in range(1, rp.max_scf + 1):
-            Hbar = 0.5 * (H0 + H1)
+            Hbar = 0.5 * (H0 + H1) + Vbar
             if method == "exact":
                 P1 = propagate_exact(Hbar, P, rp.dt)
             else:

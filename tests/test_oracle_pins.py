@@ -361,3 +361,68 @@ def test_spectrum_sum_rule_on_analytic_signal():
     assert abs(integral - np.sum(4 * w0 * c)) < 0.02 * np.sum(4 * w0 * c)
     for w in w0:
         assert S[np.argmin(np.abs(om - w))] > 0
+
+
+# ---------------------------------------------------------------------------
+# External field V_j = sum_q E_q(t_j) M_q in the midpoint (Algorithm 1)
+# ---------------------------------------------------------------------------
+def _frozen_c1():
+    s = c1_system()
+    psi, eps = c1_ground_state()
+    base = c1_model()
+    rho_gs = hamiltonian.density(np.diag(s.occupations()), base.psi)
+    return s, eps, oracle.Model(s, psi, frozen_rho=rho_gs)
+
+
+def test_constant_field_frozen_hxc_closed_form():
+    """With the Hartree-exchange potential frozen, H = diag(eps) is constant; a
+    constant field E0 along x makes the midpoint step exact, so
+    P(t) = exp(-i (H + E0 M_x) t) P0 exp(+i (H + E0 M_x) t)."""
+    s, eps, m = _frozen_c1()
+    rp = synth.config_run("c1_parity_32", n_steps=60)
+    rp.kappa = 0.0
+    E0 = 2e-3
+    out = oracle.run(m, rp, field=lambda t: (E0, 0.0, 0.0))
+    Htot = np.diag(eps[: m.N]) + E0 * m.M[0]
+    w, W = np.linalg.eigh(Htot)
+    P0 = np.diag(s.occupations()).astype(complex)
+    for j in (1, 17, 60):
+        U = (W * np.exp(-1j * w * j * rp.dt)[None, :]) @ W.T
+        mu = np.real(np.trace(U @ P0 @ U.conj().T @ m.M[0]))
+        assert abs(mu - out["mu"][j, 0]) < 1e-9
+    assert abs(out["mu"][60, 0] - out["mu"][0, 0]) > 1e-5  # the field did act
+
+
+def test_pulse_midpoint_converges_at_second_order():
+    """Trapezoid field average + first Magnus term: local error O(dt^3), so the
+    dipole at a fixed time converges as dt^2 (frozen Hxc, sin^2 pulse)."""
+    from oracle.propagate import pulse
+
+    s, eps, m = _frozen_c1()
+    T = 2.0
+    f = lambda t: pulse(t, 5e-3, 1.0, T, 0.3, (1.0, 0.5, 0.0))  # noqa: E731
+
+    def mu_end(dt):
+        rp = synth.config_run("c1_parity_32", n_steps=int(round(T / dt)), dt=dt)
+        rp.kappa = 0.0
+        return oracle.run(m, rp, field=f)["mu"][-1]
+
+    ref = mu_end(T / 1280)
+    errs = [np.max(np.abs(mu_end(T / n) - ref)) for n in (40, 80, 160)]
+    for a, b in zip(errs, errs[1:]):
+        assert 3.7 < a / b < 4.3, errs
+
+
+def test_weak_pulse_response_is_linear_in_amplitude():
+    from oracle.propagate import pulse
+
+    s, eps, m = _frozen_c1()
+    rp = synth.config_run("c1_parity_32", n_steps=60)
+    rp.kappa = 0.0
+    resp = []
+    for a in (1e-4, 2e-4):
+        out = oracle.run(m, rp, field=lambda t, a=a: pulse(t, a, 2.0, 2.0, 0.0, (0.0, 1.0, 0.0)))
+        resp.append(out["mu"] - out["mu"][0])
+    d1, d2 = resp
+    assert np.max(np.abs(d1)) > 1e-8
+    assert np.max(np.abs(d2 - 2 * d1)) < 1e-3 * np.max(np.abs(d1))
