@@ -128,6 +128,16 @@ typedef struct {
   const int* traj_axis;      /* [n_traj] 0 = x, 1 = y, 2 = z                     */
   const float* mlp_params;   /* RT_PRED_MLP: packed network (host, rt_mlp_n_params of
                                 rt_mlp_dims floats, layout under "Learned predictor")   */
+  /* External field (Algorithm 1 inputs E_x(t), E_y(t), E_z(t)), nullable; host
+     [n_traj][7] = a, omega, tau, phase, d_x, d_y, d_z per trajectory:
+       E(t) = a sin^2(pi t / tau) sin(omega t + phase) (d_x, d_y, d_z), 0 <= t <= tau,
+       E(t) = 0 otherwise, t measured from the kick (t_j = j dt after j steps).
+     V(t) = sum_q E_q(t) M_q enters the midpoint of step j -> j+1 as
+     (V(t_j) + V(t_(j+1)))/2 (Magnus line of Algorithm 1); the self-consistency
+     residual compares the Kohn-Sham part only.  Requires tau > 0.              */
+  const double* traj_field;
+  int magnus_order;          /* 0 or 2: Omega_1 only (the paper's midpoint); other
+                                values are rejected (RT_EINVAL)                     */
 } rt_run;
 
 /* Per-trajectory, per-step counters written by rt_step when stats != NULL. */

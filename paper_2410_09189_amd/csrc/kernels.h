@@ -97,10 +97,13 @@ hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
 hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* kmin_out, double* rows, int T,
                       const int* active);
 // series start: Pout = dP = Pin; Hbar = (H0 + H1)/2 when H0 != nullptr; slots, stop flags and
-// resid (nullable) zeroed; kmin from the Gershgorin width of Hbar (rows: scratch [T][N][2])
+// resid (nullable) zeroed; kmin from the Gershgorin width of Hbar (rows: scratch [T][N][2]).
+// fieldp (nullable, needs H0): per-trajectory pulse parameters [T][7]; Hbar then also gets
+// (V(t_a) + V(t_a + dt))/2 with V = sum_q E_q M_q (M3: [3][N^2]).
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
-                        int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active);
+                        int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active,
+                        const double* fieldp, const double* M3, double t_a);
 // slot[t] = max |a_t - b_t| (atomic max; zeroed beforehand), then b_t = a_t
 hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, unsigned long long* slot, int T,
                            const int* active);

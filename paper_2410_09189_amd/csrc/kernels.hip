@@ -1259,12 +1259,22 @@ hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* 
 // 2 N^2 each); when H0 != nullptr also Hbar = (H0 + H1)/2; block 0 of each
 // trajectory zeroes its term slots, stop flags and residual slot.  kmin =
 // ceil(|dt| (max_i (h_ii + r_i) - min_i (h_ii - r_i))) of Hbar (Gershgorin) follows
-// from the row kernels, reading (H0 + H1)/2 directly when given.
+// from the row kernels, reading (H0 + H1)/2 directly when given.  With pulse
+// parameters (fieldp[t] = a, omega, tau, phase, d_x, d_y, d_z), Hbar also takes the
+// external field (V(t_a) + V(t_b))/2, V(t) = sum_q E_q(t) M_q (Algorithm 1).
+__device__ __forceinline__ double pulse_env(const double* f, double t) {
+  if (!(t >= 0.0 && t <= f[2])) return 0.0;
+  const double s = sin(M_PI * t / f[2]);
+  return f[0] * s * s * sin(f[1] * t + f[3]);
+}
+
 __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__ Pin, double* __restrict__ Pout,
                                                       double* __restrict__ dP, const double* __restrict__ H0,
                                                       const double* __restrict__ H1, double* Hbar, int N,
                                                       unsigned long long* slots, int stride, int* done,
-                                                      unsigned long long* resid, const int* active) {
+                                                      unsigned long long* resid, const int* active,
+                                                      const double* __restrict__ fieldp,
+                                                      const double* __restrict__ M3, double t_a, double t_b) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   const long NN = (long)N * N;
@@ -1276,11 +1286,23 @@ __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__
     H0 += t * NN;
     H1 += t * NN;
   }
+  double cq[3] = {0.0, 0.0, 0.0};
+  if (fieldp) {
+    const double* f = fieldp + 7L * t;
+    const double s = 0.5 * (pulse_env(f, t_a) + pulse_env(f, t_b));
+    cq[0] = s * f[4];
+    cq[1] = s * f[5];
+    cq[2] = s * f[6];
+  }
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * NN; e += (long)gridDim.x * blockDim.x) {
     double v = Pin[e];
     Pout[e] = v;
     dP[e] = v;
-    if (H0 && e < NN) Hbar[e] = 0.5 * H0[e] + 0.5 * H1[e];
+    if (H0 && e < NN) {
+      double hb = 0.5 * H0[e] + 0.5 * H1[e];
+      if (fieldp) hb += (cq[0] * M3[e] + cq[1] * M3[NN + e]) + cq[2] * M3[2 * NN + e];
+      Hbar[e] = hb;
+    }
   }
   if (blockIdx.x != 0) return;
   for (int q = threadIdx.x; q < stride; q += 256) slots[(long)t * stride + q] = 0ULL;
@@ -1292,12 +1314,16 @@ __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__
 }
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
-                        int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active) {
+                        int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active,
+                        const double* fieldp, const double* M3, double t_a) {
+  if (fieldp && !(H0 && M3)) return hipErrorInvalidValue;
   long n2 = 2L * N * N;
   int nb = ew_blocks(n2) > 256 ? 256 : ew_blocks(n2);
   hipLaunchKernelGGL(k_series_begin, dim3(nb, T), dim3(256), 0, s, Pin, Pout, dP, H0, H1, Hbar, N, slots, stride,
-                     done, resid, active);
-  return gersh_launch(s, H0 ? H0 : Hbar, H0 ? H1 : nullptr, N, dt, kmin, rows, T, active);
+                     done, resid, active, fieldp, M3, t_a, t_a + dt);
+  // Gershgorin floor of the Hbar the series uses (read back when the field is in it)
+  const bool direct = H0 && !fieldp;
+  return gersh_launch(s, direct ? H0 : Hbar, direct ? H1 : nullptr, N, dt, kmin, rows, T, active);
 }
 
 // max_t |a_t - b_t| into slot[t] (zeroed beforehand), then b_t = a_t.

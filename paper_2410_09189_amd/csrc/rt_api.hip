@@ -158,6 +158,8 @@ struct SysDev {
   // per-trajectory state [T][...]
   double *P0, *P1, *dP, *dPn, *C;          // stacked [S'; A'], 2 N^2 each
   double* gwork = nullptr;                 // Gershgorin rows [T][N][2] / observable partials [T][160]
+  double* fieldp = nullptr;                // pulse parameters per slot [T][7]
+  bool field = false;                      // any slot with a nonzero pulse amplitude
   double *H0, *H1, *Hm1, *Hn, *Hbar;       // N^2 each
   double* hist;                            // [T][cap + 1][5]
   double* kmin;                            // [T]
@@ -183,6 +185,7 @@ inline rtk::MlpDims pred_dims() { return rtk::MlpDims{kNIn, kNH, kNOut}; }
 struct TrajDev {
   int sys, slot, axis;
   double kappa;
+  double field[7];  // a, omega, tau, phase, d_x, d_y, d_z (a = 0: no field)
 };
 
 }  // namespace
@@ -318,6 +321,15 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
       }
   }
   if (run->hupdate != RT_HUPDATE_FULL && run->hupdate != RT_HUPDATE_LOCAL) { why = "hupdate"; return RT_EINVAL; }
+  if (run->magnus_order != 0 && run->magnus_order != 2) { why = "magnus_order must be 0 or 2"; return RT_EINVAL; }
+  if (run->traj_field) {
+    for (int t = 0; t < run->n_traj; ++t) {
+      const double* f = run->traj_field + 7L * t;
+      for (int q = 0; q < 7; ++q)
+        if (!std::isfinite(f[q])) { why = "traj_field must be finite"; return RT_EINVAL; }
+      if (f[0] != 0.0 && !(f[2] > 0.0)) { why = "traj_field: pulse duration tau must be positive"; return RT_EINVAL; }
+    }
+  }
   if (run->n_traj < 0 || (run->n_traj > 0 && (!run->traj_sys || !run->traj_kappa || !run->traj_axis))) {
     why = "trajectory arrays"; return RT_EINVAL;
   }
@@ -423,6 +435,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.Hn = a.take<double>(T * NN);
     d.Hbar = a.take<double>(T * NN);
     d.hist = a.take<double>(T * 5L * (hist_cap + 1));
+    d.fieldp = a.take<double>(T * 7L);
     d.kmin = a.take<double>(T);
     d.slots = a.take<unsigned long long>(T * (run.max_terms + 2));
     d.resid = a.take<unsigned long long>(T);
@@ -477,6 +490,7 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
     T[t].slot = (int)d.slot_traj.size();
     T[t].axis = run->traj_axis[t];
     T[t].kappa = run->traj_kappa[t];
+    for (int q = 0; q < 7; ++q) T[t].field[q] = run->traj_field ? run->traj_field[7L * t + q] : 0.0;
     d.slot_traj.push_back(t);
   }
   for (auto& d : S) {
@@ -623,7 +637,8 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
 // (kmin, slots, done, dP, dPn, C) are the system's, offset by `first`.
 rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const std::vector<int>& act_host,
                  const double* Hbar, double dt, const double* Pin, double* Pout, std::vector<int>& terms,
-                 const double* H0 = nullptr, const double* H1 = nullptr, unsigned long long* resid = nullptr) {
+                 const double* H0 = nullptr, const double* H1 = nullptr, unsigned long long* resid = nullptr,
+                 double t_a = 0.0) {
   hipStream_t s = c->stream;
   const long NN = nsq(d.N), n2 = 2 * NN;
   const int max_terms = c->run.max_terms;
@@ -637,8 +652,11 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
   int* done = d.done + 2 * first;
   {
     Timed tm(c, PH_SMALL);
+    // the external field joins the midpoint Hamiltonian of a time step (H0 given):
+    // + (V(t_a) + V(t_a + dt))/2, V = sum_q E_q M_q
+    const double* fp = (H0 && d.field) ? d.fieldp + 7L * first : nullptr;
     CK(rtk::series_begin(s, Pin, Pout, dP, H0, H1, const_cast<double*>(Hbar), d.N, dt, kmin, slots, stride, done,
-                         resid, d.gwork, T, act));
+                         resid, d.gwork, T, act, fp, d.M3, t_a));
   }
   int k = 1;
   const int CH = 8;
@@ -809,6 +827,19 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
     std::vector<int> terms, on(1, 1);
     RET(series(c, d, t, 1, nullptr, on, d.Hbar + t * NN, tr.kappa, d.P1 + t * 2 * NN, d.P0 + t * 2 * NN, terms));
   }
+  {
+    // pulse parameters per slot (zero amplitude where the trajectory has no field)
+    std::vector<double> fp((long)d.T * 7, 0.0);
+    d.field = false;
+    for (int t = 0; t < d.T; ++t) {
+      int g = d.slot_traj[t];
+      if (g < 0) continue;
+      for (int q = 0; q < 7; ++q) fp[7L * t + q] = c->traj[g].field[q];
+      d.field = d.field || fp[7L * t] != 0.0;
+    }
+    CK(hipMemcpyAsync(d.fieldp, fp.data(), fp.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));
+  }
   std::vector<int> all(d.T, 1);
   RET(eval_h(c, d, d.T, nullptr, all, d.P0, 2 * NN, d.H0, false));
   CK(rtk::copy_d(st, d.Hm1, d.H0, (long)d.T * NN));
@@ -843,7 +874,8 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   int n_active = T;
   for (int m = 1; m <= run.max_scf && n_active > 0; ++m) {
     std::vector<int> terms;
-    RET(series(c, d, 0, T, d.active, d.active_host, d.Hbar, run.dt, d.P0, d.P1, terms, d.H0, d.H1, d.resid));
+    RET(series(c, d, 0, T, d.active, d.active_host, d.Hbar, run.dt, d.P0, d.P1, terms, d.H0, d.H1, d.resid,
+               d.step * run.dt));
     RET(eval_h(c, d, T, d.active, d.active_host, d.P1, 2 * NN, d.Hn, false));
     {
       Timed tm(c, PH_SMALL);

@@ -42,6 +42,7 @@ class rt_run(ctypes.Structure):
         ("precision", ctypes.c_int), ("predictor", ctypes.c_int), ("hupdate", ctypes.c_int),
         ("frozen_hxc", ctypes.c_int), ("n_traj", ctypes.c_int), ("traj_sys", _ip),
         ("traj_kappa", _dp), ("traj_axis", _ip), ("mlp_params", ctypes.POINTER(ctypes.c_float)),
+        ("traj_field", _dp), ("magnus_order", ctypes.c_int),
     ]
 
 
@@ -150,7 +151,7 @@ class SystemArgs:
 class RunArgs:
     def __init__(self, dt, n_steps_max, h_thrs, dp_thrs, max_scf, max_terms, traj_sys, traj_kappa,
                  traj_axis, precision=RT_FP64, predictor=RT_PRED_LINEAR, hupdate=RT_HUPDATE_FULL,
-                 frozen_hxc=False, mlp_params=None):
+                 frozen_hxc=False, mlp_params=None, traj_field=None, magnus_order=0):
         self.traj_sys = np.ascontiguousarray(traj_sys, dtype=np.int32)
         self.traj_kappa = np.ascontiguousarray(traj_kappa, dtype=np.float64)
         self.traj_axis = np.ascontiguousarray(traj_axis, dtype=np.int32)
@@ -164,6 +165,11 @@ class RunArgs:
         r.traj_axis = _ptr(self.traj_axis, ctypes.c_int)
         self.mlp_params = None if mlp_params is None else np.ascontiguousarray(mlp_params, dtype=np.float32)
         r.mlp_params = _ptr(self.mlp_params, ctypes.c_float)
+        # traj_field: per trajectory (a, omega, tau, phase, d_x, d_y, d_z) of a sin^2 pulse
+        self.traj_field = (None if traj_field is None else
+                           np.ascontiguousarray(np.reshape(traj_field, (r.n_traj, 7)), dtype=np.float64))
+        r.traj_field = _ptr(self.traj_field)
+        r.magnus_order = int(magnus_order)
         self.struct = r
 
 

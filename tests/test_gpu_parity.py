@@ -3,6 +3,8 @@ by element on the same seeded inputs.  Tolerances: FP64 stages within 1e-12
 relative of the oracle (rounding order only); whole trajectories within 1e-10
 a.u. on the dipole and energy."""
 
+import functools
+
 import numpy as np
 import pytest
 
@@ -304,3 +306,47 @@ def test_batched_trajectories_equal_single_runs_bitwise(precision, hupdate):
         single, _ = run((q,))
         assert np.array_equal(batch[q][0], single[0][0]), q
         assert np.array_equal(batch[q][1], single[0][1]), q
+
+
+# External field (sin^2 pulse along a tilted direction, no kick): the library adds
+# (V(t_j) + V(t_j+1))/2 to the midpoint Hamiltonian; parity with the oracle route.
+PULSE = (2e-3, 2.0, 4.0, 0.3, 1.0, 0.5, -0.2)  # a, omega, tau, phase, d_x, d_y, d_z
+PULSE_STEPS = 80
+
+
+@functools.lru_cache(maxsize=None)
+def _pulse_oracle_run():
+    from oracle.propagate import pulse
+
+    rp = synth.config_run("c1_parity_32", n_steps=PULSE_STEPS)
+    rp.kappa = 0.0
+    a, w, tau, ph = PULSE[:4]
+    return oracle.run(c1_model(), rp, field=lambda t: pulse(t, a, w, tau, ph, PULSE[4:]))
+
+
+@pytest.mark.parametrize("precision,hupdate", [(0, 0), (0, 1), (1, 1)])
+def test_c1_pulse_matches_oracle(precision, hupdate):
+    _say(f"C1 pulse {PULSE_STEPS} steps precision={precision} hupdate={hupdate}")
+    from paper_2410_09189_amd import rt
+
+    ref = _pulse_oracle_run()
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    rp = synth.config_run("c1_parity_32", n_steps=PULSE_STEPS, h_thrs=1e-9 if precision else 1e-12)
+    rp.kappa = 0.0
+    ses = _session([system_args(s, psi)], run_args(rp, hupdate=hupdate, precision=precision, traj_field=[PULSE]))
+    rt.rt_step(ses.ctx, PULSE_STEPS, n_traj=1)
+    mu, E, tr = rt.rt_dipole(ses.ctx, 0, 0, PULSE_STEPS + 1)
+    ses.close()
+    dmu = mu - mu[0]
+    dref = ref["mu"] - ref["mu"][0]
+    scale = np.max(np.abs(dref))
+    err = np.max(np.abs(dmu - dref))
+    print(f"pulse: max|dmu| {scale:.3e}, max err {err:.3e}", flush=True)
+    assert scale > 1e-5  # the field drove the system
+    if precision == 0:
+        assert np.max(np.abs(mu - ref["mu"])) < 1e-10
+        assert np.max(np.abs(E - ref["E"])) < 1e-10
+    else:
+        assert err < 1e-5 * scale
+    assert np.max(np.abs(tr - 16.0)) < 1e-12
