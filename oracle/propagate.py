@@ -16,6 +16,10 @@ Paper passages:
   * Delta-kick perturbation (Sec. Numerical Results, kick equation).
   * External field (Algorithm 1 inputs and Magnus line): V_j = sum_q E_q(t_j) M_q
     enters the midpoint as Omega = -i dt (H_0 + H_1 + V_(j-1) + V_j)/2, t_j = j dt.
+  * Fourth-order Magnus (Sec. Magnus expansion, eq. omega2 for a Hamiltonian
+    linear over the step): Omega = Omega_1 + Omega_2, Omega_2 = (dt^2/12)[H_0, H_1];
+    the series becomes dP^(k) = (1/k)(Omega dP^(k-1) + dP^(k-1) Omega^dagger)
+    (eq. commutator-expansion-general).
 
 Readings where the paper is silent:
   * The kick is an instantaneous unitary at t = 0+, P(0+) = e^{-i kappa M_q}
@@ -29,6 +33,9 @@ Readings where the paper is silent:
     compares Kohn-Sham Hamiltonians only (the field matrix is known exactly).
   * Pulse shape (the paper names no shape): E(t) = a sin^2(pi t / tau)
     sin(omega t + phase) along a fixed direction for 0 <= t <= tau, zero after.
+  * Omega_2 takes the full endpoint Hamiltonians including the field,
+    [H_0 + V_(j-1), H_1 + V_j]; its series stop floor is the Gershgorin width of
+    the Hermitian matrix i Omega.
 """
 
 import math
@@ -59,13 +66,38 @@ def gershgorin_width(A: np.ndarray) -> float:
     return float(np.max(d + r) - np.min(d - r))
 
 
-def propagate_series(Hbar: np.ndarray, P: np.ndarray, dt: float, thrs: float, max_terms: int = 200):
+def propagate_omega_exact(omega: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """P -> U P U^dagger, U = exp(Omega) for anti-Hermitian Omega, from the eigenpairs
+    of the Hermitian matrix i Omega (spectral form of the Magnus propagator)."""
+    w, W = np.linalg.eigh(1j * omega)
+    U = (W * np.exp(-1j * w)[None, :]) @ W.conj().T
+    return U @ P @ U.conj().T
+
+
+def gershgorin_width_herm(X: np.ndarray) -> float:
+    """Width of the Gershgorin interval of a Hermitian matrix (centres Re x_ii)."""
+    d = np.real(np.diag(X))
+    r = np.sum(np.abs(X), axis=1) - np.abs(np.diag(X))
+    return float(np.max(d + r) - np.min(d - r))
+
+
+def omega2(A0: np.ndarray, A1: np.ndarray, dt: float) -> np.ndarray:
+    """Second Magnus term for a Hamiltonian linear over the step: (dt^2/12)[A0, A1]."""
+    return dt * dt / 12.0 * (A0 @ A1 - A1 @ A0)
+
+
+def propagate_series(Hbar: np.ndarray, P: np.ndarray, dt: float, thrs: float, max_terms: int = 200,
+                     B: np.ndarray = None):
     """Commutator series for P(t + dt): dP^(0) = P,
-    dP^(k) = (1/k) (Omega dP^(k-1) + dP^(k-1) Omega^dagger) with Omega = -i dt Hbar,
-    i.e. (1/k)(-i dt)[Hbar, dP^(k-1)]; summed until max|dP^(k)| <= thrs.
-    Returns (P(t + dt), number of terms)."""
+    dP^(k) = (1/k) (Omega dP^(k-1) + dP^(k-1) Omega^dagger) with Omega = -i dt Hbar (+ B,
+    the real antisymmetric Omega_2 when given), i.e. (1/k)[Omega, dP^(k-1)]; summed
+    until max|dP^(k)| <= thrs.  Returns (P(t + dt), number of terms)."""
     omega = -1j * dt * Hbar
-    k_min = math.ceil(dt * gershgorin_width(Hbar))
+    if B is None:
+        k_min = math.ceil(dt * gershgorin_width(Hbar))
+    else:
+        omega = omega + B
+        k_min = math.ceil(gershgorin_width_herm(1j * omega))
     P1 = P.astype(np.complex128).copy()
     dP = P1.copy()
     k = 0
@@ -97,13 +129,14 @@ def field_matrix(model, e3) -> np.ndarray:
 
 
 def run(model, rp, method: str = "exact", predictor: str = "linear", record_p: bool = False,
-        P_start=None, H_start=None, field=None):
+        P_start=None, H_start=None, field=None, magnus_order: int = 2):
     """Self-consistent midpoint time loop (Algorithm 1, time integration block).
 
     method: "exact" (spectral exponential, the fixed point the method converges
     to) or "series" (the commutator series of Algorithm 1).
     field: optional callable t -> (E_x, E_y, E_z); V(t) = sum_q E_q(t) M_q is
     added to the midpoint Hamiltonian as (V(t_(j-1)) + V(t_j))/2.
+    magnus_order: 2 (Omega_1, the paper's midpoint) or 4 (adds Omega_2).
     Returns a dict with per-step dipole mu[j, 3], energy E[j], trace N[j],
     update counts scf[j] and series terms.
     """
@@ -126,15 +159,20 @@ def run(model, rp, method: str = "exact", predictor: str = "linear", record_p: b
     for j in range(1, rp.n_steps + 1):
         H1 = 2.0 * H0 - Hm1 if predictor == "linear" else H0.copy()
         n_terms = 0
-        Vbar = 0.0
+        Va = Vb = 0.0
         if field is not None:
-            Vbar = 0.5 * (field_matrix(model, field((j - 1) * rp.dt)) + field_matrix(model, field(j * rp.dt)))
+            Va, Vb = field_matrix(model, field((j - 1) * rp.dt)), field_matrix(model, field(j * rp.dt))
+        Vbar = 0.5 * (Va + Vb)
         for m in range(1, rp.max_scf + 1):
             Hbar = 0.5 * (H0 + H1) + Vbar
+            B = omega2(H0 + Va, H1 + Vb, rp.dt) if magnus_order == 4 else None
             if method == "exact":
-                P1 = propagate_exact(Hbar, P, rp.dt)
+                if B is None:
+                    P1 = propagate_exact(Hbar, P, rp.dt)
+                else:
+                    P1 = propagate_omega_exact(-1j * rp.dt * Hbar + B, P)
             else:
-                P1, kk = propagate_series(Hbar, P, rp.dt, rp.dp_thrs, rp.max_terms)
+                P1, kk = propagate_series(Hbar, P, rp.dt, rp.dp_thrs, rp.max_terms, B)
                 n_terms += kk
             Hn, aux = model.h_of_p(P1)
             r = float(np.max(np.abs(Hn - H1)))

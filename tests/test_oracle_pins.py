@@ -426,3 +426,45 @@ def test_weak_pulse_response_is_linear_in_amplitude():
     d1, d2 = resp
     assert np.max(np.abs(d1)) > 1e-8
     assert np.max(np.abs(d2 - 2 * d1)) < 1e-3 * np.max(np.abs(d1))
+
+
+# ---------------------------------------------------------------------------
+# Fourth-order Magnus: Omega = Omega_1 + (dt^2/12)[H_0, H_1]
+# ---------------------------------------------------------------------------
+def test_magnus4_reduces_to_midpoint_when_hamiltonians_commute():
+    """Frozen Hartree-exchange and no field: H_0 = H_1 at every step, Omega_2 = 0."""
+    s, eps, m = _frozen_c1()
+    rp = synth.config_run("c1_parity_32", n_steps=30)
+    a = oracle.run(m, rp)
+    b = oracle.run(m, rp, magnus_order=4)
+    assert np.max(np.abs(a["mu"] - b["mu"])) < 1e-11  # rounding of the complex eigensolver path
+
+
+def test_magnus4_converges_at_fourth_order_for_a_linear_hamiltonian():
+    """H(t) = H + alpha t M_x is linear in t (frozen Hxc, field ramp): the two-term
+    Magnus step has local error O(dt^5), the midpoint O(dt^3)."""
+    s, eps, m = _frozen_c1()
+    T, alpha = 2.0, 0.05
+    ramp = lambda t: (alpha * t, 0.0, 0.0)  # noqa: E731
+
+    def mu_end(n, order):
+        rp = synth.config_run("c1_parity_32", n_steps=n, dt=T / n)
+        rp.kappa = 0.0
+        return oracle.run(m, rp, field=ramp, magnus_order=order)["mu"][-1]
+
+    ref = mu_end(640, 4)
+    e4 = [np.max(np.abs(mu_end(n, 4) - ref)) for n in (10, 20, 40)]
+    e2 = [np.max(np.abs(mu_end(n, 2) - ref)) for n in (10, 20, 40)]
+    for a, b in zip(e4, e4[1:]):
+        assert 13.0 < a / b < 19.0, e4
+    for a, b in zip(e2, e2[1:]):
+        assert 3.5 < a / b < 4.5, e2
+    assert e4[-1] < 1e-2 * e2[-1]
+
+
+def test_magnus4_self_consistent_run_keeps_trace_and_idempotency():
+    rp = synth.config_run("c1_parity_32", n_steps=20, dt=0.2)
+    out = oracle.run(c1_model(), rp, magnus_order=4, record_p=True, method="series")
+    assert np.max(np.abs(out["trace"] - 16.0)) < 1e-12
+    for P in out["Ps"][::5]:
+        assert np.max(np.abs(P @ P / 2.0 - P)) < 1e-11
