@@ -100,10 +100,15 @@ hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* 
 // resid (nullable) zeroed; kmin from the Gershgorin width of Hbar (rows: scratch [T][N][2]).
 // fieldp (nullable, needs H0): per-trajectory pulse parameters [T][7]; Hbar then also gets
 // (V(t_a) + V(t_a + dt))/2 with V = sum_q E_q M_q (M3: [3][N^2]).
+// Bm (nullable): Omega_2, whose i Bm / dt joins Hbar in the Gershgorin floor.
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
                         int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active,
-                        const double* fieldp, const double* M3, double t_a);
+                        const double* fieldp, const double* M3, double t_a, const double* Bm);
+// Omega_2 = (dt^2/12)[H0 + V(t_a), H1 + V(t_a + dt)] into B ([T][N^2]); A0, A1, X: scratch [T][N^2]
+hipError_t magnus2(hipStream_t s, const double* H0, const double* H1, const double* fieldp, const double* M3,
+                   double t_a, double dt, double* A0, double* A1, double* X, double* B, int N, int T,
+                   const int* active);
 // slot[t] = max |a_t - b_t| (atomic max; zeroed beforehand), then b_t = a_t
 hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, unsigned long long* slot, int T,
                            const int* active);
@@ -112,9 +117,10 @@ hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, un
 hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, const double* dP, double* C,
                               int k, const unsigned long long* slots, int stride, const double* kmin,
                               double thrs, const int* done, const int* active);
-hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1, int N, double dt, int k,
-                         unsigned long long* slots, int stride, const double* kmin, double thrs, int* done,
-                         int T, const int* active);
+// C2 (nullable): B . [S;A]^T for Omega_2 = B
+hipError_t series_update(hipStream_t s, const double* C, const double* C2, double* dPn, double* P1, int N,
+                         double dt, int k, unsigned long long* slots, int stride, const double* kmin, double thrs,
+                         int* done, int T, const int* active);
 hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, int stride,
                          const double* kmin, double thrs, int* done, int T, const int* active);
 // rows_t = (mu_x, mu_y, mu_z, E, TrP) from S'_t (stride 2N^2) and eparts_t; work: [T][160]

@@ -1202,8 +1202,11 @@ hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
 // Gershgorin rows of A_t (or of (A_t + A2_t)/2 when A2 != nullptr, the value the
 // series uses for Hbar): rows[t][i] = (a_ii + r_i, a_ii - r_i), r_i = sum_{j != i} |a_ij|.
 // One wave per row (lanes stride the row, fixed shuffle tree), blockIdx.y = t.
+// With Bm (Omega_2, real antisymmetric) the rows are those of i Omega / dt = Hbar + i Bm / dt:
+// off-diagonal moduli sqrt(h_ij^2 + (b_ij / dt)^2).
 __global__ __launch_bounds__(256) void k_gersh_rows(const double* __restrict__ A, const double* __restrict__ A2,
-                                                    int N, double* __restrict__ rows, const int* active) {
+                                                    int N, double* __restrict__ rows, const int* active,
+                                                    const double* __restrict__ Bm, double inv_dt) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1211,10 +1214,13 @@ __global__ __launch_bounds__(256) void k_gersh_rows(const double* __restrict__ A
   const long NN = (long)N * N;
   const double* a = A + t * NN + (long)i * N;
   const double* a2 = A2 ? A2 + t * NN + (long)i * N : nullptr;
+  const double* b = Bm ? Bm + t * NN + (long)i * N : nullptr;
   double r = 0.0, dg = 0.0;
   for (int j = lane; j < N; j += 64) {
     const double v = a2 ? 0.5 * a[j] + 0.5 * a2[j] : a[j];
-    if (j != i) r += fabs(v); else dg = v;
+    if (j == i) dg = v;
+    else if (b) r += sqrt(v * v + (b[j] * inv_dt) * (b[j] * inv_dt));
+    else r += fabs(v);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -1244,8 +1250,8 @@ __global__ __launch_bounds__(256) void k_gersh_final(const double* __restrict__ 
 }
 
 static hipError_t gersh_launch(hipStream_t s, const double* A, const double* A2, int N, double dt, double* kmin,
-                               double* rows, int T, const int* active) {
-  hipLaunchKernelGGL(k_gersh_rows, dim3(cdiv(N, 4), T), dim3(256), 0, s, A, A2, N, rows, active);
+                               double* rows, int T, const int* active, const double* Bm = nullptr) {
+  hipLaunchKernelGGL(k_gersh_rows, dim3(cdiv(N, 4), T), dim3(256), 0, s, A, A2, N, rows, active, Bm, 1.0 / dt);
   hipLaunchKernelGGL(k_gersh_final, dim3(T), dim3(256), 0, s, rows, N, dt, kmin, active);
   return hipGetLastError();
 }
@@ -1315,7 +1321,7 @@ __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
                         int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active,
-                        const double* fieldp, const double* M3, double t_a) {
+                        const double* fieldp, const double* M3, double t_a, const double* Bm) {
   if (fieldp && !(H0 && M3)) return hipErrorInvalidValue;
   long n2 = 2L * N * N;
   int nb = ew_blocks(n2) > 256 ? 256 : ew_blocks(n2);
@@ -1323,7 +1329,57 @@ hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* 
                      done, resid, active, fieldp, M3, t_a, t_a + dt);
   // Gershgorin floor of the Hbar the series uses (read back when the field is in it)
   const bool direct = H0 && !fieldp;
-  return gersh_launch(s, direct ? H0 : Hbar, direct ? H1 : nullptr, N, dt, kmin, rows, T, active);
+  return gersh_launch(s, direct ? H0 : Hbar, direct ? H1 : nullptr, N, dt, kmin, rows, T, active, Bm);
+}
+
+// Fourth-order Magnus term Omega_2 = (dt^2/12)[A0, A1] for the endpoint Hamiltonians
+// A0 = H0 + V(t_a), A1 = H1 + V(t_a + dt) (V from the pulse parameters, or none):
+// endpoints into A0/A1 (only with a field), X = A0 . A1^T = A0 A1 by the FP64 GEMM,
+// B = (dt^2/12)(X - X^T).
+__global__ void k_magnus2_ends(const double* __restrict__ H0, const double* __restrict__ H1,
+                               const double* __restrict__ fieldp, const double* __restrict__ M3, double t_a,
+                               double t_b, double* __restrict__ A0, double* __restrict__ A1, int N,
+                               const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  const long NN = (long)N * N;
+  const double* f = fieldp + 7L * t;
+  const double ea = pulse_env(f, t_a), eb = pulse_env(f, t_b);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += (long)gridDim.x * blockDim.x) {
+    const double v = (f[4] * M3[e] + f[5] * M3[NN + e]) + f[6] * M3[2 * NN + e];
+    A0[t * NN + e] = H0[t * NN + e] + ea * v;
+    A1[t * NN + e] = H1[t * NN + e] + eb * v;
+  }
+}
+__global__ void k_antisym_scale(const double* __restrict__ X, double* __restrict__ B, int N, double c,
+                                const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  const long NN = (long)N * N;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e - (long)i * N);
+    B[t * NN + e] = c * (X[t * NN + e] - X[t * NN + (long)j * N + i]);
+  }
+}
+hipError_t magnus2(hipStream_t s, const double* H0, const double* H1, const double* fieldp, const double* M3,
+                   double t_a, double dt, double* A0, double* A1, double* X, double* B, int N, int T,
+                   const int* active) {
+  const long NN = (long)N * N;
+  const int nb = ew_blocks(NN) > 256 ? 256 : ew_blocks(NN);
+  const double* e0 = H0;
+  const double* e1 = H1;
+  if (fieldp) {
+    hipLaunchKernelGGL(k_magnus2_ends, dim3(nb, T), dim3(256), 0, s, H0, H1, fieldp, M3, t_a, t_a + dt, A0, A1, N,
+                       active);
+    e0 = A0;
+    e1 = A1;
+  }
+  Batch bt{T, active, NN, NN, 0, NN};
+  SeriesSkip sk{nullptr, nullptr, nullptr, 0.0, 0, 0};
+  hipError_t err = gemm_launch(s, N, N, N, e0, N, e1, N, nullptr, X, N, 1, 0, 0, bt, sk);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_antisym_scale, dim3(nb, T), dim3(256), 0, s, X, B, N, dt * dt / 12.0, active);
+  return hipGetLastError();
 }
 
 // max_t |a_t - b_t| into slot[t] (zeroed beforehand), then b_t = a_t.
@@ -1353,9 +1409,11 @@ hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, un
 // dP_k = (1/k)(-i dt)[Hbar, S + iA]:  S_k = (dt/k)[Hbar, A],  A_k = -(dt/k)[Hbar, S].
 // C = Hbar . [S; A]^T, so C[:, :N] = Hbar S and C[:, N:] = -Hbar A (S symmetric, A antisymmetric).
 // blockIdx.y = trajectory; C, dPn, P1 have stride 2 N^2.
-__global__ __launch_bounds__(256) void k_series_update(const double* __restrict__ C, double* __restrict__ dPn,
-                                                       double* __restrict__ P1, int N, double dt,
-                                                       SeriesSkip sk, int* done, const int* active) {
+// With Omega_2 = B (real antisymmetric), C2 = B . [S; A]^T adds (1/k)[B, S] =
+// (1/k)(C2_S + C2_S^T) to S_k and (1/k)[B, A] = (1/k)(-C2_A + C2_A^T) to A_k.
+__global__ __launch_bounds__(256) void k_series_update(const double* __restrict__ C, const double* __restrict__ C2,
+                                                       double* __restrict__ dPn, double* __restrict__ P1, int N,
+                                                       double dt, SeriesSkip sk, int* done, const int* active) {
   __shared__ double sh[256];
   const int t = blockIdx.y;
   if (active && !active[t]) return;
@@ -1366,10 +1424,11 @@ __global__ __launch_bounds__(256) void k_series_update(const double* __restrict_
     }
     return;
   }
-  const double f = dt / sk.k;
+  const double f = dt / sk.k, f2 = 1.0 / sk.k;
   const long NN = (long)N * N;
   const long N2 = 2L * N;
   C += t * 2 * NN;
+  if (C2) C2 += t * 2 * NN;
   dPn += t * 2 * NN;
   P1 += t * 2 * NN;
   double m = 0.0;
@@ -1379,6 +1438,10 @@ __global__ __launch_bounds__(256) void k_series_update(const double* __restrict_
     double gS_ij = C[(long)i * N2 + j], gS_ji = C[(long)j * N2 + i];
     double sv = -f * (gA_ij + gA_ji);
     double av = -f * (gS_ij - gS_ji);
+    if (C2) {
+      sv += f2 * (C2[(long)i * N2 + j] + C2[(long)j * N2 + i]);
+      av += f2 * (C2[(long)j * N2 + N + i] - C2[(long)i * N2 + N + j]);
+    }
     dPn[e] = sv;
     dPn[NN + e] = av;
     P1[e] += sv;
@@ -1389,14 +1452,14 @@ __global__ __launch_bounds__(256) void k_series_update(const double* __restrict_
   if (threadIdx.x == 0)
     atomic_max_nonneg(const_cast<unsigned long long*>(sk.slots) + (long)t * sk.stride + sk.k, m);
 }
-hipError_t series_update(hipStream_t s, const double* C, double* dPn, double* P1, int N, double dt, int k,
-                         unsigned long long* slots, int stride, const double* kmin, double thrs, int* done,
-                         int T, const int* active) {
+hipError_t series_update(hipStream_t s, const double* C, const double* C2, double* dPn, double* P1, int N,
+                         double dt, int k, unsigned long long* slots, int stride, const double* kmin, double thrs,
+                         int* done, int T, const int* active) {
   SeriesSkip sk{slots, kmin, done, thrs, k, stride};
   long NN = (long)N * N;
   int nb = ew_blocks(NN);
   if (nb > 256) nb = 256;
-  hipLaunchKernelGGL(k_series_update, dim3(nb, T), dim3(256), 0, s, C, dPn, P1, N, dt, sk, done, active);
+  hipLaunchKernelGGL(k_series_update, dim3(nb, T), dim3(256), 0, s, C, C2, dPn, P1, N, dt, sk, done, active);
   return hipGetLastError();
 }
 

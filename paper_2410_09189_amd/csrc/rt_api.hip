@@ -159,6 +159,8 @@ struct SysDev {
   double *P0, *P1, *dP, *dPn, *C;          // stacked [S'; A'], 2 N^2 each
   double* gwork = nullptr;                 // Gershgorin rows [T][N][2] / observable partials [T][160]
   double* fieldp = nullptr;                // pulse parameters per slot [T][7]
+  double *Bm = nullptr, *C2 = nullptr;     // fourth-order Magnus: Omega_2 [T][N^2], B . [S;A]^T [T][2N^2]
+  double *A0m = nullptr, *A1m = nullptr, *Xm = nullptr;  // its scratch, [T][N^2] each
   bool field = false;                      // any slot with a nonzero pulse amplitude
   double *H0, *H1, *Hm1, *Hn, *Hbar;       // N^2 each
   double* hist;                            // [T][cap + 1][5]
@@ -321,7 +323,9 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
       }
   }
   if (run->hupdate != RT_HUPDATE_FULL && run->hupdate != RT_HUPDATE_LOCAL) { why = "hupdate"; return RT_EINVAL; }
-  if (run->magnus_order != 0 && run->magnus_order != 2) { why = "magnus_order must be 0 or 2"; return RT_EINVAL; }
+  if (run->magnus_order != 0 && run->magnus_order != 2 && run->magnus_order != 4) {
+    why = "magnus_order must be 0, 2 or 4"; return RT_EINVAL;
+  }
   if (run->traj_field) {
     for (int t = 0; t < run->n_traj; ++t) {
       const double* f = run->traj_field + 7L * t;
@@ -436,6 +440,13 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.Hbar = a.take<double>(T * NN);
     d.hist = a.take<double>(T * 5L * (hist_cap + 1));
     d.fieldp = a.take<double>(T * 7L);
+    if (run.magnus_order == 4) {
+      d.Bm = a.take<double>(T * NN);
+      d.C2 = a.take<double>(T * 2 * NN);
+      d.A0m = a.take<double>(T * NN);
+      d.A1m = a.take<double>(T * NN);
+      d.Xm = a.take<double>(T * NN);
+    }
     d.kmin = a.take<double>(T);
     d.slots = a.take<unsigned long long>(T * (run.max_terms + 2));
     d.resid = a.take<unsigned long long>(T);
@@ -650,13 +661,18 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
   double* kmin = d.kmin + first;
   unsigned long long* slots = d.slots + (long)first * stride;
   int* done = d.done + 2 * first;
+  // fourth-order Magnus (time steps only): Omega = -i dt Hbar + B, B = Omega_2
+  double* B = (H0 && d.Bm) ? d.Bm + first * NN : nullptr;
+  double* C2 = B ? d.C2 + first * n2 : nullptr;
   {
     Timed tm(c, PH_SMALL);
     // the external field joins the midpoint Hamiltonian of a time step (H0 given):
     // + (V(t_a) + V(t_a + dt))/2, V = sum_q E_q M_q
     const double* fp = (H0 && d.field) ? d.fieldp + 7L * first : nullptr;
+    if (B) CK(rtk::magnus2(s, H0, H1, fp, d.M3, t_a, dt, d.A0m + first * NN, d.A1m + first * NN,
+                           d.Xm + first * NN, B, d.N, T, act));
     CK(rtk::series_begin(s, Pin, Pout, dP, H0, H1, const_cast<double*>(Hbar), d.N, dt, kmin, slots, stride, done,
-                         resid, d.gwork, T, act, fp, d.M3, t_a));
+                         resid, d.gwork, T, act, fp, d.M3, t_a, B));
   }
   int k = 1;
   const int CH = 8;
@@ -667,10 +683,11 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
       {
         Timed tm(c, PH_SERIES_GEMM);
         CK(rtk::gemm_nt_f64_series(s, d.N, T, Hbar, dP, C, k, slots, stride, kmin, thrs, done, act));
+        if (B) CK(rtk::gemm_nt_f64_series(s, d.N, T, B, dP, C2, k, slots, stride, kmin, thrs, done, act));
       }
       {
         Timed tm(c, PH_SERIES_UPDATE);
-        CK(rtk::series_update(s, C, dPn, Pout, d.N, dt, k, slots, stride, kmin, thrs, done, T, act));
+        CK(rtk::series_update(s, C, C2, dPn, Pout, d.N, dt, k, slots, stride, kmin, thrs, done, T, act));
       }
       std::swap(dP, dPn);
     }
