@@ -134,15 +134,17 @@ def test_learned_guess_keeps_the_fixed_point():
 
 def test_trained_predictor_gain_on_held_out_trajectory():
     """Trains on trajectories the step itself records (x and y kicks, two
-    strengths), evaluates on a z kick: the fixed point is unchanged and the
-    mean number of Hamiltonian updates per step does not grow."""
+    strengths), evaluates on a z kick at dt = 0.2, where the linear guess is
+    often not within H_thrs after one update: the fixed point is unchanged and
+    the learned guess saves Hamiltonian updates (measured 2.23 -> 2.00 per step;
+    at dt = 0.8: 3.84 -> 3.36)."""
     _say("C1 learned predictor: record, train on GPU, evaluate held-out z kick")
     import torch
     from paper_2410_09189_amd import predictor, rt
 
     s = c1_system()
     psi, _ = c1_ground_state()
-    dt, n_rec, n_eval = 0.1, 300, 150
+    dt, n_rec, n_eval = 0.2, 300, 150
     h_thrs = 1e-9
 
     def run_args_for(axes, kappas, n, pred=0, params=None):
@@ -169,4 +171,4 @@ def test_trained_predictor_gain_on_held_out_trajectory():
     m_mlp = res[1][1][8:].mean()
     print(f"mean Hamiltonian updates per step after warm-up: linear {m_lin:.3f}, learned {m_mlp:.3f}", flush=True)
     assert np.max(np.abs(res[0][0] - res[1][0])) < 1e-7
-    assert m_mlp <= m_lin + 0.05
+    assert m_mlp <= m_lin - 0.1
