@@ -186,6 +186,13 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
   const int wm = wave >> 1, wn = wave & 1;
   const long m0 = (long)tm * XB, n0 = (long)tn * XB;
   const long va = min((long)XB, N - m0), vb = min((long)XB, N - n0);
+  // matrix work only where the upper triangle has entries: on a diagonal tile the
+  // wave below the diagonal idles and the diagonal waves skip their strictly lower
+  // 16 x 16 blocks; 16-row / 16-column blocks past N are skipped everywhere
+  const bool idle = (tm == tn) && (wm > wn);
+  const bool lowdiag = (tm == tn) && (wm == wn);
+  const int nib = (int)min(4L, max(0L, (N - m0 - wm * 64 + 15) / 16));
+  const int njb = (int)min(4L, max(0L, (N - n0 - wn * 64 + 15) / 16));
   const auto rAh = buf_rsrc(Ahi + m0 * ng + k0, (int)((va * ng - k0) * 2));
   const auto rAl = buf_rsrc(Alo + m0 * ng + k0, (int)((va * ng - k0) * 2));
   const auto rBh = buf_rsrc(Ahi + n0 * ng + k0, (int)((vb * ng - k0) * 2));
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
     __syncthreads();
     if (kb + XK < k1) fetch(kb + XK);
 #pragma unroll
-    for (int kk = 0; kk < XK; kk += 32) {
+    for (int kk = 0; kk < XK && !idle; kk += 32) {
       bf16x8 fah[4], fal[4], fbh[4], fbl[4];
       const int kc = kk + 8 * (lane >> 4);
 #pragma unroll
@@ -258,6 +265,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+          if (i >= nib || j >= njb || (lowdiag && i > j)) continue;
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fbh[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
@@ -265,6 +273,7 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
     }
     __syncthreads();
   }
+  if (idle) return;
   float* P = part + (long)by * N * N;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
