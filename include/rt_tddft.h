@@ -71,7 +71,7 @@ enum { RT_HUPDATE_FULL = 0, RT_HUPDATE_LOCAL = 1 };/* how H[P] is rebuilt, below
  * occ: occupations f_i (nullable: 2 for the first n_occ, 0 for the rest).
  */
 typedef struct {
-  int n[3];            /* nx, ny, nz; each in [8, 1024]                          */
+  int n[3];            /* nx, ny, nz; each in [8, 256]                           */
   double h;            /* grid spacing (bohr)                                    */
   int n_atoms;
   const double* pos;   /* [n_atoms][3] bohr                                      */
@@ -122,7 +122,7 @@ typedef struct {
   int predictor;       /* RT_PRED_LINEAR | RT_PRED_MLP (see Learned predictor)   */
   int hupdate;         /* RT_HUPDATE_FULL | RT_HUPDATE_LOCAL                     */
   int frozen_hxc;      /* test switch: V_H and v_x fixed at the ground state     */
-  int n_traj;
+  int n_traj;                /* at most 256 trajectories per system              */
   const int* traj_sys;       /* [n_traj] index into the system array             */
   const double* traj_kappa;  /* [n_traj] kick strength                           */
   const int* traj_axis;      /* [n_traj] 0 = x, 1 = y, 2 = z                     */
@@ -136,8 +136,11 @@ typedef struct {
      (V(t_j) + V(t_(j+1)))/2 (Magnus line of Algorithm 1); the self-consistency
      residual compares the Kohn-Sham part only.  Requires tau > 0.              */
   const double* traj_field;
-  int magnus_order;          /* 0 or 2: Omega_1 only (the paper's midpoint); other
-                                values are rejected (RT_EINVAL)                     */
+  int magnus_order;          /* 0 or 2: Omega_1 only (the paper's midpoint);
+                                4: Omega_1 + Omega_2, Omega_2 = (dt^2/12)
+                                [H_0 + V(t_j), H_1 + V(t_(j+1))] (Sec. Magnus
+                                expansion, H linear over the step), taken into
+                                every series term; other values: RT_EINVAL      */
 } rt_run;
 
 /* Per-trajectory, per-step counters written by rt_step when stats != NULL. */

@@ -123,6 +123,14 @@ hipError_t series_update(hipStream_t s, const double* C, const double* C2, doubl
                          int* done, int T, const int* active);
 hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, int stride,
                          const double* kmin, double thrs, int* done, int T, const int* active);
+// dst[t] = bit t of f (t < T <= 256), flags passed by value
+struct Flags256 {
+  unsigned long long w[4];
+};
+hipError_t set_flags(hipStream_t s, int* dst, Flags256 f, int T);
+// Copies n32 32-bit words of device memory to box[16..] (host-mapped, coherent) and then
+// stores seq into box[0..1] with system-scope release, so a host that sees seq sees the words.
+hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long seq);
 // rows_t = (mu_x, mu_y, mu_z, E, TrP) from S'_t (stride 2N^2) and eparts_t; work: [T][160]
 hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
                        const double* eparts, int estride, double* rows, long rstride, double* work, int T);

@@ -1478,6 +1478,29 @@ hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slot
   return hipGetLastError();
 }
 
+__global__ void k_set_flags(int* dst, Flags256 f, int T) {
+  const int t = threadIdx.x;
+  if (t < T) dst[t] = (int)((f.w[t >> 6] >> (t & 63)) & 1ull);
+}
+hipError_t set_flags(hipStream_t s, int* dst, Flags256 f, int T) {
+  if (T < 0 || T > 256) return hipErrorInvalidValue;
+  if (T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(256), 0, s, dst, f, T);
+  return hipGetLastError();
+}
+
+// One lane copies the words into the host-mapped mailbox and then stores the sequence
+// number with a system-scope release: a host thread that reads seq also reads the words.
+__global__ void k_publish(const unsigned* src, int n, unsigned* box, unsigned long long seq) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < n; ++i) box[16 + i] = src[i];
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(box), seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long seq) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, static_cast<const unsigned*>(src), n32, box, seq);
+  return hipGetLastError();
+}
+
 // mu_q = sum_ij S_ij M_q,ij ; E = sum_ij S_ij Hcore_ij + E_x + E_H ; TrP = sum_i S_ii.
 // S_t = S + t 2N^2, eparts_t = eparts + t estride, row_t = rows + t rstride.  Stage 1:
 // kObsBlocks blocks per trajectory write partial sums part[t][b][5]; stage 2 adds

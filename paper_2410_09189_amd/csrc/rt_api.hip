@@ -182,6 +182,7 @@ struct SysDev {
 };
 
 constexpr int kNIn = 8 * 9 + 2 * 4096, kNH = 256, kNOut = 4096;
+constexpr int kMaxTraj = 256;  // trajectories per system (one series-control block)
 inline rtk::MlpDims pred_dims() { return rtk::MlpDims{kNIn, kNH, kNOut}; }
 
 struct TrajDev {
@@ -216,6 +217,15 @@ struct rt_ctx {
   int hist_cap = 0;
   float *rec_x = nullptr, *rec_y = nullptr;
   int rec_cap = 0, rec_count = 0;
+  // host-mapped mailbox for the per-iteration convergence flags: the device writes them
+  // with a sequence number and the host polls it (no copy, no interrupt-driven wait)
+  unsigned* box_host = nullptr;
+  unsigned* box_dev = nullptr;
+  size_t box_bytes = 0;
+  unsigned long long box_seq = 0;
+  ~rt_ctx() {
+    if (box_host) (void)hipHostFree(box_host);
+  }
 };
 
 namespace {
@@ -237,6 +247,36 @@ rt_status fail(rt_ctx* c, rt_status st, const std::string& msg) {
 }
 
 long nsq(int N) { return (long)N * N; }
+
+// Waits until the mailbox holds sequence number seq.  Spins on the host-mapped word; every
+// few thousand polls it asks the stream whether work is still pending, so a stream that
+// drained without writing seq, or that failed, ends the wait with an error.
+rt_status wait_box(rt_ctx* c, unsigned long long seq) {
+  const unsigned long long* f = reinterpret_cast<const unsigned long long*>(c->box_host);
+  for (long spin = 1;; ++spin) {
+    if (__atomic_load_n(f, __ATOMIC_ACQUIRE) == seq) return RT_OK;
+    if ((spin & 4095) == 0) {
+      hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(f, __ATOMIC_ACQUIRE) == seq) return RT_OK;
+        return fail(c, RT_EDEVICE, "stream drained without writing the mailbox");
+      }
+      if (e != hipErrorNotReady) return fail(c, RT_EDEVICE, std::string("wait_box: ") + hipGetErrorString(e));
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// Device-to-host read of nbytes (a multiple of 4) that orders after all work queued on the
+// context's stream: a publish kernel writes them to the mailbox, the host waits for it.
+rt_status read_back(rt_ctx* c, const void* src, size_t nbytes, void* out) {
+  if (nbytes % 4 != 0 || nbytes + 64 > c->box_bytes) return fail(c, RT_EINVAL, "read_back size");
+  const unsigned long long seq = ++c->box_seq;
+  CK(rtk::publish(c->stream, src, (int)(nbytes / 4), c->box_dev, seq));
+  RET(wait_box(c, seq));
+  std::memcpy(out, c->box_host + 16, nbytes);
+  return RT_OK;
+}
 
 hipEvent_t take_event(rt_ctx* c) {
   if (!c->pool.empty()) {
@@ -337,9 +377,11 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
   if (run->n_traj < 0 || (run->n_traj > 0 && (!run->traj_sys || !run->traj_kappa || !run->traj_axis))) {
     why = "trajectory arrays"; return RT_EINVAL;
   }
+  std::vector<int> per_sys(n_sys > 0 ? n_sys : 0, 0);
   for (int t = 0; t < run->n_traj; ++t) {
     if (run->traj_sys[t] < 0 || run->traj_sys[t] >= n_sys) { why = "traj_sys out of range"; return RT_EINVAL; }
     if (run->traj_axis[t] < 0 || run->traj_axis[t] > 2) { why = "traj_axis out of range"; return RT_EINVAL; }
+    if (++per_sys[run->traj_sys[t]] > kMaxTraj) { why = "more than 256 trajectories on one system"; return RT_EINVAL; }
   }
   return RT_OK;
 }
@@ -521,10 +563,17 @@ rt_status upload(rt_ctx* c, void* dst, const std::vector<V>& v) {
   return RT_OK;
 }
 
-rt_status push_active(rt_ctx* c, SysDev& d) {
-  CK(hipMemcpyAsync(d.active, d.active_host.data(), d.T * sizeof(int), hipMemcpyHostToDevice, c->stream));
+// Per-trajectory 0/1 flags go to the device as kernel arguments: no pageable copy, which
+// would wait for the stream to drain, inside the step loop.
+rt_status upload_flags(rt_ctx* c, int* dst, const std::vector<int>& v) {
+  rtk::Flags256 f{};
+  for (size_t t = 0; t < v.size(); ++t)
+    if (v[t]) f.w[t >> 6] |= 1ull << (t & 63);
+  CK(rtk::set_flags(c->stream, dst, f, (int)v.size()));
   return RT_OK;
 }
+
+rt_status push_active(rt_ctx* c, SysDev& d) { return upload_flags(c, d.active, d.active_host); }
 
 // ---------------------------------------------------------------------------
 // Stages
@@ -692,8 +741,7 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
       std::swap(dP, dPn);
     }
     CK(rtk::series_finish(s, kend, slots, stride, kmin, thrs, done, T, act));
-    CK(hipMemcpyAsync(hd.data(), done, 2 * T * sizeof(int), hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
+    RET(read_back(c, done, 2 * T * sizeof(int), hd.data()));
     bool all = true;
     for (int t = 0; t < T; ++t)
       if (act_host[t] && !hd[2 * t]) all = false;
@@ -898,8 +946,7 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
       Timed tm(c, PH_SMALL);
       CK(rtk::max_diff_assign(st, d.Hn, d.H1, NN, d.resid, T, d.active));
     }
-    CK(hipMemcpyAsync(bits.data(), d.resid, T * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
+    RET(read_back(c, d.resid, T * sizeof(unsigned long long), bits.data()));
     bool changed = false;
     bool mask_changed = false;
     for (int t = 0; t < T; ++t) {
@@ -929,7 +976,7 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
     }
     if (changed && n_active > 0) RET(push_active(c, d));
     if (mask_changed)
-      CK(hipMemcpyAsync(d.mlp_mask, d.mlp_on.data(), T * sizeof(int), hipMemcpyHostToDevice, st));
+      RET(upload_flags(c, d.mlp_mask, d.mlp_on));
   }
   if (n_active > 0) return fail(c, RT_ENOCONV, "self-consistent Hamiltonian loop reached max_scf");
   // H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 (all slots together)
@@ -951,7 +998,6 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   (void)n_traj_total;
   RET(observe(c, d, d.step));
   RET(update_features(c, d));
-  if (d.mlp) CK(hipStreamSynchronize(st));  // mlp_on (host) feeds async copies
   return RT_OK;
 }
 
@@ -1003,6 +1049,19 @@ rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* work
   Arena b;
   b.base = reinterpret_cast<char*>(((uintptr_t)workspace_dev + 255) & ~uintptr_t(255));
   layout(b, c->sys, *run, c->hist_cap);
+  int max_t = 1;
+  for (const SysDev& d : c->sys) max_t = std::max(max_t, d.T);
+  c->box_bytes = (64 + 16 * (size_t)max_t + 4095) / 4096 * 4096;
+  void* box = nullptr;
+  if (hipHostMalloc(&box, c->box_bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->box_dev, box, 0) != hipSuccess) {
+    if (box) (void)hipHostFree(box);
+    g_init_error = "rt_init: pinned host mailbox";
+    delete c;
+    return RT_ENOMEM;
+  }
+  c->box_host = static_cast<unsigned*>(box);
+  std::memset(c->box_host, 0, c->box_bytes);
   for (int i = 0; i < n_sys; ++i) {
     st = init_system(c, c->sys[i], sys[i]);
     if (st != RT_OK) { g_init_error = c->err; delete c; return st; }
