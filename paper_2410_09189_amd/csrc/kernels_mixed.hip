@@ -444,22 +444,26 @@ __global__ __launch_bounds__(256) void k_density_bf16x3(int N, long ng, const un
 }
 
 // Resident-tile density for N <= 256.  One block owns BN grid points and every
-// trajectory: the point-major hi/lo orbital tile [BN][NP] (NP = N rounded up to 32,
-// zero padded) is loaded into LDS once; for each trajectory Z = W Psi_tile is
-// accumulated with 32x32x16 matrix instructions, W (upper triangular, stored in
-// A-fragment order) read straight from L2, j-chunks of 32 outermost so each B
-// fragment read from LDS serves all of a wave's row blocks, lower-triangle blocks
-// skipped; then rho_t = rho0 + sum_i psi_i Z_i with psi_i again from the LDS tile.
+// trajectory: the point-major hi/lo orbital tile [BN][NP] (NP = 32 NC, zero padded)
+// is loaded into LDS once; for each trajectory Z = W Psi_tile is accumulated with
+// 32x32x16 matrix instructions, W (upper triangular, stored in A-fragment order) read
+// straight from L2, j-chunks of 32 outermost so each B fragment read from LDS serves
+// all of a wave's row blocks, lower-triangle blocks skipped; then
+// rho_t = rho0 + sum_i psi_i Z_i with psi_i again from the LDS tile.
 // Waves: 4 row groups x WP point groups; row group g owns the 32-row blocks g and
 // 7 - g (equal triangular work), a point group owns BN / WP points.
-template <int BN, int WP>
-__global__ __launch_bounds__(256 * WP) void k_density_tile32(int NP, long ng, const unsigned short* __restrict__ whi,
+// The chunk loop is unrolled (NC is a template argument) so the W fragments of chunk
+// c + PF load into a fixed register slot while chunks c + 1 .. c + PF - 1 compute:
+// no register rotation, hence no wait for loads still in flight.
+template <int BN, int WP, int NC, int PF>
+__global__ __launch_bounds__(256 * WP) void k_density_tile32(long ng, const unsigned short* __restrict__ whi,
                                                              const unsigned short* __restrict__ wlo,
                                                              const unsigned short* __restrict__ pth,
                                                              const unsigned short* __restrict__ ptl,
                                                              const double* __restrict__ rho0,
                                                              double* __restrict__ rho, int T, const int* active) {
-  constexpr int LDP = 256 + 8;  // LDS row pitch (bf16)
+  constexpr int NP = 32 * NC;
+  constexpr int LDP = NP + 8;  // LDS row pitch (bf16)
   constexpr int RB = 2, PC = BN / 32 / WP, NTH = 256 * WP;
   __shared__ __attribute__((aligned(16))) unsigned short sT[2][BN][LDP];
   __shared__ float red[4][BN];
@@ -467,30 +471,27 @@ __global__ __launch_bounds__(256 * WP) void k_density_tile32(int NP, long ng, co
   const int wr = wave & 3, wp = wave >> 2;
   const long p0 = (long)blockIdx.x * BN;
   {
-    constexpr int U = BN * 32 / NTH;
-    const int q = tid & 31, rb = tid >> 5;
-    const bool colok = q < (NP >> 3);
+    constexpr int QN = NP / 8, U = BN * QN / NTH;  // 16-byte pieces per tile row, per thread
+    static_assert(BN * QN % NTH == 0, "tile pieces must divide over the block");
     uint4 vh[U], vl[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const long r = p0 + rb + (NTH / 32) * u;
+      const int e = tid + NTH * u;
+      const long r = p0 + e / QN;
       vh[u] = vl[u] = make_uint4(0u, 0u, 0u, 0u);
-      if (colok && r < ng) {
-        vh[u] = *reinterpret_cast<const uint4*>(pth + r * NP + 8 * q);
-        vl[u] = *reinterpret_cast<const uint4*>(ptl + r * NP + 8 * q);
+      if (r < ng) {
+        vh[u] = *reinterpret_cast<const uint4*>(pth + r * NP + 8 * (e % QN));
+        vl[u] = *reinterpret_cast<const uint4*>(ptl + r * NP + 8 * (e % QN));
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int row = rb + (NTH / 32) * u;
-      if (colok) {
-        *reinterpret_cast<uint4*>(&sT[0][row][8 * q]) = vh[u];
-        *reinterpret_cast<uint4*>(&sT[1][row][8 * q]) = vl[u];
-      }
+      const int e = tid + NTH * u;
+      *reinterpret_cast<uint4*>(&sT[0][e / QN][8 * (e % QN)]) = vh[u];
+      *reinterpret_cast<uint4*>(&sT[1][e / QN][8 * (e % QN)]) = vl[u];
     }
   }
   __syncthreads();
-  const int NB = NP >> 5, NC = NP >> 5;
   const int Ib[RB] = {wr, 7 - wr};
   const int kq = 8 * (lane >> 5), l32 = lane & 31;
   const int pb = wp * (BN / WP);
@@ -505,20 +506,16 @@ __global__ __launch_bounds__(256 * WP) void k_density_tile32(int NP, long ng, co
       for (int p = 0; p < PC; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[k][p][r] = 0.f;
-    // W fragments (A operand, stored in fragment order: one coalesced 1 KB block per
-    // load) through a buffer resource over W_t: the loads of the
-    // next PF chunks are always in flight (inactive lower-triangle blocks get an
-    // out-of-range offset and read zero without memory traffic), so their count
-    // is fixed and the wait for chunk c leaves the later ones outstanding.
+    // W fragments through a buffer resource over W_t: one coalesced 1 KB block per
+    // load; blocks below the diagonal (or past NC) get an out-of-range offset and read
+    // zero without memory traffic.
     const auto rWh = buf_rsrc(Wh, NP * NP * 2), rWl = buf_rsrc(Wl, NP * NP * 2);
-    constexpr int PF = 3;
-    auto wofs = [&](int k, int cc, int s2) -> int {  // W in 32x32x16 A-fragment order
-      return (cc < NC && Ib[k] <= cc && Ib[k] < NB) ? ((Ib[k] * (NP >> 4) + 2 * cc + s2) * 64 + lane) * 16
-                                                    : (int)0x80000000;
+    auto wofs = [&](int k, int cc, int s2) -> int {
+      return (Ib[k] <= cc && Ib[k] < NC) ? ((Ib[k] * (NP >> 4) + 2 * cc + s2) * 64 + lane) * 16 : (int)0x80000000;
     };
     uint4 wh[PF][RB][2], wl[PF][RB][2];
 #pragma unroll
-    for (int d = 0; d < PF; ++d)
+    for (int d = 0; d < PF && d < NC; ++d)
 #pragma unroll
       for (int k = 0; k < RB; ++k)
 #pragma unroll
@@ -527,51 +524,40 @@ __global__ __launch_bounds__(256 * WP) void k_density_tile32(int NP, long ng, co
           wh[d][k][s2] = buf_ld16(rWh, o, 0);
           wl[d][k][s2] = buf_ld16(rWl, o, 0);
         }
+#pragma unroll
     for (int c = 0; c < NC; ++c) {
-      bf16x8 ah[RB][2], al[RB][2];
-#pragma unroll
-      for (int k = 0; k < RB; ++k)
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-          ah[k][s2] = __builtin_bit_cast(bf16x8, wh[0][k][s2]);
-          al[k][s2] = __builtin_bit_cast(bf16x8, wl[0][k][s2]);
-        }
-#pragma unroll
-      for (int d = 0; d + 1 < PF; ++d)
-#pragma unroll
-        for (int k = 0; k < RB; ++k)
-#pragma unroll
-          for (int s2 = 0; s2 < 2; ++s2) {
-            wh[d][k][s2] = wh[d + 1][k][s2];
-            wl[d][k][s2] = wl[d + 1][k][s2];
-          }
-#pragma unroll
-      for (int k = 0; k < RB; ++k)
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) {
-          const int o = wofs(k, c + PF, s2);
-          wh[PF - 1][k][s2] = buf_ld16(rWh, o, 0);
-          wl[PF - 1][k][s2] = buf_ld16(rWl, o, 0);
-        }
+      const int sl = c % PF;
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2) {
         bf16x8 bh[PC], bl[PC];
 #pragma unroll
         for (int p = 0; p < PC; ++p) {
-          int pt = pb + 32 * p + l32;
+          const int pt = pb + 32 * p + l32;
           bh[p] = *reinterpret_cast<const bf16x8*>(&sT[0][pt][32 * c + 16 * s2 + kq]);
           bl[p] = *reinterpret_cast<const bf16x8*>(&sT[1][pt][32 * c + 16 * s2 + kq]);
         }
 #pragma unroll
         for (int k = 0; k < RB; ++k) {
-          if (Ib[k] > c || Ib[k] >= NB) continue;
+          if (Ib[k] > c) continue;
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, wh[sl][k][s2]);
+          const bf16x8 al = __builtin_bit_cast(bf16x8, wl[sl][k][s2]);
 #pragma unroll
           for (int p = 0; p < PC; ++p) {
-            acc[k][p] = mfma32(al[k][s2], bh[p], acc[k][p]);
-            acc[k][p] = mfma32(ah[k][s2], bl[p], acc[k][p]);
-            acc[k][p] = mfma32(ah[k][s2], bh[p], acc[k][p]);
+            acc[k][p] = mfma32(al, bh[p], acc[k][p]);
+            acc[k][p] = mfma32(ah, bl[p], acc[k][p]);
+            acc[k][p] = mfma32(ah, bh[p], acc[k][p]);
           }
         }
+      }
+      if (c + PF < NC) {
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            const int o = wofs(k, c + PF, s2);
+            wh[sl][k][s2] = buf_ld16(rWh, o, 0);
+            wl[sl][k][s2] = buf_ld16(rWl, o, 0);
+          }
       }
     }
     float part[PC];
@@ -579,7 +565,7 @@ __global__ __launch_bounds__(256 * WP) void k_density_tile32(int NP, long ng, co
     for (int p = 0; p < PC; ++p) part[p] = 0.f;
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-      if (Ib[k] >= NB) continue;
+      if (Ib[k] >= NC) continue;
 #pragma unroll
       for (int p = 0; p < PC; ++p) {
         const int pt = pb + 32 * p + l32;
@@ -621,9 +607,18 @@ hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* w
                           const unsigned short* ptlo, const double* rho0, double* rho, int T, const int* active) {
   if (N <= 256) {
     if (!pthi || !ptlo) return hipErrorInvalidValue;
-    const int NP = density_tile_ld(N);
-    hipLaunchKernelGGL((k_density_tile32<128, 2>), dim3(cdivm(ng, 128)), dim3(512), 0, s, NP, ng, whi, wlo, pthi,
-                       ptlo, rho0, rho, T, active);
+    const dim3 grid(cdivm(ng, 128)), blk(512);
+    switch (density_tile_ld(N) / 32) {
+#define RT_DENSITY_NC(nc)                                                                                         \
+  case nc:                                                                                                        \
+    hipLaunchKernelGGL((k_density_tile32<128, 2, nc, 2>), grid, blk, 0, s, ng, whi, wlo, pthi, ptlo, rho0, rho, T, \
+                       active);                                                                                   \
+    break;
+      RT_DENSITY_NC(1) RT_DENSITY_NC(2) RT_DENSITY_NC(3) RT_DENSITY_NC(4)
+      RT_DENSITY_NC(5) RT_DENSITY_NC(6) RT_DENSITY_NC(7) RT_DENSITY_NC(8)
+#undef RT_DENSITY_NC
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_density_bf16x3, dim3(cdivm(ng, 64) * T), dim3(256), 0, s, N, ng, whi, wlo, phi, plo, rho0,
