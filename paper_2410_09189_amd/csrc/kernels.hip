@@ -179,8 +179,10 @@ struct StencilCoef {
   double c[5];  // -1/2 a_k / h^2
 };
 
+// Aligned to its full width so LDS accesses compile to single 16-byte instructions
+// (an element-aligned struct splits into pairs of narrower accesses that conflict).
 template <typename T, int V>
-struct SVec {
+struct alignas(sizeof(T) * V) SVec {
   T e[V];
 };
 
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
                                                  const T* __restrict__ v, int nx, int ny, int nz,
                                                  int TY, int ZC, StencilCoef cf) {
   typedef SVec<T, V> Vec;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T* const sp0 = reinterpret_cast<T*>(smem_raw);  // [2][TY + 8][nx + 8], x = 0 at column 4
   const int P = nx + 8;
   const int pln = (TY + 8) * P;
