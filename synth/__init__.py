@@ -14,5 +14,6 @@ from .systems import (  # noqa: F401
     config_run,
     batch_systems,
     lowpass_orbitals,
+    basis_mixing,
     CONFIGS,
 )

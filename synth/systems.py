@@ -234,3 +234,14 @@ def lowpass_orbitals(n, h, n_orb, seed, g_cut=1.5, dtype=np.float64) -> np.ndarr
         f /= np.sqrt(np.sum(f * f) * h ** 3)
         out[i] = f
     return out
+
+
+def basis_mixing(n: int, seed: int, strength: float = 0.3, lower: bool = False) -> np.ndarray:
+    """Random well-conditioned N x N matrix A = I + strength * G / sqrt(N), G standard
+    normal (strictly lower triangular when lower=True, so A is unit lower
+    triangular).  A non-orthogonal basis for tests is Phi = A Psi."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    if lower:
+        G = np.tril(G, -1)
+    return np.eye(n) + strength * G / np.sqrt(n)

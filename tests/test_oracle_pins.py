@@ -468,3 +468,94 @@ def test_magnus4_self_consistent_run_keeps_trace_and_idempotency():
     assert np.max(np.abs(out["trace"] - 16.0)) < 1e-12
     for P in out["Ps"][::5]:
         assert np.max(np.abs(P @ P / 2.0 - P)) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# Non-orthogonal basis: dP^(k) = (1/k)(-i dt)(S^-1 Hbar dP - dP Hbar S^-1)
+# (eq. commutator-expansion-nonort; Appendix, propagation in a non-orthogonal basis)
+# ---------------------------------------------------------------------------
+def _rand_spd(n, seed):
+    A = synth.basis_mixing(n, seed, strength=0.6)
+    return A @ A.T
+
+
+@pytest.mark.parametrize("dt,seed", [(0.05, 21), (0.3, 22), (-0.2, 23)])
+def test_nonorthogonal_step_matches_pade_exponential(dt, seed):
+    """For constant Hbar, eq. LvN_nonort is solved by
+    P(dt) = exp(-i dt S^-1 H) P exp(+i dt H S^-1); scipy's Pade exponential of the
+    non-symmetric S^-1 H is an independent route to both the series and the
+    orthonormal-basis transform."""
+    n = 10
+    S = _rand_spd(n, seed)
+    H = _rand_h(n, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    P = A @ A.conj().T
+    G = np.linalg.solve(S, H)
+    ref = scipy.linalg.expm(-1j * dt * G) @ P @ scipy.linalg.expm(1j * dt * G.T)
+    ser, k = propagate.propagate_series(H, P, dt, 1e-15, Sinv=np.linalg.inv(S))
+    ex = propagate.propagate_exact_nonorth(H, P, dt, S)
+    scale = np.max(np.abs(P))
+    assert np.max(np.abs(ser - ref)) < 1e-12 * scale
+    assert np.max(np.abs(ex - ref)) < 1e-12 * scale
+    assert k > 3
+
+
+def test_nonorthogonal_series_with_unit_overlap_is_the_commutator_series():
+    H = _rand_h(8, 31)
+    P = propagate.kick(np.diag([2.0] * 3 + [0.0] * 5), _rand_h(8, 32), 0.3)
+    a, ka = propagate.propagate_series(H, P, 0.2, 1e-15)
+    b, kb = propagate.propagate_series(H, P, 0.2, 1e-15, Sinv=np.eye(8))
+    assert ka == kb
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_nonorthogonal_ground_density_is_idempotent_in_the_metric():
+    """P_0 = R^-1 diag(f) L^-1 with f in {0, 2}: (P S)^2 = 2 P S, Tr(P S) = N_e."""
+    S = _rand_spd(9, 41)
+    occ = np.array([2.0] * 4 + [0.0] * 5)
+    P = propagate.ground_density_nonorth(occ, S)
+    PS = P @ S
+    assert np.max(np.abs(PS @ PS - 2.0 * PS)) < 1e-12
+    assert abs(np.trace(PS) - 8.0) < 1e-12
+
+
+def _nonorth_c1(mixing_seed, lower):
+    """The 32^3 parity molecule in the basis Phi = A Psi, with its overlap."""
+    psi, _ = c1_ground_state()
+    s = c1_system()
+    N = psi.shape[0]
+    A = synth.basis_mixing(N, mixing_seed, strength=0.4, lower=lower)
+    phi = A @ psi.reshape(N, -1)
+    S = s.h ** 3 * (phi @ phi.T)
+    return A, oracle.Model(s, phi.reshape(psi.shape)), 0.5 * (S + S.T)
+
+
+def test_nonorthogonal_run_reproduces_orthonormal_physics_lower_triangular_basis():
+    """Phi = A Psi with A unit lower triangular: the Cholesky factor of Phi's overlap
+    is A, so the default P_0 occupies the same orbitals; mu(t), E(t) and the
+    electron count must equal the orthonormal run (basis-invariant observables,
+    Appendix trace identities)."""
+    A, m, S = _nonorth_c1(51, lower=True)
+    assert np.max(np.abs(np.linalg.cholesky(S) - A)) < 1e-10
+    rp = synth.config_run("c1_parity_32", n_steps=20, h_thrs=1e-12)
+    ref = c1_oracle_run(n_steps=20)
+    for method in ("exact", "series"):
+        out = oracle.run(m, rp, method=method, S=S)
+        assert np.max(np.abs(out["mu"] - ref["mu"])) < 1e-10, method
+        assert np.max(np.abs(out["E"] - ref["E"])) < 1e-9, method
+        assert np.max(np.abs(out["trace"] - 16.0)) < 1e-11, method
+
+
+def test_nonorthogonal_run_reproduces_orthonormal_physics_general_basis():
+    """A general mixing A: the ground state in Phi is P_0 = A^-T diag(f) A^-1; kicked
+    through S it must give the orthonormal run's dipole history."""
+    A, m, S = _nonorth_c1(52, lower=False)
+    rp = synth.config_run("c1_parity_32", n_steps=20, h_thrs=1e-12)
+    Ai = np.linalg.inv(A)
+    P0 = Ai.T @ np.diag(c1_system().occupations()) @ Ai
+    P = propagate.kick(P0, m.M[rp.axis], rp.kappa, S)
+    out = oracle.run(m, rp, method="series", S=S, P_start=P)
+    ref = c1_oracle_run(n_steps=20)
+    assert np.max(np.abs(out["mu"] - ref["mu"])) < 1e-10
+    assert np.max(np.abs(out["trace"] - 16.0)) < 1e-11
