@@ -68,6 +68,15 @@ enum { RT_HUPDATE_FULL = 0, RT_HUPDATE_LOCAL = 1 };/* how H[P] is rebuilt, below
  *   host memory unless psi0_on_device != 0.  If orthonormalize != 0 they are
  *   first made h^3-orthonormal by S = h^3 Psi Psi^T = L L^T, Psi <- L^-1 Psi
  *   (basis transform of the paper's non-orthogonal formulation, Appendix).
+ *   If nonorthogonal != 0 (excludes orthonormalize) they are kept as a
+ *   non-orthogonal basis with overlap S = h^3 Psi Psi^T = L L^T and every
+ *   propagation runs the series of eq. commutator-expansion-nonort,
+ *   dP^(k) = (1/k)(-i dt)(S^-1 Hbar dP^(k-1) - dP^(k-1) Hbar S^-1); the initial
+ *   density matrix is L^-T diag(f) L^-1 (the occupations of the basis
+ *   orthonormalised by L, written in the given basis), the kick and the field
+ *   act through S^-1 M_q, and the reported electron count is Tr(P S).  Not
+ *   combined with magnus_order 4 or the learned predictor (RT_EINVAL); a basis
+ *   whose overlap is not positive definite gives RT_EINVAL at rt_init.
  * occ: occupations f_i (nullable: 2 for the first n_occ, 0 for the rest).
  */
 typedef struct {
@@ -88,6 +97,7 @@ typedef struct {
   const double* psi0;  /* [N][nz][ny][nx]                                        */
   int psi0_on_device;
   int orthonormalize;
+  int nonorthogonal;   /* propagate in the given basis with its overlap (above)  */
 } rt_system;
 
 /*

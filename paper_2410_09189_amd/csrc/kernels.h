@@ -131,9 +131,11 @@ hipError_t set_flags(hipStream_t s, int* dst, Flags256 f, int T);
 // Copies n32 32-bit words of device memory to box[16..] (host-mapped, coherent) and then
 // stores seq into box[0..1] with system-scope release, so a host that sees seq sees the words.
 hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long seq);
-// rows_t = (mu_x, mu_y, mu_z, E, TrP) from S'_t (stride 2N^2) and eparts_t; work: [T][160]
-hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
-                       const double* eparts, int estride, double* rows, long rstride, double* work, int T);
+// rows_t = (mu_x, mu_y, mu_z, E, N_e) from S'_t (stride 2N^2) and eparts_t; work: [T][160].
+// N_e = Tr P, or Tr(P ovl) for a non-orthogonal basis with overlap ovl (nullable).
+hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, const double* ovl,
+                       int N, const double* eparts, int estride, double* rows, long rstride, double* work, int T);
+hipError_t transpose(hipStream_t s, const double* A, double* out, int N);
 hipError_t cholesky(hipStream_t s, double* A, int N, int* info);
 hipError_t tri_inverse_lower(hipStream_t s, const double* L, double* Linv, int N);
 hipError_t upper_weighted(hipStream_t s, const double* S, double* W, int N, long sstride, int T,

@@ -1508,8 +1508,8 @@ hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsig
 // kObsBlocks blocks per trajectory write partial sums part[t][b][5]; stage 2 adds
 // them in block order (deterministic, independent of T).
 constexpr int kObsBlocks = 32;
-__global__ __launch_bounds__(256) void k_observables_part(const double* S, const double* M3, const double* hc, int N,
-                                                          double* part) {
+__global__ __launch_bounds__(256) void k_observables_part(const double* S, const double* M3, const double* hc,
+                                                          const double* ovl, int N, double* part) {
   __shared__ double sh[256];
   const int t = blockIdx.y;
   const long NN = (long)N * N;
@@ -1522,7 +1522,11 @@ __global__ __launch_bounds__(256) void k_observables_part(const double* S, const
     a2 += sv * M3[2 * NN + e];
     a3 += sv * hc[e];
   }
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += kObsBlocks * 256) a4 += S[(long)i * N + i];
+  if (ovl) {
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < NN; e += (long)kObsBlocks * 256) a4 += S[e] * ovl[e];
+  } else {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += kObsBlocks * 256) a4 += S[(long)i * N + i];
+  }
   a0 = block_sum_256(a0, sh);
   a1 = block_sum_256(a1, sh);
   a2 = block_sum_256(a2, sh);
@@ -1546,10 +1550,24 @@ __global__ void k_observables_final(const double* part, const double* eparts, in
   if (q == 3) a += eparts[(long)t * estride] + eparts[(long)t * estride + 1];
   rows[t * rstride + q] = a;
 }
-hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, int N,
-                       const double* eparts, int estride, double* rows, long rstride, double* work, int T) {
-  hipLaunchKernelGGL(k_observables_part, dim3(kObsBlocks, T), dim3(256), 0, s, S, M3, hcore, N, work);
+hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, const double* ovl,
+                       int N, const double* eparts, int estride, double* rows, long rstride, double* work, int T) {
+  hipLaunchKernelGGL(k_observables_part, dim3(kObsBlocks, T), dim3(256), 0, s, S, M3, hcore, ovl, N, work);
   hipLaunchKernelGGL(k_observables_final, dim3(T), dim3(64), 0, s, work, eparts, estride, rows, rstride);
+  return hipGetLastError();
+}
+
+// out = A^T (N x N)
+__global__ void k_transpose(const double* __restrict__ A, double* __restrict__ out, int N) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)N * N) return;
+  const int i = (int)(e / N), j = (int)(e - (long)i * N);
+  out[(long)j * N + i] = A[e];
+}
+hipError_t transpose(hipStream_t s, const double* A, double* out, int N) {
+  const long n = (long)N * N;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, out, N);
   return hipGetLastError();
 }
 

@@ -132,6 +132,8 @@ struct SysDev {
   int n_split_x = 1;  // splits of the BF16x3 projection
   long kps_x = 0;
   bool mixed = false;
+  bool nonorth = false;  // propagate in the given (non-orthogonal) basis with its overlap
+  double *Sov = nullptr, *Sinv = nullptr, *G = nullptr;  // overlap, its inverse, [T] S^-1 Hbar
   int T = 1;          // trajectory slots of this system (>= 1)
   int step = 0;       // steps taken (lockstep)
   std::vector<int> slot_traj;  // global trajectory index of each slot (-1: none)
@@ -342,6 +344,9 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
     }
     if (s.n_occ < 0 || s.n_virt < 0 || s.n_occ + s.n_virt < 1) { why = "active space"; return RT_EINVAL; }
     if (!s.psi0) { why = "psi0 is NULL"; return RT_EINVAL; }
+    if (s.nonorthogonal && s.orthonormalize) { why = "nonorthogonal and orthonormalize exclude each other"; return RT_EINVAL; }
+    if (s.nonorthogonal && run->magnus_order == 4) { why = "magnus_order 4 needs an orthonormal basis"; return RT_EINVAL; }
+    if (s.nonorthogonal && run->predictor == RT_PRED_MLP) { why = "the learned predictor needs an orthonormal basis"; return RT_EINVAL; }
   }
   if (!(run->dt != 0.0) || run->n_steps_max < 0 || run->max_scf < 1 || run->max_terms < 1 ||
       !(run->h_thrs > 0) || !(run->dp_thrs > 0)) { why = "run parameters"; return RT_EINVAL; }
@@ -482,6 +487,11 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.Hbar = a.take<double>(T * NN);
     d.hist = a.take<double>(T * 5L * (hist_cap + 1));
     d.fieldp = a.take<double>(T * 7L);
+    if (d.nonorth) {
+      d.Sov = a.take<double>(NN);
+      d.Sinv = a.take<double>(NN);
+      d.G = a.take<double>(T * NN);
+    }
     if (run.magnus_order == 4) {
       d.Bm = a.take<double>(T * NN);
       d.C2 = a.take<double>(T * 2 * NN);
@@ -532,6 +542,7 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
     d.nl = build_nl(s);
     d.n_union = (int)d.nl.u_idx.size();
     d.mixed = run->precision == RT_MIXED;
+    d.nonorth = s.nonorthogonal != 0;
     d.feat = d.nx % 16 == 0 && d.ny % 16 == 0 && d.nz % 16 == 0;
     d.mlp = run->predictor == RT_PRED_MLP;
     d.slot_traj.clear();
@@ -722,7 +733,15 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
                            d.Xm + first * NN, B, d.N, T, act));
     CK(rtk::series_begin(s, Pin, Pout, dP, H0, H1, const_cast<double*>(Hbar), d.N, dt, kmin, slots, stride, done,
                          resid, d.gwork, T, act, fp, d.M3, t_a, B));
+    if (d.nonorth) {
+      // non-orthogonal basis: the series runs on G = S^-1 Hbar (dP_k = (1/k)(-i dt)(G dP - dP G^T)),
+      // and its stop floor is the Gershgorin width of G
+      CK(rtk::gemm_nt_f64(s, d.N, d.N, d.N, d.Sinv, d.N, Hbar, d.N, nullptr, d.G + first * NN, d.N, 1, 0, 0,
+                          rtk::Batch{T, act, 0, NN, 0, NN}));
+      CK(rtk::gershgorin(s, d.G + first * NN, d.N, dt, kmin, d.gwork, T, act));
+    }
   }
+  const double* Gs = d.nonorth ? d.G + first * NN : Hbar;
   int k = 1;
   const int CH = 8;
   std::vector<int> hd(2 * T);
@@ -731,7 +750,7 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
     for (; k <= kend; ++k) {
       {
         Timed tm(c, PH_SERIES_GEMM);
-        CK(rtk::gemm_nt_f64_series(s, d.N, T, Hbar, dP, C, k, slots, stride, kmin, thrs, done, act));
+        CK(rtk::gemm_nt_f64_series(s, d.N, T, Gs, dP, C, k, slots, stride, kmin, thrs, done, act));
         if (B) CK(rtk::gemm_nt_f64_series(s, d.N, T, B, dP, C2, k, slots, stride, kmin, thrs, done, act));
       }
       {
@@ -758,7 +777,7 @@ rt_status observe(rt_ctx* c, SysDev& d, int row) {
   const double* Hc = c->run.frozen_hxc ? d.Hgs : d.hcore;
   const double* ep = c->run.frozen_hxc ? d.ezero : d.eparts;
   const int es = c->run.frozen_hxc ? 0 : 2;
-  CK(rtk::observables(c->stream, d.P0, d.M3, Hc, d.N, ep, es, d.hist + 5L * row, 5L * (c->hist_cap + 1), d.gwork,
+  CK(rtk::observables(c->stream, d.P0, d.M3, Hc, d.nonorth ? d.Sov : nullptr, d.N, ep, es, d.hist + 5L * row, 5L * (c->hist_cap + 1), d.gwork,
                       d.T));
   return RT_OK;
 }
@@ -857,10 +876,28 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   }
   RET(apply_h64(c, d, d.psi, d.hpsi, d.vion, d.N));
   RET(project(c, d, d.psi, d.hpsi, nullptr, d.hcore));
-  // ground-state Hamiltonian H_gs = H[diag(f)] with the full FP64 apply (slot 0 fields)
+  // ground-state Hamiltonian H_gs = H[P_gs] with the full FP64 apply (slot 0 fields);
+  // P_gs = diag(f), or for a non-orthogonal basis with overlap S = h^3 Phi Phi^T = L L^T:
+  // S^-1 = L^-T L^-1 and P_gs = L^-T diag(f) L^-1 (the occupations of the basis
+  // orthonormalised by L, written in the given basis; Appendix transformation rules)
   std::vector<double> pgs(NN, 0.0);
   for (long i = 0; i < N; ++i) pgs[i * N + i] = occ[i];
-  CK(hipMemcpyAsync(d.tmp, pgs.data(), NN * sizeof(double), hipMemcpyHostToDevice, st));
+  if (d.nonorth) {
+    RET(project(c, d, d.psi, d.psi, nullptr, d.Sov));
+    CK(rtk::copy_d(st, d.tmp, d.Sov, NN));
+    CK(rtk::cholesky(st, d.tmp, d.N, d.info));
+    int info = 0;
+    CK(hipMemcpyAsync(&info, d.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (info) return fail(c, RT_EINVAL, "basis overlap matrix is not positive definite");
+    CK(rtk::tri_inverse_lower(st, d.tmp, d.tmp2, d.N));
+    CK(rtk::transpose(st, d.tmp2, d.tmp, d.N));  // X = L^-T
+    CK(rtk::gemm_nt_f64(st, d.N, d.N, d.N, d.tmp, d.N, d.tmp, d.N, nullptr, d.Sinv, d.N, 1, 0, 0, rtk::single()));
+    CK(rtk::gemm_nt_f64(st, d.N, d.N, d.N, d.tmp, d.N, d.tmp, d.N, d.occ, d.tmp2, d.N, 1, 0, 0, rtk::single()));
+    CK(rtk::copy_d(st, d.tmp, d.tmp2, NN));
+  } else {
+    CK(hipMemcpyAsync(d.tmp, pgs.data(), NN * sizeof(double), hipMemcpyHostToDevice, st));
+  }
   std::vector<int> one(1, 1);
   RET(eval_h(c, d, 1, nullptr, one, d.tmp, NN, d.Hgs, true));
   CK(rtk::copy_d(st, d.vloc_gs, d.vloc, d.ng));
@@ -876,11 +913,14 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
     CK(rtk::split_bf16(st, d.psi, d.psi_hi, d.psi_lo, N * ng));
     if (d.psiT_hi) CK(rtk::split_bf16_t(st, d.psi, d.psiT_hi, d.psiT_lo, (int)N, d.wld, ng));
   }
-  // trajectories: P_0 = diag(f), then each slot's kick through the series
+  // trajectories: P_0 = P_gs, then each slot's kick through the series
   std::vector<double> p0((long)d.T * 2 * NN, 0.0);
-  for (int t = 0; t < d.T; ++t)
-    for (long i = 0; i < N; ++i) p0[(long)t * 2 * NN + i * N + i] = occ[i];
+  if (!d.nonorth)
+    for (int t = 0; t < d.T; ++t)
+      for (long i = 0; i < N; ++i) p0[(long)t * 2 * NN + i * N + i] = occ[i];
   CK(hipMemcpyAsync(d.P1, p0.data(), p0.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  if (d.nonorth)
+    for (int t = 0; t < d.T; ++t) CK(rtk::copy_d(st, d.P1 + (long)t * 2 * NN, d.tmp, NN));
   CK(rtk::copy_d(st, d.P0, d.P1, (long)d.T * 2 * NN));
   for (int t = 0; t < d.T; ++t) {
     int g = d.slot_traj[t];

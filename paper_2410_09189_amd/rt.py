@@ -32,6 +32,7 @@ class rt_system(ctypes.Structure):
         ("nl_sigma", ctypes.c_double), ("nl_D", _dp), ("n_occ", ctypes.c_int),
         ("n_virt", ctypes.c_int), ("occ", _dp), ("psi0", ctypes.c_void_p),
         ("psi0_on_device", ctypes.c_int), ("orthonormalize", ctypes.c_int),
+        ("nonorthogonal", ctypes.c_int),
     ]
 
 
@@ -120,7 +121,8 @@ class SystemArgs:
     """Holds the host arrays referenced by one rt_system struct."""
 
     def __init__(self, n, h, pos, depth, width, n_occ, n_virt, psi0, nl_rank=0, nl_rcut=2.0,
-                 nl_sigma=0.6, nl_D=None, n_images=2, occ=None, orthonormalize=False):
+                 nl_sigma=0.6, nl_D=None, n_images=2, occ=None, orthonormalize=False,
+                 nonorthogonal=False):
         self.pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         self.depth = np.ascontiguousarray(depth, dtype=np.float64)
         self.width = np.ascontiguousarray(width, dtype=np.float64)
@@ -145,6 +147,7 @@ class SystemArgs:
             s.psi0 = psi0.data_ptr()
             s.psi0_on_device = 1
         s.orthonormalize = int(orthonormalize)
+        s.nonorthogonal = int(nonorthogonal)
         self.struct = s
 
 

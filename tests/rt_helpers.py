@@ -6,12 +6,12 @@ import numpy as np
 from paper_2410_09189_amd import rt
 
 
-def system_args(s, psi, orthonormalize=False, device_psi=None):
+def system_args(s, psi, orthonormalize=False, device_psi=None, nonorthogonal=False):
     psi = np.ascontiguousarray(psi, dtype=np.float64)
     return rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
                          n_virt=s.n_virt, psi0=psi if device_psi is None else device_psi,
                          nl_rank=s.nl_rank, nl_rcut=s.nl_rcut, nl_sigma=s.nl_sigma, nl_D=s.nl_D,
-                         n_images=s.n_images, orthonormalize=orthonormalize)
+                         n_images=s.n_images, orthonormalize=orthonormalize, nonorthogonal=nonorthogonal)
 
 
 def run_args(rp, n_traj_axes=(0,), sys_index=None, kappas=None, **kw):

@@ -452,3 +452,72 @@ def test_several_molecules_in_one_context_equal_separate_runs_bitwise(precision,
         assert np.array_equal(together[q][0], alone[0]), q
         assert np.array_equal(together[q][1], alone[1]), q
         assert np.max(np.abs(together[q][0] - together[q][0][0])) > 1e-7  # the kick acted
+
+
+# Non-orthogonal basis (eq. commutator-expansion-nonort): the parity molecule in the
+# mixed basis Phi = A Psi, propagated through S^-1 of its overlap.
+NONORTH_STEPS = 40
+
+
+@functools.lru_cache(maxsize=None)
+def _nonorth_basis(seed, lower):
+    psi, _ = c1_ground_state()
+    s = c1_system()
+    N = psi.shape[0]
+    A = synth.basis_mixing(N, seed, strength=0.4, lower=lower)
+    phi = (A @ psi.reshape(N, -1)).reshape(psi.shape)
+    S = s.h ** 3 * (phi.reshape(N, -1) @ phi.reshape(N, -1).T)
+    return phi, 0.5 * (S + S.T)
+
+
+@functools.lru_cache(maxsize=None)
+def _nonorth_oracle_run(seed, lower):
+    phi, S = _nonorth_basis(seed, lower)
+    rp = synth.config_run("c1_parity_32", n_steps=NONORTH_STEPS, h_thrs=1e-12)
+    return oracle.run(oracle.Model(c1_system(), phi), rp, S=S)
+
+
+def _nonorth_gpu_run(phi, precision, hupdate):
+    from paper_2410_09189_amd import rt
+
+    s = c1_system()
+    rp = synth.config_run("c1_parity_32", n_steps=NONORTH_STEPS, h_thrs=1e-9 if precision else 1e-12)
+    ses = _session([system_args(s, phi, nonorthogonal=True)], run_args(rp, hupdate=hupdate, precision=precision))
+    rt.rt_step(ses.ctx, NONORTH_STEPS, n_traj=1)
+    out = rt.rt_dipole(ses.ctx, 0, 0, NONORTH_STEPS + 1)
+    ses.close()
+    return out
+
+
+@pytest.mark.parametrize("precision,hupdate", [(0, 0), (0, 1), (1, 1)])
+def test_c1_nonorthogonal_basis_matches_oracle(precision, hupdate):
+    """General mixing A: the series runs on S^-1 Hbar; dipole, energy and Tr(P S)
+    against the oracle's literal non-orthogonal propagation."""
+    _say(f"C1 non-orthogonal basis {NONORTH_STEPS} steps precision={precision} hupdate={hupdate}")
+    phi, S = _nonorth_basis(52, False)
+    ref = _nonorth_oracle_run(52, False)
+    mu, E, tr = _nonorth_gpu_run(phi, precision, hupdate)
+    dmu, dref = mu - mu[0], ref["mu"] - ref["mu"][0]
+    scale = np.max(np.abs(dref))
+    err = np.max(np.abs(dmu - dref))
+    print(f"non-orthogonal: max|dmu| {scale:.3e}, max err {err:.3e}", flush=True)
+    assert scale > 1e-5
+    if precision == 0:
+        assert np.max(np.abs(mu - ref["mu"])) < 1e-10
+        assert np.max(np.abs(E - ref["E"])) < 1e-10
+    else:
+        assert err < 1e-5 * scale
+    assert np.max(np.abs(tr - 16.0)) < 1e-11
+
+
+def test_c1_nonorthogonal_basis_reproduces_orthonormal_physics():
+    """Unit lower-triangular mixing: the Cholesky factor of the overlap is A itself,
+    so the initial state is the orthonormal ground state and the dipole history
+    must equal the orthonormal-basis oracle run (basis-invariant observables)."""
+    _say(f"C1 non-orthogonal (triangular) basis vs orthonormal oracle, {NONORTH_STEPS} steps")
+    phi, S = _nonorth_basis(51, True)
+    mu, E, tr = _nonorth_gpu_run(phi, 0, 0)
+    ref = c1_oracle_run(n_steps=NONORTH_STEPS)
+    assert np.max(np.abs(mu - ref["mu"])) < 1e-10
+    assert np.max(np.abs(E - ref["E"])) < 1e-9
+    assert np.max(np.abs(tr - 16.0)) < 1e-11
