@@ -49,7 +49,12 @@ typedef enum {
 } rt_status;
 
 enum { RT_FP64 = 0, RT_MIXED = 1 };               /* arithmetic of the time step   */
-enum { RT_PRED_LINEAR = 0, RT_PRED_MLP = 1 };     /* first guess of H(t + dt)      */
+/* first guess of H(t + dt): RT_PRED_LINEAR 2 H_0 - H_-1 (Algorithm 1);
+   RT_PRED_MLP the linear guess plus a learned correction (below);
+   RT_PRED_QUADRATIC 3 H_0 - 3 H_-1 + H_-2 (extrapolation error O(dt^3) instead of
+   O(dt^2); the fixed point is the same, only the number of updates changes).
+   H_-1 = H_-2 = H_0 at the first step and after rt_set_state with hm1 (H_-2 = hm1). */
+enum { RT_PRED_LINEAR = 0, RT_PRED_MLP = 1, RT_PRED_QUADRATIC = 2 };
 enum { RT_HUPDATE_FULL = 0, RT_HUPDATE_LOCAL = 1 };/* how H[P] is rebuilt, below    */
 
 /*
@@ -129,7 +134,7 @@ typedef struct {
   int max_scf;         /* cap on Hamiltonian updates per step (>= 1)             */
   int max_terms;       /* cap on series terms per propagation (>= 1)             */
   int precision;       /* RT_FP64 | RT_MIXED                                     */
-  int predictor;       /* RT_PRED_LINEAR | RT_PRED_MLP (see Learned predictor)   */
+  int predictor;       /* RT_PRED_LINEAR | RT_PRED_MLP | RT_PRED_QUADRATIC        */
   int hupdate;         /* RT_HUPDATE_FULL | RT_HUPDATE_LOCAL                     */
   int frozen_hxc;      /* test switch: V_H and v_x fixed at the ground state     */
   int n_traj;                /* at most 256 trajectories per system              */

@@ -9,7 +9,9 @@ Paper passages:
   * Commutator expansion P(t + dt) = P + sum_k dP^(k),
     dP^(k) = (1/k)(-i dt)[Hbar, dP^(k-1)] for an orthonormal basis
     (eq. commutator-expansion-ort), stopped when max|dP| <= dP_thrs (Algorithm 1).
-  * Self-consistent midpoint loop of Algorithm 1: predictor H_1 = 2 H_0 - H_-1,
+  * Self-consistent midpoint loop of Algorithm 1: predictor H_1 = 2 H_0 - H_-1
+    (or, as an option that changes only the number of updates, the quadratic
+    extrapolation 3 H_0 - 3 H_-1 + H_-2 through the last three steps),
     repeat { Omega from (H_0 + H_1)/2; propagate; H_1 <- DFT(rho(P_1)) } until
     the update of H_1 is below H_thrs; then shift H_-1 <- H_0, H_0 <- H_1,
     P_0 <- P_1.
@@ -212,13 +214,19 @@ def run(model, rp, method: str = "exact", predictor: str = "linear", record_p: b
         Hm1 = H_start
     else:
         Hm1 = H0.copy()
+    Hm2 = Hm1.copy()
     mu = [model.dipole(P)]
     E = [model.energy(P, aux)]
     tr = [electrons(P)]
     scf, terms = [0], [0]
     Ps = [P.copy()] if record_p else None
     for j in range(1, rp.n_steps + 1):
-        H1 = 2.0 * H0 - Hm1 if predictor == "linear" else H0.copy()
+        if predictor == "linear":
+            H1 = 2.0 * H0 - Hm1
+        elif predictor == "quadratic":
+            H1 = 3.0 * H0 - 3.0 * Hm1 + Hm2
+        else:
+            H1 = H0.copy()
         n_terms = 0
         Va = Vb = 0.0
         if field is not None:
@@ -244,7 +252,7 @@ def run(model, rp, method: str = "exact", predictor: str = "linear", record_p: b
                 break
         else:
             raise NoConvergence(f"self-consistent loop did not converge at step {j}")
-        Hm1, H0, P = H0, H1, P1
+        Hm2, Hm1, H0, P = Hm1, H0, H1, P1
         mu.append(model.dipole(P))
         E.append(model.energy(P, aux))
         tr.append(electrons(P))

@@ -90,6 +90,9 @@ hipError_t reduce_cols(hipStream_t s, const double* part, int nblk, int ncol, co
 // ---- N x N kernels (batched over T trajectories with stacked buffers) ----------
 hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double b, const double* y,
                    long n);
+// out = (a x + b y) + c z
+hipError_t lincomb3(hipStream_t s, double* out, double a, const double* x, double b, const double* y, double c,
+                    const double* z, long n);
 hipError_t copy_masked(hipStream_t s, double* dst, const double* src, long n, int T, const int* active);
 hipError_t max_abs_diff(hipStream_t s, const double* a, const double* b, long n,
                         unsigned long long* slot, int T, const int* active);

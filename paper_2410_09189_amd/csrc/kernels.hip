@@ -1166,6 +1166,17 @@ hipError_t lincomb(hipStream_t s, double* out, double a, const double* x, double
   return hipGetLastError();
 }
 
+__global__ void k_lincomb3(double* out, double a, const double* x, double b, const double* y, double c,
+                           const double* z, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = (a * x[i] + b * y[i]) + c * z[i];
+}
+hipError_t lincomb3(hipStream_t s, double* out, double a, const double* x, double b, const double* y, double c,
+                    const double* z, long n) {
+  hipLaunchKernelGGL(k_lincomb3, dim3(ew_blocks(n)), dim3(256), 0, s, out, a, x, b, y, c, z, n);
+  return hipGetLastError();
+}
+
 // dst_t = src_t for active trajectories (blockIdx.y = t), n elements each.
 __global__ void k_copy_masked(double* dst, const double* src, long n, const int* active) {
   const int t = blockIdx.y;

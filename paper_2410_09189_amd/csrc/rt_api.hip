@@ -164,7 +164,7 @@ struct SysDev {
   double *Bm = nullptr, *C2 = nullptr;     // fourth-order Magnus: Omega_2 [T][N^2], B . [S;A]^T [T][2N^2]
   double *A0m = nullptr, *A1m = nullptr, *Xm = nullptr;  // its scratch, [T][N^2] each
   bool field = false;                      // any slot with a nonzero pulse amplitude
-  double *H0, *H1, *Hm1, *Hn, *Hbar;       // N^2 each
+  double *H0, *H1, *Hm1, *Hm2, *Hn, *Hbar;  // N^2 each
   double* hist;                            // [T][cap + 1][5]
   double* kmin;                            // [T]
   unsigned long long *slots, *resid;       // [T][max_terms + 2], [T]
@@ -359,7 +359,9 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
         why = "mixed precision supports below 2^23 grid points (32-bit buffer offsets)"; return RT_EINVAL;
       }
   }
-  if (run->predictor != RT_PRED_LINEAR && run->predictor != RT_PRED_MLP) { why = "predictor"; return RT_EINVAL; }
+  if (run->predictor != RT_PRED_LINEAR && run->predictor != RT_PRED_MLP && run->predictor != RT_PRED_QUADRATIC) {
+    why = "predictor"; return RT_EINVAL;
+  }
   if (run->predictor == RT_PRED_MLP) {
     if (!run->mlp_params) { why = "RT_PRED_MLP needs mlp_params"; return RT_EINVAL; }
     for (int i = 0; i < n_sys; ++i)
@@ -483,6 +485,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.H0 = a.take<double>(T * NN);
     d.H1 = a.take<double>(T * NN);
     d.Hm1 = a.take<double>(T * NN);
+    d.Hm2 = a.take<double>(T * NN);
     d.Hn = a.take<double>(T * NN);
     d.Hbar = a.take<double>(T * NN);
     d.hist = a.take<double>(T * 5L * (hist_cap + 1));
@@ -948,6 +951,7 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   std::vector<int> all(d.T, 1);
   RET(eval_h(c, d, d.T, nullptr, all, d.P0, 2 * NN, d.H0, false));
   CK(rtk::copy_d(st, d.Hm1, d.H0, (long)d.T * NN));
+  CK(rtk::copy_d(st, d.Hm2, d.H0, (long)d.T * NN));
   d.step = 0;
   RET(observe(c, d, 0));
   RET(update_features(c, d));
@@ -961,7 +965,12 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   const rt_run& run = c->run;
   const long NN = nsq(d.N);
   const int T = d.T;
-  CK(rtk::lincomb(st, d.H1, 2.0, d.H0, -1.0, d.Hm1, T * NN));
+  // first guess of H(t + dt): linear extrapolation 2 H_0 - H_-1 (Algorithm 1), or the
+  // quadratic one 3 H_0 - 3 H_-1 + H_-2 (error O(dt^3) instead of O(dt^2))
+  if (run.predictor == RT_PRED_QUADRATIC)
+    CK(rtk::lincomb3(st, d.H1, 3.0, d.H0, -3.0, d.Hm1, 1.0, d.Hm2, T * NN));
+  else
+    CK(rtk::lincomb(st, d.H1, 2.0, d.H0, -1.0, d.Hm1, T * NN));
   bool predicted = false;
   if (d.mlp && d.x_valid) {
     bool any = false;
@@ -1020,7 +1029,9 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   }
   if (n_active > 0) return fail(c, RT_ENOCONV, "self-consistent Hamiltonian loop reached max_scf");
   // H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 (all slots together)
-  double* old_m1 = d.Hm1;
+  double* old_m2 = d.Hm2;
+  d.Hm2 = d.Hm1;
+  double* old_m1 = old_m2;
   d.Hm1 = d.H0;
   d.H0 = d.H1;
   d.H1 = old_m1;
@@ -1230,7 +1241,10 @@ rt_status rt_set_state(rt_ctx* c, int traj, const double* p_re, const double* p_
   if (p_re) CK(hipMemcpyAsync(d.P0 + t.slot * 2 * NN, p_re, NN * 8, hipMemcpyHostToDevice, s));
   if (p_im) CK(hipMemcpyAsync(d.P0 + t.slot * 2 * NN + NN, p_im, NN * 8, hipMemcpyHostToDevice, s));
   if (h0) CK(hipMemcpyAsync(d.H0 + t.slot * NN, h0, NN * 8, hipMemcpyHostToDevice, s));
-  if (hm1) CK(hipMemcpyAsync(d.Hm1 + t.slot * NN, hm1, NN * 8, hipMemcpyHostToDevice, s));
+  if (hm1) {
+    CK(hipMemcpyAsync(d.Hm1 + t.slot * NN, hm1, NN * 8, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(d.Hm2 + t.slot * NN, hm1, NN * 8, hipMemcpyHostToDevice, s));
+  }
   CK(hipStreamSynchronize(s));
   return RT_OK;
 }

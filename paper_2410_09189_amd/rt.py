@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librt_tddft.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ENOCONV, RT_ESTATE = 0, -1, -2, -3, -4, -5
 RT_FP64, RT_MIXED = 0, 1
-RT_PRED_LINEAR, RT_PRED_MLP = 0, 1
+RT_PRED_LINEAR, RT_PRED_MLP, RT_PRED_QUADRATIC = 0, 1, 2
 RT_HUPDATE_FULL, RT_HUPDATE_LOCAL = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)

@@ -521,3 +521,43 @@ def test_c1_nonorthogonal_basis_reproduces_orthonormal_physics():
     assert np.max(np.abs(mu - ref["mu"])) < 1e-10
     assert np.max(np.abs(E - ref["E"])) < 1e-9
     assert np.max(np.abs(tr - 16.0)) < 1e-11
+
+
+# Quadratic first guess 3 H_0 - 3 H_-1 + H_-2: same fixed point, fewer updates.
+@functools.lru_cache(maxsize=None)
+def _quad_oracle_run():
+    rp = synth.config_run("c1_parity_32", n_steps=40, dt=0.2, h_thrs=1e-12)
+    return oracle.run(c1_model(), rp, predictor="quadratic")
+
+
+@pytest.mark.parametrize("precision,hupdate", [(0, 0), (1, 1)])
+def test_c1_quadratic_predictor_matches_oracle_and_saves_updates(precision, hupdate):
+    _say(f"C1 quadratic predictor dt 0.2, precision={precision} hupdate={hupdate}")
+    from paper_2410_09189_amd import rt
+
+    s = c1_system()
+    psi, _ = c1_ground_state()
+
+    def gpu(predictor, h_thrs):
+        rp = synth.config_run("c1_parity_32", n_steps=40, dt=0.2, h_thrs=h_thrs)
+        ses = _session([system_args(s, psi)], run_args(rp, hupdate=hupdate, precision=precision,
+                                                        predictor=predictor))
+        st = rt.rt_step(ses.ctx, 40, n_traj=1, stats=True)
+        mu = rt.rt_dipole(ses.ctx, 0, 0, 41)[0]
+        ses.close()
+        return mu, np.array([x[0] for x in st])
+
+    ref = _quad_oracle_run()
+    mu, _ = gpu(rt.RT_PRED_QUADRATIC, 1e-9 if precision else 1e-12)
+    dref = ref["mu"] - ref["mu"][0]
+    err = np.max(np.abs((mu - mu[0]) - dref))
+    print(f"quadratic predictor: max err {err:.3e} of {np.max(np.abs(dref)):.3e}", flush=True)
+    if precision == 0:
+        assert np.max(np.abs(mu - ref["mu"])) < 1e-10
+    else:
+        assert err < 1e-5 * np.max(np.abs(dref))
+    # at the paper's threshold the quadratic guess needs fewer Hamiltonian updates
+    _, m_lin = gpu(rt.RT_PRED_LINEAR, 1e-7)
+    _, m_quad = gpu(rt.RT_PRED_QUADRATIC, 1e-7)
+    print(f"updates per step: linear {m_lin[3:].mean():.3f}, quadratic {m_quad[3:].mean():.3f}", flush=True)
+    assert m_quad[3:].mean() < m_lin[3:].mean() - 0.3

@@ -559,3 +559,44 @@ def test_nonorthogonal_run_reproduces_orthonormal_physics_general_basis():
     ref = c1_oracle_run(n_steps=20)
     assert np.max(np.abs(out["mu"] - ref["mu"])) < 1e-10
     assert np.max(np.abs(out["trace"] - 16.0)) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# Quadratic first guess 3 H_0 - 3 H_-1 + H_-2 (a predictor option: same fixed point)
+# ---------------------------------------------------------------------------
+def _guess_errors(dt, t_end, predictor):
+    """max |guess - converged H| at the steps that end near t_end, on a tightly
+    converged trajectory of the parity molecule."""
+    n = int(round(t_end / dt))
+    rp = synth.config_run("c1_parity_32", n_steps=n + 1, dt=dt, h_thrs=1e-13)
+    m = c1_model()
+    out = oracle.run(m, rp, record_p=True)
+    H = [m.h_of_p(P)[0] for P in out["Ps"]]
+    j = n
+    if predictor == "linear":
+        g = 2 * H[j - 1] - H[j - 2]
+    else:
+        g = 3 * H[j - 1] - 3 * H[j - 2] + H[j - 3]
+    return np.max(np.abs(g - H[j]))
+
+
+def test_quadratic_guess_error_is_third_order_in_dt():
+    """The linear guess misses the converged H by O(dt^2), the quadratic one by
+    O(dt^3): halving dt at a fixed time divides them by ~4 and ~8."""
+    el = [_guess_errors(dt, 1.6, "linear") for dt in (0.2, 0.1)]
+    eq = [_guess_errors(dt, 1.6, "quadratic") for dt in (0.2, 0.1)]
+    assert 3.0 < el[0] / el[1] < 5.0, el
+    assert 6.0 < eq[0] / eq[1] < 10.0, eq
+    assert eq[1] < 0.2 * el[1]
+
+
+def test_quadratic_predictor_keeps_the_fixed_point_and_saves_updates():
+    tight = synth.config_run("c1_parity_32", n_steps=40, dt=0.2, h_thrs=1e-12)
+    a = oracle.run(c1_model(), tight)
+    b = oracle.run(c1_model(), tight, predictor="quadratic")
+    assert np.max(np.abs(a["mu"] - b["mu"])) < 1e-10
+    paper = synth.config_run("c1_parity_32", n_steps=40, dt=0.2, h_thrs=1e-7)
+    lin = oracle.run(c1_model(), paper)
+    quad = oracle.run(c1_model(), paper, predictor="quadratic")
+    assert np.mean(quad["scf"][3:]) < np.mean(lin["scf"][3:]) - 0.3, (np.mean(lin["scf"][3:]), np.mean(quad["scf"][3:]))
+    assert np.max(np.abs(quad["mu"] - a["mu"])) < 1e-6
