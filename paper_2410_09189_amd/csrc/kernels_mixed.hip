@@ -217,8 +217,11 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
       rbh[u] = buf_ld16(rBh, v[u], so);
       rbl[u] = buf_ld16(rBl, v[u], so);
     }
-    rw0 = buf_ld16(rW, c8 * 4, 2 * so);
-    rw1 = buf_ld16(rW, c8 * 4 + 16, 2 * so);
+    // the range check covers the vector offset only, so columns past the end of the
+    // split take an out-of-range vector offset (zero, no memory access) as the rows do
+    const int wv = (tail && kb + c8 >= k1) ? (int)0x80000000 : c8 * 4;
+    rw0 = buf_ld16(rW, wv, 2 * so);
+    rw1 = buf_ld16(rW, wv + 16, 2 * so);
   };
   f32x4 acc[4][4];
 #pragma unroll
