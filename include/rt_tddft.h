@@ -156,6 +156,13 @@ typedef struct {
                                 [H_0 + V(t_j), H_1 + V(t_(j+1))] (Sec. Magnus
                                 expansion, H linear over the step), taken into
                                 every series term; other values: RT_EINVAL      */
+  int graph_capture;         /* 1: every Hamiltonian update (density, Hartree, LDA,
+                                projection, residual) and every series start with
+                                its first 8 terms is launched as an executable
+                                hipGraph captured once per buffer arrangement
+                                (at most a few per system: the buffers rotate);
+                                0: eager launches.  Off while the phase timers of
+                                rt_profile are on.  Results are identical.        */
 } rt_run;
 
 /* Per-trajectory, per-step counters written by rt_step when stats != NULL. */

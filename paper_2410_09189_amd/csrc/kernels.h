@@ -102,15 +102,17 @@ hipError_t gershgorin(hipStream_t s, const double* A, int N, double dt, double* 
 // series start: Pout = dP = Pin; Hbar = (H0 + H1)/2 when H0 != nullptr; slots, stop flags and
 // resid (nullable) zeroed; kmin from the Gershgorin width of Hbar (rows: scratch [T][N][2]).
 // fieldp (nullable, needs H0): per-trajectory pulse parameters [T][7]; Hbar then also gets
-// (V(t_a) + V(t_a + dt))/2 with V = sum_q E_q M_q (M3: [3][N^2]).
+// (V(t_a) + V(t_a + dt))/2 with V = sum_q E_q M_q (M3: [3][N^2]), t_a = *tptr (device scalar;
+// nullptr: 0).
 // Bm (nullable): Omega_2, whose i Bm / dt joins Hbar in the Gershgorin floor.
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
                         int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active,
-                        const double* fieldp, const double* M3, double t_a, const double* Bm);
-// Omega_2 = (dt^2/12)[H0 + V(t_a), H1 + V(t_a + dt)] into B ([T][N^2]); A0, A1, X: scratch [T][N^2]
+                        const double* fieldp, const double* M3, const double* tptr, const double* Bm);
+// Omega_2 = (dt^2/12)[H0 + V(t_a), H1 + V(t_a + dt)] into B ([T][N^2]); A0, A1, X: scratch [T][N^2];
+// t_a = *tptr (device scalar; nullptr: 0)
 hipError_t magnus2(hipStream_t s, const double* H0, const double* H1, const double* fieldp, const double* M3,
-                   double t_a, double dt, double* A0, double* A1, double* X, double* B, int N, int T,
+                   const double* tptr, double dt, double* A0, double* A1, double* X, double* B, int N, int T,
                    const int* active);
 // slot[t] = max |a_t - b_t| (atomic max; zeroed beforehand), then b_t = a_t
 hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, unsigned long long* slot, int T,
@@ -132,8 +134,9 @@ struct Flags256 {
 };
 hipError_t set_flags(hipStream_t s, int* dst, Flags256 f, int T);
 // Copies n32 32-bit words of device memory to box[16..] (host-mapped, coherent) and then
-// stores seq into box[0..1] with system-scope release, so a host that sees seq sees the words.
-hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long seq);
+// stores seq = ++(*ctr) (device counter) into box[0..1] with system-scope release, so a
+// host that sees seq sees the words.
+hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long* ctr);
 // rows_t = (mu_x, mu_y, mu_z, E, N_e) from S'_t (stride 2N^2) and eparts_t; work: [T][160].
 // N_e = Tr P, or Tr(P ovl) for a non-orthogonal basis with overlap ovl (nullable).
 hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, const double* ovl,

@@ -1293,9 +1293,10 @@ __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__
                                                       unsigned long long* slots, int stride, int* done,
                                                       unsigned long long* resid, const int* active,
                                                       const double* __restrict__ fieldp,
-                                                      const double* __restrict__ M3, double t_a, double t_b) {
+                                                      const double* __restrict__ M3, const double* tptr, double dt) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
+  const double t_a = tptr ? *tptr : 0.0, t_b = t_a + dt;
   const long NN = (long)N * N;
   Pin += t * 2 * NN;
   Pout += t * 2 * NN;
@@ -1334,12 +1335,12 @@ __global__ __launch_bounds__(256) void k_series_begin(const double* __restrict__
 hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* dP, const double* H0,
                         const double* H1, double* Hbar, int N, double dt, double* kmin, unsigned long long* slots,
                         int stride, int* done, unsigned long long* resid, double* rows, int T, const int* active,
-                        const double* fieldp, const double* M3, double t_a, const double* Bm) {
+                        const double* fieldp, const double* M3, const double* tptr, const double* Bm) {
   if (fieldp && !(H0 && M3)) return hipErrorInvalidValue;
   long n2 = 2L * N * N;
   int nb = ew_blocks(n2) > 256 ? 256 : ew_blocks(n2);
   hipLaunchKernelGGL(k_series_begin, dim3(nb, T), dim3(256), 0, s, Pin, Pout, dP, H0, H1, Hbar, N, slots, stride,
-                     done, resid, active, fieldp, M3, t_a, t_a + dt);
+                     done, resid, active, fieldp, M3, tptr, dt);
   // Gershgorin floor of the Hbar the series uses (read back when the field is in it)
   const bool direct = H0 && !fieldp;
   return gersh_launch(s, direct ? H0 : Hbar, direct ? H1 : nullptr, N, dt, kmin, rows, T, active, Bm);
@@ -1350,11 +1351,12 @@ hipError_t series_begin(hipStream_t s, const double* Pin, double* Pout, double* 
 // endpoints into A0/A1 (only with a field), X = A0 . A1^T = A0 A1 by the FP64 GEMM,
 // B = (dt^2/12)(X - X^T).
 __global__ void k_magnus2_ends(const double* __restrict__ H0, const double* __restrict__ H1,
-                               const double* __restrict__ fieldp, const double* __restrict__ M3, double t_a,
-                               double t_b, double* __restrict__ A0, double* __restrict__ A1, int N,
+                               const double* __restrict__ fieldp, const double* __restrict__ M3, const double* tptr,
+                               double dt, double* __restrict__ A0, double* __restrict__ A1, int N,
                                const int* active) {
   const int t = blockIdx.y;
   if (active && !active[t]) return;
+  const double t_a = tptr ? *tptr : 0.0, t_b = t_a + dt;
   const long NN = (long)N * N;
   const double* f = fieldp + 7L * t;
   const double ea = pulse_env(f, t_a), eb = pulse_env(f, t_b);
@@ -1375,14 +1377,14 @@ __global__ void k_antisym_scale(const double* __restrict__ X, double* __restrict
   }
 }
 hipError_t magnus2(hipStream_t s, const double* H0, const double* H1, const double* fieldp, const double* M3,
-                   double t_a, double dt, double* A0, double* A1, double* X, double* B, int N, int T,
+                   const double* tptr, double dt, double* A0, double* A1, double* X, double* B, int N, int T,
                    const int* active) {
   const long NN = (long)N * N;
   const int nb = ew_blocks(NN) > 256 ? 256 : ew_blocks(NN);
   const double* e0 = H0;
   const double* e1 = H1;
   if (fieldp) {
-    hipLaunchKernelGGL(k_magnus2_ends, dim3(nb, T), dim3(256), 0, s, H0, H1, fieldp, M3, t_a, t_a + dt, A0, A1, N,
+    hipLaunchKernelGGL(k_magnus2_ends, dim3(nb, T), dim3(256), 0, s, H0, H1, fieldp, M3, tptr, dt, A0, A1, N,
                        active);
     e0 = A0;
     e1 = A1;
@@ -1504,13 +1506,17 @@ hipError_t set_flags(hipStream_t s, int* dst, Flags256 f, int T) {
 
 // One lane copies the words into the host-mapped mailbox and then stores the sequence
 // number with a system-scope release: a host thread that reads seq also reads the words.
-__global__ void k_publish(const unsigned* src, int n, unsigned* box, unsigned long long seq) {
+// The sequence number is a device-side counter (ctr) advanced by every publish, so the
+// same launch can be replayed from a captured graph.
+__global__ void k_publish(const unsigned* src, int n, unsigned* box, unsigned long long* ctr) {
   if (threadIdx.x != 0) return;
+  const unsigned long long seq = *ctr + 1;
+  *ctr = seq;
   for (int i = 0; i < n; ++i) box[16 + i] = src[i];
   __hip_atomic_store(reinterpret_cast<unsigned long long*>(box), seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long seq) {
-  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, static_cast<const unsigned*>(src), n32, box, seq);
+hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long* ctr) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, static_cast<const unsigned*>(src), n32, box, ctr);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -133,6 +134,10 @@ struct SysDev {
   long kps_x = 0;
   bool mixed = false;
   bool nonorth = false;  // propagate in the given (non-orthogonal) basis with its overlap
+  double* tcur = nullptr;                  // device scalar: time t_j of the step being taken
+  unsigned long long* box_ctr = nullptr;   // device mailbox counter (system 0 holds the context's)
+  // executable graphs of the captured launch sequences, keyed by the buffers they use
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
   double *Sov = nullptr, *Sinv = nullptr, *G = nullptr;  // overlap, its inverse, [T] S^-1 Hbar
   int T = 1;          // trajectory slots of this system (>= 1)
   int step = 0;       // steps taken (lockstep)
@@ -225,7 +230,14 @@ struct rt_ctx {
   unsigned* box_dev = nullptr;
   size_t box_bytes = 0;
   unsigned long long box_seq = 0;
+  unsigned long long* box_ctr = nullptr;  // device-side count of mailbox writes
+  // graph capture of the per-update launch sequences (rt_run.graph_capture)
+  bool graphs = false;
+  hipStream_t cap = nullptr;  // capture-only stream (captured work is replayed on `stream`)
   ~rt_ctx() {
+    for (auto& d : sys)
+      for (auto& kv : d.graphs) (void)hipGraphExecDestroy(kv.second);
+    if (cap) (void)hipStreamDestroy(cap);
     if (box_host) (void)hipHostFree(box_host);
   }
 };
@@ -271,12 +283,52 @@ rt_status wait_box(rt_ctx* c, unsigned long long seq) {
 
 // Device-to-host read of nbytes (a multiple of 4) that orders after all work queued on the
 // context's stream: a publish kernel writes them to the mailbox, the host waits for it.
-rt_status read_back(rt_ctx* c, const void* src, size_t nbytes, void* out) {
+rt_status enqueue_publish(rt_ctx* c, const void* src, size_t nbytes) {
   if (nbytes % 4 != 0 || nbytes + 64 > c->box_bytes) return fail(c, RT_EINVAL, "read_back size");
-  const unsigned long long seq = ++c->box_seq;
-  CK(rtk::publish(c->stream, src, (int)(nbytes / 4), c->box_dev, seq));
-  RET(wait_box(c, seq));
+  CK(rtk::publish(c->stream, src, (int)(nbytes / 4), c->box_dev, c->box_ctr));
+  return RT_OK;
+}
+// Waits for the next mailbox write (one publish launched, eagerly or inside a graph)
+// and copies its words out.
+rt_status collect(rt_ctx* c, size_t nbytes, void* out) {
+  RET(wait_box(c, ++c->box_seq));
   std::memcpy(out, c->box_host + 16, nbytes);
+  return RT_OK;
+}
+rt_status read_back(rt_ctx* c, const void* src, size_t nbytes, void* out) {
+  RET(enqueue_publish(c, src, nbytes));
+  return collect(c, nbytes, out);
+}
+
+// Runs the launch sequence `enqueue` on the context's stream: from an executable graph
+// captured once per key (the buffers the sequence uses; all changing scalars live in
+// device memory), or eagerly when capture is off or the phase timers are on.  Capture
+// happens on a private stream and executes nothing; the graph then runs on `stream`.
+template <class F>
+rt_status run_graph(rt_ctx* c, SysDev& d, const std::vector<uintptr_t>& key, F&& enqueue) {
+  if (!c->graphs || c->prof) return enqueue();
+  auto it = d.graphs.find(key);
+  if (it == d.graphs.end() && d.graphs.size() >= 64) return enqueue();  // bounded cache
+  if (it == d.graphs.end()) {
+    hipStream_t user = c->stream;
+    CK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap;
+    rt_status st = enqueue();
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (st != RT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(c, RT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, RT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    it = d.graphs.emplace(key, ex).first;
+  }
+  CK(hipGraphLaunch(it->second, c->stream));
   return RT_OK;
 }
 
@@ -421,6 +473,8 @@ void choose_split(SysDev& d) {
 void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
   for (auto& d : S) {
     const long ng = d.ng, N = d.N, T = d.T, NN = N * N;
+    d.tcur = a.take<double>(1);
+    d.box_ctr = a.take<unsigned long long>(1);
     d.psi = a.take<double>(N * ng);
     d.hpsi = a.take<double>(N * ng);
     d.vion = a.take<double>(ng);
@@ -712,14 +766,13 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
 rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const std::vector<int>& act_host,
                  const double* Hbar, double dt, const double* Pin, double* Pout, std::vector<int>& terms,
                  const double* H0 = nullptr, const double* H1 = nullptr, unsigned long long* resid = nullptr,
-                 double t_a = 0.0) {
-  hipStream_t s = c->stream;
+                 const double* tptr = nullptr) {
   const long NN = nsq(d.N), n2 = 2 * NN;
   const int max_terms = c->run.max_terms;
   const int stride = max_terms + 2;
   const double thrs = c->run.dp_thrs;
-  double* dP = d.dP + first * n2;
-  double* dPn = d.dPn + first * n2;
+  double* const dP0 = d.dP + first * n2;
+  double* const dPn0 = d.dPn + first * n2;
   double* C = d.C + first * n2;
   double* kmin = d.kmin + first;
   unsigned long long* slots = d.slots + (long)first * stride;
@@ -727,43 +780,58 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
   // fourth-order Magnus (time steps only): Omega = -i dt Hbar + B, B = Omega_2
   double* B = (H0 && d.Bm) ? d.Bm + first * NN : nullptr;
   double* C2 = B ? d.C2 + first * n2 : nullptr;
-  {
-    Timed tm(c, PH_SMALL);
-    // the external field joins the midpoint Hamiltonian of a time step (H0 given):
-    // + (V(t_a) + V(t_a + dt))/2, V = sum_q E_q M_q
-    const double* fp = (H0 && d.field) ? d.fieldp + 7L * first : nullptr;
-    if (B) CK(rtk::magnus2(s, H0, H1, fp, d.M3, t_a, dt, d.A0m + first * NN, d.A1m + first * NN,
-                           d.Xm + first * NN, B, d.N, T, act));
-    CK(rtk::series_begin(s, Pin, Pout, dP, H0, H1, const_cast<double*>(Hbar), d.N, dt, kmin, slots, stride, done,
-                         resid, d.gwork, T, act, fp, d.M3, t_a, B));
-    if (d.nonorth) {
-      // non-orthogonal basis: the series runs on G = S^-1 Hbar (dP_k = (1/k)(-i dt)(G dP - dP G^T)),
-      // and its stop floor is the Gershgorin width of G
-      CK(rtk::gemm_nt_f64(s, d.N, d.N, d.N, d.Sinv, d.N, Hbar, d.N, nullptr, d.G + first * NN, d.N, 1, 0, 0,
-                          rtk::Batch{T, act, 0, NN, 0, NN}));
-      CK(rtk::gershgorin(s, d.G + first * NN, d.N, dt, kmin, d.gwork, T, act));
-    }
-  }
+  // the external field joins the midpoint Hamiltonian of a time step (H0 given):
+  // + (V(t_a) + V(t_a + dt))/2, V = sum_q E_q M_q, t_a = *tptr
+  const double* fp = (H0 && d.field) ? d.fieldp + 7L * first : nullptr;
   const double* Gs = d.nonorth ? d.G + first * NN : Hbar;
-  int k = 1;
-  const int CH = 8;
-  std::vector<int> hd(2 * T);
-  while (true) {
-    int kend = std::min(max_terms, k + CH - 1);
-    for (; k <= kend; ++k) {
+  const int CH = 8;  // terms per chunk between stop-flag reads (even: dP/dPn end where they began)
+  auto terms_k = [&](int k_from, int k_to) -> rt_status {
+    double* dP = dP0;
+    double* dPn = dPn0;
+    for (int k = k_from; k <= k_to; ++k) {
       {
         Timed tm(c, PH_SERIES_GEMM);
-        CK(rtk::gemm_nt_f64_series(s, d.N, T, Gs, dP, C, k, slots, stride, kmin, thrs, done, act));
-        if (B) CK(rtk::gemm_nt_f64_series(s, d.N, T, B, dP, C2, k, slots, stride, kmin, thrs, done, act));
+        CK(rtk::gemm_nt_f64_series(c->stream, d.N, T, Gs, dP, C, k, slots, stride, kmin, thrs, done, act));
+        if (B) CK(rtk::gemm_nt_f64_series(c->stream, d.N, T, B, dP, C2, k, slots, stride, kmin, thrs, done, act));
       }
       {
         Timed tm(c, PH_SERIES_UPDATE);
-        CK(rtk::series_update(s, C, C2, dPn, Pout, d.N, dt, k, slots, stride, kmin, thrs, done, T, act));
+        CK(rtk::series_update(c->stream, C, C2, dPn, Pout, d.N, dt, k, slots, stride, kmin, thrs, done, T, act));
       }
       std::swap(dP, dPn);
     }
-    CK(rtk::series_finish(s, kend, slots, stride, kmin, thrs, done, T, act));
-    RET(read_back(c, done, 2 * T * sizeof(int), hd.data()));
+    CK(rtk::series_finish(c->stream, k_to, slots, stride, kmin, thrs, done, T, act));
+    return enqueue_publish(c, done, 2 * T * sizeof(int));
+  };
+  // begin + first chunk + stop flags: one captured sequence
+  const int kend0 = std::min(max_terms, CH);
+  auto begin_chunk = [&]() -> rt_status {
+    {
+      Timed tm(c, PH_SMALL);
+      if (B) CK(rtk::magnus2(c->stream, H0, H1, fp, d.M3, tptr, dt, d.A0m + first * NN, d.A1m + first * NN,
+                             d.Xm + first * NN, B, d.N, T, act));
+      CK(rtk::series_begin(c->stream, Pin, Pout, dP0, H0, H1, const_cast<double*>(Hbar), d.N, dt, kmin, slots,
+                           stride, done, resid, d.gwork, T, act, fp, d.M3, tptr, B));
+      if (d.nonorth) {
+        // non-orthogonal basis: the series runs on G = S^-1 Hbar (dP_k = (1/k)(-i dt)(G dP - dP G^T)),
+        // and its stop floor is the Gershgorin width of G
+        CK(rtk::gemm_nt_f64(c->stream, d.N, d.N, d.N, d.Sinv, d.N, Hbar, d.N, nullptr, d.G + first * NN, d.N, 1, 0,
+                            0, rtk::Batch{T, act, 0, NN, 0, NN}));
+        CK(rtk::gershgorin(c->stream, d.G + first * NN, d.N, dt, kmin, d.gwork, T, act));
+      }
+    }
+    return terms_k(1, kend0);
+  };
+  uint64_t dtb;
+  std::memcpy(&dtb, &dt, sizeof(dtb));
+  const std::vector<uintptr_t> key{1, (uintptr_t)first, (uintptr_t)T, (uintptr_t)act, (uintptr_t)Hbar, (uintptr_t)Pin,
+                                   (uintptr_t)Pout, (uintptr_t)H0, (uintptr_t)H1, (uintptr_t)resid,
+                                   (uintptr_t)tptr, (uintptr_t)dtb};
+  RET(run_graph(c, d, key, begin_chunk));
+  std::vector<int> hd(2 * T);
+  int kend = kend0;
+  while (true) {
+    RET(collect(c, 2 * T * sizeof(int), hd.data()));
     bool all = true;
     for (int t = 0; t < T; ++t)
       if (act_host[t] && !hd[2 * t]) all = false;
@@ -773,6 +841,9 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
       return RT_OK;
     }
     if (kend >= max_terms) return fail(c, RT_ENOCONV, "commutator series reached max_terms");
+    const int k_to = std::min(max_terms, kend + CH);
+    RET(terms_k(kend + 1, k_to));
+    kend = k_to;
   }
 }
 
@@ -982,6 +1053,7 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   }
   d.active_host.assign(T, 1);
   RET(push_active(c, d));
+  CK(rtk::fill(st, d.tcur, 1, d.step * run.dt));  // t_j for the field terms of this step
   std::vector<int> m_of(T, 0), terms_of(T, 0);
   std::vector<double> res_of(T, 0.0);
   std::vector<unsigned long long> bits(T);
@@ -989,13 +1061,21 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
   for (int m = 1; m <= run.max_scf && n_active > 0; ++m) {
     std::vector<int> terms;
     RET(series(c, d, 0, T, d.active, d.active_host, d.Hbar, run.dt, d.P0, d.P1, terms, d.H0, d.H1, d.resid,
-               d.step * run.dt));
-    RET(eval_h(c, d, T, d.active, d.active_host, d.P1, 2 * NN, d.Hn, false));
-    {
-      Timed tm(c, PH_SMALL);
-      CK(rtk::max_diff_assign(st, d.Hn, d.H1, NN, d.resid, T, d.active));
-    }
-    RET(read_back(c, d.resid, T * sizeof(unsigned long long), bits.data()));
+               d.tcur));
+    // Hamiltonian update and its residual: one captured sequence (the host loops over
+    // trajectories in the full-apply mode, so the active pattern is part of the key)
+    auto update = [&]() -> rt_status {
+      RET(eval_h(c, d, T, d.active, d.active_host, d.P1, 2 * NN, d.Hn, false));
+      {
+        Timed tm(c, PH_SMALL);
+        CK(rtk::max_diff_assign(c->stream, d.Hn, d.H1, NN, d.resid, T, d.active));
+      }
+      return enqueue_publish(c, d.resid, T * sizeof(unsigned long long));
+    };
+    std::vector<uintptr_t> key{2, (uintptr_t)T, (uintptr_t)d.P1, (uintptr_t)d.H1};
+    for (int t = 0; t < T; ++t) key.push_back((uintptr_t)d.active_host[t]);
+    RET(run_graph(c, d, key, update));
+    RET(collect(c, T * sizeof(unsigned long long), bits.data()));
     bool changed = false;
     bool mask_changed = false;
     for (int t = 0; t < T; ++t) {
@@ -1113,6 +1193,18 @@ rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* work
   }
   c->box_host = static_cast<unsigned*>(box);
   std::memset(c->box_host, 0, c->box_bytes);
+  c->box_ctr = c->sys[0].box_ctr;
+  if (rtk::fill_u64(c->stream, c->box_ctr, 1, 0ull) != hipSuccess) {
+    g_init_error = "rt_init: mailbox counter";
+    delete c;
+    return RT_EDEVICE;
+  }
+  if (run->graph_capture && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    c->cap = nullptr;
+    g_init_error = "rt_init: capture stream";
+    delete c;
+    return RT_EDEVICE;
+  }
   for (int i = 0; i < n_sys; ++i) {
     st = init_system(c, c->sys[i], sys[i]);
     if (st != RT_OK) { g_init_error = c->err; delete c; return st; }
@@ -1123,6 +1215,7 @@ rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* work
     delete c;
     return RT_EDEVICE;
   }
+  c->graphs = run->graph_capture != 0;  // the one-off kicks of init ran eagerly
   *out = c;
   return RT_OK;
 }
@@ -1270,7 +1363,11 @@ rt_status rt_propagate(rt_ctx* c, int si, const double* hbar_dev, double dt, dou
   CK(hipMemcpyAsync(in, p_re_dev, NN * 8, hipMemcpyDeviceToDevice, s));
   CK(hipMemcpyAsync(in + NN, p_im_dev, NN * 8, hipMemcpyDeviceToDevice, s));
   std::vector<int> terms, one(1, 1);
-  RET(series(c, d, 0, 1, nullptr, one, hbar_dev, dt, in, outp, terms));
+  const bool g = c->graphs;
+  c->graphs = false;  // caller-owned buffers: not worth a graph per pointer set
+  const rt_status st = series(c, d, 0, 1, nullptr, one, hbar_dev, dt, in, outp, terms);
+  c->graphs = g;
+  RET(st);
   CK(hipMemcpyAsync(p_re_dev, outp, NN * 8, hipMemcpyDeviceToDevice, s));
   CK(hipMemcpyAsync(p_im_dev, outp + NN, NN * 8, hipMemcpyDeviceToDevice, s));
   CK(hipStreamSynchronize(s));

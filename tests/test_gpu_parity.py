@@ -563,3 +563,38 @@ def test_c1_quadratic_predictor_matches_oracle_and_saves_updates(precision, hupd
     _, m_quad = gpu(rt.RT_PRED_QUADRATIC, 1e-7)
     print(f"updates per step: linear {m_lin[3:].mean():.3f}, quadratic {m_quad[3:].mean():.3f}", flush=True)
     assert m_quad[3:].mean() < m_lin[3:].mean() - 0.3
+
+
+# hipGraph capture of the per-update sequences: every replay (one per Hamiltonian
+# update and series start, with the step's own eager launches and mailbox reads in
+# between) must reproduce the eager launches bit for bit.
+@pytest.mark.parametrize("precision,hupdate,case", [(0, 0, "kick"), (1, 1, "kick"), (0, 1, "pulse_m4"),
+                                                    (1, 1, "pulse")])
+def test_graph_capture_equals_eager_launches_bitwise(precision, hupdate, case):
+    _say(f"graph capture vs eager, precision={precision} hupdate={hupdate} {case}")
+    from paper_2410_09189_amd import rt
+
+    s = c1_system()
+    psi, _ = c1_ground_state()
+    n = 24
+    rp = synth.config_run("c1_parity_32", n_steps=n, dt=0.1, h_thrs=1e-9 if precision else 1e-11)
+    kw = dict(hupdate=hupdate, precision=precision)
+    axes = (0, 1, 2)
+    if case != "kick":
+        rp.kappa = 0.0
+        kw["traj_field"] = [PULSE, PULSE[:4] + (0.0, 1.0, 0.0), PULSE[:4] + (0.2, 0.0, 1.0)]
+    if case == "pulse_m4":
+        kw["magnus_order"] = 4
+    out = []
+    for graphs in (False, True):
+        ses = _session([system_args(s, psi)], run_args(rp, n_traj_axes=axes, graph_capture=graphs, **kw))
+        st = rt.rt_step(ses.ctx, n, n_traj=3, stats=True)
+        res = [rt.rt_dipole(ses.ctx, t, 0, n + 1) for t in range(3)]
+        ses.close()
+        out.append((st, res))
+    (st0, r0), (st1, r1) = out
+    assert st0 == st1
+    for a, b in zip(r0, r1):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    assert max(x[0] for x in st0) >= 2  # several updates per step: several replays per step
