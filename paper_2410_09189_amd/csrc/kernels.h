@@ -117,6 +117,8 @@ hipError_t magnus2(hipStream_t s, const double* H0, const double* H1, const doub
 // slot[t] = max |a_t - b_t| (atomic max; zeroed beforehand), then b_t = a_t
 hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, unsigned long long* slot, int T,
                            const int* active);
+// K splits of a series product; C and C2 take series_splits(N) x 2 N^2 doubles per trajectory
+int series_splits(int N);
 // series term k (1-based) for T trajectories: C_t = Hbar_t . [S;A]_t^T (N x 2N), dP_k -> dPn_t,
 // P1_t += dP_k, max |dP_k| -> slots[t][k]; skips trajectories whose series stopped.
 hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, const double* dP, double* C,

@@ -620,13 +620,22 @@ hipError_t gemm_nt_f64(hipStream_t s, int M, int N, long K, const double* A, lon
   return gemm_launch(s, M, N, K, A, lda, B, ldb, w, part, kps, n_split, upper, big, bt, sk);
 }
 
+// K = N split into series_splits(N) ranges of 16-aligned length so that a series
+// term, a latency-bound N x 2N x N product, spreads over several times more blocks.
+int series_splits(int N) { return N <= 64 ? 1 : (N <= 128 ? 2 : (N <= 192 ? 3 : 4)); }
+static long series_kps(int N) {
+  const int S = series_splits(N);
+  return ((N + S - 1) / S + 15) / 16 * 16;
+}
 hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, const double* dP, double* C,
                               int k, const unsigned long long* slots, int stride, const double* kmin,
                               double thrs, const int* done, const int* active) {
   SeriesSkip sk{slots, kmin, done, thrs, k, stride};
-  long NN = (long)N * N;
-  Batch bt{T, active, NN, 2 * NN, 0, 2 * NN};
-  return gemm_launch(s, N, 2 * N, N, Hbar, N, dP, N, nullptr, C, N, 1, 0, 0, bt, sk);
+  const long NN = (long)N * N;
+  const long kps = series_kps(N);
+  const int S = (int)((N + kps - 1) / kps);
+  Batch bt{T, active, NN, 2 * NN, 0, (long)series_splits(N) * 2 * NN};
+  return gemm_launch(s, N, 2 * N, N, Hbar, N, dP, N, nullptr, C, kps, S, 0, 0, bt, sk);
 }
 
 // C_t[m][n] = base_t[m][n] + alpha * sum_s part_t[s][m][n]; with mirror the upper
@@ -1426,9 +1435,14 @@ hipError_t max_diff_assign(hipStream_t s, const double* a, double* b, long n, un
 // blockIdx.y = trajectory; C, dPn, P1 have stride 2 N^2.
 // With Omega_2 = B (real antisymmetric), C2 = B . [S; A]^T adds (1/k)[B, S] =
 // (1/k)(C2_S + C2_S^T) to S_k and (1/k)[B, A] = (1/k)(-C2_A + C2_A^T) to A_k.
+// One block per 16 x 16 tile (i, j) of a trajectory, one element per thread: the
+// transposed entries (j, i) the update needs come from the mirror tile, read row-wise
+// into LDS, so every global read is coalesced.
 __global__ __launch_bounds__(256) void k_series_update(const double* __restrict__ C, const double* __restrict__ C2,
                                                        double* __restrict__ dPn, double* __restrict__ P1, int N,
-                                                       double dt, SeriesSkip sk, int* done, const int* active) {
+                                                       double dt, SeriesSkip sk, int* done, const int* active,
+                                                       int ns, int nsp) {
+  __shared__ double sT[4][16][17];  // mirror tile: C_S, C_A, C2_S, C2_A at (j, i)
   __shared__ double sh[256];
   const int t = blockIdx.y;
   if (active && !active[t]) return;
@@ -1442,26 +1456,56 @@ __global__ __launch_bounds__(256) void k_series_update(const double* __restrict_
   const double f = dt / sk.k, f2 = 1.0 / sk.k;
   const long NN = (long)N * N;
   const long N2 = 2L * N;
-  C += t * 2 * NN;
-  if (C2) C2 += t * 2 * NN;
+  C += t * (long)nsp * 2 * NN;
+  if (C2) C2 += t * (long)nsp * 2 * NN;
+  // C (and C2) hold ns K-split partial products [s][N][2N]; summed in split order
+  auto cs = [&](const double* X, long idx) {
+    double v = X[idx];
+    for (int q = 1; q < ns; ++q) v += X[q * 2 * NN + idx];
+    return v;
+  };
   dPn += t * 2 * NN;
   P1 += t * 2 * NN;
-  double m = 0.0;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < NN; e += (long)gridDim.x * blockDim.x) {
-    int i = (int)(e / N), j = (int)(e - (long)i * N);
-    double gA_ij = C[(long)i * N2 + N + j], gA_ji = C[(long)j * N2 + N + i];
-    double gS_ij = C[(long)i * N2 + j], gS_ji = C[(long)j * N2 + i];
-    double sv = -f * (gA_ij + gA_ji);
-    double av = -f * (gS_ij - gS_ji);
-    if (C2) {
-      sv += f2 * (C2[(long)i * N2 + j] + C2[(long)j * N2 + i]);
-      av += f2 * (C2[(long)j * N2 + N + i] - C2[(long)i * N2 + N + j]);
+  const int nt = (N + 15) / 16;
+  const int i0 = (blockIdx.x / nt) * 16, j0 = (blockIdx.x % nt) * 16;
+  {
+    const int r = threadIdx.x >> 4, q = threadIdx.x & 15;  // mirror element (j0 + r, i0 + q)
+    const int j = j0 + r, i = i0 + q;
+    double a = 0.0, b = 0.0, a2 = 0.0, b2 = 0.0;
+    if (j < N && i < N) {
+      a = cs(C, (long)j * N2 + i);
+      b = cs(C, (long)j * N2 + N + i);
+      if (C2) {
+        a2 = cs(C2, (long)j * N2 + i);
+        b2 = cs(C2, (long)j * N2 + N + i);
+      }
     }
-    dPn[e] = sv;
-    dPn[NN + e] = av;
-    P1[e] += sv;
-    P1[NN + e] += av;
-    m = fmax(m, sqrt(sv * sv + av * av));
+    sT[0][r][q] = a;
+    sT[1][r][q] = b;
+    sT[2][r][q] = a2;
+    sT[3][r][q] = b2;
+  }
+  __syncthreads();
+  double m = 0.0;
+  {
+    const int r = threadIdx.x >> 4, q = threadIdx.x & 15;  // element (i0 + r, j0 + q)
+    const int i = i0 + r, j = j0 + q;
+    if (i < N && j < N) {
+      const double gS_ij = cs(C, (long)i * N2 + j), gA_ij = cs(C, (long)i * N2 + N + j);
+      const double gS_ji = sT[0][q][r], gA_ji = sT[1][q][r];
+      double sv = -f * (gA_ij + gA_ji);
+      double av = -f * (gS_ij - gS_ji);
+      if (C2) {
+        sv += f2 * (cs(C2, (long)i * N2 + j) + sT[2][q][r]);
+        av += f2 * (sT[3][q][r] - cs(C2, (long)i * N2 + N + j));
+      }
+      const long o = (long)i * N + j;
+      dPn[o] = sv;
+      dPn[NN + o] = av;
+      P1[o] += sv;
+      P1[NN + o] += av;
+      m = fmax(m, sqrt(sv * sv + av * av));
+    }
   }
   m = block_max_256(m, sh);
   if (threadIdx.x == 0)
@@ -1471,10 +1515,11 @@ hipError_t series_update(hipStream_t s, const double* C, const double* C2, doubl
                          double dt, int k, unsigned long long* slots, int stride, const double* kmin, double thrs,
                          int* done, int T, const int* active) {
   SeriesSkip sk{slots, kmin, done, thrs, k, stride};
-  long NN = (long)N * N;
-  int nb = ew_blocks(NN);
-  if (nb > 256) nb = 256;
-  hipLaunchKernelGGL(k_series_update, dim3(nb, T), dim3(256), 0, s, C, C2, dPn, P1, N, dt, sk, done, active);
+  const int nb = ((N + 15) / 16) * ((N + 15) / 16);
+  const long kps = series_kps(N);
+  const int ns = (int)((N + kps - 1) / kps);
+  hipLaunchKernelGGL(k_series_update, dim3(nb, T), dim3(256), 0, s, C, C2, dPn, P1, N, dt, sk, done, active, ns,
+                     series_splits(N));
   return hipGetLastError();
 }
 

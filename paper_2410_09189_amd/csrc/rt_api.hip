@@ -535,7 +535,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.P1 = a.take<double>(T * 2 * NN);
     d.dP = a.take<double>(T * 2 * NN);
     d.dPn = a.take<double>(T * 2 * NN);
-    d.C = a.take<double>(T * 2 * NN);
+    d.C = a.take<double>(T * rtk::series_splits(d.N) * 2 * NN);
     d.H0 = a.take<double>(T * NN);
     d.H1 = a.take<double>(T * NN);
     d.Hm1 = a.take<double>(T * NN);
@@ -551,7 +551,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     }
     if (run.magnus_order == 4) {
       d.Bm = a.take<double>(T * NN);
-      d.C2 = a.take<double>(T * 2 * NN);
+      d.C2 = a.take<double>(T * rtk::series_splits(d.N) * 2 * NN);
       d.A0m = a.take<double>(T * NN);
       d.A1m = a.take<double>(T * NN);
       d.Xm = a.take<double>(T * NN);
@@ -773,13 +773,13 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
   const double thrs = c->run.dp_thrs;
   double* const dP0 = d.dP + first * n2;
   double* const dPn0 = d.dPn + first * n2;
-  double* C = d.C + first * n2;
+  double* C = d.C + first * rtk::series_splits(d.N) * n2;
   double* kmin = d.kmin + first;
   unsigned long long* slots = d.slots + (long)first * stride;
   int* done = d.done + 2 * first;
   // fourth-order Magnus (time steps only): Omega = -i dt Hbar + B, B = Omega_2
   double* B = (H0 && d.Bm) ? d.Bm + first * NN : nullptr;
-  double* C2 = B ? d.C2 + first * n2 : nullptr;
+  double* C2 = B ? d.C2 + first * rtk::series_splits(d.N) * n2 : nullptr;
   // the external field joins the midpoint Hamiltonian of a time step (H0 given):
   // + (V(t_a) + V(t_a + dt))/2, V = sum_q E_q M_q, t_a = *tptr
   const double* fp = (H0 && d.field) ? d.fieldp + 7L * first : nullptr;
