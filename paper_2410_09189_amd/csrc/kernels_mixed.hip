@@ -457,9 +457,11 @@ __global__ __launch_bounds__(256) void k_density_bf16x3(int N, long ng, const un
 // 7 - g (equal triangular work), a point group owns BN / WP points.
 // The chunk loop is unrolled (NC is a template argument) so the W fragments of chunk
 // c + PF load into a fixed register slot while chunks c + 1 .. c + PF - 1 compute:
-// no register rotation, hence no wait for loads still in flight.
-template <int BN, int WP, int NC, int PF>
-__global__ __launch_bounds__(256 * WP) void k_density_tile32(long ng, const unsigned short* __restrict__ whi,
+// no register rotation, hence no wait for loads still in flight.  With 64-point tiles
+// (67 KB of LDS) two blocks share a CU, so one block's tile load overlaps the other's
+// matrix work.
+template <int BN, int WP, int NC, int PF, int MINB>
+__global__ __launch_bounds__(256 * WP, MINB) void k_density_tile32(long ng, const unsigned short* __restrict__ whi,
                                                              const unsigned short* __restrict__ wlo,
                                                              const unsigned short* __restrict__ pth,
                                                              const unsigned short* __restrict__ ptl,
@@ -610,11 +612,11 @@ hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* w
                           const unsigned short* ptlo, const double* rho0, double* rho, int T, const int* active) {
   if (N <= 256) {
     if (!pthi || !ptlo) return hipErrorInvalidValue;
-    const dim3 grid(cdivm(ng, 128)), blk(512);
+    const dim3 grid(cdivm(ng, 64)), blk(256);
     switch (density_tile_ld(N) / 32) {
 #define RT_DENSITY_NC(nc)                                                                                         \
   case nc:                                                                                                        \
-    hipLaunchKernelGGL((k_density_tile32<128, 2, nc, 2>), grid, blk, 0, s, ng, whi, wlo, pthi, ptlo, rho0, rho, T, \
+    hipLaunchKernelGGL((k_density_tile32<64, 1, nc, 2, 2>), grid, blk, 0, s, ng, whi, wlo, pthi, ptlo, rho0, rho, T, \
                        active);                                                                                   \
     break;
       RT_DENSITY_NC(1) RT_DENSITY_NC(2) RT_DENSITY_NC(3) RT_DENSITY_NC(4)
