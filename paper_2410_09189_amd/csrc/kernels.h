@@ -135,10 +135,10 @@ struct Flags256 {
   unsigned long long w[4];
 };
 hipError_t set_flags(hipStream_t s, int* dst, Flags256 f, int T);
-// Copies n32 32-bit words of device memory to box[16..] (host-mapped, coherent) and then
-// stores seq = ++(*ctr) (device counter) into box[0..1] with system-scope release, so a
-// host that sees seq sees the words.
-hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long* ctr);
+// Copies n32 32-bit words of device memory to box[off + 2 ..] (host-mapped, coherent) and
+// then stores seq = ++(*ctr) (device counter) into box[off .. off + 1] with system-scope
+// release, so a host that sees seq sees the words.
+hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, int off, unsigned long long* ctr);
 // rows_t = (mu_x, mu_y, mu_z, E, N_e) from S'_t (stride 2N^2) and eparts_t; work: [T][160].
 // N_e = Tr P, or Tr(P ovl) for a non-orthogonal basis with overlap ovl (nullable).
 hipError_t observables(hipStream_t s, const double* S, const double* M3, const double* hcore, const double* ovl,

@@ -1549,19 +1549,20 @@ hipError_t set_flags(hipStream_t s, int* dst, Flags256 f, int T) {
   return hipGetLastError();
 }
 
-// One lane copies the words into the host-mapped mailbox and then stores the sequence
-// number with a system-scope release: a host thread that reads seq also reads the words.
-// The sequence number is a device-side counter (ctr) advanced by every publish, so the
-// same launch can be replayed from a captured graph.
-__global__ void k_publish(const unsigned* src, int n, unsigned* box, unsigned long long* ctr) {
+// One lane copies the words into a slot of the host-mapped mailbox and then stores the
+// slot's sequence number with a system-scope release: a host thread that reads seq also
+// reads the words.  The sequence number is a device-side counter (ctr) of the slot's
+// owner, advanced by every publish, so the same launch can be replayed from a graph.
+__global__ void k_publish(const unsigned* src, int n, unsigned* box, int off, unsigned long long* ctr) {
   if (threadIdx.x != 0) return;
   const unsigned long long seq = *ctr + 1;
   *ctr = seq;
-  for (int i = 0; i < n; ++i) box[16 + i] = src[i];
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(box), seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  for (int i = 0; i < n; ++i) box[off + 2 + i] = src[i];
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(box + off), seq, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
 }
-hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, unsigned long long* ctr) {
-  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, static_cast<const unsigned*>(src), n32, box, ctr);
+hipError_t publish(hipStream_t s, const void* src, int n32, unsigned* box, int off, unsigned long long* ctr) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, static_cast<const unsigned*>(src), n32, box, off, ctr);
   return hipGetLastError();
 }
 

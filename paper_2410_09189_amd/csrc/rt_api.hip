@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -135,7 +136,11 @@ struct SysDev {
   bool mixed = false;
   bool nonorth = false;  // propagate in the given (non-orthogonal) basis with its overlap
   double* tcur = nullptr;                  // device scalar: time t_j of the step being taken
-  unsigned long long* box_ctr = nullptr;   // device mailbox counter (system 0 holds the context's)
+  int box_off = 0;                         // this system's mailbox slot (words): seq, then payload
+  unsigned long long box_seq = 0;          // publishes of this system the host has consumed
+  hipStream_t sst = nullptr;               // own stream when the context steps several systems
+  hipEvent_t ev = nullptr;                 // joins sst back into the caller's stream
+  unsigned long long* box_ctr = nullptr;   // device count of this system's mailbox writes
   // executable graphs of the captured launch sequences, keyed by the buffers they use
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
   double *Sov = nullptr, *Sinv = nullptr, *G = nullptr;  // overlap, its inverse, [T] S^-1 Hbar
@@ -225,18 +230,22 @@ struct rt_ctx {
   float *rec_x = nullptr, *rec_y = nullptr;
   int rec_cap = 0, rec_count = 0;
   // host-mapped mailbox for the per-iteration convergence flags: the device writes them
-  // with a sequence number and the host polls it (no copy, no interrupt-driven wait)
+  // with a sequence number per system slot and the host polls it (no copy, no
+  // interrupt-driven wait)
   unsigned* box_host = nullptr;
   unsigned* box_dev = nullptr;
   size_t box_bytes = 0;
-  unsigned long long box_seq = 0;
-  unsigned long long* box_ctr = nullptr;  // device-side count of mailbox writes
   // graph capture of the per-update launch sequences (rt_run.graph_capture)
   bool graphs = false;
   hipStream_t cap = nullptr;  // capture-only stream (captured work is replayed on `stream`)
+  hipEvent_t join = nullptr;  // caller's stream position at the start of rt_step
   ~rt_ctx() {
-    for (auto& d : sys)
+    for (auto& d : sys) {
       for (auto& kv : d.graphs) (void)hipGraphExecDestroy(kv.second);
+      if (d.sst) (void)hipStreamDestroy(d.sst);
+      if (d.ev) (void)hipEventDestroy(d.ev);
+    }
+    if (join) (void)hipEventDestroy(join);
     if (cap) (void)hipStreamDestroy(cap);
     if (box_host) (void)hipHostFree(box_host);
   }
@@ -265,40 +274,66 @@ long nsq(int N) { return (long)N * N; }
 // Waits until the mailbox holds sequence number seq.  Spins on the host-mapped word; every
 // few thousand polls it asks the stream whether work is still pending, so a stream that
 // drained without writing seq, or that failed, ends the wait with an error.
-rt_status wait_box(rt_ctx* c, unsigned long long seq) {
-  const unsigned long long* f = reinterpret_cast<const unsigned long long*>(c->box_host);
+// Mailbox: every system owns a slot [seq (2 words)][payload], written by a publish kernel
+// on the system's stream.  The host waits for the slots of several systems at once, so
+// their flags are read after one round trip.
+const unsigned long long* slot_seq(rt_ctx* c, const SysDev& d) {
+  return reinterpret_cast<const unsigned long long*>(c->box_host + d.box_off);
+}
+hipStream_t stream_of(rt_ctx* c, const SysDev& d) { return d.sst ? d.sst : c->stream; }
+
+// Waits until every listed system's slot holds its next sequence number.  Spins on the
+// host-mapped words; every few thousand polls it asks the streams (the caller's and the
+// system's own) whether work is still pending, so streams that drained without writing
+// the slot, or failed, end the wait.
+rt_status wait_slots(rt_ctx* c, const std::vector<SysDev*>& ds) {
   for (long spin = 1;; ++spin) {
-    if (__atomic_load_n(f, __ATOMIC_ACQUIRE) == seq) return RT_OK;
+    bool all = true;
+    for (const SysDev* d : ds)
+      if (__atomic_load_n(slot_seq(c, *d), __ATOMIC_ACQUIRE) != d->box_seq + 1) all = false;
+    if (all) break;
     if ((spin & 4095) == 0) {
-      hipError_t e = hipStreamQuery(c->stream);
-      if (e == hipSuccess) {
-        if (__atomic_load_n(f, __ATOMIC_ACQUIRE) == seq) return RT_OK;
-        return fail(c, RT_EDEVICE, "stream drained without writing the mailbox");
+      for (const SysDev* d : ds) {
+        if (__atomic_load_n(slot_seq(c, *d), __ATOMIC_ACQUIRE) == d->box_seq + 1) continue;
+        // the publish went to the caller's stream or to the system's own one
+        hipError_t e = hipStreamQuery(c->stream);
+        if (e == hipSuccess && d->sst) e = hipStreamQuery(d->sst);
+        if (e == hipSuccess) {
+          if (__atomic_load_n(slot_seq(c, *d), __ATOMIC_ACQUIRE) == d->box_seq + 1) continue;
+          return fail(c, RT_EDEVICE, "stream drained without writing the mailbox");
+        }
+        if (e != hipErrorNotReady) return fail(c, RT_EDEVICE, std::string("wait_slots: ") + hipGetErrorString(e));
       }
-      if (e != hipErrorNotReady) return fail(c, RT_EDEVICE, std::string("wait_box: ") + hipGetErrorString(e));
     }
     __builtin_ia32_pause();
   }
+  for (SysDev* d : ds) d->box_seq += 1;
+  return RT_OK;
+}
+rt_status wait_slot(rt_ctx* c, SysDev& d) { return wait_slots(c, std::vector<SysDev*>{&d}); }
+
+rt_status enqueue_publish(rt_ctx* c, const SysDev& d, const void* src, size_t nbytes) {
+  if (nbytes % 4 != 0 || nbytes / 4 > (size_t)(2 * d.T + 2)) return fail(c, RT_EINVAL, "mailbox slot size");
+  CK(rtk::publish(c->stream, src, (int)(nbytes / 4), c->box_dev, d.box_off, d.box_ctr));
+  return RT_OK;
+}
+void slot_read(rt_ctx* c, const SysDev& d, size_t nbytes, void* out) {
+  std::memcpy(out, c->box_host + d.box_off + 2, nbytes);
+}
+rt_status read_back(rt_ctx* c, SysDev& d, const void* src, size_t nbytes, void* out) {
+  RET(enqueue_publish(c, d, src, nbytes));
+  RET(wait_slot(c, d));
+  slot_read(c, d, nbytes, out);
+  return RT_OK;
 }
 
-// Device-to-host read of nbytes (a multiple of 4) that orders after all work queued on the
-// context's stream: a publish kernel writes them to the mailbox, the host waits for it.
-rt_status enqueue_publish(rt_ctx* c, const void* src, size_t nbytes) {
-  if (nbytes % 4 != 0 || nbytes + 64 > c->box_bytes) return fail(c, RT_EINVAL, "read_back size");
-  CK(rtk::publish(c->stream, src, (int)(nbytes / 4), c->box_dev, c->box_ctr));
-  return RT_OK;
-}
-// Waits for the next mailbox write (one publish launched, eagerly or inside a graph)
-// and copies its words out.
-rt_status collect(rt_ctx* c, size_t nbytes, void* out) {
-  RET(wait_box(c, ++c->box_seq));
-  std::memcpy(out, c->box_host + 16, nbytes);
-  return RT_OK;
-}
-rt_status read_back(rt_ctx* c, const void* src, size_t nbytes, void* out) {
-  RET(enqueue_publish(c, src, nbytes));
-  return collect(c, nbytes, out);
-}
+// Launches issued in its scope go to the given stream.
+struct OnStream {
+  rt_ctx* c;
+  hipStream_t saved;
+  OnStream(rt_ctx* c_, hipStream_t s) : c(c_), saved(c_->stream) { c->stream = s; }
+  ~OnStream() { c->stream = saved; }
+};
 
 // Runs the launch sequence `enqueue` on the context's stream: from an executable graph
 // captured once per key (the buffers the sequence uses; all changing scalars live in
@@ -762,30 +797,56 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
 
 // P_t -> U_t P_t U_t^dagger, U_t = exp(-i dt Hbar_t), by the commutator series, for the
 // T slots starting at the given buffers (stacked [S; A], stride 2 N^2).  flags/scratch
-// (kmin, slots, done, dP, dPn, C) are the system's, offset by `first`.
-rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const std::vector<int>& act_host,
-                 const double* Hbar, double dt, const double* Pin, double* Pout, std::vector<int>& terms,
-                 const double* H0 = nullptr, const double* H1 = nullptr, unsigned long long* resid = nullptr,
-                 const double* tptr = nullptr) {
-  const long NN = nsq(d.N), n2 = 2 * NN;
-  const int max_terms = c->run.max_terms;
-  const int stride = max_terms + 2;
-  const double thrs = c->run.dp_thrs;
-  double* const dP0 = d.dP + first * n2;
-  double* const dPn0 = d.dPn + first * n2;
-  double* C = d.C + first * rtk::series_splits(d.N) * n2;
-  double* kmin = d.kmin + first;
-  unsigned long long* slots = d.slots + (long)first * stride;
-  int* done = d.done + 2 * first;
-  // fourth-order Magnus (time steps only): Omega = -i dt Hbar + B, B = Omega_2
-  double* B = (H0 && d.Bm) ? d.Bm + first * NN : nullptr;
-  double* C2 = B ? d.C2 + first * rtk::series_splits(d.N) * n2 : nullptr;
-  // the external field joins the midpoint Hamiltonian of a time step (H0 given):
-  // + (V(t_a) + V(t_a + dt))/2, V = sum_q E_q M_q, t_a = *tptr
-  const double* fp = (H0 && d.field) ? d.fieldp + 7L * first : nullptr;
-  const double* Gs = d.nonorth ? d.G + first * NN : Hbar;
-  const int CH = 8;  // terms per chunk between stop-flag reads (even: dP/dPn end where they began)
-  auto terms_k = [&](int k_from, int k_to) -> rt_status {
+// (kmin, slots, done, dP, dPn, C) are the system's, offset by `first`.  start() launches
+// the series start with its first terms and the stop-flag publish; complete() reads the
+// flags (after the caller's wait) and runs further chunks of terms until every active
+// trajectory has stopped.
+struct Series {
+  static constexpr int CH = 8;  // terms per chunk between flag reads (even: dP/dPn end where they began)
+  rt_ctx* c;
+  SysDev& d;
+  int first, T;
+  const int* act;
+  const double* Hbar;
+  double dt;
+  const double *Pin, *H0, *H1, *tptr;
+  double* Pout;
+  unsigned long long* resid;
+  long NN, n2;
+  int max_terms, stride;
+  double thrs;
+  double *dP0, *dPn0, *C, *kmin, *B, *C2;
+  unsigned long long* slots;
+  int* done;
+  const double *fp, *Gs;
+  int kend = 0;
+
+  Series(rt_ctx* c_, SysDev& d_, int first_, int T_, const int* act_, const double* Hbar_, double dt_,
+         const double* Pin_, double* Pout_, const double* H0_, const double* H1_, unsigned long long* resid_,
+         const double* tptr_)
+      : c(c_), d(d_), first(first_), T(T_), act(act_), Hbar(Hbar_), dt(dt_), Pin(Pin_), H0(H0_), H1(H1_),
+        tptr(tptr_), Pout(Pout_), resid(resid_) {
+    NN = nsq(d.N);
+    n2 = 2 * NN;
+    max_terms = c->run.max_terms;
+    stride = max_terms + 2;
+    thrs = c->run.dp_thrs;
+    dP0 = d.dP + first * n2;
+    dPn0 = d.dPn + first * n2;
+    C = d.C + first * rtk::series_splits(d.N) * n2;
+    kmin = d.kmin + first;
+    slots = d.slots + (long)first * stride;
+    done = d.done + 2 * first;
+    // fourth-order Magnus (time steps only): Omega = -i dt Hbar + B, B = Omega_2
+    B = (H0 && d.Bm) ? d.Bm + first * NN : nullptr;
+    C2 = B ? d.C2 + first * rtk::series_splits(d.N) * n2 : nullptr;
+    // the external field joins the midpoint Hamiltonian of a time step (H0 given):
+    // + (V(t_a) + V(t_a + dt))/2, V = sum_q E_q M_q, t_a = *tptr
+    fp = (H0 && d.field) ? d.fieldp + 7L * first : nullptr;
+    Gs = d.nonorth ? d.G + first * NN : Hbar;
+  }
+
+  rt_status terms_k(int k_from, int k_to) {
     double* dP = dP0;
     double* dPn = dPn0;
     for (int k = k_from; k <= k_to; ++k) {
@@ -801,11 +862,10 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
       std::swap(dP, dPn);
     }
     CK(rtk::series_finish(c->stream, k_to, slots, stride, kmin, thrs, done, T, act));
-    return enqueue_publish(c, done, 2 * T * sizeof(int));
-  };
-  // begin + first chunk + stop flags: one captured sequence
-  const int kend0 = std::min(max_terms, CH);
-  auto begin_chunk = [&]() -> rt_status {
+    return enqueue_publish(c, d, done, 2 * T * sizeof(int));
+  }
+
+  rt_status begin_chunk() {
     {
       Timed tm(c, PH_SMALL);
       if (B) CK(rtk::magnus2(c->stream, H0, H1, fp, d.M3, tptr, dt, d.A0m + first * NN, d.A1m + first * NN,
@@ -820,31 +880,51 @@ rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const s
         CK(rtk::gershgorin(c->stream, d.G + first * NN, d.N, dt, kmin, d.gwork, T, act));
       }
     }
-    return terms_k(1, kend0);
-  };
-  uint64_t dtb;
-  std::memcpy(&dtb, &dt, sizeof(dtb));
-  const std::vector<uintptr_t> key{1, (uintptr_t)first, (uintptr_t)T, (uintptr_t)act, (uintptr_t)Hbar, (uintptr_t)Pin,
-                                   (uintptr_t)Pout, (uintptr_t)H0, (uintptr_t)H1, (uintptr_t)resid,
-                                   (uintptr_t)tptr, (uintptr_t)dtb};
-  RET(run_graph(c, d, key, begin_chunk));
-  std::vector<int> hd(2 * T);
-  int kend = kend0;
-  while (true) {
-    RET(collect(c, 2 * T * sizeof(int), hd.data()));
-    bool all = true;
-    for (int t = 0; t < T; ++t)
-      if (act_host[t] && !hd[2 * t]) all = false;
-    if (all) {
-      terms.assign(T, 0);
-      for (int t = 0; t < T; ++t) terms[t] = act_host[t] ? hd[2 * t + 1] : 0;
-      return RT_OK;
-    }
-    if (kend >= max_terms) return fail(c, RT_ENOCONV, "commutator series reached max_terms");
-    const int k_to = std::min(max_terms, kend + CH);
-    RET(terms_k(kend + 1, k_to));
-    kend = k_to;
+    return terms_k(1, kend);
   }
+
+  // begin + first chunk + stop-flag publish: one captured sequence
+  rt_status start() {
+    kend = std::min(max_terms, CH);
+    uint64_t dtb;
+    std::memcpy(&dtb, &dt, sizeof(dtb));
+    const std::vector<uintptr_t> key{1, (uintptr_t)first, (uintptr_t)T, (uintptr_t)act, (uintptr_t)Hbar,
+                                     (uintptr_t)Pin, (uintptr_t)Pout, (uintptr_t)H0, (uintptr_t)H1,
+                                     (uintptr_t)resid, (uintptr_t)tptr, (uintptr_t)dtb};
+    return run_graph(c, d, key, [&]() { return begin_chunk(); });
+  }
+
+  // after the wait for start()'s publish
+  rt_status complete(const std::vector<int>& act_host, std::vector<int>& terms) {
+    std::vector<int> hd(2 * T);
+    slot_read(c, d, 2 * T * sizeof(int), hd.data());
+    while (true) {
+      bool all = true;
+      for (int t = 0; t < T; ++t)
+        if (act_host[t] && !hd[2 * t]) all = false;
+      if (all) {
+        terms.assign(T, 0);
+        for (int t = 0; t < T; ++t) terms[t] = act_host[t] ? hd[2 * t + 1] : 0;
+        return RT_OK;
+      }
+      if (kend >= max_terms) return fail(c, RT_ENOCONV, "commutator series reached max_terms");
+      const int k_to = std::min(max_terms, kend + CH);
+      RET(terms_k(kend + 1, k_to));
+      kend = k_to;
+      RET(wait_slot(c, d));
+      slot_read(c, d, 2 * T * sizeof(int), hd.data());
+    }
+  }
+};
+
+rt_status series(rt_ctx* c, SysDev& d, int first, int T, const int* act, const std::vector<int>& act_host,
+                 const double* Hbar, double dt, const double* Pin, double* Pout, std::vector<int>& terms,
+                 const double* H0 = nullptr, const double* H1 = nullptr, unsigned long long* resid = nullptr,
+                 const double* tptr = nullptr) {
+  Series sr(c, d, first, T, act, Hbar, dt, Pin, Pout, H0, H1, resid, tptr);
+  RET(sr.start());
+  RET(wait_slot(c, d));
+  return sr.complete(act_host, terms);
 }
 
 rt_status observe(rt_ctx* c, SysDev& d, int row) {
@@ -1031,7 +1111,19 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
 }
 
 // One lockstep time step of every trajectory of a system (Algorithm 1 time loop body).
-rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_total) {
+// One time step of every system with trajectories.  The systems advance through the
+// self-consistency rounds together: each round launches every live system's series
+// start, waits once for all their stop flags, then launches every live system's
+// Hamiltonian update and waits once for all residuals, so the host round trips per
+// step do not grow with the number of molecules.
+struct StepState {
+  bool predicted = false;
+  int n_active = 0;
+  std::vector<int> m_of, terms_of, terms;
+  std::vector<double> res_of;
+};
+
+rt_status step_prologue(rt_ctx* c, SysDev& d, StepState& ss) {
   hipStream_t st = c->stream;
   const rt_run& run = c->run;
   const long NN = nsq(d.N);
@@ -1042,93 +1134,164 @@ rt_status step_system(rt_ctx* c, SysDev& d, rt_step_stats* stats, int n_traj_tot
     CK(rtk::lincomb3(st, d.H1, 3.0, d.H0, -3.0, d.Hm1, 1.0, d.Hm2, T * NN));
   else
     CK(rtk::lincomb(st, d.H1, 2.0, d.H0, -1.0, d.Hm1, T * NN));
-  bool predicted = false;
+  ss.predicted = false;
   if (d.mlp && d.x_valid) {
     bool any = false;
     for (int t = 0; t < T; ++t) any = any || d.mlp_on[t];
     if (any) {
       RET(predict_correction(c, d));
-      predicted = true;
+      ss.predicted = true;
     }
   }
   d.active_host.assign(T, 1);
   RET(push_active(c, d));
   CK(rtk::fill(st, d.tcur, 1, d.step * run.dt));  // t_j for the field terms of this step
-  std::vector<int> m_of(T, 0), terms_of(T, 0);
-  std::vector<double> res_of(T, 0.0);
+  ss.m_of.assign(T, 0);
+  ss.terms_of.assign(T, 0);
+  ss.res_of.assign(T, 0.0);
+  ss.n_active = T;
+  return RT_OK;
+}
+
+// Hamiltonian update and its residual: one captured sequence (the host loops over
+// trajectories in the full-apply mode, so the active pattern is part of the key)
+rt_status launch_update(rt_ctx* c, SysDev& d) {
+  const long NN = nsq(d.N);
+  const int T = d.T;
+  auto update = [&]() -> rt_status {
+    RET(eval_h(c, d, T, d.active, d.active_host, d.P1, 2 * NN, d.Hn, false));
+    {
+      Timed tm(c, PH_SMALL);
+      CK(rtk::max_diff_assign(c->stream, d.Hn, d.H1, NN, d.resid, T, d.active));
+    }
+    return enqueue_publish(c, d, d.resid, T * sizeof(unsigned long long));
+  };
+  std::vector<uintptr_t> key{2, (uintptr_t)T, (uintptr_t)d.P1, (uintptr_t)d.H1};
+  for (int t = 0; t < T; ++t) key.push_back((uintptr_t)d.active_host[t]);
+  return run_graph(c, d, key, update);
+}
+
+// after the wait for launch_update's publish: residuals, convergence, learned-guess fallback
+rt_status process_update(rt_ctx* c, SysDev& d, StepState& ss, int m) {
+  const rt_run& run = c->run;
+  const int T = d.T;
   std::vector<unsigned long long> bits(T);
-  int n_active = T;
-  for (int m = 1; m <= run.max_scf && n_active > 0; ++m) {
-    std::vector<int> terms;
-    RET(series(c, d, 0, T, d.active, d.active_host, d.Hbar, run.dt, d.P0, d.P1, terms, d.H0, d.H1, d.resid,
-               d.tcur));
-    // Hamiltonian update and its residual: one captured sequence (the host loops over
-    // trajectories in the full-apply mode, so the active pattern is part of the key)
-    auto update = [&]() -> rt_status {
-      RET(eval_h(c, d, T, d.active, d.active_host, d.P1, 2 * NN, d.Hn, false));
-      {
-        Timed tm(c, PH_SMALL);
-        CK(rtk::max_diff_assign(c->stream, d.Hn, d.H1, NN, d.resid, T, d.active));
-      }
-      return enqueue_publish(c, d.resid, T * sizeof(unsigned long long));
-    };
-    std::vector<uintptr_t> key{2, (uintptr_t)T, (uintptr_t)d.P1, (uintptr_t)d.H1};
-    for (int t = 0; t < T; ++t) key.push_back((uintptr_t)d.active_host[t]);
-    RET(run_graph(c, d, key, update));
-    RET(collect(c, T * sizeof(unsigned long long), bits.data()));
-    bool changed = false;
-    bool mask_changed = false;
-    for (int t = 0; t < T; ++t) {
-      if (!d.active_host[t]) continue;
-      double r;
-      std::memcpy(&r, &bits[t], sizeof(r));
-      if (m == 1 && d.mlp) {
-        if (predicted && d.mlp_on[t]) {
-          // fallback: the network's first residual against the median of linear first residuals
-          std::vector<double> v = d.r1_linear[t];
-          if (!v.empty()) {
-            std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
-            if (r > 10.0 * v[v.size() / 2]) { d.mlp_on[t] = 0; mask_changed = true; }
-          }
-        } else {
-          d.r1_linear[t].push_back(r);
+  slot_read(c, d, T * sizeof(unsigned long long), bits.data());
+  bool changed = false;
+  bool mask_changed = false;
+  for (int t = 0; t < T; ++t) {
+    if (!d.active_host[t]) continue;
+    double r;
+    std::memcpy(&r, &bits[t], sizeof(r));
+    if (m == 1 && d.mlp) {
+      if (ss.predicted && d.mlp_on[t]) {
+        // fallback: the network's first residual against the median of linear first residuals
+        std::vector<double> v = d.r1_linear[t];
+        if (!v.empty()) {
+          std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+          if (r > 10.0 * v[v.size() / 2]) { d.mlp_on[t] = 0; mask_changed = true; }
         }
-      }
-      m_of[t] = m;
-      terms_of[t] += terms[t];
-      res_of[t] = r;
-      if (r <= run.h_thrs) {
-        d.active_host[t] = 0;
-        --n_active;
-        changed = true;
+      } else {
+        d.r1_linear[t].push_back(r);
       }
     }
-    if (changed && n_active > 0) RET(push_active(c, d));
-    if (mask_changed)
-      RET(upload_flags(c, d.mlp_mask, d.mlp_on));
+    ss.m_of[t] = m;
+    ss.terms_of[t] += ss.terms[t];
+    ss.res_of[t] = r;
+    if (r <= run.h_thrs) {
+      d.active_host[t] = 0;
+      --ss.n_active;
+      changed = true;
+    }
   }
-  if (n_active > 0) return fail(c, RT_ENOCONV, "self-consistent Hamiltonian loop reached max_scf");
-  // H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 (all slots together)
+  if (changed && ss.n_active > 0) RET(push_active(c, d));
+  if (mask_changed) RET(upload_flags(c, d.mlp_mask, d.mlp_on));
+  return RT_OK;
+}
+
+rt_status step_epilogue(rt_ctx* c, SysDev& d, StepState& ss, rt_step_stats* stats) {
+  const int T = d.T;
+  // H_-2 <- H_-1, H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 (all slots together)
   double* old_m2 = d.Hm2;
   d.Hm2 = d.Hm1;
-  double* old_m1 = old_m2;
   d.Hm1 = d.H0;
   d.H0 = d.H1;
-  d.H1 = old_m1;
+  d.H1 = old_m2;
   std::swap(d.P0, d.P1);
   d.step += 1;
   if (stats) {
     for (int t = 0; t < T; ++t) {
       int g = d.slot_traj[t];
       if (g < 0) continue;
-      stats[g].scf_iters = m_of[t];
-      stats[g].series_terms = terms_of[t];
-      stats[g].residual = res_of[t];
+      stats[g].scf_iters = ss.m_of[t];
+      stats[g].series_terms = ss.terms_of[t];
+      stats[g].residual = ss.res_of[t];
     }
   }
-  (void)n_traj_total;
   RET(observe(c, d, d.step));
   RET(update_features(c, d));
+  return RT_OK;
+}
+
+rt_status step_all(rt_ctx* c, rt_step_stats* stats) {
+  const rt_run& run = c->run;
+  std::vector<SysDev*> sv;
+  for (auto& d : c->sys)
+    if (d.slot_traj[0] >= 0) sv.push_back(&d);  // systems without trajectories stay put
+  const int n = (int)sv.size();
+  // several systems run on their own streams, joined to the caller's stream at both ends
+  if (n > 1) {
+    CK(hipEventRecord(c->join, c->stream));
+    for (SysDev* d : sv) CK(hipStreamWaitEvent(d->sst, c->join, 0));
+  }
+  std::vector<StepState> ss(n);
+  for (int i = 0; i < n; ++i) {
+    OnStream on(c, stream_of(c, *sv[i]));
+    RET(step_prologue(c, *sv[i], ss[i]));
+  }
+  for (int m = 1; m <= run.max_scf; ++m) {
+    std::vector<int> live;
+    std::vector<SysDev*> lv;
+    for (int i = 0; i < n; ++i)
+      if (ss[i].n_active > 0) {
+        live.push_back(i);
+        lv.push_back(sv[i]);
+      }
+    if (live.empty()) break;
+    std::vector<std::unique_ptr<Series>> sr(n);
+    for (int i : live) {
+      SysDev& d = *sv[i];
+      OnStream on(c, stream_of(c, d));
+      sr[i].reset(new Series(c, d, 0, d.T, d.active, d.Hbar, run.dt, d.P0, d.P1, d.H0, d.H1, d.resid, d.tcur));
+      RET(sr[i]->start());
+    }
+    RET(wait_slots(c, lv));
+    for (int i : live) {
+      OnStream on(c, stream_of(c, *sv[i]));
+      RET(sr[i]->complete(sv[i]->active_host, ss[i].terms));
+    }
+    for (int i : live) {
+      OnStream on(c, stream_of(c, *sv[i]));
+      RET(launch_update(c, *sv[i]));
+    }
+    RET(wait_slots(c, lv));
+    for (int i : live) {
+      OnStream on(c, stream_of(c, *sv[i]));
+      RET(process_update(c, *sv[i], ss[i], m));
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (ss[i].n_active > 0) return fail(c, RT_ENOCONV, "self-consistent Hamiltonian loop reached max_scf");
+  for (int i = 0; i < n; ++i) {
+    OnStream on(c, stream_of(c, *sv[i]));
+    RET(step_epilogue(c, *sv[i], ss[i], stats));
+  }
+  if (n > 1) {
+    for (SysDev* d : sv) {
+      CK(hipEventRecord(d->ev, d->sst));
+      CK(hipStreamWaitEvent(c->stream, d->ev, 0));
+    }
+  }
   return RT_OK;
 }
 
@@ -1180,9 +1343,12 @@ rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* work
   Arena b;
   b.base = reinterpret_cast<char*>(((uintptr_t)workspace_dev + 255) & ~uintptr_t(255));
   layout(b, c->sys, *run, c->hist_cap);
-  int max_t = 1;
-  for (const SysDev& d : c->sys) max_t = std::max(max_t, d.T);
-  c->box_bytes = (64 + 16 * (size_t)max_t + 4095) / 4096 * 4096;
+  size_t words = 0;
+  for (SysDev& d : c->sys) {
+    d.box_off = (int)words;  // even: the 8-byte sequence word stays aligned
+    words += 2 * (size_t)d.T + 4;
+  }
+  c->box_bytes = (64 + 4 * words + 4095) / 4096 * 4096;
   void* box = nullptr;
   if (hipHostMalloc(&box, c->box_bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void**)&c->box_dev, box, 0) != hipSuccess) {
@@ -1193,11 +1359,28 @@ rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* work
   }
   c->box_host = static_cast<unsigned*>(box);
   std::memset(c->box_host, 0, c->box_bytes);
-  c->box_ctr = c->sys[0].box_ctr;
-  if (rtk::fill_u64(c->stream, c->box_ctr, 1, 0ull) != hipSuccess) {
-    g_init_error = "rt_init: mailbox counter";
-    delete c;
-    return RT_EDEVICE;
+  for (SysDev& d : c->sys)
+    if (rtk::fill_u64(c->stream, d.box_ctr, 1, 0ull) != hipSuccess) {
+      g_init_error = "rt_init: mailbox counter";
+      delete c;
+      return RT_EDEVICE;
+    }
+  {
+    int n_stepped = 0;
+    for (SysDev& d : c->sys) n_stepped += d.slot_traj[0] >= 0;
+    if (n_stepped > 1) {
+      bool ok = hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;
+      for (SysDev& d : c->sys) {
+        if (d.slot_traj[0] < 0) continue;
+        ok = ok && hipStreamCreateWithFlags(&d.sst, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&d.ev, hipEventDisableTiming) == hipSuccess;
+      }
+      if (!ok) {
+        g_init_error = "rt_init: system streams";
+        delete c;
+        return RT_EDEVICE;
+      }
+    }
   }
   if (run->graph_capture && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
     c->cap = nullptr;
@@ -1246,12 +1429,7 @@ rt_status rt_step(rt_ctx* c, int n_steps, rt_step_stats* stats) {
   for (auto& d : c->sys)
     if (d.step + n_steps > c->hist_cap) return fail(c, RT_ESTATE, "history capacity n_steps_max exhausted");
   const int nt = (int)c->traj.size();
-  for (int k = 0; k < n_steps; ++k) {
-    for (auto& d : c->sys) {
-      if (d.slot_traj[0] < 0) continue;  // system without trajectories
-      RET(step_system(c, d, stats ? stats + (long)k * nt : nullptr, nt));
-    }
-  }
+  for (int k = 0; k < n_steps; ++k) RET(step_all(c, stats ? stats + (long)k * nt : nullptr));
   if (c->prof) {
     CK(hipStreamSynchronize(c->stream));
     prof_collect(c);
