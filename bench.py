@@ -207,6 +207,54 @@ def roofline_of(prof, N, ng, mixed, full):
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes}
 
 
+def batched_molecules(rt, torch, steps, warmup):
+    """Ragged batch: 16 synthetic molecules (grids 32^3..64^3, 10..60 orbitals) x the
+    three kicks, mixed precision, stepped in one context (each molecule on its own
+    stream, all advancing through the self-consistency rounds together), against the
+    same 16 molecules in 16 contexts stepped one after another."""
+    import synth
+
+    mols = synth.batch_systems()
+    psis = [synth.lowpass_orbitals(m.n, m.h, m.n_orb, seed=m.seed) for m in mols]
+
+    def sa(m, p):
+        return rt.SystemArgs(n=m.n, h=m.h, pos=m.pos, depth=m.depth, width=m.width, n_occ=m.n_occ,
+                             n_virt=m.n_virt, psi0=p, nl_rank=m.nl_rank, nl_rcut=m.nl_rcut, nl_sigma=m.nl_sigma,
+                             nl_D=m.nl_D, n_images=m.n_images, orthonormalize=True)
+
+    def ra(n_mol):
+        return rt.RunArgs(dt=0.05, n_steps_max=steps + warmup, h_thrs=1e-7, dp_thrs=1e-10, max_scf=50,
+                          max_terms=200, traj_sys=[i for i in range(n_mol) for _ in AXES],
+                          traj_kappa=[1e-3] * (len(AXES) * n_mol), traj_axis=list(AXES) * n_mol,
+                          precision=rt.RT_MIXED, hupdate=rt.RT_HUPDATE_LOCAL)
+
+    nm, nt = len(mols), len(AXES) * len(mols)
+    ses = rt.Session([sa(m, p) for m, p in zip(mols, psis)], ra(nm))
+    rt.rt_step(ses.ctx, warmup, n_traj=nt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rt.rt_step(ses.ctx, steps, n_traj=nt)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    ses.close()
+    sess = [rt.Session([sa(m, p)], ra(1)) for m, p in zip(mols, psis)]
+    for x in sess:
+        rt.rt_step(x.ctx, warmup, n_traj=len(AXES))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for x in sess:
+            rt.rt_step(x.ctx, 1, n_traj=len(AXES))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for x in sess:
+        x.close()
+    return {"workload": "16 molecules (grid edges " + ",".join(str(m.n[0]) for m in mols) + "; orbitals "
+                        + ",".join(str(m.n_orb) for m in mols) + ") x 3 kicks, mixed, dt 0.05, H_thrs 1e-7",
+            "steps_per_s": steps / t_one, "trajectory_steps_per_s": nt * steps / t_one,
+            "sequential_contexts_steps_per_s": steps / t_seq, "speedup_vs_sequential_contexts": t_seq / t_one}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +265,7 @@ def main():
                     help="self-consistency thresholds of the equal-dipole-error sweep (must include --h-thrs)")
     ap.add_argument("--dp-thrs", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 16-molecule batch leg")
     args = ap.parse_args()
     if args.h_thrs not in args.sweep:
         args.sweep = sorted(set(args.sweep) | {args.h_thrs}, reverse=True)
@@ -373,6 +422,9 @@ def main():
         "fp64_tight_reference_steps_per_s": args.steps / ref["elapsed"],
         "apply_h_standalone": rates,
     }
+    if not args.no_batch:
+        log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")
+        out["batched_16_molecules"] = batched_molecules(rt, torch, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(s, psi.reshape(N, -1), sm_plain["mean_scf_updates_per_step"], 0.05,
