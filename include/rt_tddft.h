@@ -313,6 +313,87 @@ rt_status rt_mlp_colstats(void* hip_stream, const float* x_dev, int rows, int co
 rt_status rt_record(rt_ctx* ctx, float* x_dev, float* y_dev, int capacity);
 rt_status rt_record_count(rt_ctx* ctx, int* rows);
 
+/*
+ * Ground state on the GPU.  Algorithm 1 starts from the ground-state orbitals
+ * and Hamiltonian of the system; this call computes them for a system described
+ * as for rt_init: the self-consistent Kohn-Sham problem
+ *   H[rho] psi_i = eps_i psi_i,  rho = sum_i f_i psi_i^2,
+ * H[rho] = T + V_ion + V_nl + V_H[rho] + v_x[rho] (the operator of rt_apply_h;
+ * spectral Hartree, LDA exchange), f_i as for rt_init (2 for the first n_occ).
+ *
+ * Method: Chebyshev-filtered subspace iteration (Zhou, Saad, Tiago and
+ * Chelikowsky, J. Comput. Phys. 219, 172 (2006)) on a block of
+ * nb = N + n_guard vectors, N = n_occ + n_virt.  A pass applies the scaled
+ * degree-`degree` Chebyshev polynomial of H that damps [largest Ritz value,
+ * upper bound of the spectrum], orthonormalises the block (Cholesky QR, twice)
+ * and rotates it to the Ritz vectors of H on the block (Jacobi eigensolver of
+ * rt_eigh).  The spectral bound is rigorous: kinetic symbol at the zone corner
+ * + max|V_loc| + a block Gershgorin bound of V_nl.  Density loop: V_loc[rho_in]
+ * -> filter passes until the wanted residuals are below
+ * max(tol_res, min(1e-3, 0.01 err)) (at most max_passes) -> rho_out;
+ * err = max|rho_out - rho_in|; stop when err < tol_rho, else Pulay (DIIS)
+ * mixing of the last pulay_depth densities with residual weight mix.  The
+ * final orbitals are the lowest N eigenvectors of H[rho_in] at the converged
+ * rho_in, refined until max_i ||(H - eps_i) psi_i|| <= tol_res (norm
+ * (h^3 sum |.|^2)^(1/2)), each signed so that its entry of largest modulus
+ * (first one on ties) is positive.
+ *
+ * sys: as for rt_init except that psi0 holds nb = N + n_guard linearly
+ *   independent start vectors [nb][nz][ny][nx] (host, or device with
+ *   psi0_on_device), orthonormalize and nonorthogonal must be 0.
+ * psi_out_dev: device [N][nz][ny][nx], h^3-orthonormal orbitals (caller-owned);
+ *   pass it to rt_init as psi0 with psi0_on_device = 1.
+ * eps_out_host: [nb] Ritz values in ascending order (nullable).
+ * rho_out_dev: device [nz][ny][nx] density of the returned orbitals (nullable).
+ * workspace_dev: at least rt_ground_state_workspace_size bytes, caller-owned;
+ *   the call allocates no device memory.  All work is on hip_stream and the
+ *   call synchronises it (the loop reads its convergence measures).
+ * Errors: RT_EINVAL for arguments outside the ranges below (no side effects),
+ *   RT_ENOMEM for a short workspace, RT_ENOCONV when max_scf or max_passes is
+ *   exhausted or the block loses rank; rt_last_error(NULL) names the cause.
+ */
+typedef struct {
+  int n_guard;        /* extra block vectors (>= 2; N + n_guard <= 1024)        */
+  int degree;         /* Chebyshev filter degree (1..64)                         */
+  int max_scf;        /* cap on density iterations (>= 1)                        */
+  int max_passes;     /* cap on filter passes per potential (>= 1)               */
+  double tol_rho;     /* max|rho_out - rho_in| that ends the density loop        */
+  double tol_res;     /* final max_i ||(H - eps_i) psi_i||, i < N                */
+  double mix;         /* Pulay residual weight, 0 < mix <= 1                      */
+  int pulay_depth;    /* stored iterations, 1..8                                 */
+} rt_gs_params;
+
+typedef struct {
+  int32_t scf_iters;      /* density iterations                                  */
+  int32_t filter_passes;  /* filter + Rayleigh-Ritz passes                        */
+  int64_t h_applies;      /* applications of H to the whole block                */
+  int64_t eigensolves;    /* Rayleigh-Ritz eigensolves                            */
+  int64_t jacobi_sweeps;  /* Jacobi sweeps summed over them                       */
+  double rho_err;         /* max|rho(psi_out) - rho_in| at the end               */
+  double residual;        /* max_i ||(H - eps_i) psi_i||, i < N                  */
+} rt_gs_stats;
+
+rt_status rt_ground_state_workspace_size(const rt_system* sys, const rt_gs_params* params, size_t* bytes);
+rt_status rt_ground_state(const rt_system* sys, const rt_gs_params* params, void* workspace_dev,
+                          size_t ws_bytes, void* hip_stream, double* psi_out_dev, double* eps_out_host,
+                          double* rho_out_dev, rt_gs_stats* stats);
+
+/*
+ * Dense symmetric eigensolver (the Rayleigh-Ritz step above): the symmetric
+ * part (A + A^T)/2 of a_dev [n][n] (device, row-major, 1 <= n <= 4096) is
+ * diagonalised by parallel cyclic Jacobi sweeps (round-robin pair ordering;
+ * Golub & Van Loan, Matrix Computations, Sec. 8.5) until the off-diagonal
+ * Frobenius norm is below 1e-15 of the matrix norm (or stops shrinking below
+ * 1e-13 of it).  evals_dev [n]: eigenvalues in ascending order (ties by
+ * index); vecs_dev [n][n]: row k is the unit eigenvector of evals[k]; vecs_dev
+ * may alias a_dev.  workspace_dev: rt_eigh_workspace_size bytes.  Synchronises
+ * hip_stream.  sweeps_out: sweeps taken (nullable).  RT_EINVAL for bad
+ * arguments or non-finite entries, RT_ENOCONV after 60 sweeps.
+ */
+rt_status rt_eigh_workspace_size(int n, size_t* bytes);
+rt_status rt_eigh(void* hip_stream, int n, const double* a_dev, double* evals_dev, double* vecs_dev,
+                  void* workspace_dev, size_t ws_bytes, int* sweeps_out);
+
 /* Releases host-side state; the caller then frees the workspace. */
 void rt_free(rt_ctx* ctx);
 

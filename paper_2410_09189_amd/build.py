@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt_tddft.so")
-SOURCES = ["kernels.hip", "kernels_mixed.hip", "kernels_mlp.hip", "rt_api.hip"]
+SOURCES = ["kernels.hip", "kernels_gs.hip", "kernels_mixed.hip", "kernels_mlp.hip", "rt_api.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of the generated code

@@ -3,6 +3,7 @@
 // and the self-consistent time loop of Algorithm 1 driving the kernels.
 #include "../../include/rt_tddft.h"
 #include "kernels.h"
+#include "kernels_gs.h"
 #include "kernels_mixed.h"
 #include "kernels_mlp.h"
 
@@ -408,29 +409,35 @@ void prof_collect(rt_ctx* c) {
   c->pending.clear();
 }
 
+// Grid, atoms, projectors and active space of one system.
+rt_status validate_system(const rt_system& s, std::string& why) {
+  for (int q = 0; q < 3; ++q)
+    if (s.n[q] < 8 || s.n[q] > 256) { why = "grid edge outside [8, 256]"; return RT_EINVAL; }
+  for (int q = 0; q < 3; ++q) {
+    int m = s.n[q];
+    for (int f : {2, 3, 5})
+      while (m % f == 0) m /= f;
+    if (m != 1) { why = "grid edges must have no prime factor above 5 (FFT Poisson)"; return RT_EINVAL; }
+  }
+  if (!(s.h > 0)) { why = "h must be positive"; return RT_EINVAL; }
+  if (s.n_atoms < 0 || (s.n_atoms > 0 && (!s.pos || !s.depth || !s.width))) { why = "atom arrays"; return RT_EINVAL; }
+  if (s.n_images < 0 || s.n_images > 3) { why = "n_images outside [0, 3]"; return RT_EINVAL; }
+  if (s.nl_rank != 0 && s.nl_rank != 4) { why = "nl_rank must be 0 or 4"; return RT_EINVAL; }
+  if (s.nl_rank && (!s.nl_D || !(s.nl_rcut > 0) || !(s.nl_sigma > 0))) { why = "nonlocal parameters"; return RT_EINVAL; }
+  if (s.nl_rank) {
+    for (int q = 0; q < 3; ++q)
+      if (2.0 * s.nl_rcut / s.h + 3 >= s.n[q]) { why = "projector sphere wider than the cell"; return RT_EINVAL; }
+  }
+  if (s.n_occ < 0 || s.n_virt < 0 || s.n_occ + s.n_virt < 1) { why = "active space"; return RT_EINVAL; }
+  if (!s.psi0) { why = "psi0 is NULL"; return RT_EINVAL; }
+  return RT_OK;
+}
+
 rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::string& why) {
   if (!sys || n_sys < 1 || !run) { why = "null system/run or n_sys < 1"; return RT_EINVAL; }
   for (int i = 0; i < n_sys; ++i) {
     const rt_system& s = sys[i];
-    for (int q = 0; q < 3; ++q)
-      if (s.n[q] < 8 || s.n[q] > 256) { why = "grid edge outside [8, 256]"; return RT_EINVAL; }
-    for (int q = 0; q < 3; ++q) {
-      int m = s.n[q];
-      for (int f : {2, 3, 5})
-        while (m % f == 0) m /= f;
-      if (m != 1) { why = "grid edges must have no prime factor above 5 (FFT Poisson)"; return RT_EINVAL; }
-    }
-    if (!(s.h > 0)) { why = "h must be positive"; return RT_EINVAL; }
-    if (s.n_atoms < 0 || (s.n_atoms > 0 && (!s.pos || !s.depth || !s.width))) { why = "atom arrays"; return RT_EINVAL; }
-    if (s.n_images < 0 || s.n_images > 3) { why = "n_images outside [0, 3]"; return RT_EINVAL; }
-    if (s.nl_rank != 0 && s.nl_rank != 4) { why = "nl_rank must be 0 or 4"; return RT_EINVAL; }
-    if (s.nl_rank && (!s.nl_D || !(s.nl_rcut > 0) || !(s.nl_sigma > 0))) { why = "nonlocal parameters"; return RT_EINVAL; }
-    if (s.nl_rank) {
-      for (int q = 0; q < 3; ++q)
-        if (2.0 * s.nl_rcut / s.h + 3 >= s.n[q]) { why = "projector sphere wider than the cell"; return RT_EINVAL; }
-    }
-    if (s.n_occ < 0 || s.n_virt < 0 || s.n_occ + s.n_virt < 1) { why = "active space"; return RT_EINVAL; }
-    if (!s.psi0) { why = "psi0 is NULL"; return RT_EINVAL; }
+    RET(validate_system(s, why));
     if (s.nonorthogonal && s.orthonormalize) { why = "nonorthogonal and orthonormalize exclude each other"; return RT_EINVAL; }
     if (s.nonorthogonal && run->magnus_order == 4) { why = "magnus_order 4 needs an orthonormal basis"; return RT_EINVAL; }
     if (s.nonorthogonal && run->predictor == RT_PRED_MLP) { why = "the learned predictor needs an orthonormal basis"; return RT_EINVAL; }
@@ -1295,6 +1302,440 @@ rt_status step_all(rt_ctx* c, rt_step_stats* stats) {
   return RT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Dense symmetric eigensolver (Rayleigh-Ritz step of the ground-state solve,
+// also exported as rt_eigh): parallel cyclic Jacobi sweeps until the
+// off-diagonal Frobenius norm is below 1e-15 of the matrix norm.
+// ---------------------------------------------------------------------------
+struct EighWork {
+  int n = 0, ld = 0;
+  double *A = nullptr, *A2 = nullptr, *V = nullptr, *off = nullptr;
+  int* rank = nullptr;
+};
+
+void eigh_layout(Arena& a, EighWork& w, int n) {
+  w.n = n;
+  w.ld = n + (n & 1);
+  const long LL = (long)w.ld * w.ld;
+  w.A = a.take<double>(LL);
+  w.A2 = a.take<double>(LL);
+  w.V = a.take<double>(LL);
+  w.off = a.take<double>(2);
+  w.rank = a.take<int>(w.ld);
+}
+
+constexpr int kMaxSweeps = 60;
+
+// evals[k] ascending, vecs row k its eigenvector; *sweeps the sweeps taken.
+rt_status eigh_run(rt_ctx* c, EighWork& w, const double* A, double* evals, double* vecs, int* sweeps) {
+  hipStream_t st = c->stream;
+  CK(rtk::jacobi_setup(st, A, w.n, w.ld, w.A, w.V));
+  double* a = w.A;
+  double* b = w.A2;
+  double off[2] = {0.0, 0.0};
+  CK(rtk::jacobi_offdiag(st, a, w.ld, w.off));
+  CK(hipMemcpyAsync(off, w.off, sizeof(off), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  const double total = off[0] + off[1];  // Frobenius norm^2, invariant under the rotations
+  if (!std::isfinite(total)) return fail(c, RT_EINVAL, "eigensolver: matrix has non-finite entries");
+  int sw = 0;
+  double prev = off[0];
+  while (off[0] > 1e-30 * total) {
+    if (sw == kMaxSweeps) return fail(c, RT_ENOCONV, "eigensolver: Jacobi sweeps did not converge");
+    for (int r = 0; r < w.ld - 1; ++r) {
+      CK(rtk::jacobi_round(st, a, b, w.V, w.ld, r));
+      std::swap(a, b);
+    }
+    ++sw;
+    CK(rtk::jacobi_offdiag(st, a, w.ld, w.off));
+    CK(hipMemcpyAsync(off, w.off, sizeof(off), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (!std::isfinite(off[0])) return fail(c, RT_ENOCONV, "eigensolver: non-finite iterate");
+    // rounding floor: no longer shrinking once at the level of a few ulps
+    if (off[0] <= 1e-26 * total && off[0] > 0.25 * prev) break;
+    prev = off[0];
+  }
+  CK(rtk::jacobi_sort(st, a, w.V, w.n, w.ld, evals, vecs, w.rank));
+  if (sweeps) *sweeps = sw;
+  return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Ground state: Chebyshev-filtered subspace iteration (Zhou, Saad, Tiago and
+// Chelikowsky, J. Comput. Phys. 219, 172 (2006)) inside a Pulay-mixed density
+// loop.  The system's grid operator is the one of the time step (stencil,
+// V_loc, projectors); the orbital block holds nb = N + n_guard vectors.
+// ---------------------------------------------------------------------------
+struct GsDev {
+  double* blk[3] = {nullptr, nullptr, nullptr};  // orbital blocks [nb][ng]
+  double *Hs = nullptr, *vecs = nullptr, *evals = nullptr, *res = nullptr, *occ = nullptr;
+  double *rho_out = nullptr, *hin = nullptr, *hres = nullptr, *Bp = nullptr, *coef = nullptr, *dpart = nullptr;
+  unsigned long long* slot = nullptr;
+  EighWork eig;
+  int depth = 1;
+};
+
+void layout_gs(Arena& a, SysDev& d, GsDev& g) {
+  const long ng = d.ng, nb = d.N, NN = nb * nb;
+  for (auto& p : g.blk) p = a.take<double>(nb * ng);
+  d.vion = a.take<double>(ng);
+  d.z = a.take<double2>(ng);
+  d.twx = a.take<double2>(d.nx);
+  d.twy = a.take<double2>(d.ny);
+  d.twz = a.take<double2>(d.nz);
+  d.pos = a.take<double>(3 * std::max(1, d.n_atoms));
+  d.depth = a.take<double>(std::max(1, d.n_atoms));
+  d.width = a.take<double>(std::max(1, d.n_atoms));
+  d.atom_off = a.take<int>(d.nl.atom_off.size() + 1);
+  d.sph_idx = a.take<int>(d.nl.sph_idx.size() + 1);
+  d.beta = a.take<double>(d.nl.beta.size() + 1);
+  d.Dd = a.take<double>(d.nl.D.size() + 1);
+  d.u_idx = a.take<int>(d.nl.u_idx.size() + 1);
+  d.u_ptr = a.take<int>(d.nl.u_ptr.size() + 1);
+  d.ent_pt = a.take<int>(d.nl.ent_pt.size() + 1);
+  d.ent_atom = a.take<int>(d.nl.ent_atom.size() + 1);
+  d.cnl = a.take<double>(nb * std::max(1, d.nl.n_proj));
+  d.tmp = a.take<double>(NN);
+  d.tmp2 = a.take<double>(NN);
+  d.info = a.take<int>(4);
+  d.red2 = a.take<double>(2 * rtk::kRedBlocks);
+  d.escale = a.take<double>(2);
+  d.eparts = a.take<double>(2);
+  d.rho = a.take<double>(ng);
+  d.vh = a.take<double>(ng);
+  d.vx = a.take<double>(ng);
+  d.vloc = a.take<double>(ng);
+  d.part = a.take<double>(d.n_split * NN);
+  g.Hs = a.take<double>(NN);
+  g.vecs = a.take<double>(NN);
+  g.evals = a.take<double>(nb);
+  g.res = a.take<double>(nb);
+  g.occ = a.take<double>(nb);
+  g.rho_out = a.take<double>(ng);
+  g.hin = a.take<double>(g.depth * ng);
+  g.hres = a.take<double>(g.depth * ng);
+  g.Bp = a.take<double>(64);
+  g.coef = a.take<double>(8);
+  g.dpart = a.take<double>(8 * 256);
+  g.slot = a.take<unsigned long long>(1);
+  eigh_layout(a, g.eig, (int)nb);
+}
+
+rt_status validate_gs(const rt_system* s, const rt_gs_params* p, std::string& why) {
+  if (!s || !p) { why = "null system or parameters"; return RT_EINVAL; }
+  RET(validate_system(*s, why));
+  if (s->nonorthogonal || s->orthonormalize) { why = "the ground state takes neither nonorthogonal nor orthonormalize"; return RT_EINVAL; }
+  const int N = s->n_occ + s->n_virt;
+  if (p->n_guard < 2 || N + p->n_guard > 1024) { why = "n_guard >= 2 and N + n_guard <= 1024"; return RT_EINVAL; }
+  if (p->degree < 1 || p->degree > 64) { why = "degree outside [1, 64]"; return RT_EINVAL; }
+  if (p->max_scf < 1 || p->max_passes < 1) { why = "max_scf and max_passes must be >= 1"; return RT_EINVAL; }
+  if (!(p->tol_rho > 0) || !(p->tol_res > 0)) { why = "tolerances must be positive"; return RT_EINVAL; }
+  if (!(p->mix > 0 && p->mix <= 1)) { why = "mix outside (0, 1]"; return RT_EINVAL; }
+  if (p->pulay_depth < 1 || p->pulay_depth > 8) { why = "pulay_depth outside [1, 8]"; return RT_EINVAL; }
+  if (s->occ)
+    for (int i = 0; i < N; ++i)
+      if (!std::isfinite(s->occ[i])) { why = "occupations must be finite"; return RT_EINVAL; }
+  return RT_OK;
+}
+
+void describe_gs(const rt_system* s, const rt_gs_params* p, SysDev& d, GsDev& g) {
+  rt_run r{};
+  r.precision = RT_FP64;
+  std::vector<SysDev> S;
+  std::vector<TrajDev> T;
+  describe(s, 1, &r, S, T);
+  d = std::move(S[0]);
+  d.N = s->n_occ + s->n_virt + p->n_guard;  // block size: wanted pairs + guard vectors
+  choose_split(d);
+  g.depth = p->pulay_depth;
+}
+
+// Upper bound of the spectrum of H = T + V_loc + V_nl: the FD kinetic symbol is
+// largest at the zone corner, |T| <= (1/2) h^-2 3 (|a_0| + 2 sum_k |a_k|) (the
+// alternating signs of the coefficients make this exact); V_loc <= max|V_loc|;
+// ||V_nl|| <= max_a sum_b sqrt(d_a g_a d_b g_b) over atoms b whose spheres share a
+// grid point with a's (d: largest |D| of an atom, g: Gershgorin bound of its
+// projector Gram matrix h^3 beta^T beta), a block Gershgorin bound.
+double kinetic_max(const SysDev& d) {
+  double s = std::fabs(d.coef[0]);
+  for (int k = 1; k <= 4; ++k) s += 2.0 * std::fabs(d.coef[k]);
+  return 0.5 * 3.0 * s / (d.h * d.h);
+}
+
+double nonlocal_bound(const SysDev& d) {
+  const NlTables& t = d.nl;
+  if (!t.rank || !t.n_atoms) return 0.0;
+  const int na = t.n_atoms, R = t.rank;
+  std::vector<double> dg(na, 0.0);
+  for (int a = 0; a < na; ++a) {
+    double dm = 0.0, gm = 0.0;
+    for (int p = 0; p < R; ++p) dm = std::max(dm, std::fabs(t.D[a * R + p]));
+    std::vector<double> G(R * R, 0.0);
+    for (int e = t.atom_off[a]; e < t.atom_off[a + 1]; ++e)
+      for (int p = 0; p < R; ++p)
+        for (int q = 0; q < R; ++q) G[p * R + q] += t.beta[(long)e * R + p] * t.beta[(long)e * R + q];
+    for (int p = 0; p < R; ++p) {
+      double row = 0.0;
+      for (int q = 0; q < R; ++q) row += std::fabs(G[p * R + q]) * d.h3;
+      gm = std::max(gm, row);
+    }
+    dg[a] = dm * gm;
+  }
+  std::vector<char> adj((size_t)na * na, 0);
+  for (int a = 0; a < na; ++a) adj[(size_t)a * na + a] = 1;
+  for (size_t u = 0; u + 1 < t.u_ptr.size(); ++u)
+    for (int e = t.u_ptr[u]; e < t.u_ptr[u + 1]; ++e)
+      for (int f = t.u_ptr[u]; f < t.u_ptr[u + 1]; ++f)
+        adj[(size_t)t.ent_atom[e] * na + t.ent_atom[f]] = 1;
+  double nu = 0.0;
+  for (int a = 0; a < na; ++a) {
+    double row = 0.0;
+    for (int b = 0; b < na; ++b)
+      if (adj[(size_t)a * na + b]) row += std::sqrt(dg[a] * dg[b]);
+    nu = std::max(nu, row);
+  }
+  return nu;
+}
+
+struct GsRun {
+  rt_ctx* c;
+  SysDev& d;
+  GsDev& g;
+  int N;
+  int cur = 0;                       // block holding the current Ritz vectors
+  double a0 = 0, acut = 0, bup = 0;  // filter: damped interval [acut, bup], scale point a0
+  double static_bound = 0;           // kinetic + nonlocal part of bup
+  std::vector<double> ev, res;
+  long applies = 0;
+  int passes = 0, eighs = 0;
+  long sweeps = 0;
+  GsRun(rt_ctx* c_, SysDev& d_, GsDev& g_, int N_) : c(c_), d(d_), g(g_), N(N_) {}
+
+  rt_status apply(const double* x, double* y) {
+    ++applies;
+    return apply_h64(c, d, x, y, d.vloc, d.N);
+  }
+
+  // bup from the current V_loc
+  rt_status bound() {
+    hipStream_t st = c->stream;
+    CK(rtk::fill_u64(st, g.slot, 1, 0ull));
+    CK(rtk::abs_max(st, d.vloc, d.ng, g.slot));
+    unsigned long long bits = 0;
+    CK(hipMemcpyAsync(&bits, g.slot, 8, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    double vmax;
+    std::memcpy(&vmax, &bits, 8);
+    bup = static_bound + vmax;
+    bup += 1e-12 * std::fabs(bup);
+    return RT_OK;
+  }
+
+  // block i <- its h^3-orthonormal basis by Cholesky QR, twice (j: scratch block)
+  rt_status orth(int i, int j) {
+    hipStream_t st = c->stream;
+    const int nb = d.N;
+    for (int pass = 0; pass < 2; ++pass) {
+      double* src = g.blk[pass ? j : i];
+      double* dst = g.blk[pass ? i : j];
+      RET(project(c, d, src, src, nullptr, d.tmp));
+      CK(rtk::cholesky(st, d.tmp, nb, d.info + pass));
+      CK(rtk::tri_inverse_lower(st, d.tmp, d.tmp2, nb));
+      CK(rtk::smalltall_f64(st, nb, d.ng, d.tmp2, src, dst, 0, 2, 1, nullptr));
+    }
+    int info[2] = {0, 0};
+    CK(hipMemcpyAsync(info, d.info, sizeof(info), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (info[0] || info[1]) return fail(c, RT_ENOCONV, "ground state: the orbital block lost rank");
+    return RT_OK;
+  }
+
+  // Rayleigh-Ritz on the orthonormal block i: Ritz vectors and values, residual norms
+  rt_status ritz(int i) {
+    hipStream_t st = c->stream;
+    const int nb = d.N, j = (i + 1) % 3, k = (i + 2) % 3;
+    RET(apply(g.blk[i], g.blk[k]));
+    RET(project(c, d, g.blk[i], g.blk[k], nullptr, g.Hs));
+    int sw = 0;
+    RET(eigh_run(c, g.eig, g.Hs, g.evals, g.vecs, &sw));
+    sweeps += sw;
+    ++eighs;
+    CK(rtk::smalltall_f64(st, nb, d.ng, g.vecs, g.blk[i], g.blk[j], 0, 0, 1, nullptr));  // X
+    CK(rtk::smalltall_f64(st, nb, d.ng, g.vecs, g.blk[k], g.blk[i], 0, 0, 1, nullptr));  // H X
+    CK(rtk::row_residuals(st, g.blk[i], g.blk[j], g.evals, nb, d.ng, d.h3, g.res));
+    ev.resize(nb);
+    res.resize(nb);
+    CK(hipMemcpyAsync(ev.data(), g.evals, nb * 8, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(res.data(), g.res, nb * 8, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    for (int q = 0; q < nb; ++q)
+      if (!std::isfinite(ev[q]) || !std::isfinite(res[q])) return fail(c, RT_ENOCONV, "ground state: non-finite Ritz pairs");
+    cur = j;
+    a0 = ev[0];
+    acut = ev[nb - 1];
+    return RT_OK;
+  }
+
+  // Scaled Chebyshev filter of degree m on block cur (the damped interval
+  // [acut, bup] maps to [-1, 1], the scale point a0 to -1/sigma_1); returns the
+  // block that holds the filtered vectors.
+  rt_status filter(int m, int& out) {
+    if (!(bup > acut)) return fail(c, RT_ENOCONV, "ground state: Ritz value above the spectral bound");
+    const long n = (long)d.N * d.ng;
+    const double e = 0.5 * (bup - acut), cc = 0.5 * (bup + acut);
+    double lo = a0;
+    if (!(lo < acut - 1e-12 * e)) lo = acut - 0.05 * e;
+    double sigma = e / (lo - cc);
+    const double tau = 2.0 / sigma;
+    int x = cur, y = (cur + 1) % 3, z = (cur + 2) % 3;
+    RET(apply(g.blk[x], g.blk[z]));
+    CK(rtk::lincomb(c->stream, g.blk[y], sigma / e, g.blk[z], -sigma * cc / e, g.blk[x], n));
+    for (int k = 2; k <= m; ++k) {
+      const double sn = 1.0 / (tau - sigma);
+      RET(apply(g.blk[y], g.blk[z]));
+      CK(rtk::lincomb3(c->stream, g.blk[x], 2.0 * sn / e, g.blk[z], -2.0 * sn * cc / e, g.blk[y], -sigma * sn,
+                       g.blk[x], n));
+      std::swap(x, y);
+      sigma = sn;
+    }
+    out = y;
+    return RT_OK;
+  }
+
+  rt_status pass(int m) {
+    int f = 0;
+    RET(filter(m, f));
+    RET(orth(f, (f + 1) % 3));
+    RET(ritz(f));
+    ++passes;
+    return RT_OK;
+  }
+
+  double wanted_res() const {
+    double r = 0.0;
+    for (int q = 0; q < N; ++q) r = std::max(r, res[q]);
+    return r;
+  }
+
+  // filter passes at fixed V_loc until the wanted residuals are below tol
+  rt_status solve(int m, double tol, int max_passes) {
+    for (int p = 0; p < max_passes; ++p) {
+      RET(pass(m));
+      if (wanted_res() <= tol) return RT_OK;
+    }
+    return RT_OK;
+  }
+
+  double read_slot() {
+    unsigned long long bits = 0;
+    if (hipMemcpyAsync(&bits, g.slot, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return NAN;
+    double v;
+    std::memcpy(&v, &bits, 8);
+    return v;
+  }
+};
+
+rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs_params& p, double* psi_out,
+                 double* eps_out, double* rho_out, rt_gs_stats* stats) {
+  hipStream_t st = c->stream;
+  const int N = s.n_occ + s.n_virt, nb = d.N;
+  const long ng = d.ng;
+  // static fields and tables
+  double esc[2] = {d.h3, 0.5 * d.h3};
+  CK(hipMemcpyAsync(d.escale, esc, sizeof(esc), hipMemcpyHostToDevice, st));
+  if (d.n_atoms) {
+    CK(hipMemcpyAsync(d.pos, s.pos, 3 * d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(d.depth, s.depth, d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(d.width, s.width, d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  RET(upload(c, d.atom_off, d.nl.atom_off));
+  RET(upload(c, d.sph_idx, d.nl.sph_idx));
+  RET(upload(c, d.beta, d.nl.beta));
+  RET(upload(c, d.Dd, d.nl.D));
+  RET(upload(c, d.u_idx, d.nl.u_idx));
+  RET(upload(c, d.u_ptr, d.nl.u_ptr));
+  RET(upload(c, d.ent_pt, d.nl.ent_pt));
+  RET(upload(c, d.ent_atom, d.nl.ent_atom));
+  CK(rtk::twiddles(st, d.twx, d.nx));
+  CK(rtk::twiddles(st, d.twy, d.ny));
+  CK(rtk::twiddles(st, d.twz, d.nz));
+  CK(rtk::vion(st, d.vion, d.nx, d.ny, d.nz, d.h, d.n_atoms, d.pos, d.depth, d.width, d.n_images));
+  std::vector<double> occ(nb, 0.0);
+  for (int i = 0; i < N; ++i) occ[i] = s.occ ? s.occ[i] : (i < s.n_occ ? 2.0 : 0.0);
+  CK(hipMemcpyAsync(g.occ, occ.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(g.blk[0], s.psi0, (size_t)nb * ng * sizeof(double),
+                    s.psi0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  CK(rtk::fill(st, g.Bp, 64, 0.0));
+
+  GsRun R(c, d, g, N);
+  R.static_bound = kinetic_max(d) + nonlocal_bound(d);
+  const int m = p.degree;
+  // start: the given block, orthonormalised, and its Ritz pairs for V_loc = V_ion
+  RET(R.orth(0, 1));
+  CK(rtk::copy_d(st, d.vloc, d.vion, ng));
+  RET(R.bound());
+  RET(R.ritz(0));
+  RET(R.solve(m, std::max(1e-2, p.tol_res), p.max_passes));
+  CK(rtk::occ_density(st, g.blk[R.cur], g.occ, nb, ng, d.rho));
+  // density loop: V_loc[rho_in] -> filtered Ritz pairs -> rho_out, Pulay-mixed
+  double err = INFINITY;
+  int it = 0, count = 0;
+  bool conv = false;
+  for (it = 1; it <= p.max_scf; ++it) {
+    RET(poisson_lda(c, d, 1, nullptr));
+    RET(R.bound());
+    RET(R.solve(m, std::max(p.tol_res, std::min(1e-3, 0.01 * err)), p.max_passes));
+    CK(rtk::occ_density(st, g.blk[R.cur], g.occ, nb, ng, g.rho_out));
+    const int sn = count % g.depth;
+    double* hres = g.hres + (long)sn * ng;
+    CK(rtk::lincomb(st, hres, 1.0, g.rho_out, -1.0, d.rho, ng));
+    CK(rtk::copy_d(st, g.hin + (long)sn * ng, d.rho, ng));
+    CK(rtk::fill_u64(st, g.slot, 1, 0ull));
+    CK(rtk::abs_max(st, hres, ng, g.slot));
+    err = R.read_slot();
+    if (!std::isfinite(err)) return fail(c, RT_ENOCONV, "ground state: non-finite density");
+    if (err < p.tol_rho) {
+      conv = true;
+      break;
+    }
+    ++count;
+    const int mm = std::min(count, g.depth);
+    CK(rtk::pulay_dots(st, g.hres, mm, sn, ng, g.dpart));
+    CK(rtk::pulay_solve(st, g.dpart, mm, sn, g.depth, g.Bp, g.coef));
+    CK(rtk::pulay_mix(st, g.hin, g.hres, g.coef, mm, p.mix, ng, d.rho));
+  }
+  if (!conv) return fail(c, RT_ENOCONV, "ground state: density loop hit max_scf");
+  // final orbitals: eigenpairs of H[rho_in] at the converged input density
+  RET(poisson_lda(c, d, 1, nullptr));
+  RET(R.bound());
+  RET(R.solve(m, p.tol_res, p.max_passes));
+  const double res = R.wanted_res();
+  if (!(res <= p.tol_res)) return fail(c, RT_ENOCONV, "ground state: eigen-residual above tol_res after max_passes");
+  double* X = g.blk[R.cur];
+  CK(rtk::fix_signs(st, X, N, ng));
+  CK(rtk::occ_density(st, X, g.occ, nb, ng, g.rho_out));
+  CK(rtk::lincomb(st, g.hres, 1.0, g.rho_out, -1.0, d.rho, ng));
+  CK(rtk::fill_u64(st, g.slot, 1, 0ull));
+  CK(rtk::abs_max(st, g.hres, ng, g.slot));
+  const double rho_err = R.read_slot();
+  CK(hipMemcpyAsync(psi_out, X, (size_t)N * ng * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (rho_out) CK(hipMemcpyAsync(rho_out, g.rho_out, ng * sizeof(double), hipMemcpyDeviceToDevice, st));
+  CK(hipStreamSynchronize(st));
+  if (eps_out) std::copy(R.ev.begin(), R.ev.end(), eps_out);
+  if (stats) {
+    stats->scf_iters = it;
+    stats->filter_passes = R.passes;
+    stats->h_applies = R.applies;
+    stats->eigensolves = R.eighs;
+    stats->jacobi_sweeps = R.sweeps;
+    stats->rho_err = rho_err;
+    stats->residual = res;
+  }
+  return RT_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1569,6 +2010,77 @@ rt_status rt_get_grid(rt_ctx* c, int si, int which, double* out_host) {
   CK(hipMemcpyAsync(out_host, src, d.ng * 8, hipMemcpyDeviceToHost, c->stream));
   CK(hipStreamSynchronize(c->stream));
   return RT_OK;
+}
+
+rt_status rt_eigh_workspace_size(int n, size_t* bytes) {
+  if (!bytes || n < 1 || n > 4096) { g_init_error = "rt_eigh_workspace_size: n outside [1, 4096] or bytes NULL"; return RT_EINVAL; }
+  Arena a;
+  EighWork w;
+  eigh_layout(a, w, n);
+  *bytes = a.used + 256;
+  return RT_OK;
+}
+
+rt_status rt_eigh(void* hip_stream, int n, const double* a_dev, double* evals_dev, double* vecs_dev,
+                  void* workspace_dev, size_t ws_bytes, int* sweeps_out) {
+  size_t need = 0;
+  if (!a_dev || !evals_dev || !vecs_dev || !workspace_dev || rt_eigh_workspace_size(n, &need) != RT_OK) {
+    g_init_error = "rt_eigh arguments";
+    return RT_EINVAL;
+  }
+  if (ws_bytes < need) {
+    g_init_error = "rt_eigh: workspace too small: need " + std::to_string(need) + " bytes";
+    return RT_ENOMEM;
+  }
+  Arena a;
+  a.base = reinterpret_cast<char*>(((uintptr_t)workspace_dev + 255) & ~uintptr_t(255));
+  EighWork w;
+  eigh_layout(a, w, n);
+  rt_ctx c;
+  c.stream = (hipStream_t)hip_stream;
+  rt_status st = eigh_run(&c, w, a_dev, evals_dev, vecs_dev, sweeps_out);
+  if (st != RT_OK) g_init_error = c.err;
+  return st;
+}
+
+rt_status rt_ground_state_workspace_size(const rt_system* sys, const rt_gs_params* params, size_t* bytes) {
+  std::string why;
+  if (!bytes) { g_init_error = "bytes is NULL"; return RT_EINVAL; }
+  rt_status st = validate_gs(sys, params, why);
+  if (st != RT_OK) { g_init_error = why; return st; }
+  SysDev d;
+  GsDev g;
+  describe_gs(sys, params, d, g);
+  Arena a;
+  layout_gs(a, d, g);
+  *bytes = a.used + 256;
+  return RT_OK;
+}
+
+rt_status rt_ground_state(const rt_system* sys, const rt_gs_params* params, void* workspace_dev, size_t ws_bytes,
+                          void* hip_stream, double* psi_out_dev, double* eps_out_host, double* rho_out_dev,
+                          rt_gs_stats* stats) {
+  std::string why;
+  rt_status st = validate_gs(sys, params, why);
+  if (st != RT_OK) { g_init_error = why; return st; }
+  if (!workspace_dev || !psi_out_dev) { g_init_error = "workspace or psi_out is NULL"; return RT_EINVAL; }
+  SysDev d;
+  GsDev g;
+  describe_gs(sys, params, d, g);
+  Arena sz;
+  layout_gs(sz, d, g);
+  if (ws_bytes < sz.used + 256) {
+    g_init_error = "rt_ground_state: workspace too small: need " + std::to_string(sz.used + 256) + " bytes";
+    return RT_ENOMEM;
+  }
+  Arena a;
+  a.base = reinterpret_cast<char*>(((uintptr_t)workspace_dev + 255) & ~uintptr_t(255));
+  layout_gs(a, d, g);
+  rt_ctx c;
+  c.stream = (hipStream_t)hip_stream;
+  st = gs_run(&c, d, g, *sys, *params, psi_out_dev, eps_out_host, rho_out_dev, stats);
+  if (st != RT_OK) g_init_error = c.err;
+  return st;
 }
 
 void rt_mlp_dims(int* n_in, int* n_h, int* n_out) {

@@ -52,6 +52,18 @@ class rt_step_stats(ctypes.Structure):
                 ("residual", ctypes.c_double)]
 
 
+class rt_gs_params(ctypes.Structure):
+    _fields_ = [("n_guard", ctypes.c_int), ("degree", ctypes.c_int), ("max_scf", ctypes.c_int),
+                ("max_passes", ctypes.c_int), ("tol_rho", ctypes.c_double), ("tol_res", ctypes.c_double),
+                ("mix", ctypes.c_double), ("pulay_depth", ctypes.c_int)]
+
+
+class rt_gs_stats(ctypes.Structure):
+    _fields_ = [("scf_iters", ctypes.c_int32), ("filter_passes", ctypes.c_int32), ("h_applies", ctypes.c_int64),
+                ("eigensolves", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64), ("rho_err", ctypes.c_double),
+                ("residual", ctypes.c_double)]
+
+
 class RTError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"status {status}: {msg}")
@@ -94,6 +106,12 @@ def _load():
         "rt_mlp_colstats": ([vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_float], ctypes.c_int),
         "rt_record": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
         "rt_record_count": ([vp, _ip], ctypes.c_int),
+        "rt_ground_state_workspace_size": ([ctypes.POINTER(rt_system), ctypes.POINTER(rt_gs_params),
+                                            ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "rt_ground_state": ([ctypes.POINTER(rt_system), ctypes.POINTER(rt_gs_params), vp, ctypes.c_size_t, vp, vp,
+                             _dp, vp, ctypes.POINTER(rt_gs_stats)], ctypes.c_int),
+        "rt_eigh_workspace_size": ([ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "rt_eigh": ([vp, ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t, _ip], ctypes.c_int),
         "rt_free": ([vp], None),
         "rt_last_error": ([vp], ctypes.c_char_p),
     }
@@ -299,6 +317,81 @@ def rt_record_count(ctx):
     n = ctypes.c_int(0)
     _check(lib.rt_record_count(ctx, ctypes.byref(n)), ctx)
     return n.value
+
+
+def gs_params(n_guard=8, degree=10, max_scf=100, max_passes=30, tol_rho=1e-11, tol_res=1e-10, mix=0.3,
+              pulay_depth=8):
+    p = rt_gs_params()
+    p.n_guard, p.degree, p.max_scf, p.max_passes = n_guard, degree, max_scf, max_passes
+    p.tol_rho, p.tol_res, p.mix, p.pulay_depth = tol_rho, tol_res, mix, pulay_depth
+    return p
+
+
+def rt_ground_state_workspace_size(system, params) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib.rt_ground_state_workspace_size(ctypes.byref(system.struct), ctypes.byref(params),
+                                              ctypes.byref(out)))
+    return out.value
+
+
+def rt_ground_state(system, params, workspace_ptr, ws_bytes, stream_ptr, psi_out_ptr, rho_out_ptr=None):
+    """Runs the solve; returns (Ritz values [N + n_guard], stats dict)."""
+    n = system.struct.n_occ + system.struct.n_virt + params.n_guard
+    eps = np.zeros(n)
+    st = rt_gs_stats()
+    _check(lib.rt_ground_state(ctypes.byref(system.struct), ctypes.byref(params), ctypes.c_void_p(workspace_ptr),
+                               ws_bytes, ctypes.c_void_p(stream_ptr), ctypes.c_void_p(psi_out_ptr), _ptr(eps),
+                               ctypes.c_void_p(rho_out_ptr), ctypes.byref(st)))
+    return eps, {f: getattr(st, f) for f, _ in rt_gs_stats._fields_}
+
+
+def rt_eigh_workspace_size(n) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib.rt_eigh_workspace_size(n, ctypes.byref(out)))
+    return out.value
+
+
+def rt_eigh(stream_ptr, n, a_ptr, evals_ptr, vecs_ptr, workspace_ptr, ws_bytes):
+    """Returns the number of Jacobi sweeps."""
+    sw = ctypes.c_int(0)
+    _check(lib.rt_eigh(ctypes.c_void_p(stream_ptr), n, ctypes.c_void_p(a_ptr), ctypes.c_void_p(evals_ptr),
+                       ctypes.c_void_p(vecs_ptr), ctypes.c_void_p(workspace_ptr), ws_bytes, ctypes.byref(sw)))
+    return sw.value
+
+
+def ground_state(system, params, device="cuda"):
+    """Device workspace from torch, then rt_ground_state on torch's current stream.
+    Returns (psi [N][ng] torch tensor on the device, Ritz values, rho tensor, stats)."""
+    import torch
+
+    s = system.struct
+    ng = s.n[0] * s.n[1] * s.n[2]
+    N = s.n_occ + s.n_virt
+    ws_bytes = rt_ground_state_workspace_size(system, params)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    psi = torch.empty((N, ng), dtype=torch.float64, device=device)
+    rho = torch.empty(ng, dtype=torch.float64, device=device)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    eps, stats = rt_ground_state(system, params, ws.data_ptr(), ws_bytes, stream, psi.data_ptr(), rho.data_ptr())
+    del ws
+    return psi, eps, rho, stats
+
+
+def eigh(a, device="cuda"):
+    """Eigen-decomposition of the symmetric part of a (numpy [n][n]) by rt_eigh.
+    Returns (eigenvalues ascending, eigenvectors as rows, sweeps)."""
+    import torch
+
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    ws_bytes = rt_eigh_workspace_size(n)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    A = torch.from_numpy(a).to(device)
+    ev = torch.empty(n, dtype=torch.float64, device=device)
+    V = torch.empty((n, n), dtype=torch.float64, device=device)
+    stream = torch.cuda.current_stream(device).cuda_stream
+    sw = rt_eigh(stream, n, A.data_ptr(), ev.data_ptr(), V.data_ptr(), ws.data_ptr(), ws_bytes)
+    return ev.cpu().numpy(), V.cpu().numpy(), sw
 
 
 def rt_free(ctx):

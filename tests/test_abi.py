@@ -109,3 +109,39 @@ def test_nonorthogonal_basis_takes_overlap_buffers():
     sa, ra = _args(nonorthogonal=1)
     b = rt.rt_workspace_size([sa], ra)
     assert b >= a + 3 * 4 * 4 * 8  # overlap, its inverse and S^-1 Hbar per trajectory (N = 4)
+
+
+def test_ground_state_and_eigh_reject_bad_arguments_without_a_gpu():
+    import synth
+    from paper_2410_09189_amd import rt
+    from rt_helpers import system_args
+
+    s = synth.make_system(16, 0.4, 2, 2, 2, seed=1, nl_rank=4, region=(0.3, 0.7))
+    sa = system_args(s, synth.lowpass_orbitals(16, 0.4, 4 + 6, 1))
+    size = rt.rt_ground_state_workspace_size(sa, rt.gs_params(n_guard=6))
+    assert size > 3 * 10 * 16 ** 3 * 8
+    bad = [dict(n_guard=1), dict(n_guard=1100), dict(degree=0), dict(degree=65), dict(max_scf=0),
+           dict(max_passes=0), dict(tol_rho=0.0), dict(tol_res=-1.0), dict(mix=0.0), dict(mix=1.5),
+           dict(pulay_depth=0), dict(pulay_depth=9)]
+    for kw in bad:
+        p = rt.gs_params(**{"n_guard": 6, **kw})
+        with pytest.raises(rt.RTError) as e:
+            rt.rt_ground_state_workspace_size(sa, p)
+        assert e.value.status == rt.RT_EINVAL, kw
+        with pytest.raises(rt.RTError) as e:  # rejected before any device work
+            rt.rt_ground_state(sa, p, 0, 0, 0, 0)
+        assert e.value.status == rt.RT_EINVAL, kw
+    sa.struct.orthonormalize = 1
+    with pytest.raises(rt.RTError):
+        rt.rt_ground_state_workspace_size(sa, rt.gs_params(n_guard=6))
+    sa.struct.orthonormalize = 0
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_ground_state(sa, rt.gs_params(n_guard=6), 0, size, 0, 0)
+    assert e.value.status == rt.RT_EINVAL and "NULL" in rt.rt_last_error(None)
+    assert rt.rt_eigh_workspace_size(255) >= 3 * 256 * 256 * 8
+    for n in (0, 4097):
+        with pytest.raises(rt.RTError):
+            rt.rt_eigh_workspace_size(n)
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_eigh(0, 8, 0, 0, 0, 0, 1 << 20)
+    assert e.value.status == rt.RT_EINVAL
