@@ -351,6 +351,8 @@ rt_status rt_record_count(rt_ctx* ctx, int* rows);
  * Errors: RT_EINVAL for arguments outside the ranges below (no side effects),
  *   RT_ENOMEM for a short workspace, RT_ENOCONV when max_scf or max_passes is
  *   exhausted or the block loses rank; rt_last_error(NULL) names the cause.
+ *   When the density loop hits max_scf, stats (rho_err: the last
+ *   max|rho_out - rho_in|) and eps_out_host still describe the last iterate.
  */
 typedef struct {
   int n_guard;        /* extra block vectors (>= 2; N + n_guard <= 1024)        */

@@ -1686,7 +1686,7 @@ rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs
   for (it = 1; it <= p.max_scf; ++it) {
     RET(poisson_lda(c, d, 1, nullptr));
     RET(R.bound());
-    RET(R.solve(m, std::max(p.tol_res, std::min(1e-3, 0.01 * err)), p.max_passes));
+    RET(R.solve(m, std::max(p.tol_res, std::min(1e-2, 0.1 * err)), p.max_passes));
     CK(rtk::occ_density(st, g.blk[R.cur], g.occ, nb, ng, g.rho_out));
     const int sn = count % g.depth;
     double* hres = g.hres + (long)sn * ng;
@@ -1706,7 +1706,22 @@ rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs
     CK(rtk::pulay_solve(st, g.dpart, mm, sn, g.depth, g.Bp, g.coef));
     CK(rtk::pulay_mix(st, g.hin, g.hres, g.coef, mm, p.mix, ng, d.rho));
   }
-  if (!conv) return fail(c, RT_ENOCONV, "ground state: density loop hit max_scf");
+  auto report = [&](double rho_err, double res) {
+    if (eps_out) std::copy(R.ev.begin(), R.ev.end(), eps_out);
+    if (stats) {
+      stats->scf_iters = std::min(it, p.max_scf);
+      stats->filter_passes = R.passes;
+      stats->h_applies = R.applies;
+      stats->eigensolves = R.eighs;
+      stats->jacobi_sweeps = R.sweeps;
+      stats->rho_err = rho_err;
+      stats->residual = res;
+    }
+  };
+  if (!conv) {
+    report(err, R.wanted_res());  // the last iterate, for diagnosis
+    return fail(c, RT_ENOCONV, "ground state: density loop hit max_scf");
+  }
   // final orbitals: eigenpairs of H[rho_in] at the converged input density
   RET(poisson_lda(c, d, 1, nullptr));
   RET(R.bound());
@@ -1723,16 +1738,7 @@ rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs
   CK(hipMemcpyAsync(psi_out, X, (size_t)N * ng * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (rho_out) CK(hipMemcpyAsync(rho_out, g.rho_out, ng * sizeof(double), hipMemcpyDeviceToDevice, st));
   CK(hipStreamSynchronize(st));
-  if (eps_out) std::copy(R.ev.begin(), R.ev.end(), eps_out);
-  if (stats) {
-    stats->scf_iters = it;
-    stats->filter_passes = R.passes;
-    stats->h_applies = R.applies;
-    stats->eigensolves = R.eighs;
-    stats->jacobi_sweeps = R.sweeps;
-    stats->rho_err = rho_err;
-    stats->residual = res;
-  }
+  report(rho_err, res);
   return RT_OK;
 }
 

@@ -335,14 +335,20 @@ def rt_ground_state_workspace_size(system, params) -> int:
 
 
 def rt_ground_state(system, params, workspace_ptr, ws_bytes, stream_ptr, psi_out_ptr, rho_out_ptr=None):
-    """Runs the solve; returns (Ritz values [N + n_guard], stats dict)."""
+    """Runs the solve; returns (Ritz values [N + n_guard], stats dict).  On a
+    failure the RTError carries .eps and .stats of the last iterate."""
     n = system.struct.n_occ + system.struct.n_virt + params.n_guard
     eps = np.zeros(n)
     st = rt_gs_stats()
-    _check(lib.rt_ground_state(ctypes.byref(system.struct), ctypes.byref(params), ctypes.c_void_p(workspace_ptr),
-                               ws_bytes, ctypes.c_void_p(stream_ptr), ctypes.c_void_p(psi_out_ptr), _ptr(eps),
-                               ctypes.c_void_p(rho_out_ptr), ctypes.byref(st)))
-    return eps, {f: getattr(st, f) for f, _ in rt_gs_stats._fields_}
+    status = lib.rt_ground_state(ctypes.byref(system.struct), ctypes.byref(params), ctypes.c_void_p(workspace_ptr),
+                                 ws_bytes, ctypes.c_void_p(stream_ptr), ctypes.c_void_p(psi_out_ptr), _ptr(eps),
+                                 ctypes.c_void_p(rho_out_ptr), ctypes.byref(st))
+    stats = {f: getattr(st, f) for f, _ in rt_gs_stats._fields_}
+    if status != RT_OK:
+        err = RTError(status, rt_last_error(None))
+        err.eps, err.stats = eps, stats
+        raise err
+    return eps, stats
 
 
 def rt_eigh_workspace_size(n) -> int:
