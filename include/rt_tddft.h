@@ -223,7 +223,8 @@ rt_status rt_dipole(rt_ctx* ctx, int traj, int first_step, int count, double* mu
 /*
  * Matrix getters (synchronise the stream); out: host [N][N] double.
  * which: 0 = H_0, 1 = H_-1, 2 = Re P_0 (S'), 3 = Im P_0 (A'), 4 = H_core,
- * 5/6/7 = M_x/M_y/M_z (traj selects the system through traj_sys).
+ * 5/6/7 = M_x/M_y/M_z, 8 = H_gs = H[P_gs] of the ground state (traj selects
+ * the system through traj_sys for 4..8).
  */
 rt_status rt_get_matrix(rt_ctx* ctx, int traj, int which, double* out);
 
