@@ -13,6 +13,15 @@ hipError_t jacobi_setup(hipStream_t s, const double* A, int n, int ld, double* W
 // are rotated at once, Aout = J^T A J (J the product of the pair rotations that
 // zero A_pq), V <- V J.  A and Aout must differ.
 hipError_t jacobi_round(hipStream_t s, const double* A, double* Aout, double* V, int ld, int round);
+// Largest order of the single-block (LDS-resident) eigensolve and Cholesky.
+int jacobi_small_max();
+// All sweeps in one block for even ld <= jacobi_small_max(): A (set up by
+// jacobi_setup) iterated in LDS and written back, V updated in place; at most
+// max_sweeps; stat[0..2] = sweeps, off-diagonal norm^2, total norm^2.
+hipError_t jacobi_small(hipStream_t s, double* A, double* V, int ld, int max_sweeps, double* stat);
+// Linv = L^-1 with A = L L^T (lower) for n <= jacobi_small_max(), one block, L in
+// LDS; info = first non-positive pivot column + 1 (0: success).
+hipError_t chol_inv_small(hipStream_t s, const double* A, double* Linv, int n, int* info);
 // out[0] = sum_{i != j} A_ij^2, out[1] = sum_i A_ii^2 (one block, fixed order)
 hipError_t jacobi_offdiag(hipStream_t s, const double* A, int ld, double* out);
 // evals[k] = k-th smallest diag(A) over the first n indices (ties by index);

@@ -128,6 +128,168 @@ __global__ __launch_bounds__(256) void k_jacobi_round(const double* __restrict__
   V[(long)r * ld + qj] = sj * vp + cj * vq;
 }
 
+// The whole eigensolve of a matrix of order ld <= kSmallLd in one block: A in LDS,
+// V in global memory (each (row, pair) is owned by one thread), the rotations of a
+// round computed into LDS first, then every 2x2 block rotated in place by the thread
+// that owns it.  The same stopping rule as the multi-launch path, tested after every
+// sweep; stat = (sweeps, off-diagonal norm^2, total norm^2).
+constexpr int kSmallLd = 128;
+
+__global__ __launch_bounds__(1024) void k_jacobi_small(double* __restrict__ Ag, double* __restrict__ V, int ld,
+                                                       int max_sweeps, double* __restrict__ stat) {
+  __shared__ double A[kSmallLd * kSmallLd];
+  __shared__ double cs[kSmallLd / 2], sn[kSmallLd / 2], tn[kSmallLd / 2];
+  __shared__ double red[1024 / 64];
+  __shared__ int flag;
+  const int tid = threadIdx.x, nt = blockDim.x, h = ld >> 1;
+  const int LL = ld * ld;
+  for (int e = tid; e < LL; e += nt) A[e] = Ag[e];
+  __syncthreads();
+  // Frobenius norms: off-diagonal and total (fixed order: per-thread strided, then waves, then lanes)
+  auto norms = [&](double& off, double& tot) {
+    double o = 0.0, d = 0.0;
+    for (int e = tid; e < LL; e += nt) {
+      const int i = e / ld, j = e - i * ld;
+      const double a = A[e];
+      if (i == j) d += a * a;
+      else o += a * a;
+    }
+    double v2[2] = {o, d};
+    for (int k = 0; k < 2; ++k) {
+      double v = v2[k];
+      for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+      if ((tid & 63) == 0) red[tid >> 6] = v;
+      __syncthreads();
+      double r = 0.0;
+      for (int w = 0; w < nt / 64; ++w) r += red[w];
+      __syncthreads();
+      v2[k] = r;
+    }
+    off = v2[0];
+    tot = v2[0] + v2[1];
+  };
+  double off, total;
+  norms(off, total);
+  double prev = off;
+  int sw = 0;
+  while (off > 1e-30 * total && sw < max_sweeps) {
+    for (int r = 0; r < ld - 1; ++r) {
+      for (int k = tid; k < h; k += nt) {
+        int p, q;
+        rr_pair(ld, r, k, p, q);
+        double c, s, t;
+        jrot(A, ld, p, q, c, s, t);
+        cs[k] = c;
+        sn[k] = s;
+        tn[k] = t;
+      }
+      __syncthreads();
+      for (long e = tid; e < (long)h * h + (long)ld * h; e += nt) {
+        if (e < (long)h * h) {
+          const int i = (int)(e / h), j = (int)(e - (long)i * h);
+          if (i > j) continue;
+          int pi, qi;
+          rr_pair(ld, r, i, pi, qi);
+          const double ci = cs[i], si = sn[i];
+          if (i == j) {
+            const double apq = A[pi * ld + qi], ti = tn[i];
+            A[pi * ld + pi] -= ti * apq;
+            A[qi * ld + qi] += ti * apq;
+            A[pi * ld + qi] = 0.0;
+            A[qi * ld + pi] = 0.0;
+            continue;
+          }
+          int pj, qj;
+          rr_pair(ld, r, j, pj, qj);
+          const double cj = cs[j], sj = sn[j];
+          const double b00 = A[pi * ld + pj], b01 = A[pi * ld + qj];
+          const double b10 = A[qi * ld + pj], b11 = A[qi * ld + qj];
+          const double m00 = ci * b00 - si * b10, m01 = ci * b01 - si * b11;
+          const double m10 = si * b00 + ci * b10, m11 = si * b01 + ci * b11;
+          const double r00 = cj * m00 - sj * m01, r01 = sj * m00 + cj * m01;
+          const double r10 = cj * m10 - sj * m11, r11 = sj * m10 + cj * m11;
+          A[pi * ld + pj] = r00;
+          A[pi * ld + qj] = r01;
+          A[qi * ld + pj] = r10;
+          A[qi * ld + qj] = r11;
+          A[pj * ld + pi] = r00;
+          A[qj * ld + pi] = r01;
+          A[pj * ld + qi] = r10;
+          A[qj * ld + qi] = r11;
+        } else {
+          const long e2 = e - (long)h * h;
+          const int row = (int)(e2 / h), j = (int)(e2 - (long)row * h);
+          int pj, qj;
+          rr_pair(ld, r, j, pj, qj);
+          const double cj = cs[j], sj = sn[j];
+          const double vp = V[(long)row * ld + pj], vq = V[(long)row * ld + qj];
+          V[(long)row * ld + pj] = cj * vp - sj * vq;
+          V[(long)row * ld + qj] = sj * vp + cj * vq;
+        }
+      }
+      __syncthreads();
+    }
+    ++sw;
+    norms(off, total);
+    if (tid == 0) flag = (off <= 1e-26 * total && off > 0.25 * prev) ? 1 : 0;
+    __syncthreads();
+    const int stop = flag;
+    __syncthreads();
+    if (stop) break;
+    prev = off;
+  }
+  for (int e = tid; e < LL; e += nt) Ag[e] = A[e];
+  if (tid == 0) {
+    stat[0] = (double)sw;
+    stat[1] = off;
+    stat[2] = total;
+  }
+}
+
+// L = chol(A) (lower) in LDS, then Linv = L^-1 (one column per thread, forward
+// substitution reading L from LDS) for n <= kSmallLd; info = first failing column + 1.
+__global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restrict__ Ag, double* __restrict__ Linv,
+                                                         int n, int* info) {
+  __shared__ double L[kSmallLd * kSmallLd];
+  __shared__ double djj;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < n * n; e += nt) L[e] = Ag[e];
+  if (tid == 0) *info = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    // d = A_jj - sum_k<j L_jk^2 (one wave, fixed shuffle tree)
+    if (tid < 64) {
+      double acc = 0.0;
+      for (int k = tid; k < j; k += 64) acc += L[j * n + k] * L[j * n + k];
+      for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+      if (tid == 0) {
+        double d = L[j * n + j] - acc;
+        if (!(d > 0.0)) {
+          if (*info == 0) *info = j + 1;
+          d = 1.0;
+        }
+        djj = sqrt(d);
+        L[j * n + j] = djj;
+      }
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < n; i += nt) {
+      double t = L[i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / djj;
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < n; c += nt) {
+    for (int i = 0; i < c; ++i) Linv[(long)i * n + c] = 0.0;
+    for (int i = c; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) t -= L[i * n + k] * Linv[(long)k * n + c];
+      Linv[(long)i * n + c] = t / L[i * n + i];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_jacobi_offdiag(const double* __restrict__ A, int ld, double* out) {
   __shared__ double sh[256];
   double off = 0.0, dg = 0.0;
@@ -342,6 +504,20 @@ hipError_t jacobi_round(hipStream_t s, const double* A, double* Aout, double* V,
   const long h = ld / 2;
   const long threads = h * h + (long)ld * h;
   hipLaunchKernelGGL(k_jacobi_round, dim3(gs_cdiv(threads, 256)), dim3(256), 0, s, A, Aout, V, ld, round);
+  return hipGetLastError();
+}
+
+int jacobi_small_max() { return kSmallLd; }
+
+hipError_t jacobi_small(hipStream_t s, double* A, double* V, int ld, int max_sweeps, double* stat) {
+  if (ld > kSmallLd || ld < 2 || (ld & 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), 0, s, A, V, ld, max_sweeps, stat);
+  return hipGetLastError();
+}
+
+hipError_t chol_inv_small(hipStream_t s, const double* A, double* Linv, int n, int* info) {
+  if (n > kSmallLd || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(1024), 0, s, A, Linv, n, info);
   return hipGetLastError();
 }
 

@@ -1320,7 +1320,7 @@ void eigh_layout(Arena& a, EighWork& w, int n) {
   w.A = a.take<double>(LL);
   w.A2 = a.take<double>(LL);
   w.V = a.take<double>(LL);
-  w.off = a.take<double>(2);
+  w.off = a.take<double>(3);
   w.rank = a.take<int>(w.ld);
 }
 
@@ -1330,6 +1330,20 @@ constexpr int kMaxSweeps = 60;
 rt_status eigh_run(rt_ctx* c, EighWork& w, const double* A, double* evals, double* vecs, int* sweeps) {
   hipStream_t st = c->stream;
   CK(rtk::jacobi_setup(st, A, w.n, w.ld, w.A, w.V));
+  if (w.ld <= rtk::jacobi_small_max()) {
+    // one block holds the matrix in LDS and runs every sweep
+    double stat[3] = {0.0, 0.0, 0.0};
+    CK(rtk::jacobi_small(st, w.A, w.V, w.ld, kMaxSweeps, w.off));
+    CK(hipMemcpyAsync(stat, w.off, sizeof(stat), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (!std::isfinite(stat[2])) return fail(c, RT_EINVAL, "eigensolver: matrix has non-finite entries");
+    if (!std::isfinite(stat[1])) return fail(c, RT_ENOCONV, "eigensolver: non-finite iterate");
+    if ((int)stat[0] >= kMaxSweeps && stat[1] > 1e-26 * stat[2])
+      return fail(c, RT_ENOCONV, "eigensolver: Jacobi sweeps did not converge");
+    CK(rtk::jacobi_sort(st, w.A, w.V, w.n, w.ld, evals, vecs, w.rank));
+    if (sweeps) *sweeps = (int)stat[0];
+    return RT_OK;
+  }
   double* a = w.A;
   double* b = w.A2;
   double off[2] = {0.0, 0.0};
@@ -1539,8 +1553,12 @@ struct GsRun {
       double* src = g.blk[pass ? j : i];
       double* dst = g.blk[pass ? i : j];
       RET(project(c, d, src, src, nullptr, d.tmp));
-      CK(rtk::cholesky(st, d.tmp, nb, d.info + pass));
-      CK(rtk::tri_inverse_lower(st, d.tmp, d.tmp2, nb));
+      if (nb <= rtk::jacobi_small_max()) {
+        CK(rtk::chol_inv_small(st, d.tmp, d.tmp2, nb, d.info + pass));
+      } else {
+        CK(rtk::cholesky(st, d.tmp, nb, d.info + pass));
+        CK(rtk::tri_inverse_lower(st, d.tmp, d.tmp2, nb));
+      }
       CK(rtk::smalltall_f64(st, nb, d.ng, d.tmp2, src, dst, 0, 2, 1, nullptr));
     }
     int info[2] = {0, 0};

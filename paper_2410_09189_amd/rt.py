@@ -319,7 +319,7 @@ def rt_record_count(ctx):
     return n.value
 
 
-def gs_params(n_guard=8, degree=10, max_scf=100, max_passes=30, tol_rho=1e-11, tol_res=1e-10, mix=0.3,
+def gs_params(n_guard=8, degree=24, max_scf=100, max_passes=30, tol_rho=1e-11, tol_res=1e-10, mix=0.3,
               pulay_depth=8):
     p = rt_gs_params()
     p.n_guard, p.degree, p.max_scf, p.max_passes = n_guard, degree, max_scf, max_passes
