@@ -183,7 +183,7 @@ rt_status rt_workspace_size(const rt_system* sys, int n_sys, const rt_run* run, 
  * workspace_dev: device memory of at least rt_workspace_size bytes, owned by
  * the caller, untouched by the caller until rt_free.  hip_stream: a
  * hipStream_t (NULL = default stream).  The library never allocates device
- * memory itself.
+ * memory itself.  psi0 with NaN or infinite entries gives RT_EINVAL.
  */
 rt_status rt_init(const rt_system* sys, int n_sys, const rt_run* run, void* workspace_dev,
                   size_t ws_bytes, void* hip_stream, rt_ctx** out);
@@ -206,8 +206,10 @@ rt_status rt_apply_h(rt_ctx* ctx, int sys_index, const void* psi_dev, void* hpsi
  * max|dP^(k)| <= dp_thrs (eq. commutator-expansion-ort); H_new = H[P_1] } until
  * max|H_new - H_1| <= h_thrs; then H_-1 <- H_0, H_0 <- H_1, P_0 <- P_1 and
  * record mu_q = Tr(P M_q) and E.  stats: host [n_steps][n_traj] or NULL.
- * Returns RT_ENOCONV if a cap is hit; the state then stays at the last
- * completed step.  RT_ESTATE once n_steps_max steps have been taken.
+ * Returns RT_ENOCONV if a cap is hit, or at once when a Hamiltonian update
+ * is not finite (NaN / Inf; rt_last_error names the trajectory); the state
+ * then stays at the last completed step.  RT_ESTATE once n_steps_max steps
+ * have been taken.
  */
 rt_status rt_step(rt_ctx* ctx, int n_steps, rt_step_stats* stats);
 
@@ -231,7 +233,7 @@ rt_status rt_get_matrix(rt_ctx* ctx, int traj, int which, double* out);
 /*
  * Overwrites the state of trajectory traj: P = S' + i A' (host [N][N] each),
  * H_0 and H_-1 (host [N][N]); NULL keeps the current value.  For checkpoint
- * restore and tests.
+ * restore and tests.  Non-finite entries give RT_EINVAL (nothing is copied).
  */
 rt_status rt_set_state(rt_ctx* ctx, int traj, const double* p_re, const double* p_im,
                        const double* h0, const double* hm1);
@@ -349,7 +351,8 @@ rt_status rt_record_count(rt_ctx* ctx, int* rows);
  * workspace_dev: at least rt_ground_state_workspace_size bytes, caller-owned;
  *   the call allocates no device memory.  All work is on hip_stream and the
  *   call synchronises it (the loop reads its convergence measures).
- * Errors: RT_EINVAL for arguments outside the ranges below (no side effects),
+ * Errors: RT_EINVAL for arguments outside the ranges below (no side effects)
+ *   or a start block with non-finite entries,
  *   RT_ENOMEM for a short workspace, RT_ENOCONV when max_scf or max_passes is
  *   exhausted or the block loses rank; rt_last_error(NULL) names the cause.
  *   When the density loop hits max_scf, stats (rho_err: the last

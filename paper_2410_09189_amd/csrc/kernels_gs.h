@@ -37,6 +37,8 @@ hipError_t row_residuals(hipStream_t s, const double* HX, const double* X, const
 hipError_t occ_density(hipStream_t s, const double* X, const double* occ, int n, long ng, double* rho);
 // slot = max_r |v[r]| (slot zeroed beforehand; bits of a non-negative double)
 hipError_t abs_max(hipStream_t s, const double* v, long n, unsigned long long* slot);
+// count += number of entries of v that are NaN or infinite (count zeroed beforehand)
+hipError_t count_nonfinite(hipStream_t s, const double* v, long n, unsigned long long* count);
 // each row scaled by the sign of its entry of largest modulus (first such entry)
 hipError_t fix_signs(hipStream_t s, double* X, int n, long ng);
 

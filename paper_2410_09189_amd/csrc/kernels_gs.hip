@@ -378,6 +378,14 @@ __global__ __launch_bounds__(256) void k_abs_max(const double* __restrict__ v, l
   if (threadIdx.x == 0) atomicMax(slot, (unsigned long long)__double_as_longlong(sh[0]));
 }
 
+__global__ __launch_bounds__(256) void k_count_nonfinite(const double* __restrict__ v, long n,
+                                                         unsigned long long* count) {
+  unsigned long long k = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    k += isfinite(v[i]) ? 0ull : 1ull;
+  if (k) atomicAdd(count, k);
+}
+
 // First index of the largest |x| in the row, then the row times the sign there.
 __global__ __launch_bounds__(256) void k_fix_signs(double* __restrict__ X, long ng) {
   __shared__ double sv[256];
@@ -548,6 +556,12 @@ hipError_t occ_density(hipStream_t s, const double* X, const double* occ, int n,
 hipError_t abs_max(hipStream_t s, const double* v, long n, unsigned long long* slot) {
   const int nb = grid_blocks(n) > 256 ? 256 : grid_blocks(n);
   hipLaunchKernelGGL(k_abs_max, dim3(nb), dim3(256), 0, s, v, n, slot);
+  return hipGetLastError();
+}
+
+hipError_t count_nonfinite(hipStream_t s, const double* v, long n, unsigned long long* count) {
+  const int nb = grid_blocks(n) > 1024 ? 1024 : grid_blocks(n);
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(nb), dim3(256), 0, s, v, n, count);
   return hipGetLastError();
 }
 

@@ -991,11 +991,25 @@ rt_status predict_correction(rt_ctx* c, SysDev& d) {
   return RT_OK;
 }
 
+// Number of NaN / infinite entries of a device array (synchronises the stream).
+rt_status count_bad(rt_ctx* c, const double* v, long n, unsigned long long* scratch, unsigned long long& bad) {
+  CK(rtk::fill_u64(c->stream, scratch, 1, 0ull));
+  CK(rtk::count_nonfinite(c->stream, v, n, scratch));
+  CK(hipMemcpyAsync(&bad, scratch, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return RT_OK;
+}
+
 rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   hipStream_t st = c->stream;
   const long N = d.N, ng = d.ng, NN = N * N;
   CK(hipMemcpyAsync(d.psi, s.psi0, N * ng * sizeof(double),
                     s.psi0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  {
+    unsigned long long bad = 0;
+    RET(count_bad(c, d.psi, N * ng, d.resid, bad));
+    if (bad) return fail(c, RT_EINVAL, "psi0 has " + std::to_string(bad) + " non-finite entries");
+  }
   std::vector<double> occ(N);
   for (long i = 0; i < N; ++i) occ[i] = s.occ ? s.occ[i] : (i < s.n_occ ? 2.0 : 0.0);
   CK(hipMemcpyAsync(d.occ, occ.data(), N * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1202,6 +1216,9 @@ rt_status process_update(rt_ctx* c, SysDev& d, StepState& ss, int m) {
         d.r1_linear[t].push_back(r);
       }
     }
+    if (!std::isfinite(r))
+      return fail(c, RT_ENOCONV, "non-finite Hamiltonian (residual " + std::to_string(r) + ") in trajectory " +
+                                     std::to_string(d.slot_traj[t]));
     ss.m_of[t] = m;
     ss.terms_of[t] += ss.terms[t];
     ss.res_of[t] = r;
@@ -1685,6 +1702,11 @@ rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs
   CK(hipMemcpyAsync(g.occ, occ.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(g.blk[0], s.psi0, (size_t)nb * ng * sizeof(double),
                     s.psi0_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  {
+    unsigned long long bad = 0;
+    RET(count_bad(c, g.blk[0], (long)nb * ng, g.slot, bad));
+    if (bad) return fail(c, RT_EINVAL, "start block has " + std::to_string(bad) + " non-finite entries");
+  }
   CK(rtk::fill(st, g.Bp, 64, 0.0));
 
   GsRun R(c, d, g, N);
@@ -1974,6 +1996,10 @@ rt_status rt_set_state(rt_ctx* c, int traj, const double* p_re, const double* p_
   SysDev& d = c->sys[t.sys];
   const long NN = nsq(d.N);
   hipStream_t s = c->stream;
+  for (const double* m : {p_re, p_im, h0, hm1})
+    if (m)
+      for (long e = 0; e < NN; ++e)
+        if (!std::isfinite(m[e])) return fail(c, RT_EINVAL, "rt_set_state: non-finite matrix entry");
   if (p_re) CK(hipMemcpyAsync(d.P0 + t.slot * 2 * NN, p_re, NN * 8, hipMemcpyHostToDevice, s));
   if (p_im) CK(hipMemcpyAsync(d.P0 + t.slot * 2 * NN + NN, p_im, NN * 8, hipMemcpyHostToDevice, s));
   if (h0) CK(hipMemcpyAsync(d.H0 + t.slot * NN, h0, NN * 8, hipMemcpyHostToDevice, s));
