@@ -301,6 +301,55 @@ def ground_states(rt, torch):
             "molecules": rows}
 
 
+def learned_predictor(rt, torch, sa, s):
+    """The learned first guess on the 96^3 molecule (mixed precision): training
+    samples recorded by the step itself on x and y kicks of two strengths, the
+    network trained on the GPU with the library's kernels, then a held-out z kick
+    stepped with the linear and with the learned guess at dt 0.2 (where the
+    linear guess often needs a third update).  Reports Hamiltonian updates per
+    step after the 8 warm-up steps the features need, the time per step, and the
+    dipole difference between the two runs (same fixed point)."""
+    from paper_2410_09189_amd import predictor
+
+    dt, n_rec, n_eval, h_thrs = 0.2, 150, 100, 1e-9
+
+    def ra(axes, kappas, n, pred=0, params=None):
+        return rt.RunArgs(dt=dt, n_steps_max=n, h_thrs=h_thrs, dp_thrs=1e-13, max_scf=50, max_terms=200,
+                          traj_sys=[0] * len(axes), traj_kappa=list(kappas), traj_axis=list(axes),
+                          precision=rt.RT_MIXED, hupdate=rt.RT_HUPDATE_LOCAL, predictor=pred, mlp_params=params)
+
+    t0 = time.perf_counter()
+    X, Y = predictor.record(lambda: rt.Session([sa], ra((0, 1, 0, 1), (1e-3, 1e-3, 2e-3, 2e-3), n_rec)),
+                            n_rec, capacity=4 * n_rec)
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, hist = predictor.train(X, Y, epochs=30, batch=64, lr=1e-3, seed=0)
+    t_train = time.perf_counter() - t0
+    res = {}
+    for pred in (rt.RT_PRED_LINEAR, rt.RT_PRED_MLP):
+        ses = rt.Session([sa], ra((2,), (1.5e-3,), n_eval, pred=pred,
+                                  params=params if pred == rt.RT_PRED_MLP else None))
+        rt.rt_step(ses.ctx, 8, n_traj=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = rt.rt_step(ses.ctx, n_eval - 8, n_traj=1, stats=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        mu = rt.rt_dipole(ses.ctx, 0, 0, n_eval + 1)[0]
+        ses.close()
+        res[pred] = (mu, float(np.mean([x[0] for x in st])), 1e3 * el / (n_eval - 8))
+    mu_l, m_l, ms_l = res[rt.RT_PRED_LINEAR]
+    mu_m, m_m, ms_m = res[rt.RT_PRED_MLP]
+    return {"workload": f"96^3 N=240 mixed, dt {dt}, H_thrs {h_thrs:g}; trained on x/y kicks (kappa 1e-3, 2e-3), "
+                        f"{n_rec} recorded steps each; evaluated on a held-out z kick (kappa 1.5e-3), {n_eval} steps",
+            "samples": int(X.shape[0]), "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+            "record_s": round(t_rec, 2), "train_s": round(t_train, 2),
+            "updates_per_step_linear": m_l, "updates_per_step_learned": m_m,
+            "ms_per_step_linear": ms_l, "ms_per_step_learned": ms_m,
+            "dipole_max_diff_learned_vs_linear": float(np.max(np.abs(mu_m - mu_l))),
+            "dipole_max_abs": float(np.max(np.abs(mu_l - mu_l[0])))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +364,8 @@ def main():
     ap.add_argument("--no-ground-state", action="store_true", help="skip the GPU ground-state leg")
     ap.add_argument("--only-ground-state", action="store_true",
                     help="run only the GPU ground-state leg (for profiling it on its own)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-predictor leg")
+    ap.add_argument("--only-learned", action="store_true", help="run only the learned-predictor leg")
     args = ap.parse_args()
     if args.h_thrs not in args.sweep:
         args.sweep = sorted(set(args.sweep) | {args.h_thrs}, reverse=True)
@@ -340,6 +391,10 @@ def main():
     sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
                        n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
                        nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images, orthonormalize=True)
+    if args.only_learned:
+        log("learned predictor: record, train, evaluate")
+        print(json.dumps({"learned_predictor_96": learned_predictor(rt, torch, sa, s)}), flush=True)
+        return
     log("reference: FP64, tight thresholds (1e-12, 1e-15)")
     ref = run_leg(rt, torch, sa, s, args, rt.RT_FP64, rt.RT_HUPDATE_FULL, 1e-12, 1e-15, False)
     ref["ses"].close()
@@ -478,6 +533,9 @@ def main():
     if not args.no_batch:
         log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")
         out["batched_16_molecules"] = batched_molecules(rt, torch, args.steps, args.warmup)
+    if not args.no_learned:
+        log("learned predictor: record, train, evaluate")
+        out["learned_predictor_96"] = learned_predictor(rt, torch, sa, s)
     if not args.no_ground_state:
         log("ground states of the 16 batch molecules on the GPU")
         out["ground_state_16_molecules"] = ground_states(rt, torch)

@@ -67,8 +67,47 @@ __global__ __launch_bounds__(256) void k_gemm_f32(int M, int N, int K, float alp
     }
 }
 
+// Few rows (M <= kGemvRows, e.g. the network evaluated for a handful of
+// trajectories): one wave per output column j, the lanes striding K (contiguous
+// for the weight matrices), all M rows accumulated together, then a fixed
+// shuffle tree.  The tiled kernel above would run a few blocks with the whole K
+// loop each.
+constexpr int kGemvRows = 8;
+
+__global__ __launch_bounds__(256) void k_gemv_f32(int M, int N, int K, float alpha, const float* __restrict__ A,
+                                                  long sai, long sak, const float* __restrict__ B, long sbk,
+                                                  long sbj, float beta, float* __restrict__ C, long ldc,
+                                                  const float* __restrict__ bias) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= N) return;
+  float acc[kGemvRows];
+#pragma unroll
+  for (int i = 0; i < kGemvRows; ++i) acc[i] = 0.f;
+  for (int k = lane; k < K; k += 64) {
+    const float b = B[k * sbk + j * sbj];
+#pragma unroll
+    for (int i = 0; i < kGemvRows; ++i)
+      if (i < M) acc[i] += A[i * sai + k * sak] * b;
+  }
+#pragma unroll
+  for (int i = 0; i < kGemvRows; ++i)
+    for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_xor(acc[i], o);
+  if (lane == 0)
+    for (int i = 0; i < M && i < kGemvRows; ++i) {
+      float v = alpha * acc[i];
+      if (beta != 0.f) v += beta * C[i * ldc + j];
+      if (bias) v += bias[j];
+      C[i * ldc + j] = v;
+    }
+}
+
 hipError_t gemm_f32(hipStream_t s, int M, int N, int K, float alpha, const float* A, long sai, long sak,
                     const float* B, long sbk, long sbj, float beta, float* C, long ldc, const float* bias) {
+  if (M <= kGemvRows) {
+    hipLaunchKernelGGL(k_gemv_f32, dim3(cdivl(N, 4)), dim3(256), 0, s, M, N, K, alpha, A, sai, sak, B, sbk, sbj,
+                       beta, C, ldc, bias);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_gemm_f32, dim3(cdivl(N, 64), cdivl(M, 64)), dim3(256), 0, s, M, N, K, alpha, A, sai, sak,
                      B, sbk, sbj, beta, C, ldc, bias);
   return hipGetLastError();
