@@ -30,9 +30,11 @@ hipError_t jacobi_sort(hipStream_t s, const double* A, const double* V, int n, i
                        double* vecs, int* rank);
 
 // ---- block kernels of the subspace iteration ----------------------------------------
-// res[i] = sqrt(h3 sum_r (HX[i][r] - ev[i] X[i][r])^2), one block per row
+// res[i] = sqrt(h3 sum_r (HX[i][r] - ev[i] X[i][r])^2); part: scratch
+// [n][row_residual_parts()] of per-block partial sums (fixed combination order)
+int row_residual_parts();
 hipError_t row_residuals(hipStream_t s, const double* HX, const double* X, const double* ev, int n, long ng,
-                         double h3, double* res);
+                         double h3, double* res, double* part);
 // rho[r] = sum_{i < n} occ[i] X[i][r]^2 (rows in order)
 hipError_t occ_density(hipStream_t s, const double* X, const double* occ, int n, long ng, double* rho);
 // slot = max_r |v[r]| (slot zeroed beforehand; bits of a non-negative double)

@@ -246,12 +246,17 @@ __global__ __launch_bounds__(1024) void k_jacobi_small(double* __restrict__ Ag, 
   }
 }
 
-// L = chol(A) (lower) in LDS, then Linv = L^-1 (one column per thread, forward
-// substitution reading L from LDS) for n <= kSmallLd; info = first failing column + 1.
-__global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restrict__ Ag, double* __restrict__ Linv,
-                                                         int n, int* info) {
-  __shared__ double L[kSmallLd * kSmallLd];
+// L = chol(A) (lower) in LDS, then Linv = L^-1 by forward substitution, one
+// column per thread, for n <= kSmallLd; info = first failing column + 1.  For
+// 2 n^2 <= kSmallLd^2 the inverse is built in LDS next to L and copied out at
+// the end, otherwise in global memory.
+__global__ __launch_bounds__(256) void k_chol_inv_small(const double* __restrict__ Ag, double* __restrict__ Linv,
+                                                        int n, int* info) {
+  __shared__ double sm[kSmallLd * kSmallLd];
   __shared__ double djj;
+  double* const L = sm;
+  const bool lds_x = 2 * n * n <= kSmallLd * kSmallLd;
+  double* const X = lds_x ? sm + n * n : Linv;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < n * n; e += nt) L[e] = Ag[e];
   if (tid == 0) *info = 0;
@@ -281,12 +286,16 @@ __global__ __launch_bounds__(1024) void k_chol_inv_small(const double* __restric
     __syncthreads();
   }
   for (int c = tid; c < n; c += nt) {
-    for (int i = 0; i < c; ++i) Linv[(long)i * n + c] = 0.0;
+    for (int i = 0; i < c; ++i) X[i * n + c] = 0.0;
     for (int i = c; i < n; ++i) {
       double t = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) t -= L[i * n + k] * Linv[(long)k * n + c];
-      Linv[(long)i * n + c] = t / L[i * n + i];
+      for (int k = c; k < i; ++k) t -= L[i * n + k] * X[k * n + c];
+      X[i * n + c] = t / L[i * n + i];
     }
+  }
+  if (lds_x) {
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nt) Linv[e] = X[e];
   }
 }
 
@@ -332,21 +341,34 @@ __global__ void k_jacobi_perm(const double* __restrict__ V, int n, int ld, const
 // ---------------------------------------------------------------------------
 // Block kernels
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_row_residuals(const double* __restrict__ HX, const double* __restrict__ X,
-                                                       const double* __restrict__ ev, long ng, double h3,
-                                                       double* __restrict__ res) {
+// res[i] = sqrt(h3 sum_r (HX[i][r] - ev[i] X[i][r])^2): kResChunks blocks per row
+// write partial sums, then one thread per row adds them in order.
+constexpr int kResChunks = 16;
+
+__global__ __launch_bounds__(256) void k_row_residual_parts(const double* __restrict__ HX,
+                                                            const double* __restrict__ X,
+                                                            const double* __restrict__ ev, long ng,
+                                                            double* __restrict__ part) {
   __shared__ double sh[256];
-  const int i = blockIdx.x;
+  const int i = blockIdx.x, ch = blockIdx.y;
   const double l = ev[i];
   const double* hx = HX + (long)i * ng;
   const double* x = X + (long)i * ng;
   double acc = 0.0;
-  for (long r = threadIdx.x; r < ng; r += 256) {
+  for (long r = (long)ch * 256 + threadIdx.x; r < ng; r += (long)kResChunks * 256) {
     const double d = hx[r] - l * x[r];
     acc += d * d;
   }
   acc = gs_block_sum(acc, sh);
-  if (threadIdx.x == 0) res[i] = sqrt(h3 * acc);
+  if (threadIdx.x == 0) part[(long)i * kResChunks + ch] = acc;
+}
+
+__global__ void k_row_residual_final(const double* __restrict__ part, int n, double h3, double* __restrict__ res) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int c = 0; c < kResChunks; ++c) a += part[(long)i * kResChunks + c];
+  res[i] = sqrt(h3 * a);
 }
 
 __global__ void k_occ_density(const double* __restrict__ X, const double* __restrict__ occ, int n, long ng,
@@ -525,7 +547,7 @@ hipError_t jacobi_small(hipStream_t s, double* A, double* V, int ld, int max_swe
 
 hipError_t chol_inv_small(hipStream_t s, const double* A, double* Linv, int n, int* info) {
   if (n > kSmallLd || n < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(1024), 0, s, A, Linv, n, info);
+  hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(256), 0, s, A, Linv, n, info);
   return hipGetLastError();
 }
 
@@ -541,10 +563,13 @@ hipError_t jacobi_sort(hipStream_t s, const double* A, const double* V, int n, i
   return hipGetLastError();
 }
 
+int row_residual_parts() { return kResChunks; }
+
 hipError_t row_residuals(hipStream_t s, const double* HX, const double* X, const double* ev, int n, long ng,
-                         double h3, double* res) {
+                         double h3, double* res, double* part) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_residuals, dim3(n), dim3(256), 0, s, HX, X, ev, ng, h3, res);
+  hipLaunchKernelGGL(k_row_residual_parts, dim3(n, kResChunks), dim3(256), 0, s, HX, X, ev, ng, part);
+  hipLaunchKernelGGL(k_row_residual_final, dim3(gs_cdiv(n, 256)), dim3(256), 0, s, part, n, h3, res);
   return hipGetLastError();
 }
 

@@ -1401,6 +1401,7 @@ struct GsDev {
   double* blk[3] = {nullptr, nullptr, nullptr};  // orbital blocks [nb][ng]
   double *Hs = nullptr, *vecs = nullptr, *evals = nullptr, *res = nullptr, *occ = nullptr;
   double *rho_out = nullptr, *hin = nullptr, *hres = nullptr, *Bp = nullptr, *coef = nullptr, *dpart = nullptr;
+  double* rpart = nullptr;  // residual partial sums [nb][row_residual_parts()]
   unsigned long long* slot = nullptr;
   EighWork eig;
   int depth = 1;
@@ -1441,6 +1442,7 @@ void layout_gs(Arena& a, SysDev& d, GsDev& g) {
   g.vecs = a.take<double>(NN);
   g.evals = a.take<double>(nb);
   g.res = a.take<double>(nb);
+  g.rpart = a.take<double>(nb * rtk::row_residual_parts());
   g.occ = a.take<double>(nb);
   g.rho_out = a.take<double>(ng);
   g.hin = a.take<double>(g.depth * ng);
@@ -1597,7 +1599,7 @@ struct GsRun {
     ++eighs;
     CK(rtk::smalltall_f64(st, nb, d.ng, g.vecs, g.blk[i], g.blk[j], 0, 0, 1, nullptr));  // X
     CK(rtk::smalltall_f64(st, nb, d.ng, g.vecs, g.blk[k], g.blk[i], 0, 0, 1, nullptr));  // H X
-    CK(rtk::row_residuals(st, g.blk[i], g.blk[j], g.evals, nb, d.ng, d.h3, g.res));
+    CK(rtk::row_residuals(st, g.blk[i], g.blk[j], g.evals, nb, d.ng, d.h3, g.res, g.rpart));
     ev.resize(nb);
     res.resize(nb);
     CK(hipMemcpyAsync(ev.data(), g.evals, nb * 8, hipMemcpyDeviceToHost, st));
