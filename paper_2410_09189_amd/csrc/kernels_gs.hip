@@ -461,14 +461,24 @@ __global__ __launch_bounds__(256) void k_pulay_dots(const double* __restrict__ r
   if (threadIdx.x == 0) part[(long)k * kDotBlocks + b] = acc;
 }
 
-__global__ void k_pulay_solve(const double* __restrict__ part, int m, int snew, int depth, double* __restrict__ B,
-                              double* __restrict__ coef) {
+// One wave per stored residual sums its kDotBlocks partial dot products (fixed
+// lane order and shuffle tree), then one thread solves the small system.
+__global__ __launch_bounds__(64 * kMaxDepth) void k_pulay_solve(const double* __restrict__ part, int m, int snew,
+                                                                int depth, double* __restrict__ B,
+                                                                double* __restrict__ coef) {
+  __shared__ double dk[kMaxDepth];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (w < m) {
+    double d = 0.0;
+    for (int b = lane; b < kDotBlocks; b += 64) d += part[(long)w * kDotBlocks + b];
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+    if (lane == 0) dk[w] = d;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   for (int k = 0; k < m; ++k) {
-    double d = 0.0;
-    for (int b = 0; b < kDotBlocks; ++b) d += part[(long)k * kDotBlocks + b];
-    B[k * depth + snew] = d;
-    B[snew * depth + k] = d;
+    B[k * depth + snew] = dk[k];
+    B[snew * depth + k] = dk[k];
   }
   // bordered system [B 1; 1^T 0] [c; lambda] = [0; 1]
   const int n = m + 1;
@@ -603,7 +613,7 @@ hipError_t pulay_dots(hipStream_t s, const double* res, int m, int snew, long ng
 
 hipError_t pulay_solve(hipStream_t s, const double* part, int m, int snew, int depth, double* B, double* coef) {
   if (m < 1 || m > kMaxDepth || depth > kMaxDepth || snew >= m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pulay_solve, dim3(1), dim3(64), 0, s, part, m, snew, depth, B, coef);
+  hipLaunchKernelGGL(k_pulay_solve, dim3(1), dim3(64 * kMaxDepth), 0, s, part, m, snew, depth, B, coef);
   return hipGetLastError();
 }
 
