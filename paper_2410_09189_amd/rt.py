@@ -195,6 +195,20 @@ class RunArgs:
         self.struct = r
 
 
+def _check_psi_rows(system, rows):
+    """The library copies rows * ng doubles from psi0; a shorter array would be read
+    past its end (on the device that is a memory fault), so refuse it here."""
+    s = system.struct
+    need = rows * s.n[0] * s.n[1] * s.n[2]
+    a = system.psi0
+    have = a.size if isinstance(a, np.ndarray) else a.numel()
+    dtype_ok = a.dtype == np.float64 if isinstance(a, np.ndarray) else str(a.dtype) == "torch.float64"
+    if have != need or not dtype_ok:
+        raise ValueError(f"psi0 must hold {rows} x {need // max(rows, 1)} float64 values, got {have} ({a.dtype})")
+    if not isinstance(a, np.ndarray) and not a.is_contiguous():
+        raise ValueError("psi0 must be contiguous")
+
+
 def rt_workspace_size(systems, run) -> int:
     arr = (rt_system * len(systems))(*[s.struct for s in systems])
     out = ctypes.c_size_t(0)
@@ -203,6 +217,8 @@ def rt_workspace_size(systems, run) -> int:
 
 
 def rt_init(systems, run, workspace_ptr: int, ws_bytes: int, stream_ptr: int):
+    for sy in systems:
+        _check_psi_rows(sy, sy.struct.n_occ + sy.struct.n_virt)
     arr = (rt_system * len(systems))(*[s.struct for s in systems])
     ctx = ctypes.c_void_p(None)
     _check(lib.rt_init(arr, len(systems), ctypes.byref(run.struct), ctypes.c_void_p(workspace_ptr),
@@ -338,6 +354,8 @@ def rt_ground_state(system, params, workspace_ptr, ws_bytes, stream_ptr, psi_out
     """Runs the solve; returns (Ritz values [N + n_guard], stats dict).  On a
     failure the RTError carries .eps and .stats of the last iterate."""
     n = system.struct.n_occ + system.struct.n_virt + params.n_guard
+    rt_ground_state_workspace_size(system, params)  # parameter errors first (RT_EINVAL)
+    _check_psi_rows(system, n)
     eps = np.zeros(n)
     st = rt_gs_stats()
     status = lib.rt_ground_state(ctypes.byref(system.struct), ctypes.byref(params), ctypes.c_void_p(workspace_ptr),
@@ -374,6 +392,7 @@ def ground_state(system, params, device="cuda"):
     ng = s.n[0] * s.n[1] * s.n[2]
     N = s.n_occ + s.n_virt
     ws_bytes = rt_ground_state_workspace_size(system, params)
+    _check_psi_rows(system, N + params.n_guard)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
     psi = torch.empty((N, ng), dtype=torch.float64, device=device)
     rho = torch.empty(ng, dtype=torch.float64, device=device)

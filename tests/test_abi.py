@@ -145,3 +145,23 @@ def test_ground_state_and_eigh_reject_bad_arguments_without_a_gpu():
     with pytest.raises(rt.RTError) as e:
         rt.rt_eigh(0, 8, 0, 0, 0, 0, 1 << 20)
     assert e.value.status == rt.RT_EINVAL
+
+
+def test_binding_refuses_orbital_arrays_of_the_wrong_size():
+    """The library reads N (rt_init) or N + n_guard (rt_ground_state) orbitals from
+    psi0; the binding refuses shorter or wrongly typed arrays before any device work."""
+    import synth
+    from paper_2410_09189_amd import rt
+    from rt_helpers import run_args, system_args
+
+    s = synth.make_system(16, 0.4, 2, 2, 2, seed=1, nl_rank=4, region=(0.3, 0.7))
+    short = synth.lowpass_orbitals(16, 0.4, 3, 1)  # N = 4 needed
+    with pytest.raises(ValueError):
+        rt.rt_init([system_args(s, short)], run_args(synth.RunParams(dt=0.05, n_steps=2)), 0, 0, 0)
+    exact = synth.lowpass_orbitals(16, 0.4, 4, 1)  # N rows, but the ground state needs N + n_guard
+    with pytest.raises(ValueError):
+        rt.ground_state(system_args(s, exact), rt.gs_params(n_guard=6))
+    sa = system_args(s, exact)
+    sa.psi0 = exact.astype(np.float32)
+    with pytest.raises(ValueError):
+        rt.rt_init([sa], run_args(synth.RunParams(dt=0.05, n_steps=2)), 0, 0, 0)
