@@ -27,7 +27,9 @@ Sweep legs run without phase timers; the phase breakdown and roofline come from
 separate runs at the paper's threshold.
 
 Also reported (not part of `value`): the 16-molecule ragged batch stepped in one
-context, and the GPU ground-state solve of those 16 molecules.
+context, the learned first guess on this molecule, the FP32 H apply at the
+192^3 x 3000-orbital nanoparticle shape, and the GPU ground-state solve of the
+16 batch molecules.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -301,6 +303,47 @@ def ground_states(rt, torch):
             "molecules": rows}
 
 
+def apply_h_192(rt, torch, n_orb=3000, reps=3):
+    """Stencil roofline at the nanoparticle shape: the grid Hamiltonian (FD8 +
+    V_loc; this molecule has local wells only) applied in FP32 to 3000 orbitals
+    of the 192^3 grid, 85 GB in and 85 GB out, through rt_apply_h of a context
+    built on 64 random orthonormalised orbitals of that molecule.  Inputs are
+    seeded device-side random numbers (the time of an apply does not depend on
+    the values)."""
+    import synth
+
+    s = synth.config_system("c5_cluster_192")
+    ng = s.ng
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(s.seed)
+    psi0 = torch.randn((64, ng), dtype=torch.float64, device="cuda", generator=gen)
+    sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=32, n_virt=32, psi0=psi0,
+                       n_images=s.n_images, orthonormalize=True)
+    ra = rt.RunArgs(dt=0.05, n_steps_max=1, h_thrs=1e-7, dp_thrs=1e-10, max_scf=50, max_terms=200, traj_sys=[],
+                    traj_kappa=[], traj_axis=[], hupdate=rt.RT_HUPDATE_LOCAL)
+    ses = rt.Session([sa], ra)
+    del psi0
+    x = torch.randn((n_orb, ng), dtype=torch.float32, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), n_orb, 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), n_orb, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ses.close()
+    del x, y
+    nbytes = 8.0 * n_orb * ng + 4.0 * ng * ((n_orb + 63) // 64)
+    return {"workload": f"192^3 grid (h 0.3), 600-well fcc cluster, FP32 H apply of {n_orb} orbitals "
+                        "(stencil + V_loc) through rt_apply_h",
+            "ms_per_apply": ms, "orbital_gridpoints_per_s": n_orb * ng / (ms * 1e-3),
+            "hbm_GBps_algorithmic": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": nbytes / (ms * 1e-3) / 8e12,
+            "algorithmic_bytes": nbytes}
+
+
 def learned_predictor(rt, torch, sa, s):
     """The learned first guess on the 96^3 molecule (mixed precision): training
     samples recorded by the step itself on x and y kicks of two strengths, the
@@ -365,6 +408,8 @@ def main():
     ap.add_argument("--only-ground-state", action="store_true",
                     help="run only the GPU ground-state leg (for profiling it on its own)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-predictor leg")
+    ap.add_argument("--no-192", action="store_true", help="skip the 192^3 x 3000-orbital FP32 apply leg")
+    ap.add_argument("--only-192", action="store_true", help="run only the 192^3 apply leg")
     ap.add_argument("--only-learned", action="store_true", help="run only the learned-predictor leg")
     args = ap.parse_args()
     if args.h_thrs not in args.sweep:
@@ -379,6 +424,10 @@ def main():
     import synth
     from paper_2410_09189_amd import rt
 
+    if args.only_192:
+        log("FP32 H apply, 192^3 x 3000 orbitals")
+        print(json.dumps({"apply_h_192": apply_h_192(rt, torch)}), flush=True)
+        return
     if args.only_ground_state:
         log("ground states of the 16 batch molecules on the GPU")
         print(json.dumps({"ground_state_16_molecules": ground_states(rt, torch)}), flush=True)
@@ -533,6 +582,9 @@ def main():
     if not args.no_batch:
         log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")
         out["batched_16_molecules"] = batched_molecules(rt, torch, args.steps, args.warmup)
+    if not args.no_192:
+        log("FP32 H apply, 192^3 x 3000 orbitals")
+        out["apply_h_192"] = apply_h_192(rt, torch)
     if not args.no_learned:
         log("learned predictor: record, train, evaluate")
         out["learned_predictor_96"] = learned_predictor(rt, torch, sa, s)

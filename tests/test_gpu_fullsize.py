@@ -144,3 +144,41 @@ def test_full_size_step_matches_oracle(mode):
             assert rerr < (MIXED_REL if mode == "mixed" else 1e-9) * drho + 1e-13 * np.max(rho_gs)
     assert g["stats"][0][0] >= 1 and all(st[0] <= 50 for st in g["stats"])
     assert ng == 96 ** 3 and N == 240
+
+
+def test_nanoparticle_shape_fp32_apply_sampled_against_oracle():
+    """The 192^3 x 3000-orbital FP32 apply the benchmark times (85 GB in, 85 GB out,
+    the chunking over the context's 64-orbital block included): three sampled
+    orbitals against the oracle's FD8 stencil + V_loc in FP64."""
+    import torch
+
+    from paper_2410_09189_amd import rt
+
+    _say("192^3 x 3000 orbitals FP32 apply, sampled")
+    s = synth.config_system("c5_cluster_192")
+    ng = s.ng
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(s.seed)
+    psi0 = torch.randn((64, ng), dtype=torch.float64, device="cuda", generator=gen)
+    sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=32, n_virt=32, psi0=psi0,
+                       n_images=s.n_images, orthonormalize=True)
+    ra = rt.RunArgs(dt=0.05, n_steps_max=1, h_thrs=1e-7, dp_thrs=1e-10, max_scf=50, max_terms=200, traj_sys=[],
+                    traj_kappa=[], traj_axis=[], hupdate=rt.RT_HUPDATE_LOCAL)
+    ses = rt.Session([sa], ra)
+    del psi0
+    n_orb = 3000
+    x = torch.randn((n_orb, ng), dtype=torch.float32, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), n_orb, 1)
+    torch.cuda.synchronize()
+    vloc = rt.rt_get_grid(ses.ctx, 0, 4, ng)
+    ses.close()
+    coeffs = fd_coefficients_float(4)
+    nx, ny, nz = s.n
+    for j in (0, 1777, 2999):
+        xj = x[j].double().cpu().numpy()
+        ref = (-0.5 * laplacian(xj.reshape(nz, ny, nx), s.h, coeffs)).ravel() + vloc * xj
+        got = y[j].double().cpu().numpy()
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"orbital {j}: rel err {err:.2e}", flush=True)
+        assert err < 1e-5
