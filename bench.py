@@ -27,7 +27,8 @@ Sweep legs run without phase timers; the phase breakdown and roofline come from
 separate runs at the paper's threshold.
 
 Also reported (not part of `value`): the 16-molecule ragged batch stepped in one
-context, the learned first guess on this molecule, the FP32 H apply at the
+context, the non-orthogonal / fourth-order Magnus / pulse variants and the
+learned first guess on this molecule, the FP32 H apply at the
 192^3 x 3000-orbital nanoparticle shape, and the GPU ground-state solve of the
 16 batch molecules.
 
@@ -303,6 +304,45 @@ def ground_states(rt, torch):
             "molecules": rows}
 
 
+def variants(rt, torch, s, psi, args):
+    """The ranked extensions on the 96^3 workload, mixed precision, three
+    trajectories, H_thrs 1e-7, timed like the main legs: the non-orthogonal
+    basis (the smooth random orbitals taken as they are, overlap S != I),
+    fourth-order Magnus (Omega_2 in every series term), and sin^2 pulses along
+    x, y, z instead of kicks (a 1e-3, omega 0.4, tau 10).  Each against the
+    plain mixed step on the same workload."""
+    T = len(AXES)
+    total = args.warmup + args.steps
+    out = {}
+    cases = (("mixed_kick", False, {}, [1e-3] * T, None),
+             ("nonorthogonal_basis", True, {}, [1e-3] * T, None),
+             ("magnus_order_4", False, {"magnus_order": 4}, [1e-3] * T, None),
+             ("pulse_fields", False, {}, [0.0] * T,
+              [[1e-3, 0.4, 10.0, 0.0] + [1.0 if q == a else 0.0 for q in range(3)] for a in AXES]))
+    for name, nonorth, extra, kappas, field in cases:
+        sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
+                           n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut, nl_sigma=s.nl_sigma,
+                           nl_D=s.nl_D, n_images=s.n_images, orthonormalize=not nonorth, nonorthogonal=nonorth)
+        ra = rt.RunArgs(dt=0.05, n_steps_max=total, h_thrs=args.h_thrs, dp_thrs=args.dp_thrs, max_scf=50,
+                        max_terms=200, traj_sys=[0] * T, traj_kappa=kappas, traj_axis=list(AXES),
+                        precision=rt.RT_MIXED, hupdate=rt.RT_HUPDATE_LOCAL, traj_field=field, **extra)
+        ses = rt.Session([sa], ra)
+        rt.rt_step(ses.ctx, args.warmup, n_traj=T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = rt.rt_step(ses.ctx, args.steps, n_traj=T, stats=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ses.close()
+        out[name] = {"steps_per_s": args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                     "mean_scf_updates_per_step": float(np.mean([x[0] for x in st])),
+                     "mean_series_terms_per_update": float(sum(x[1] for x in st) / max(1, sum(x[0] for x in st)))}
+    base = out["mixed_kick"]["steps_per_s"]
+    for v in out.values():
+        v["relative_to_mixed_kick"] = v["steps_per_s"] / base
+    return out
+
+
 def apply_h_192(rt, torch, n_orb=3000, reps=3):
     """Stencil roofline at the nanoparticle shape: the grid Hamiltonian (FD8 +
     V_loc; this molecule has local wells only) applied in FP32 to 3000 orbitals
@@ -409,6 +449,9 @@ def main():
                     help="run only the GPU ground-state leg (for profiling it on its own)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-predictor leg")
     ap.add_argument("--no-192", action="store_true", help="skip the 192^3 x 3000-orbital FP32 apply leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the non-orthogonal / fourth-order Magnus / pulse legs")
+    ap.add_argument("--only-variants", action="store_true", help="run only those legs")
     ap.add_argument("--only-192", action="store_true", help="run only the 192^3 apply leg")
     ap.add_argument("--only-learned", action="store_true", help="run only the learned-predictor leg")
     args = ap.parse_args()
@@ -440,6 +483,10 @@ def main():
     sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
                        n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
                        nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images, orthonormalize=True)
+    if args.only_variants:
+        log("variants: non-orthogonal basis, fourth-order Magnus, pulses")
+        print(json.dumps({"variants_96": variants(rt, torch, s, psi, args)}), flush=True)
+        return
     if args.only_learned:
         log("learned predictor: record, train, evaluate")
         print(json.dumps({"learned_predictor_96": learned_predictor(rt, torch, sa, s)}), flush=True)
@@ -582,6 +629,9 @@ def main():
     if not args.no_batch:
         log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")
         out["batched_16_molecules"] = batched_molecules(rt, torch, args.steps, args.warmup)
+    if not args.no_variants:
+        log("variants: non-orthogonal basis, fourth-order Magnus, pulses")
+        out["variants_96"] = variants(rt, torch, s, psi, args)
     if not args.no_192:
         log("FP32 H apply, 192^3 x 3000 orbitals")
         out["apply_h_192"] = apply_h_192(rt, torch)
