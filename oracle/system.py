@@ -46,6 +46,12 @@ def min_image(d: np.ndarray, L: float) -> np.ndarray:
     return d - L * np.round(d / L)
 
 
+def radial_profile(s2: np.ndarray, sigma: float, rcut: float) -> np.ndarray:
+    """Unnormalised radial factor g(s) = exp(-s^2 / (2 sigma^2)) (1 - s^2/r_c^2)^2
+    of the projectors, given s^2 (valid for s < r_c; zero value and slope at r_c)."""
+    return np.exp(-s2 / (2 * sigma ** 2)) * (1.0 - s2 / rcut ** 2) ** 2
+
+
 def projectors(sys):
     """Per-atom projector tables: list of (flat grid indices, beta[n_sph, rank], D[rank]).
 
@@ -62,7 +68,7 @@ def projectors(sys):
         mask = s2 < sys.nl_rcut ** 2
         idx = np.flatnonzero(mask.ravel())
         s2m = s2.ravel()[idx]
-        g = np.exp(-s2m / (2 * sys.nl_sigma ** 2)) * (1.0 - s2m / sys.nl_rcut ** 2) ** 2
+        g = radial_profile(s2m, sys.nl_sigma, sys.nl_rcut)
         cols = [g]
         for q in range(3):
             cols.append(d[q].ravel()[idx] / sys.nl_sigma * g)
