@@ -20,6 +20,17 @@ int density_tile_ld(int N);
 // points; requires ng % 8 == 0, kps % 64 == 0 and 256 ng < 2^31
 hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, const unsigned short* lo,
                        const float* w, float* part, long kps, int n_split, int T, const int* active);
+// The same product for N <= proj_tri_max_n(): one block per (trajectory, split of
+// kps points) computes the whole upper triangle; kps a positive multiple of
+// proj_tri_chunk(), n_split = ceil(ng / kps); part layout as above.  hi/lo are
+// K-blocked ([ceil(ng / TKC)][N][TKC], TKC = proj_tri_chunk(), zero past ng;
+// proj_tri_elems(N, ng) elements each), written by split_bf16_kb.
+int proj_tri_max_n();
+int proj_tri_chunk();
+long proj_tri_elems(int N, long ng);
+hipError_t split_bf16_kb(hipStream_t s, const double* psi, unsigned short* hi, unsigned short* lo, int N, long ng);
+hipError_t proj_tri_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, const unsigned short* lo,
+                           const float* w, float* part, long kps, int n_split, int T, const int* active);
 // C = base + alpha * sum_s part[s] (upper kept, mirrored)
 hipError_t reduce_parts_f32(hipStream_t s, const float* part, int n_split, int N, double alpha,
                             const double* base, double* C, int T, const int* active, long sbase);

@@ -300,6 +300,300 @@ __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// ---------------------------------------------------------------------------
+// Projection for N <= 256 (block grid NB = ceil(N / 32) <= 8).  One block owns
+// one trajectory and one range of grid points and accumulates every 32 x 32 block
+// of the upper triangle with v_mfma_f32_32x32x16_bf16.  The block's eight waves
+// have two roles, one of each on every SIMD:
+//  * four matrix waves: wave W owns block rows W and NB - 1 - W (row r holds
+//    NB - r blocks, so a pair holds NB + 1: at NB = 8 every wave 9 blocks); its
+//    blocks are compile-time parameters of its code, so the accumulators are
+//    indexed statically;
+//  * four staging waves: global loads one chunk ahead, the weighted copy of the
+//    orbitals re-split to bf16 hi/lo, LDS writes.
+// Points pass through LDS TKC at a time, double buffered with one barrier per
+// chunk, so the staging of chunk c + 1 runs beside the matrix work on chunk c.
+// LDS holds the raw orbital hi/lo (A side) and the weighted copy (B side), each
+// 16-byte piece XOR-swizzled by row so fragment reads and staging writes are free
+// of bank conflicts.  Each block covers a long range of points (about one block
+// per CU in one round), so few FP32 partials are written.
+// ---------------------------------------------------------------------------
+constexpr int TKC = 32;       // points per staged chunk
+constexpr int TMW = 4;        // matrix waves
+constexpr int TSW = 4;        // staging waves
+constexpr int TTH = 64 * (TMW + TSW);
+
+// element offset of (row r, 16-byte piece q) in a staged [rows][TKC] bf16 array
+// (the XOR of bits 1 and 2 of the row keeps any 16 consecutive rows of one piece
+// column, a fragment read's quarter wave, on 16 distinct 16-byte bank groups)
+__device__ __forceinline__ int tri_off(int r, int q) { return r * TKC + 8 * (q ^ (((r >> 1) ^ (r >> 2)) & 3)); }
+
+// Matrix wave W: block rows I0 = W and I1 = NB - 1 - W (used when I0 <= I1, the
+// second only when I1 > I0); acc[J - I0] holds (I0, J), acc[NB - W + J - I1]
+// holds (I1, J).
+template <int NB, int W>
+struct TriWave {
+  static constexpr int I0 = W, I1 = NB - 1 - W;
+  static constexpr bool one = I0 <= I1, two = I0 < I1;
+};
+
+template <int NB, int W>
+__device__ __forceinline__ void tri_mfma(f32x16 (&acc)[NB + 1], const unsigned short* __restrict__ sm, int lane) {
+  using TW = TriWave<NB, W>;
+  constexpr int I0 = TW::I0, I1 = TW::I1;
+  constexpr int R = NB * 32 * TKC;  // elements per staged array
+  const unsigned short* sAh = sm;
+  const unsigned short* sAl = sm + R;
+  const unsigned short* sBh = sm + 2 * R;
+  const unsigned short* sBl = sm + 3 * R;
+  const int l32 = lane & 31, hk = lane >> 5;
+#pragma unroll 1
+  for (int st = 0; st < TKC / 16; ++st) {
+    const int q = 2 * st + hk;
+    bf16x8 a0h, a0l, a1h, a1l;
+    a0h = *reinterpret_cast<const bf16x8*>(sAh + tri_off(32 * I0 + l32, q));
+    a0l = *reinterpret_cast<const bf16x8*>(sAl + tri_off(32 * I0 + l32, q));
+    if constexpr (TW::two) {
+      a1h = *reinterpret_cast<const bf16x8*>(sAh + tri_off(32 * I1 + l32, q));
+      a1l = *reinterpret_cast<const bf16x8*>(sAl + tri_off(32 * I1 + l32, q));
+    }
+#pragma unroll
+    for (int J = I0; J < NB; ++J) {
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(sBh + tri_off(32 * J + l32, q));
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(sBl + tri_off(32 * J + l32, q));
+      if constexpr (TW::two) {
+        if (J >= I1) {
+          // two independent accumulation chains interleaved
+          acc[J - I0] = mfma32(a0l, bh, acc[J - I0]);
+          acc[NB - W + J - I1] = mfma32(a1l, bh, acc[NB - W + J - I1]);
+          acc[J - I0] = mfma32(a0h, bl, acc[J - I0]);
+          acc[NB - W + J - I1] = mfma32(a1h, bl, acc[NB - W + J - I1]);
+          acc[J - I0] = mfma32(a0h, bh, acc[J - I0]);
+          acc[NB - W + J - I1] = mfma32(a1h, bh, acc[NB - W + J - I1]);
+          continue;
+        }
+      }
+      acc[J - I0] = mfma32(a0l, bh, acc[J - I0]);
+      acc[J - I0] = mfma32(a0h, bl, acc[J - I0]);
+      acc[J - I0] = mfma32(a0h, bh, acc[J - I0]);
+    }
+  }
+}
+
+template <int NB, int W>
+__device__ __forceinline__ void tri_store(const f32x16 (&acc)[NB + 1], float* __restrict__ P, int N, int lane) {
+  using TW = TriWave<NB, W>;
+  constexpr int I0 = TW::I0, I1 = TW::I1;
+  const int c0 = lane & 31, r0 = 4 * (lane >> 5);
+#pragma unroll
+  for (int J = I0; J < NB; ++J) {
+    const int col = 32 * J + c0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * I0 + 8 * (r >> 2) + r0 + (r & 3);
+      if (row < N && col < N) P[(long)row * N + col] = acc[J - I0][r];
+    }
+  }
+  if constexpr (TW::two) {
+#pragma unroll
+    for (int J = I1; J < NB; ++J) {
+      const int col = 32 * J + c0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * I1 + 8 * (r >> 2) + r0 + (r & 3);
+        if (row < N && col < N) P[(long)row * N + col] = acc[NB - W + J - I1][r];
+      }
+    }
+  }
+}
+
+// Matrix wave: nc chunks, one barrier before the first and one after each (a wave
+// without blocks, at small NB, only takes part in the barriers).
+template <int NB, int W>
+__device__ __forceinline__ void tri_matrix(int N, int nc, unsigned short (*sm)[4 * NB * 32 * TKC],
+                                           float* __restrict__ P) {
+  const int lane = threadIdx.x & 63;
+  f32x16 acc[NB + 1];
+#pragma unroll
+  for (int a = 0; a < NB + 1; ++a)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[a][r] = 0.f;
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    if constexpr (TriWave<NB, W>::one) tri_mfma<NB, W>(acc, sm[c & 1], lane);
+    __syncthreads();
+  }
+  if constexpr (TriWave<NB, W>::one) tri_store<NB, W>(acc, P, N, lane);
+}
+
+// one staging thread's share of a chunk: U pieces of A hi/lo and the 8 weights
+template <int U>
+struct TriRegs {
+  uint4 h[U], l[U], w0, w1;
+};
+
+// Staging waves: the same barrier sequence as the matrix waves.  Chunk c is
+// loaded into registers while the matrix waves work on chunk c - 2 and written
+// to LDS buffer c & 1 while they work on chunk c - 1; its loads are issued once
+// the registers are free (after the previous chunk was written), so each wait
+// covers exactly the loads of the chunk being staged.  (With two register sets in
+// flight the compiler's wait counts serialise the loads of both sets.)
+template <int NB>
+__device__ __forceinline__ void tri_stage(int N, const __amdgpu_buffer_rsrc_t& rAh,
+                                          const __amdgpu_buffer_rsrc_t& rAl, const __amdgpu_buffer_rsrc_t& rW,
+                                          int nc, unsigned short (*sm)[4 * NB * 32 * TKC]) {
+  constexpr int R = NB * 32 * TKC;             // elements per staged array
+  constexpr int PIECES = NB * 32 * TKC / 8;    // 16-byte pieces per staged array
+  constexpr int NS = 64 * TSW;                 // staging threads
+  constexpr int U = (PIECES + NS - 1) / NS;    // pieces per staging thread
+  const int tid = threadIdx.x - 64 * TMW;
+  const int q = tid & 3;  // every piece of this thread sits at piece column q
+  // piece (row r, column q) of chunk c sits at byte (c N + r) 2 TKC + 16 q of the
+  // K-blocked orbitals (rows >= N read zero through an out-of-range offset)
+  int vo[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = tid + NS * u;
+    vo[u] = (e < PIECES && (e >> 2) < N) ? (e >> 2) * 2 * TKC + 16 * q : (int)0x80000000;
+  }
+  const int stride = N * 2 * TKC;  // bytes per chunk of K-blocked orbitals
+  auto fetch = [&](TriRegs<U>& g, int c) {
+    // the chunk offset is uniform (readfirstlane keeps it in a scalar register);
+    // the weights carry it in the vector offset so that points past ng, the
+    // resource's end, read zero
+    const int so = __builtin_amdgcn_readfirstlane(c * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      g.h[u] = buf_ld16(rAh, vo[u], so);
+      g.l[u] = buf_ld16(rAl, vo[u], so);
+    }
+    const int wv = 32 * q + c * 4 * TKC;
+    g.w0 = buf_ld16(rW, wv, 0);
+    g.w1 = buf_ld16(rW, wv + 16, 0);
+  };
+  auto stage = [&](const TriRegs<U>& g, unsigned short* s) {
+    const float w0 = __uint_as_float(g.w0.x), w1 = __uint_as_float(g.w0.y), w2 = __uint_as_float(g.w0.z),
+                w3 = __uint_as_float(g.w0.w), w4 = __uint_as_float(g.w1.x), w5 = __uint_as_float(g.w1.y),
+                w6 = __uint_as_float(g.w1.z), w7 = __uint_as_float(g.w1.w);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + NS * u;
+      if (e >= PIECES) break;
+      const int o = tri_off(e >> 2, q);
+      *reinterpret_cast<uint4*>(s + o) = g.h[u];
+      *reinterpret_cast<uint4*>(s + R + o) = g.l[u];
+      uint4 bh, bl;
+      split_scaled2(g.h[u].x, g.l[u].x, w0, w1, bh.x, bl.x);
+      split_scaled2(g.h[u].y, g.l[u].y, w2, w3, bh.y, bl.y);
+      split_scaled2(g.h[u].z, g.l[u].z, w4, w5, bh.z, bl.z);
+      split_scaled2(g.h[u].w, g.l[u].w, w6, w7, bh.w, bl.w);
+      *reinterpret_cast<uint4*>(s + 2 * R + o) = bh;
+      *reinterpret_cast<uint4*>(s + 3 * R + o) = bl;
+    }
+  };
+  TriRegs<U> g;
+  fetch(g, 0);
+  stage(g, sm[0]);
+  if (nc > 1) fetch(g, 1);
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    // the matrix waves work on buffer c & 1: stage chunk c + 1 into the other one
+    if (c + 1 < nc) {
+      stage(g, sm[(c + 1) & 1]);
+      if (c + 2 < nc) fetch(g, c + 2);
+    }
+    __syncthreads();
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(TTH, 1) void k_proj_tri(int N, long ng, const unsigned short* __restrict__ Ahi,
+                                                     const unsigned short* __restrict__ Alo,
+                                                     const float* __restrict__ w, float* __restrict__ part, long kps,
+                                                     int T, const int* active) {
+  __shared__ __attribute__((aligned(16))) unsigned short sm[2][4 * NB * 32 * TKC];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int tb = (int)(lid % T), sp = (int)(lid / T);
+  if (active && !active[tb]) return;
+  const long k0 = (long)sp * kps;
+  const long k1 = min(ng, k0 + kps);
+  const int nc = (int)((k1 - k0 + TKC - 1) / TKC);
+  float* P = part + ((long)tb * (gridDim.x / T) + sp) * N * N;
+  // every role below runs 1 + nc barriers; the role index is wave-uniform
+  // (readfirstlane), so each wave executes only its own branch
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: tri_matrix<NB, 0>(N, nc, sm, P); break;
+    case 1: tri_matrix<NB, 1>(N, nc, sm, P); break;
+    case 2: tri_matrix<NB, 2>(N, nc, sm, P); break;
+    case 3: tri_matrix<NB, 3>(N, nc, sm, P); break;
+    default: {
+      // K-blocked orbitals from this block's first chunk on
+      const long e0 = k0 / TKC * N * TKC, ne = (ng + TKC - 1) / TKC * N * TKC;
+      const auto rAh = buf_rsrc(Ahi + e0, (int)((ne - e0) * 2));
+      const auto rAl = buf_rsrc(Alo + e0, (int)((ne - e0) * 2));
+      const auto rW = buf_rsrc(w + (long)tb * ng + k0, (int)((ng - k0) * 4));
+      tri_stage<NB>(N, rAh, rAl, rW, nc, sm);
+      break;
+    }
+  }
+}
+
+// K-blocked bf16 hi/lo orbitals for the triangle projection: piece q (8 points)
+// of row r in chunk c (TKC points) at element (c N + r) TKC + 8 q, zero past ng.
+__global__ void k_split_bf16_kb(const double* __restrict__ psi, unsigned short* __restrict__ hi,
+                                unsigned short* __restrict__ lo, int N, long ng, long n_pieces) {
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pieces) return;
+  const int q = (int)(p & 3);
+  const long rc = p >> 2;  // c N + r
+  const long c = rc / N;
+  const int r = (int)(rc - c * N);
+  const long k = c * TKC + 8 * q;
+  unsigned short h[8], l[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double v = k + i < ng ? psi[(long)r * ng + k + i] : 0.0;
+    h[i] = f2bf((float)v);
+    l[i] = f2bf((float)(v - (double)bf2f(h[i])));
+  }
+  uint4 vh, vl;
+  vh.x = h[0] | ((unsigned)h[1] << 16); vh.y = h[2] | ((unsigned)h[3] << 16);
+  vh.z = h[4] | ((unsigned)h[5] << 16); vh.w = h[6] | ((unsigned)h[7] << 16);
+  vl.x = l[0] | ((unsigned)l[1] << 16); vl.y = l[2] | ((unsigned)l[3] << 16);
+  vl.z = l[4] | ((unsigned)l[5] << 16); vl.w = l[6] | ((unsigned)l[7] << 16);
+  *reinterpret_cast<uint4*>(hi + rc * TKC + 8 * q) = vh;
+  *reinterpret_cast<uint4*>(lo + rc * TKC + 8 * q) = vl;
+}
+
+long proj_tri_elems(int N, long ng) { return (ng + TKC - 1) / TKC * N * TKC; }
+
+hipError_t split_bf16_kb(hipStream_t s, const double* psi, unsigned short* hi, unsigned short* lo, int N, long ng) {
+  const long n_pieces = proj_tri_elems(N, ng) / 8;
+  hipLaunchKernelGGL(k_split_bf16_kb, dim3(cdivm(n_pieces, 256)), dim3(256), 0, s, psi, hi, lo, N, ng, n_pieces);
+  return hipGetLastError();
+}
+
+int proj_tri_max_n() { return 256; }
+int proj_tri_chunk() { return TKC; }
+
+hipError_t proj_tri_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, const unsigned short* lo,
+                           const float* w, float* part, long kps, int n_split, int T, const int* active) {
+  if (N < 1 || N > 256 || 2 * proj_tri_elems(N, ng) >= (1L << 31) || 4 * ng >= (1L << 31) || kps % TKC || kps < TKC || n_split < 1 ||
+      (long)(n_split - 1) * kps >= ng || (long)n_split * kps < ng)
+    return hipErrorInvalidValue;
+  const dim3 grid(T * n_split), blk(TTH);
+  switch ((N + 31) / 32) {
+#define RT_TRI_NB(nb)                                                                                            \
+  case nb:                                                                                                       \
+    hipLaunchKernelGGL(k_proj_tri<nb>, grid, blk, 0, s, N, ng, hi, lo, w, part, kps, T, active);                \
+    break;
+    RT_TRI_NB(1) RT_TRI_NB(2) RT_TRI_NB(3) RT_TRI_NB(4) RT_TRI_NB(5) RT_TRI_NB(6) RT_TRI_NB(7) RT_TRI_NB(8)
+#undef RT_TRI_NB
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t proj_bf16x3(hipStream_t s, int N, long ng, const unsigned short* hi, const unsigned short* lo,
                        const float* w, float* part, long kps, int n_split, int T, const int* active) {
   if (ng % 8 || 256 * ng >= (1L << 31) || kps % XK) return hipErrorInvalidValue;

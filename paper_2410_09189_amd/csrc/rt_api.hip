@@ -511,6 +511,22 @@ void choose_split(SysDev& d) {
   d.n_split_x = (int)((d.ng + kx - 1) / kx);
 }
 
+// BF16x3 projection for N <= 256 (whole upper triangle per block, one block per
+// CU): 85 splits of the grid, so three trajectories fill the 256 CUs of an MI355X
+// in one round; each split at least four staged chunks long.  The split does not
+// depend on the number of trajectories, so a trajectory's partial sums, and with
+// them its results, are the same batched or alone.
+constexpr int kProjTriSplits = 85;
+void choose_split_tri(SysDev& d) {
+  if (d.N > rtk::proj_tri_max_n()) return;
+  const long ck = rtk::proj_tri_chunk();
+  long ns = std::min((long)kProjTriSplits, std::max(1L, d.ng / (4 * ck)));
+  long kx = (d.ng + ns - 1) / ns;
+  kx = (kx + ck - 1) / ck * ck;
+  d.kps_x = kx;
+  d.n_split_x = (int)((d.ng + kx - 1) / kx);
+}
+
 // Places every buffer; with a.base == nullptr only sizes.
 void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
   for (auto& d : S) {
@@ -558,8 +574,10 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.W = a.take<double>(T * NN);
     d.part = a.take<double>(T * d.n_split * NN);
     if (d.mixed) {
-      d.psi_hi = a.take<unsigned short>(N * ng);
-      d.psi_lo = a.take<unsigned short>(N * ng);
+      // N <= 256: K-blocked for the triangle projection; else orbital-major [N][ng]
+      const long npsi = d.N <= rtk::proj_tri_max_n() ? rtk::proj_tri_elems(d.N, ng) : N * ng;
+      d.psi_hi = a.take<unsigned short>(npsi);
+      d.psi_lo = a.take<unsigned short>(npsi);
       d.wld = rtk::density_tile_ld(d.N);
       const long WW = (long)d.wld * d.wld;
       d.w_hi = a.take<unsigned short>(T * WW);
@@ -659,6 +677,7 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
   for (auto& d : S) {
     if (d.slot_traj.empty()) d.slot_traj.push_back(-1);
     d.T = (int)d.slot_traj.size();
+    choose_split_tri(d);
     d.active_host.assign(d.T, 1);
     d.zeros2T.assign(2 * d.T, 0);
     d.mlp_on.assign(d.T, d.mlp ? 1 : 0);
@@ -747,6 +766,13 @@ rt_status poisson_lda(rt_ctx* c, SysDev& d, int T, const int* act) {
 // Hout_t = H[P_t] for the T' slots (S_t real parts with stride sstride, Hout stride N^2).
 // act: device flags (nullable = all T); act_host mirrors them.  mode_full forces the
 // FP64 full apply (ground-state build).
+// BF16x3 weighted projection of the orbitals against d.dv32 into d.part32
+hipError_t proj_x(hipStream_t s, const SysDev& d, int T, const int* act) {
+  if (d.N <= rtk::proj_tri_max_n())
+    return rtk::proj_tri_bf16x3(s, d.N, d.ng, d.psi_hi, d.psi_lo, d.dv32, d.part32, d.kps_x, d.n_split_x, T, act);
+  return rtk::proj_bf16x3(s, d.N, d.ng, d.psi_hi, d.psi_lo, d.dv32, d.part32, d.kps_x, d.n_split_x, T, act);
+}
+
 rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<int>& act_host,
                  const double* S, long sstride, double* Hout, bool force_full) {
   hipStream_t s = c->stream;
@@ -775,7 +801,7 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
     CK(rtk::delta_f32(s, d.dv32, d.vloc, d.vloc_gs, d.ng, T, act));
     {
       Timed tm(c, PH_PROJECT);
-      CK(rtk::proj_bf16x3(s, d.N, d.ng, d.psi_hi, d.psi_lo, d.dv32, d.part32, d.kps_x, d.n_split_x, T, act));
+      CK(proj_x(s, d, T, act));
     }
     Timed tr(c, PH_REDUCE);
     CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.Hgs, Hout, T, act, 0));
@@ -980,7 +1006,7 @@ rt_status predict_correction(rt_ctx* c, SysDev& d) {
   CK(rtk::prolong16(s, d.ybuf, d.dv, d.nx, d.ny, d.nz, kNOut, d.ng, T));
   if (d.mixed) {
     CK(rtk::cast_d2f(s, d.dv32, d.dv, (long)T * d.ng));
-    CK(rtk::proj_bf16x3(s, d.N, d.ng, d.psi_hi, d.psi_lo, d.dv32, d.part32, d.kps_x, d.n_split_x, T, d.mlp_mask));
+    CK(proj_x(s, d, T, d.mlp_mask));
     CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.H1, d.H1, T, d.mlp_mask, NN));
   } else {
     const long sp = (long)d.n_split * NN;
@@ -1085,7 +1111,10 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   if (d.mixed) {
     CK(rtk::copy_d(st, d.rho_gs, d.rho, d.ng));
     CK(rtk::copy_d(st, d.S_gs, d.tmp, NN));
-    CK(rtk::split_bf16(st, d.psi, d.psi_hi, d.psi_lo, N * ng));
+    if (d.N <= rtk::proj_tri_max_n())
+      CK(rtk::split_bf16_kb(st, d.psi, d.psi_hi, d.psi_lo, d.N, ng));
+    else
+      CK(rtk::split_bf16(st, d.psi, d.psi_hi, d.psi_lo, N * ng));
     if (d.psiT_hi) CK(rtk::split_bf16_t(st, d.psi, d.psiT_hi, d.psiT_lo, (int)N, d.wld, ng));
   }
   // trajectories: P_0 = P_gs, then each slot's kick through the series

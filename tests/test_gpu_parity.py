@@ -225,14 +225,18 @@ def test_c1_three_kicks_and_bitwise_determinism():
 MIXED_REL = 1e-4
 
 
-# N = 20, 100 and 250 cover one, several and all eight 32-row blocks of the
-# resident-tile density kernel (orbitals zero padded to 32, 128 and 256); the
-# 36 x 40 x 30 grid leaves a ragged last 128-point tile; N = 300 takes the
-# row-major density kernel for N > 256 and three 128-row projection tiles;
-# 36 x 36 x 30 (38880 points, not a multiple of 64) ends the projection's last
-# K split in a partial 64-point chunk.
+# N = 20, 60, 70, 100, 150, 190, 220 and 250 give the triangle projection kernel
+# (N <= 256) every block-grid order NB = 1..8 (32-row blocks, the last one ragged)
+# and the resident-tile density kernel one to eight 32-row blocks; the
+# 36 x 40 x 30 grid leaves a ragged last 128-point density tile; N = 300 takes the
+# row-major density kernel for N > 256 and the 128-row projection tiles;
+# 36 x 36 x 30 (38880 points, not a multiple of 64) ends the 128-row kernel's last
+# K split in a partial 64-point chunk, and 36 x 30 x 30 (32400 points, not a
+# multiple of 32) the triangle kernel's last split in a partial 32-point chunk.
 @pytest.mark.parametrize("n,n_orb", [((36, 40, 32), 20), ((36, 40, 30), 100), ((36, 40, 30), 250),
-                                     ((40, 36, 36), 300), ((36, 36, 30), 60)])
+                                     ((40, 36, 36), 300), ((36, 36, 30), 60), ((36, 30, 30), 70),
+                                     ((36, 30, 30), 150), ((36, 40, 30), 190), ((36, 30, 30), 220),
+                                     ((36, 36, 30), 300)])
 def test_mixed_eval_h_error_is_relative_to_the_perturbation(n, n_orb):
     _say(f"mixed eval_h {n} N={n_orb}")
     torch = _torch()
