@@ -400,6 +400,23 @@ rt_status rt_eigh_workspace_size(int n, size_t* bytes);
 rt_status rt_eigh(void* hip_stream, int n, const double* a_dev, double* evals_dev, double* vecs_dev,
                   void* workspace_dev, size_t ws_bytes, int* sweeps_out);
 
+/*
+ * rt_eigh for callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * computation, arguments, results and errors as rt_eigh, without a workspace
+ * argument.  Its work matrices live in one static device array per GPU
+ * (~6.3 MB, 3 [n][n] FP64 matrices at n = RT_EIGH_NOALLOC_MAX_N, held until the
+ * process ends); the call allocates nothing.  Limit: 1 <= n <=
+ * RT_EIGH_NOALLOC_MAX_N, else RT_EINVAL with no side effects.  Every call on
+ * one GPU uses that GPU's array, so calls that overlap on one GPU (other host
+ * threads, other streams) race: the caller serialises them.  Synchronises
+ * hip_stream (NULL = the current device's null stream).  RT_EDEVICE if the
+ * array's device address cannot be obtained.
+ */
+#define RT_EIGH_NOALLOC_MAX_N 512
+rt_status rt_eigh_noalloc(void* hip_stream, int n, const double* a_dev, double* evals_dev, double* vecs_dev,
+                          int* sweeps_out);
+
 /* Releases host-side state; the caller then frees the workspace. */
 void rt_free(rt_ctx* ctx);
 

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -2120,6 +2121,90 @@ rt_status rt_eigh(void* hip_stream, int n, const double* a_dev, double* evals_de
   rt_ctx c;
   c.stream = (hipStream_t)hip_stream;
   rt_status st = eigh_run(&c, w, a_dev, evals_dev, vecs_dev, sweeps_out);
+  if (st != RT_OK) g_init_error = c.err;
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// rt_eigh_noalloc: the eigensolver's work matrices in one static device array
+// (one copy on every GPU the library runs on, held until the process ends).
+// Host code never passes the array's name to a kernel: its device address is
+// taken once per device with hipGetSymbolAddress and kept in eigh_scratch_ptr.
+// Nothing in it has to start at zero (every kernel writes what it later reads).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kEighScratchBytes =
+    3ull * RT_EIGH_NOALLOC_MAX_N * RT_EIGH_NOALLOC_MAX_N * sizeof(double) + 8192;
+__device__ __align__(256) unsigned char scratch[kEighScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex eigh_scratch_mu;
+void* eigh_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, looked up (with dev current) on the
+// first call for that device.
+rt_status eigh_scratch(int dev, char** out) {
+  std::lock_guard<std::mutex> lock(eigh_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_init_error = "rt_eigh_noalloc: device index " + std::to_string(dev) + " out of range";
+    return RT_EDEVICE;
+  }
+  if (!eigh_scratch_ptr[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != dev) {
+      hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess || !p) {
+      g_init_error = std::string("rt_eigh_noalloc: hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return RT_EDEVICE;
+    }
+    eigh_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(eigh_scratch_ptr[dev]);
+  return RT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rt_status rt_eigh_noalloc(void* hip_stream, int n, const double* a_dev, double* evals_dev, double* vecs_dev,
+                          int* sweeps_out) {
+  if (n < 1 || n > RT_EIGH_NOALLOC_MAX_N) {
+    g_init_error = "rt_eigh_noalloc: n = " + std::to_string(n) + " outside [1, " +
+                   std::to_string(RT_EIGH_NOALLOC_MAX_N) + "] (use rt_eigh with a workspace)";
+    return RT_EINVAL;
+  }
+  if (!a_dev || !evals_dev || !vecs_dev) {
+    g_init_error = "rt_eigh_noalloc: NULL device pointer";
+    return RT_EINVAL;
+  }
+  int dev = -1;
+  hipError_t e = hip_stream ? hipStreamGetDevice((hipStream_t)hip_stream, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    g_init_error = std::string("rt_eigh_noalloc: stream device: ") + hipGetErrorString(e);
+    return RT_EDEVICE;
+  }
+  char* base = nullptr;
+  rt_status st = eigh_scratch(dev, &base);
+  if (st != RT_OK) return st;
+  Arena a;
+  a.base = base;  // 256-byte aligned
+  EighWork w;
+  eigh_layout(a, w, n);
+  if (a.used > kEighScratchBytes) {
+    g_init_error = "rt_eigh_noalloc: scratch layout exceeds the static array";
+    return RT_EINVAL;
+  }
+  rt_ctx c;
+  c.stream = (hipStream_t)hip_stream;
+  st = eigh_run(&c, w, a_dev, evals_dev, vecs_dev, sweeps_out);
   if (st != RT_OK) g_init_error = c.err;
   return st;
 }

@@ -112,6 +112,7 @@ def _load():
                              _dp, vp, ctypes.POINTER(rt_gs_stats)], ctypes.c_int),
         "rt_eigh_workspace_size": ([ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "rt_eigh": ([vp, ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t, _ip], ctypes.c_int),
+        "rt_eigh_noalloc": ([vp, ctypes.c_int, vp, vp, vp, _ip], ctypes.c_int),
         "rt_free": ([vp], None),
         "rt_last_error": ([vp], ctypes.c_char_p),
     }
@@ -380,6 +381,18 @@ def rt_eigh(stream_ptr, n, a_ptr, evals_ptr, vecs_ptr, workspace_ptr, ws_bytes):
     sw = ctypes.c_int(0)
     _check(lib.rt_eigh(ctypes.c_void_p(stream_ptr), n, ctypes.c_void_p(a_ptr), ctypes.c_void_p(evals_ptr),
                        ctypes.c_void_p(vecs_ptr), ctypes.c_void_p(workspace_ptr), ws_bytes, ctypes.byref(sw)))
+    return sw.value
+
+
+RT_EIGH_NOALLOC_MAX_N = 512
+
+
+def rt_eigh_noalloc(stream_ptr, n, a_ptr, evals_ptr, vecs_ptr):
+    """rt_eigh without a workspace (the library's static per-GPU array, n <= 512).
+    Returns the number of Jacobi sweeps."""
+    sw = ctypes.c_int(0)
+    _check(lib.rt_eigh_noalloc(ctypes.c_void_p(stream_ptr), n, ctypes.c_void_p(a_ptr), ctypes.c_void_p(evals_ptr),
+                               ctypes.c_void_p(vecs_ptr), ctypes.byref(sw)))
     return sw.value
 
 

@@ -165,3 +165,20 @@ def test_binding_refuses_orbital_arrays_of_the_wrong_size():
     sa.psi0 = exact.astype(np.float32)
     with pytest.raises(ValueError):
         rt.rt_init([sa], run_args(synth.RunParams(dt=0.05, n_steps=2)), 0, 0, 0)
+
+
+def test_eigh_noalloc_rejects_sizes_beyond_its_static_array_without_a_gpu():
+    """The allocation-free eigensolver refuses n outside [1, RT_EIGH_NOALLOC_MAX_N]
+    and NULL pointers before touching a device."""
+    from paper_2410_09189_amd import rt
+
+    txt = open(os.path.join(ROOT, "include", "rt_tddft.h")).read()
+    assert int(re.search(r"#define RT_EIGH_NOALLOC_MAX_N (\d+)", txt).group(1)) == rt.RT_EIGH_NOALLOC_MAX_N
+    for n in (0, -3, rt.RT_EIGH_NOALLOC_MAX_N + 1, 4096):
+        with pytest.raises(rt.RTError) as e:
+            rt.rt_eigh_noalloc(0, n, 8, 8, 8)
+        assert e.value.status == rt.RT_EINVAL
+        assert "outside" in rt.rt_last_error(None)
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_eigh_noalloc(0, 8, 0, 8, 8)
+    assert e.value.status == rt.RT_EINVAL and "NULL" in rt.rt_last_error(None)
