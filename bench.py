@@ -4,8 +4,9 @@ Workload (default): the plain-vs-mixed molecule -- 96^3 periodic grid, h = 0.3
 bohr, 40 Gaussian wells with rank-4 separable projectors (r_c = 2 bohr),
 160 occupied + 80 virtual orbitals, delta kick 1e-3 along x, dt = 0.05 a.u.,
 self-consistency and series thresholds of the paper (1e-7, 1e-10).  Inputs are
-seeded synthetic: smooth random orbitals made orthonormal by the library's own
-basis transform at init (the ground-state solve is not part of the step).
+seeded synthetic; the orbitals are the molecule's stationary ground state,
+solved on the GPU by the library's ground-state solver before the timed legs
+(reported, not part of the step).
 
 One "step" = one time step of Algorithm 1 for the three delta-kick
 trajectories (x, y, z) a photoabsorption spectrum needs, stepped together:
@@ -81,30 +82,16 @@ def roof(phase, N, ng, mixed, T, full):
     return None
 
 
-def cpu_baseline(s, psi_host, m_mean, dt, n_traj):
-    """The oracle's own functions on the host's cores, timed on a bounded sample
-    of the same workload and scaled to one step of the same batch:
-    per-orbital H apply (FD8 Laplacian + local + nonlocal) on 16 orbitals,
-    density and projection contractions at N_s = 96 scaled by (N / N_s)^2,
-    Hartree + LDA on the full grid, exact exponential propagation at full N.
-    One update = N applies + density + projection + potentials + propagation;
-    one step = mean updates per step (from the GPU run) x trajectories."""
+def _oracle_sample(s, psi_host, m_mean, dt, n_traj):
+    """One timed pass over the bounded sample (see cpu_baseline); returns
+    (steps/s of the full workload, seconds per update, per-part timings)."""
     from oracle import grid, hamiltonian, propagate, system
 
-    try:
-        from threadpoolctl import threadpool_info
-
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count()
     N = psi_host.shape[0]
     nx, ny, nz = s.n
     coeffs = grid.fd_coefficients_float(4)
     vloc = np.zeros(s.ng)
-    t0 = time.perf_counter()
     projs = system.projectors(s)
-    t_tables = time.perf_counter() - t0
-    log(f"cpu baseline: projector tables {t_tables:.1f} s")
     k = 16
     t0 = time.perf_counter()
     for j in range(k):
@@ -112,7 +99,6 @@ def cpu_baseline(s, psi_host, m_mean, dt, n_traj):
         _ = (-0.5 * grid.laplacian(f, s.h, coeffs)).ravel() + vloc * psi_host[j]
     _ = system.apply_vnl(psi_host[:k], projs, s.h)
     t_apply1 = (time.perf_counter() - t0) / k
-    log(f"cpu baseline: H apply {t_apply1 * 1e3:.1f} ms per orbital")
     ns = 96
     sub = psi_host[:ns]
     rng = np.random.default_rng(0)
@@ -123,9 +109,8 @@ def cpu_baseline(s, psi_host, m_mean, dt, n_traj):
     t0 = time.perf_counter()
     _ = s.h ** 3 * (sub @ sub.T)
     t_proj = time.perf_counter() - t0
-    log(f"cpu baseline: density {t_dens:.2f} s, projection {t_proj:.2f} s at N={ns}")
     t0 = time.perf_counter()
-    vh = hamiltonian.hartree(rho, s)
+    _ = hamiltonian.hartree(rho, s)
     _ = hamiltonian.lda_x(rho)
     t_pot = time.perf_counter() - t0
     H = rng.standard_normal((N, N))
@@ -133,17 +118,68 @@ def cpu_baseline(s, psi_host, m_mean, dt, n_traj):
     t0 = time.perf_counter()
     _ = propagate.propagate_exact(0.5 * (H + H.T), P, dt)
     t_exp = time.perf_counter() - t0
-    log(f"cpu baseline: potentials {t_pot:.2f} s, exponential {t_exp:.2f} s")
     scale2 = (N / ns) ** 2
     t_update = N * t_apply1 + scale2 * (t_dens + t_proj) + t_pot + t_exp
-    steps_per_s = 1.0 / (t_update * m_mean * n_traj)
+    parts = {"h_apply_ms_per_orbital": t_apply1 * 1e3, "density_s_at_96": t_dens, "projection_s_at_96": t_proj,
+             "potentials_s": t_pot, "exponential_s": t_exp}
+    return 1.0 / (t_update * m_mean * n_traj), t_update, parts, s.ng / t_apply1
+
+
+def _oracle_c1_step(n_steps=10):
+    """Whole time steps of the 32^3 parity molecule by the oracle (exact
+    propagator, self-consistent midpoint at the paper's H_thrs 1e-7): steps/s."""
+    import oracle
+    import synth
+
+    sysm = synth.config_system("c1_parity_32")
+    d = np.load(os.path.join(ROOT, "tests", "golden", "c1_ground_state.npz"))
+    m = oracle.Model(sysm, d["psi"])
+    rp = synth.config_run("c1_parity_32", n_steps=n_steps, h_thrs=1e-7, dp_thrs=1e-10)
+    t0 = time.perf_counter()
+    oracle.run(m, rp)
+    return n_steps / (time.perf_counter() - t0)
+
+
+def cpu_baseline(s, psi_host, m_mean, dt, n_traj):
+    """The oracle's own functions on the host's cores, timed on a bounded sample
+    of the same workload and scaled to one step of the same batch:
+    per-orbital H apply (FD8 Laplacian + local + nonlocal) on 16 orbitals,
+    density and projection contractions at N_s = 96 scaled by (N / N_s)^2,
+    Hartree + LDA on the full grid, exact exponential propagation at full N.
+    One update = N applies + density + projection + potentials + propagation;
+    one step = mean updates per step (from the GPU run) x trajectories.  Timed
+    with all the host's BLAS threads and again with one; also whole oracle
+    steps of the 32^3 parity molecule (small enough to run outright)."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+        cores = os.cpu_count()
+    N = psi_host.shape[0]
+    nx, ny, nz = s.n
+    v_all, t_update, parts, h_rate = _oracle_sample(s, psi_host, m_mean, dt, n_traj)
+    log(f"cpu baseline ({cores} threads): one update {t_update:.1f} s")
+    v_one = c1_all = c1_one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            v_one, t_update1, _, _ = _oracle_sample(s, psi_host, m_mean, dt, n_traj)
+            log(f"cpu baseline (1 thread): one update {t_update1:.1f} s")
+            c1_one = _oracle_c1_step()
+    c1_all = _oracle_c1_step()
+    log(f"cpu baseline: 32^3 oracle steps/s {c1_all:.2f} ({cores} threads), {c1_one} (1 thread)")
     return {
-        "value": steps_per_s, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+        "value": v_all, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+        "value_1_core": v_one,
         "sample": (f"oracle functions on the {nx}^3 N={N} workload: H apply of 16 orbitals "
-                   f"({t_apply1 * 1e3:.0f} ms each), density+projection at N={ns} scaled by (N/{ns})^2, "
-                   f"Hartree+LDA, exact exponential; one update = {t_update:.1f} s, x {m_mean:.2f} updates "
-                   f"per trajectory-step x {n_traj} trajectories per step"),
-        "h_applies_per_s": s.ng / t_apply1,
+                   f"({parts['h_apply_ms_per_orbital']:.0f} ms each), density+projection at N=96 scaled by "
+                   f"(N/96)^2, Hartree+LDA, exact exponential; one update = {t_update:.1f} s, x {m_mean:.2f} "
+                   f"updates per trajectory-step x {n_traj} trajectories per step"),
+        "h_applies_per_s": h_rate,
+        "c1_parity_32_steps_per_s": {"all_cores": c1_all, "one_core": c1_one,
+                                     "note": "10 whole oracle steps, exact propagator, H_thrs 1e-7"},
+        "parts": parts,
     }
 
 
@@ -304,10 +340,27 @@ def ground_states(rt, torch):
             "molecules": rows}
 
 
+def no_kick_control(rt, torch, sa, n=100):
+    """The stationary input without a kick (FP64 and mixed, local update, 100
+    steps): how far the dipole and the energy move on their own."""
+    out = {}
+    for prec, name in ((rt.RT_FP64, "fp64"), (rt.RT_MIXED, "mixed")):
+        ra = rt.RunArgs(dt=0.05, n_steps_max=n, h_thrs=1e-10, dp_thrs=1e-10, max_scf=50, max_terms=200,
+                        traj_sys=[0], traj_kappa=[0.0], traj_axis=[0], hupdate=rt.RT_HUPDATE_LOCAL, precision=prec)
+        ses = rt.Session([sa], ra)
+        rt.rt_step(ses.ctx, n, n_traj=1)
+        mu, E, _ = rt.rt_dipole(ses.ctx, 0, 0, n + 1)
+        ses.close()
+        out[name] = {"max_abs_dmu": float(np.max(np.abs(mu - mu[0]))), "max_abs_dE": float(np.max(np.abs(E - E[0])))}
+    out["steps"] = n
+    return out
+
+
 def variants(rt, torch, s, psi, args):
     """The ranked extensions on the 96^3 workload, mixed precision, three
     trajectories, H_thrs 1e-7, timed like the main legs: the non-orthogonal
-    basis (the smooth random orbitals taken as they are, overlap S != I),
+    basis (the ground-state orbitals mixed by a unit lower-triangular matrix,
+    Phi = A Psi, overlap S = A A^T != I, the same occupied space),
     fourth-order Magnus (Omega_2 in every series term), and sin^2 pulses along
     x, y, z instead of kicks (a 1e-3, omega 0.4, tau 10).  Each against the
     plain mixed step on the same workload."""
@@ -319,10 +372,13 @@ def variants(rt, torch, s, psi, args):
              ("magnus_order_4", False, {"magnus_order": 4}, [1e-3] * T, None),
              ("pulse_fields", False, {}, [0.0] * T,
               [[1e-3, 0.4, 10.0, 0.0] + [1.0 if q == a else 0.0 for q in range(3)] for a in AXES]))
+    import synth
+
+    phi = torch.from_numpy(synth.basis_mixing(s.n_orb, 1, lower=True)).cuda() @ psi
     for name, nonorth, extra, kappas, field in cases:
         sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
-                           n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut, nl_sigma=s.nl_sigma,
-                           nl_D=s.nl_D, n_images=s.n_images, orthonormalize=not nonorth, nonorthogonal=nonorth)
+                           n_virt=s.n_virt, psi0=phi if nonorth else psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
+                           nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images, nonorthogonal=nonorth)
         ra = rt.RunArgs(dt=0.05, n_steps_max=total, h_thrs=args.h_thrs, dp_thrs=args.dp_thrs, max_scf=50,
                         max_terms=200, traj_sys=[0] * T, traj_kappa=kappas, traj_axis=list(AXES),
                         precision=rt.RT_MIXED, hupdate=rt.RT_HUPDATE_LOCAL, traj_field=field, **extra)
@@ -478,11 +534,28 @@ def main():
     name = "c2_mixed_96"
     s = synth.config_system(name)
     N = s.n_orb
-    log(f"generating {N} smooth random orbitals on {s.n}")
-    psi = synth.lowpass_orbitals(s.n, s.h, N, seed=s.seed)
+    # the input of the time loop: the molecule's stationary ground state, solved on
+    # the GPU from a block of smooth random vectors (not part of the timed step)
+    log(f"ground state of the {s.n[0]}^3 molecule on the GPU")
+    x0 = synth.ground_state_start(name)
+    gsp = synth.CONFIGS[name]["gs"]
+    sa0 = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
+                        n_virt=s.n_virt, psi0=x0, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
+                        nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images)
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter()
+    psi, eps_gs, _, st_gs = rt.ground_state(sa0, rt.gs_params(**gsp))
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter() - t_gs
+    del x0, sa0
+    gs_info = {"seconds": round(t_gs, 2), "density_iterations": st_gs["scf_iters"],
+               "homo_lumo_gap": float(eps_gs[s.n_occ] - eps_gs[s.n_occ - 1]),
+               "active_space_edge_gap": float(eps_gs[N] - eps_gs[N - 1]), "rho_err": st_gs["rho_err"],
+               "residual": st_gs["residual"], "params": gsp}
+    log(f"ground state: {t_gs:.1f} s, gap {gs_info['homo_lumo_gap']:.3e}")
     sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
                        n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
-                       nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images, orthonormalize=True)
+                       nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images)
     if args.only_variants:
         log("variants: non-orthogonal basis, fourth-order Magnus, pulses")
         print(json.dumps({"variants_96": variants(rt, torch, s, psi, args)}), flush=True)
@@ -497,7 +570,12 @@ def main():
     log(f"reference done: {1e3 * ref['elapsed'] / args.steps:.2f} ms/step")
     # Equal-dipole-error comparison: each method over a sweep of self-consistency
     # thresholds (the paper's 1e-7 among them), timed without phase timers.
+    # plain_fp64: the paper's step (full H apply + projection per update);
+    # fp64_local: the same FP64 arithmetic with the Hamiltonian update
+    # H[P] = H_gs + h^3 Psi^T dV Psi (exact, no grid apply in the loop), so that the
+    # mixed step's gain splits into the update shortcut and the precision
     methods = (("plain_fp64", rt.RT_FP64, rt.RT_HUPDATE_FULL, rt.RT_PRED_LINEAR),
+               ("fp64_local", rt.RT_FP64, rt.RT_HUPDATE_LOCAL, rt.RT_PRED_LINEAR),
                ("mixed_linear", rt.RT_MIXED, rt.RT_HUPDATE_LOCAL, rt.RT_PRED_LINEAR),
                ("mixed_quadratic", rt.RT_MIXED, rt.RT_HUPDATE_LOCAL, rt.RT_PRED_QUADRATIC))
     legs = {}
@@ -509,12 +587,16 @@ def main():
             legs[(mname, th)] = leg
             log(f"leg {mname} H_thrs={th:g} done: {1e3 * leg['elapsed'] / args.steps:.2f} ms/step")
     plain = legs[("plain_fp64", args.h_thrs)]
+    fp64_local = legs[("fp64_local", args.h_thrs)]
     mixed_lin = legs[("mixed_linear", args.h_thrs)]
     mixed_quad = legs[("mixed_quadratic", args.h_thrs)]
     # phase timers (events around every stage) on separate runs at the paper threshold
     log("profiled runs at the paper threshold")
     prof_plain = run_leg(rt, torch, sa, s, args, rt.RT_FP64, rt.RT_HUPDATE_FULL, args.h_thrs, args.dp_thrs, True)
     prof_plain["ses"].close()
+    prof_fp64_local = run_leg(rt, torch, sa, s, args, rt.RT_FP64, rt.RT_HUPDATE_LOCAL, args.h_thrs, args.dp_thrs,
+                              True)
+    prof_fp64_local["ses"].close()
     prof_mixed = run_leg(rt, torch, sa, s, args, rt.RT_MIXED, rt.RT_HUPDATE_LOCAL, args.h_thrs, args.dp_thrs, True)
     ctx = prof_mixed["ses"].ctx
 
@@ -524,7 +606,7 @@ def main():
         return float(np.max(np.abs(d - dr)) / np.max(np.abs(dr)))
 
     # standalone H-apply rates (FP64 and FP32 stencil + nonlocal over all orbitals)
-    x64 = torch.from_numpy(psi.reshape(N, -1)).cuda()
+    x64 = psi
     y64 = torch.empty_like(x64)
     x32 = x64.float()
     y32 = torch.empty_like(x32)
@@ -566,7 +648,11 @@ def main():
             "trajectory_steps_per_s": len(AXES) * args.steps / leg["elapsed"],
             "mean_scf_updates_per_step": m_total / len(leg["stats"]),
             "mean_series_terms_per_update": sum(x[1] for x in leg["stats"]) / max(1, m_total),
-            "h_updates_orbital_gridpoints_per_s": m_total * N * s.ng / leg["elapsed"],
+            "hamiltonian_updates_per_s": m_total / leg["elapsed"],
+            # only the full update applies the grid Hamiltonian to every orbital
+            **({"h_applies_orbital_gridpoints_per_s": m_total * N * s.ng / leg["elapsed"]} if full else
+               {"h_applies_orbital_gridpoints_per_s": None,
+                "h_applies_note": "H[P] = H_gs + h^3 Psi^T dV Psi: no grid H apply inside the step"}),
             "dipole_rel_err_vs_fp64_tight": dip_err(leg),
             "energy_change_err_vs_fp64_tight": float(np.max(np.abs((leg["E"] - leg["E"][0]) - (ref["E"] - ref["E"][0])))),
             "roofline": roofline_of(prof_leg["prof"], N, s.ng, mixed_mode, full),
@@ -575,6 +661,7 @@ def main():
         }
 
     sm_plain = summary(plain, False, True, prof_plain)
+    sm_fp64_local = summary(fp64_local, False, False, prof_fp64_local)
     sm_mixed_lin = summary(mixed_lin, True, False, prof_mixed)
     sm_mixed_quad = summary(mixed_quad, True, False, prof_mixed)
     sweep = []
@@ -585,7 +672,7 @@ def main():
     # headline: the fastest mixed configuration (either first guess, any swept threshold)
     # whose dipole error is within 3x of the plain FP64 step's at the paper's threshold
     e_ref = sm_plain["dipole_rel_err_vs_fp64_tight"]
-    ok = [r for r in sweep if r["method"] != "plain_fp64" and r["dipole_rel_err"] <= 3 * e_ref]
+    ok = [r for r in sweep if r["method"].startswith("mixed") and r["dipole_rel_err"] <= 3 * e_ref]
     head = max(ok, key=lambda r: r["steps_per_s"]) if ok else \
         {"method": "mixed_linear", "h_thrs": args.h_thrs, "steps_per_s": sm_mixed_lin["steps_per_s"]}
     value = head["steps_per_s"]
@@ -598,7 +685,7 @@ def main():
     # larger (10 % slack for equal errors), and the speedup over it
     pareto = []
     for r in sweep:
-        if r["method"] == "plain_fp64":
+        if not r["method"].startswith("mixed"):
             continue
         pl = [q for q in sweep if q["method"] == "plain_fp64" and q["dipole_rel_err"] <= 1.1 * r["dipole_rel_err"]]
         if pl:
@@ -617,15 +704,20 @@ def main():
                                f"{head['method']} at H_thrs={head['h_thrs']:g}",
                    "grid": list(s.n), "n_orb": N, "trajectories": len(AXES)},
         "vs_plain_fp64": value / sm_plain["steps_per_s"],
+        "vs_fp64_local_update": value / sm_fp64_local["steps_per_s"],
         "vs_plain_fp64_matched_error": (value / plain_match["steps_per_s"]) if plain_match else None,
         "roofline": best["roofline"],
         "equal_dipole_err_rule": "headline: fastest mixed sweep point whose dipole error is within 3x of "
                                  "the plain FP64 step's at the paper threshold",
         "headline": head, "sweep": sweep, "pareto_vs_plain": pareto,
         "mixed": sm_mixed_lin, "mixed_quadratic": sm_mixed_quad, "plain_fp64": sm_plain,
+        "fp64_local_update": sm_fp64_local,
         "fp64_tight_reference_steps_per_s": args.steps / ref["elapsed"],
         "apply_h_standalone": rates,
     }
+    out["ground_state"] = gs_info
+    log("no-kick control")
+    out["no_kick_control"] = no_kick_control(rt, torch, sa)
     if not args.no_batch:
         log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")
         out["batched_16_molecules"] = batched_molecules(rt, torch, args.steps, args.warmup)
@@ -643,7 +735,7 @@ def main():
         out["ground_state_16_molecules"] = ground_states(rt, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(s, psi.reshape(N, -1), sm_plain["mean_scf_updates_per_step"], 0.05,
+        out["cpu_baseline"] = cpu_baseline(s, psi.cpu().numpy(), sm_plain["mean_scf_updates_per_step"], 0.05,
                                            len(AXES))
     print(json.dumps(out), flush=True)
 

@@ -239,6 +239,55 @@ rt_status rt_set_state(rt_ctx* ctx, int traj, const double* p_re, const double* 
                        const double* h0, const double* hm1);
 
 /*
+ * Autotuner of the launch shapes (the paper tunes nothing; these are this
+ * library's own kernels).  Tunables per system:
+ *   RT_TUNE_STENCIL_FP64 / _FP32: y-tile rows p1 (a divisor of ny whose 16-byte
+ *     strips fit one 256-thread block) and z chunks p2 (1..nz) of the FD8 + V
+ *     stencil; the tiling changes no arithmetic (results bitwise equal);
+ *   RT_TUNE_PROJ_FP64: target block count p1 in {1024, 2048, 4096} of the FP64
+ *     projection's K split (p2 reported: the resulting splits);
+ *   RT_TUNE_PROJ_MIXED: splits p1 in {85, 128, 170, 255} of the BF16x3 projection
+ *     for N <= 256 (p2 reported: the resulting splits).
+ * The projection splits change the order of the FP64/FP32 partial sums, so
+ * results move within rounding (and a trajectory's results then depend on the
+ * splits its context uses).  0 selects the built-in choice.
+ * rt_autotune: for every system, each tunable it uses is timed over its
+ *   candidates on the context's own buffers (device time by hipEvents on the
+ *   context's stream, one warm-up and three timed launches each) and the fastest
+ *   kept.  cache_path (nullable): a text file of earlier choices, one line
+ *   "arch|kernel|nx x ny x nz|N|T p1 p2" each; matching entries are applied
+ *   without timing and new ones appended.  Call after rt_init, before rt_step;
+ *   it overwrites scratch buffers only (state and history unchanged).
+ * rt_tune_set / rt_tune_get: pin or read one tunable (RT_EINVAL for shapes the
+ *   kernel cannot take).  rt_tune_report: the last rt_autotune's choices and
+ *   timings as text, owned by the context.
+ */
+enum { RT_TUNE_STENCIL_FP64 = 0, RT_TUNE_STENCIL_FP32 = 1, RT_TUNE_PROJ_FP64 = 2, RT_TUNE_PROJ_MIXED = 3 };
+rt_status rt_autotune(rt_ctx* ctx, const char* cache_path);
+rt_status rt_tune_set(rt_ctx* ctx, int sys_index, int kernel, int p1, int p2);
+rt_status rt_tune_get(rt_ctx* ctx, int sys_index, int kernel, int* p1, int* p2);
+const char* rt_tune_report(const rt_ctx* ctx);
+
+/*
+ * Checkpoint and resume of a whole context: the time loop of Algorithm 1 carries
+ * from step j to j + 1 only P_j, the Hamiltonians H_j, H_j-1 (H_j-2 for the
+ * quadratic first guess), the observable history and, with the learned first
+ * guess, its feature rings, counters and fallback statistics; a checkpoint holds
+ * exactly these, for every system and trajectory, in a host buffer the caller
+ * owns.  rt_checkpoint_size: bytes needed now (grows with the step count).
+ * rt_checkpoint_save: writes them (RT_ENOMEM if bytes is short; synchronises the
+ * stream).  rt_checkpoint_load: into a context made by rt_init with the same
+ * systems and run arguments (n_steps_max at least the saved step count); the
+ * next rt_step continues exactly as the saving context would have (the same
+ * arithmetic, so the same bits).  RT_EINVAL, with nothing changed, for a buffer
+ * that is not a checkpoint of this library version, is truncated, or was saved
+ * from a context of other shapes or modes.
+ */
+rt_status rt_checkpoint_size(rt_ctx* ctx, size_t* bytes);
+rt_status rt_checkpoint_save(rt_ctx* ctx, void* host, size_t bytes);
+rt_status rt_checkpoint_load(rt_ctx* ctx, const void* host, size_t bytes);
+
+/*
  * Component entry points over caller-owned device buffers (for validation of
  * single stages; they run the same kernels as rt_step):
  *   rt_eval_h:    H_out = H[P] for the density matrix with real part p_re_dev

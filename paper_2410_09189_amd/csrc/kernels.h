@@ -2,6 +2,8 @@
 // Every launcher enqueues on the given stream and returns the launch status.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <cstdint>
 
 namespace rtk {
@@ -37,10 +39,15 @@ hipError_t cast_d2f(hipStream_t s, float* dst, const double* src, long n);
 hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, long n, int T, const int* active);
 
 // ---- Hamiltonian on the grid -------------------------------------------------
-// hpsi[j] = -1/2 L psi[j] + v psi[j] (8th-order FD, periodic), j < n_orb.
+// hpsi[j] = -1/2 L psi[j] + v psi[j] (8th-order FD, periodic), j < n_orb.  Tiling:
+// ty rows of y per block (a divisor of ny whose strips fit one block) and nzc z
+// chunks; 0 = the default choice.  The tiling changes no arithmetic.
 template <typename T>
 hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
-                   int nz, double h, const double* coef5);
+                   int nz, double h, const double* coef5, int ty = 0, int nzc = 0);
+// the tilings stencil<T> accepts on this grid (candidate ty values, nzc values)
+template <typename T>
+void stencil_tiles(int nx, int ny, int nz, int n_orb, std::vector<int>& ty, std::vector<int>& nzc);
 // c[j][p] = h^3 sum_s beta[s][p] psi_j[idx[s]] over atom spheres (rank 4 or 1..4).
 template <typename T>
 hipError_t nl_gather(hipStream_t s, const T* psi, long ng, int n_orb, int n_atoms, int rank,

@@ -352,22 +352,34 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
   }
 }
 
+// Default y tile: the largest divisor of ny whose strips fit one 256-thread block
+// (one strip per thread, registers for occupancy).
+static int stencil_default_ty(int spr, int ny) {
+  for (int t = 64; t >= 1; --t)
+    if (t <= ny && ny % t == 0 && t * spr <= 256) return t;
+  return 1;
+}
+
 template <typename T, int V>
 static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
-                                 int nz, const StencilCoef& cf) {
+                                 int nz, const StencilCoef& cf, int ty, int nzc) {
   const int spr = nx / V;
-  // y tile: the largest divisor of ny whose strips fit one 256-thread block (one strip
-  // per thread, registers for occupancy), block = strips rounded up to whole waves
-  int TY = 1;
-  for (int t = 64; t >= 1; --t)
-    if (t <= ny && ny % t == 0 && t * spr <= 256) { TY = t; break; }
+  // y tile (ty > 0: as given; it must divide ny and its strips fit one block),
+  // block = strips rounded up to whole waves
+  const int TY = ty > 0 ? ty : stencil_default_ty(spr, ny);
+  if (ny % TY || TY * spr > 256) return hipErrorInvalidValue;
   const int cols = (TY * spr + 255) / 256;
   const int nt = cols > 1 ? 256 : (TY * spr + 63) / 64 * 64;
   const int hs = (8 * spr + nt - 1) / nt;
   int tiles = ny / TY;
-  int nzc = 1;
-  long blocks = (long)tiles * n_orb;
-  while (blocks * nzc < 2048 && nz / (nzc * 2) >= 16) nzc *= 2;
+  // z chunks (nzc > 0: as given): by default doubled until the grid has 2048 blocks
+  // or a chunk would drop below 16 planes
+  if (nzc <= 0) {
+    nzc = 1;
+    const long blocks = (long)tiles * n_orb;
+    while (blocks * nzc < 2048 && nz / (nzc * 2) >= 16) nzc *= 2;
+  }
+  if (nzc > nz) return hipErrorInvalidValue;
   int ZC = (nz + nzc - 1) / nzc;
   nzc = (nz + ZC - 1) / ZC;
   size_t lds = 2 * (size_t)(TY + 8) * (nx + 8) * sizeof(T);
@@ -388,18 +400,32 @@ static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* 
 
 template <typename T>
 hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
-                   int nz, double h, const double* a) {
+                   int nz, double h, const double* a, int ty, int nzc) {
   if (nx > 256 || ny > 256 || nz > 256) return hipErrorInvalidValue;
   StencilCoef cf;
   for (int k = 0; k < 5; ++k) cf.c[k] = -0.5 * a[k] / (h * h);
   constexpr int VV = 16 / sizeof(T);
-  if (nx % VV == 0) return stencil_launch<T, VV>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf);
-  return stencil_launch<T, 1>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf);
+  if (nx % VV == 0) return stencil_launch<T, VV>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf, ty, nzc);
+  return stencil_launch<T, 1>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf, ty, nzc);
 }
+
+template <typename T>
+void stencil_tiles(int nx, int ny, int nz, int n_orb, std::vector<int>& ty, std::vector<int>& nzc) {
+  constexpr int VV = 16 / sizeof(T);
+  const int spr = nx % VV == 0 ? nx / VV : nx;
+  ty.clear();
+  nzc.clear();
+  for (int t = 1; t <= ny && t * spr <= 256; ++t)
+    if (ny % t == 0) ty.push_back(t);
+  for (int z = 1; z <= 16 && z <= nz; z *= 2) nzc.push_back(z);
+  (void)n_orb;
+}
+template void stencil_tiles<double>(int, int, int, int, std::vector<int>&, std::vector<int>&);
+template void stencil_tiles<float>(int, int, int, int, std::vector<int>&, std::vector<int>&);
 template hipError_t stencil<double>(hipStream_t, const double*, double*, const double*, int, int, int,
-                                    int, double, const double*);
+                                    int, double, const double*, int, int);
 template hipError_t stencil<float>(hipStream_t, const float*, float*, const float*, int, int, int, int,
-                                   double, const double*);
+                                   double, const double*, int, int);
 
 // ============================================================================
 // Separable nonlocal projectors

@@ -135,6 +135,12 @@ struct SysDev {
   long kps = 0;
   int n_split_x = 1;  // splits of the BF16x3 projection
   long kps_x = 0;
+  // tuned launch shapes (0 = the built-in choice): stencil y-tile rows and z chunks
+  // per element type, target block count of the FP64 projection, splits of the
+  // N <= 256 BF16x3 projection
+  int st_ty[2] = {0, 0}, st_nzc[2] = {0, 0};
+  int gemm_target = 0, tri_splits = 0;
+  int n_split_cap = 1, n_split_x_cap = 1;  // partial buffers are sized for these
   bool mixed = false;
   bool nonorth = false;  // propagate in the given (non-orthogonal) basis with its overlap
   double* tcur = nullptr;                  // device scalar: time t_j of the step being taken
@@ -228,6 +234,7 @@ struct rt_ctx {
   std::vector<SysDev> sys;
   std::vector<TrajDev> traj;
   std::string err;
+  std::string tune_report;  // last rt_autotune's choices and timings
   int hist_cap = 0;
   float *rec_x = nullptr, *rec_y = nullptr;
   int rec_cap = 0, rec_count = 0;
@@ -488,12 +495,15 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
   return RT_OK;
 }
 
+constexpr int kGemmTargets[3] = {1024, 2048, 4096};  // candidate block counts, FP64 projection
+constexpr int kTriSplits[4] = {85, 128, 170, 255};   // candidate splits, BF16x3 projection (N <= 256)
+
 void choose_split(SysDev& d) {
-  // FP64 projection: 64 x 64 upper tiles, K chunks of 16, ~2048 blocks
+  // FP64 projection: 64 x 64 upper tiles, K chunks of 16, ~2048 blocks (or the tuned count)
   d.big = 0;
   int ntm = (d.N + 63) / 64;
   int tiles = ntm * (ntm + 1) / 2;
-  long target = 2048;
+  long target = d.gemm_target > 0 ? d.gemm_target : 2048;
   long ns = (target + tiles - 1) / tiles;
   long maxs = std::max(1L, d.ng / 1024);
   ns = std::min(ns, maxs);
@@ -502,6 +512,12 @@ void choose_split(SysDev& d) {
   kps = (kps + bk - 1) / bk * bk;
   d.kps = kps;
   d.n_split = (int)((d.ng + kps - 1) / kps);
+  // room for the largest candidate count
+  {
+    long nsm = std::min((kGemmTargets[2] + (long)tiles - 1) / tiles, maxs);
+    long km = ((d.ng + nsm - 1) / nsm + bk - 1) / bk * bk;
+    d.n_split_cap = std::max(d.n_split_cap, std::max(d.n_split, (int)((d.ng + km - 1) / km)));
+  }
   // BF16x3 projection: 128 x 128 upper tiles, K chunks of 64
   int ntx = (d.N + 127) / 128;
   int tx = ntx * (ntx + 1) / 2;
@@ -517,15 +533,19 @@ void choose_split(SysDev& d) {
 // in one round; each split at least four staged chunks long.  The split does not
 // depend on the number of trajectories, so a trajectory's partial sums, and with
 // them its results, are the same batched or alone.
-constexpr int kProjTriSplits = 85;
 void choose_split_tri(SysDev& d) {
   if (d.N > rtk::proj_tri_max_n()) return;
   const long ck = rtk::proj_tri_chunk();
-  long ns = std::min((long)kProjTriSplits, std::max(1L, d.ng / (4 * ck)));
-  long kx = (d.ng + ns - 1) / ns;
-  kx = (kx + ck - 1) / ck * ck;
+  auto split = [&](long want, long& kx) {
+    long ns = std::min(want, std::max(1L, d.ng / (4 * ck)));
+    kx = (d.ng + ns - 1) / ns;
+    kx = (kx + ck - 1) / ck * ck;
+    return (int)((d.ng + kx - 1) / kx);
+  };
+  long kx = 0, km = 0;
+  d.n_split_x = split(d.tri_splits > 0 ? d.tri_splits : kTriSplits[0], kx);
   d.kps_x = kx;
-  d.n_split_x = (int)((d.ng + kx - 1) / kx);
+  d.n_split_x_cap = std::max(d.n_split_x, split(kTriSplits[3], km));
 }
 
 // Places every buffer; with a.base == nullptr only sizes.
@@ -573,7 +593,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.dv = a.take<double>(T * ng);
     d.eparts = a.take<double>(2 * T);
     d.W = a.take<double>(T * NN);
-    d.part = a.take<double>(T * d.n_split * NN);
+    d.part = a.take<double>(T * std::max(d.n_split, d.n_split_cap) * NN);
     if (d.mixed) {
       // N <= 256: K-blocked for the triangle projection; else orbital-major [N][ng]
       const long npsi = d.N <= rtk::proj_tri_max_n() ? rtk::proj_tri_elems(d.N, ng) : N * ng;
@@ -590,7 +610,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
       d.rho_gs = a.take<double>(ng);
       d.S_gs = a.take<double>(NN);
       d.dv32 = a.take<float>(T * ng);
-      d.part32 = a.take<float>(T * d.n_split_x * NN);
+      d.part32 = a.take<float>(T * std::max(d.n_split_x, d.n_split_x_cap) * NN);
     }
     d.P0 = a.take<double>(T * 2 * NN);
     d.P1 = a.take<double>(T * 2 * NN);
@@ -724,7 +744,7 @@ rt_status project(rt_ctx* c, SysDev& d, const double* A, const double* B, const 
 rt_status apply_h64(rt_ctx* c, SysDev& d, const double* psi, double* hpsi, const double* vloc, int n) {
   {
     Timed tm(c, PH_STENCIL);
-    CK(rtk::stencil<double>(c->stream, psi, hpsi, vloc, n, d.nx, d.ny, d.nz, d.h, d.coef));
+    CK(rtk::stencil<double>(c->stream, psi, hpsi, vloc, n, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[0], d.st_nzc[0]));
   }
   if (d.nl.rank) {
     Timed tm(c, PH_NONLOCAL);
@@ -739,7 +759,7 @@ rt_status apply_h64(rt_ctx* c, SysDev& d, const double* psi, double* hpsi, const
 rt_status apply_h32(rt_ctx* c, SysDev& d, const float* psi, float* hpsi, int n) {
   {
     Timed tm(c, PH_STENCIL);
-    CK(rtk::stencil<float>(c->stream, psi, hpsi, d.vloc32, n, d.nx, d.ny, d.nz, d.h, d.coef));
+    CK(rtk::stencil<float>(c->stream, psi, hpsi, d.vloc32, n, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[1], d.st_nzc[1]));
   }
   if (d.nl.rank) {
     Timed tm(c, PH_NONLOCAL);
@@ -1814,6 +1834,283 @@ rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs
   return RT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoints: every value the next step reads, per system in context order.
+// Layout: header {magic, version, n_sys, hist_cap}; per system: shape and counters
+// (N, T, nx, ny, nz, step, feat, mlp, mom_head, cd_cur, cv_head, n_hist, x_valid),
+// mlp_on[T], per slot the fallback history (count, then doubles); then the arrays
+// P_0 [T][2N^2], H_0, H_-1, H_-2 [T][N^2], the observables [T][step + 1][5], and
+// with features the moment ring, coarse density and potential rings and the
+// assembled feature vector.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kCkptMagic = 0x4b435452u;  // "RTCK"
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptWriter {
+  char* p;
+  size_t n = 0, cap;
+  bool sizing;
+  void put(const void* src, size_t bytes) {
+    if (!sizing && n + bytes <= cap) std::memcpy(p + n, src, bytes);
+    n += bytes;
+  }
+  template <class V>
+  void val(const V& v) { put(&v, sizeof(V)); }
+};
+
+struct CkptReader {
+  const char* p;
+  size_t n = 0, cap;
+  bool ok = true;
+  const char* take(size_t bytes) {
+    if (!ok || n + bytes > cap) { ok = false; return nullptr; }
+    const char* r = p + n;
+    n += bytes;
+    return r;
+  }
+  template <class V>
+  V val() {
+    V v{};
+    if (const char* r = take(sizeof(V))) std::memcpy(&v, r, sizeof(V));
+    return v;
+  }
+};
+
+struct CkptArray {
+  const void* dev;
+  size_t bytes;
+};
+
+// device arrays of system d in checkpoint order (hist rows: step + 1 of each slot)
+std::vector<CkptArray> ckpt_arrays(const rt_ctx* c, const SysDev& d) {
+  const size_t NN = (size_t)d.N * d.N, T = d.T;
+  std::vector<CkptArray> a{{d.P0, T * 2 * NN * 8}, {d.H0, T * NN * 8}, {d.Hm1, T * NN * 8}, {d.Hm2, T * NN * 8}};
+  for (int t = 0; t < d.T; ++t) a.push_back({d.hist + (size_t)t * 5 * (c->hist_cap + 1), (size_t)5 * (d.step + 1) * 8});
+  if (d.feat) {
+    a.push_back({d.mom_ring, T * 72 * 4});
+    a.push_back({d.cd_ring, T * 2 * 4096 * 4});
+    a.push_back({d.cv_ring, T * 3 * 4096 * 8});
+    a.push_back({d.xbuf, T * (size_t)kNIn * 4});
+  }
+  return a;
+}
+
+// Serialises (w.sizing) or writes the checkpoint; device arrays are copied with
+// dev_copy(host_offset, array).
+template <class F>
+void ckpt_walk(const rt_ctx* c, CkptWriter& w, F&& dev_copy) {
+  w.val(kCkptMagic);
+  w.val(kCkptVersion);
+  w.val((int32_t)c->sys.size());
+  w.val((int32_t)c->hist_cap);
+  for (const SysDev& d : c->sys) {
+    const int32_t hdr[13] = {d.N, d.T, d.nx, d.ny, d.nz, d.step, d.feat, d.mlp, d.mom_head, d.cd_cur, d.cv_head,
+                             d.n_hist, d.x_valid};
+    w.put(hdr, sizeof(hdr));
+    for (int t = 0; t < d.T; ++t) w.val((int32_t)d.mlp_on[t]);
+    for (int t = 0; t < d.T; ++t) {
+      w.val((int64_t)d.r1_linear[t].size());
+      w.put(d.r1_linear[t].data(), d.r1_linear[t].size() * sizeof(double));
+    }
+    for (const CkptArray& a : ckpt_arrays(c, d)) {
+      if (!w.sizing && w.n + a.bytes <= w.cap) dev_copy(w.n, a);
+      w.n += a.bytes;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: each tunable launch shape of a system is timed over its candidates
+// on the context's own buffers (hipEvents on the context's stream, one warm-up
+// and three timed launches each) and the fastest kept.  Choices are cached in a
+// text file, one line per (GPU architecture, kernel, grid, N, trajectories):
+// "key value1 value2"; a later context with the same key takes the cached value
+// without timing.  The stencil tiling changes no arithmetic; the projection
+// splits change the order of the partial sums (results within rounding).
+// ---------------------------------------------------------------------------
+enum { TUNE_STENCIL64 = 0, TUNE_STENCIL32 = 1, TUNE_PROJ64 = 2, TUNE_PROJ_MIXED = 3 };
+const char* kTuneNames[4] = {"stencil_fp64", "stencil_fp32", "projection_fp64", "projection_bf16x3"};
+
+std::string tune_arch() {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+std::string tune_key(const std::string& arch, int kernel, const SysDev& d) {
+  char b[160];
+  std::snprintf(b, sizeof(b), "%s|%s|%dx%dx%d|N%d|T%d", arch.c_str(), kTuneNames[kernel], d.nx, d.ny, d.nz, d.N,
+                d.T);
+  return b;
+}
+
+std::map<std::string, std::vector<int>> tune_cache_read(const char* path) {
+  std::map<std::string, std::vector<int>> m;
+  if (!path) return m;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return m;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char key[256];
+    int v0 = 0, v1 = 0;
+    if (std::sscanf(line, "%255s %d %d", key, &v0, &v1) == 3) m[key] = {v0, v1};
+  }
+  std::fclose(f);
+  return m;
+}
+
+void drop_graphs(SysDev& d) {
+  for (auto& kv : d.graphs) (void)hipGraphExecDestroy(kv.second);
+  d.graphs.clear();
+}
+
+// applies a launch shape (validated); the projections re-split
+rt_status tune_apply(rt_ctx* c, SysDev& d, int kernel, int p1, int p2) {
+  switch (kernel) {
+    case TUNE_STENCIL64:
+    case TUNE_STENCIL32: {
+      std::vector<int> ty, nz;
+      if (kernel == TUNE_STENCIL64) rtk::stencil_tiles<double>(d.nx, d.ny, d.nz, d.N, ty, nz);
+      else rtk::stencil_tiles<float>(d.nx, d.ny, d.nz, d.N, ty, nz);
+      if ((p1 && std::find(ty.begin(), ty.end(), p1) == ty.end()) || p2 < 0 || p2 > d.nz)
+        return fail(c, RT_EINVAL, "stencil tiling (y rows " + std::to_string(p1) + ", z chunks " +
+                                      std::to_string(p2) + ") not available on this grid");
+      d.st_ty[kernel] = p1;
+      d.st_nzc[kernel] = p2;
+      break;
+    }
+    case TUNE_PROJ64:
+      if (p1 && std::find(std::begin(kGemmTargets), std::end(kGemmTargets), p1) == std::end(kGemmTargets))
+        return fail(c, RT_EINVAL, "FP64 projection target must be 0, 1024, 2048 or 4096 blocks");
+      d.gemm_target = p1;
+      choose_split(d);
+      break;
+    case TUNE_PROJ_MIXED:
+      if (!d.mixed || d.N > rtk::proj_tri_max_n())
+        return fail(c, RT_EINVAL, "the BF16x3 triangle projection is not used by this system");
+      if (p1 && std::find(std::begin(kTriSplits), std::end(kTriSplits), p1) == std::end(kTriSplits))
+        return fail(c, RT_EINVAL, "BF16x3 projection splits must be 0, 85, 128, 170 or 255");
+      d.tri_splits = p1;
+      choose_split_tri(d);
+      break;
+    default:
+      return fail(c, RT_EINVAL, "unknown tunable kernel");
+  }
+  drop_graphs(d);  // captured sequences hold the old launch shapes
+  return RT_OK;
+}
+
+// average device milliseconds of one call of f (one warm-up, three timed)
+template <class F>
+rt_status tune_time(rt_ctx* c, F&& f, double& ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  CK(hipEventCreate(&a));
+  CK(hipEventCreate(&b));
+  rt_status st = f();
+  if (st == RT_OK) {
+    CK(hipEventRecord(a, c->stream));
+    for (int i = 0; i < 3 && st == RT_OK; ++i) st = f();
+    CK(hipEventRecord(b, c->stream));
+    CK(hipEventSynchronize(b));
+    float e = 0.f;
+    CK(hipEventElapsedTime(&e, a, b));
+    ms = e / 3.0;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
+// one launch of the tunable kernel as the time step runs it
+rt_status tune_run(rt_ctx* c, SysDev& d, int kernel) {
+  hipStream_t s = c->stream;
+  const long NN = nsq(d.N);
+  switch (kernel) {
+    case TUNE_STENCIL64:
+      CK(rtk::stencil<double>(s, d.psi, d.hpsi, d.vloc_gs, d.N, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[0],
+                              d.st_nzc[0]));
+      return RT_OK;
+    case TUNE_STENCIL32: {
+      float* in = reinterpret_cast<float*>(d.hpsi);  // FP32 copy of the orbitals, then the output
+      CK(rtk::stencil<float>(s, in, in + (long)d.N * d.ng, d.vloc32, d.N, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[1],
+                             d.st_nzc[1]));
+      return RT_OK;
+    }
+    case TUNE_PROJ64:
+      if (c->run.hupdate == RT_HUPDATE_FULL) return project(c, d, d.psi, d.hpsi, nullptr, d.Hn);
+      {
+        const long sp = (long)d.n_split * NN;
+        CK(rtk::gemm_nt_f64(s, d.N, d.N, d.ng, d.psi, d.ng, d.psi, d.ng, d.dv, d.part, d.kps, d.n_split, 1, d.big,
+                            rtk::Batch{d.T, nullptr, 0, 0, d.ng, sp}));
+        CK(rtk::reduce_parts(s, d.part, d.n_split, d.N, d.N, d.h3, d.Hn, 1, d.Hgs, d.T, sp, 0, NN, nullptr));
+      }
+      return RT_OK;
+    default:
+      CK(proj_x(s, d, d.T, nullptr));
+      CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.Hgs, d.Hn, d.T, nullptr, 0));
+      return RT_OK;
+  }
+}
+
+rt_status autotune_system(rt_ctx* c, SysDev& d, int si, const std::string& arch,
+                          std::map<std::string, std::vector<int>>& cache, FILE* out, std::string& rep) {
+  hipStream_t s = c->stream;
+  std::vector<int> kernels{TUNE_STENCIL64, TUNE_STENCIL32};
+  if (!d.mixed) kernels.push_back(TUNE_PROJ64);
+  if (d.mixed && d.N <= rtk::proj_tri_max_n()) kernels.push_back(TUNE_PROJ_MIXED);
+  // inputs of the timed launches: FP32 orbitals and potential, the ground-state
+  // potential change (zero) as projection weights
+  CK(rtk::cast_d2f(s, reinterpret_cast<float*>(d.hpsi), d.psi, (long)d.N * d.ng));
+  CK(rtk::cast_d2f(s, d.vloc32, d.vloc_gs, d.ng));
+  if (!d.mixed) CK(rtk::sub_d(s, d.dv, d.vloc, d.vloc_gs, d.ng, d.T, nullptr));
+  else CK(rtk::delta_f32(s, d.dv32, d.vloc, d.vloc_gs, d.ng, d.T, nullptr));
+  for (int k : kernels) {
+    const std::string key = tune_key(arch, k, d);
+    auto it = cache.find(key);
+    char line[320];
+    if (it != cache.end()) {
+      RET(tune_apply(c, d, k, it->second[0], it->second[1]));
+      std::snprintf(line, sizeof(line), "system %d %s: %d %d (cached)\n", si, kTuneNames[k], it->second[0],
+                    it->second[1]);
+      rep += line;
+      continue;
+    }
+    std::vector<std::pair<int, int>> cand;
+    if (k == TUNE_STENCIL64 || k == TUNE_STENCIL32) {
+      std::vector<int> ty, nz;
+      if (k == TUNE_STENCIL64) rtk::stencil_tiles<double>(d.nx, d.ny, d.nz, d.N, ty, nz);
+      else rtk::stencil_tiles<float>(d.nx, d.ny, d.nz, d.N, ty, nz);
+      cand.push_back({0, 0});
+      for (int a : ty)
+        for (int b : nz) cand.push_back({a, b});
+    } else if (k == TUNE_PROJ64) {
+      cand.push_back({0, 0});
+      for (int v : kGemmTargets) cand.push_back({v, 0});
+    } else {
+      cand.push_back({0, 0});
+      for (int v : kTriSplits) cand.push_back({v, 0});
+    }
+    double best = 1e300, t_def = 0.0;
+    std::pair<int, int> pick{0, 0};
+    for (auto& p : cand) {
+      RET(tune_apply(c, d, k, p.first, p.second));
+      double ms = 0.0;
+      RET(tune_time(c, [&] { return tune_run(c, d, k); }, ms));
+      if (p.first == 0 && p.second == 0) t_def = ms;
+      if (ms < best) { best = ms; pick = p; }
+    }
+    RET(tune_apply(c, d, k, pick.first, pick.second));
+    cache[key] = {pick.first, pick.second};
+    if (out) std::fprintf(out, "%s %d %d\n", key.c_str(), pick.first, pick.second);
+    std::snprintf(line, sizeof(line), "system %d %s: %d %d, %.1f us (built-in choice %.1f us, %zu candidates)\n",
+                  si, kTuneNames[k], pick.first, pick.second, 1e3 * best, 1e3 * t_def, cand.size());
+    rep += line;
+  }
+  return RT_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2040,6 +2337,135 @@ rt_status rt_set_state(rt_ctx* c, int traj, const double* p_re, const double* p_
     CK(hipMemcpyAsync(d.Hm2 + t.slot * NN, hm1, NN * 8, hipMemcpyHostToDevice, s));
   }
   CK(hipStreamSynchronize(s));
+  return RT_OK;
+}
+
+rt_status rt_autotune(rt_ctx* c, const char* cache_path) {
+  if (!c) return RT_EINVAL;
+  const std::string arch = tune_arch();
+  auto cache = tune_cache_read(cache_path);
+  FILE* out = cache_path ? std::fopen(cache_path, "a") : nullptr;
+  std::string rep = "architecture " + arch + "\n";
+  rt_status st = RT_OK;
+  for (size_t i = 0; i < c->sys.size() && st == RT_OK; ++i) st = autotune_system(c, c->sys[i], (int)i, arch, cache, out, rep);
+  if (out) std::fclose(out);
+  c->tune_report = rep;
+  if (st == RT_OK) CK(hipStreamSynchronize(c->stream));
+  return st;
+}
+
+rt_status rt_tune_set(rt_ctx* c, int si, int kernel, int p1, int p2) {
+  if (!c) return RT_EINVAL;
+  if (si < 0 || si >= (int)c->sys.size()) return fail(c, RT_EINVAL, "sys_index out of range");
+  return tune_apply(c, c->sys[si], kernel, p1, p2);
+}
+
+rt_status rt_tune_get(rt_ctx* c, int si, int kernel, int* p1, int* p2) {
+  if (!c || !p1 || !p2) return RT_EINVAL;
+  if (si < 0 || si >= (int)c->sys.size()) return fail(c, RT_EINVAL, "sys_index out of range");
+  const SysDev& d = c->sys[si];
+  switch (kernel) {
+    case TUNE_STENCIL64: case TUNE_STENCIL32: *p1 = d.st_ty[kernel]; *p2 = d.st_nzc[kernel]; break;
+    case TUNE_PROJ64: *p1 = d.gemm_target; *p2 = d.n_split; break;
+    case TUNE_PROJ_MIXED: *p1 = d.tri_splits; *p2 = d.n_split_x; break;
+    default: return fail(c, RT_EINVAL, "unknown tunable kernel");
+  }
+  return RT_OK;
+}
+
+const char* rt_tune_report(const rt_ctx* c) { return c ? c->tune_report.c_str() : ""; }
+
+rt_status rt_checkpoint_size(rt_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return RT_EINVAL;
+  CkptWriter w{nullptr, 0, 0, true};
+  ckpt_walk(c, w, [](size_t, const CkptArray&) {});
+  *bytes = w.n;
+  return RT_OK;
+}
+
+rt_status rt_checkpoint_save(rt_ctx* c, void* host, size_t bytes) {
+  if (!c || !host) return RT_EINVAL;
+  size_t need = 0;
+  RET(rt_checkpoint_size(c, &need));
+  if (bytes < need) return fail(c, RT_ENOMEM, "rt_checkpoint_save: buffer of " + std::to_string(bytes) +
+                                                   " bytes, need " + std::to_string(need));
+  CkptWriter w{static_cast<char*>(host), 0, bytes, false};
+  hipError_t err = hipSuccess;
+  ckpt_walk(c, w, [&](size_t off, const CkptArray& a) {
+    if (err == hipSuccess && a.bytes)
+      err = hipMemcpyAsync(static_cast<char*>(host) + off, a.dev, a.bytes, hipMemcpyDeviceToHost, c->stream);
+  });
+  CK(err);
+  CK(hipStreamSynchronize(c->stream));
+  return RT_OK;
+}
+
+rt_status rt_checkpoint_load(rt_ctx* c, const void* host, size_t bytes) {
+  if (!c || !host) return RT_EINVAL;
+  // validate everything before anything is changed
+  CkptReader r{static_cast<const char*>(host), 0, bytes};
+  if (r.val<uint32_t>() != kCkptMagic || r.val<uint32_t>() != kCkptVersion)
+    return fail(c, RT_EINVAL, "rt_checkpoint_load: not a checkpoint of this library version");
+  if (r.val<int32_t>() != (int32_t)c->sys.size()) return fail(c, RT_EINVAL, "rt_checkpoint_load: system count differs");
+  r.val<int32_t>();  // the saving context's history capacity (any)
+  struct SysState {
+    int32_t hdr[13];
+    std::vector<int> mlp_on;
+    std::vector<std::vector<double>> r1;
+    size_t arrays_at;
+  };
+  std::vector<SysState> st(c->sys.size());
+  for (size_t i = 0; i < c->sys.size(); ++i) {
+    const SysDev& d = c->sys[i];
+    SysState& x = st[i];
+    const char* h = r.take(sizeof(x.hdr));
+    if (!h) break;
+    std::memcpy(x.hdr, h, sizeof(x.hdr));
+    if (x.hdr[0] != d.N || x.hdr[1] != d.T || x.hdr[2] != d.nx || x.hdr[3] != d.ny || x.hdr[4] != d.nz ||
+        x.hdr[6] != (int)d.feat || x.hdr[7] != (int)d.mlp)
+      return fail(c, RT_EINVAL, "rt_checkpoint_load: system " + std::to_string(i) + " has a different shape or mode");
+    if (x.hdr[5] < 0 || x.hdr[5] > c->hist_cap)
+      return fail(c, RT_EINVAL, "rt_checkpoint_load: step beyond this context's history capacity");
+    x.mlp_on.resize(d.T);
+    for (int t = 0; t < d.T; ++t) x.mlp_on[t] = r.val<int32_t>();
+    x.r1.resize(d.T);
+    for (int t = 0; t < d.T; ++t) {
+      const int64_t k = r.val<int64_t>();
+      if (k < 0 || k > (int64_t)(1L << 30)) { r.ok = false; break; }
+      const char* v = r.take((size_t)k * sizeof(double));
+      if (!v) break;
+      x.r1[t].resize(k);
+      std::memcpy(x.r1[t].data(), v, (size_t)k * sizeof(double));
+    }
+    x.arrays_at = r.n;
+    // arrays: sizes as this context would write them at the saved step
+    SysDev probe = d;
+    probe.step = x.hdr[5];
+    for (const CkptArray& a : ckpt_arrays(c, probe))
+      if (!r.take(a.bytes)) break;
+  }
+  if (!r.ok || r.n != bytes) return fail(c, RT_EINVAL, "rt_checkpoint_load: truncated or oversized checkpoint");
+  for (size_t i = 0; i < c->sys.size(); ++i) {
+    SysDev& d = c->sys[i];
+    const SysState& x = st[i];
+    d.step = x.hdr[5];
+    d.mom_head = x.hdr[8];
+    d.cd_cur = x.hdr[9];
+    d.cv_head = x.hdr[10];
+    d.n_hist = x.hdr[11];
+    d.x_valid = x.hdr[12] != 0;
+    d.mlp_on = x.mlp_on;
+    d.r1_linear = x.r1;
+    size_t off = x.arrays_at;
+    for (const CkptArray& a : ckpt_arrays(c, d)) {
+      if (a.bytes)
+        CK(hipMemcpyAsync(const_cast<void*>(a.dev), static_cast<const char*>(host) + off, a.bytes,
+                          hipMemcpyHostToDevice, c->stream));
+      off += a.bytes;
+    }
+    if (d.feat) RET(upload_flags(c, d.mlp_mask, d.mlp_on));
+  }
+  CK(hipStreamSynchronize(c->stream));
   return RT_OK;
 }
 

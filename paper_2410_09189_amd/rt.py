@@ -90,6 +90,13 @@ def _load():
         "rt_dipole": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp], ctypes.c_int),
         "rt_get_matrix": ([vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
         "rt_set_state": ([vp, ctypes.c_int, _dp, _dp, _dp, _dp], ctypes.c_int),
+        "rt_autotune": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "rt_tune_set": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "rt_tune_get": ([vp, ctypes.c_int, ctypes.c_int, _ip, _ip], ctypes.c_int),
+        "rt_tune_report": ([vp], ctypes.c_char_p),
+        "rt_checkpoint_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "rt_checkpoint_save": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "rt_checkpoint_load": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "rt_eval_h": ([vp, ctypes.c_int, vp, vp], ctypes.c_int),
         "rt_propagate": ([vp, ctypes.c_int, vp, ctypes.c_double, vp, vp, _ip], ctypes.c_int),
         "rt_get_grid": ([vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
@@ -368,6 +375,40 @@ def rt_ground_state(system, params, workspace_ptr, ws_bytes, stream_ptr, psi_out
         err.eps, err.stats = eps, stats
         raise err
     return eps, stats
+
+
+RT_TUNE_STENCIL_FP64, RT_TUNE_STENCIL_FP32, RT_TUNE_PROJ_FP64, RT_TUNE_PROJ_MIXED = 0, 1, 2, 3
+
+
+def rt_autotune(ctx, cache_path=None) -> str:
+    """Times the launch-shape candidates of the context's kernels and keeps the
+    fastest (cache_path: text cache of earlier choices).  Returns the report."""
+    _check(lib.rt_autotune(ctx, None if cache_path is None else str(cache_path).encode()), ctx)
+    return lib.rt_tune_report(ctx).decode()
+
+
+def rt_tune_set(ctx, sys_index, kernel, p1, p2=0):
+    _check(lib.rt_tune_set(ctx, sys_index, kernel, p1, p2), ctx)
+
+
+def rt_tune_get(ctx, sys_index, kernel):
+    a, b = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib.rt_tune_get(ctx, sys_index, kernel, ctypes.byref(a), ctypes.byref(b)), ctx)
+    return a.value, b.value
+
+
+def rt_checkpoint_save(ctx) -> np.ndarray:
+    """The context's checkpoint as a host byte array."""
+    n = ctypes.c_size_t(0)
+    _check(lib.rt_checkpoint_size(ctx, ctypes.byref(n)), ctx)
+    buf = np.empty(n.value, dtype=np.uint8)
+    _check(lib.rt_checkpoint_save(ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.size), ctx)
+    return buf
+
+
+def rt_checkpoint_load(ctx, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(lib.rt_checkpoint_load(ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.size), ctx)
 
 
 def rt_eigh_workspace_size(n) -> int:

@@ -15,5 +15,6 @@ from .systems import (  # noqa: F401
     batch_systems,
     lowpass_orbitals,
     basis_mixing,
+    ground_state_start,
     CONFIGS,
 )

@@ -176,8 +176,14 @@ CONFIGS = {
     # and 2 have a degenerate highest occupied level).
     "c1_parity_32": dict(n=32, h=0.35, n_atoms=4, n_occ=8, n_virt=8, seed=3,
                          region=(0.25, 0.75), nl_rank=0, dt=0.05, n_steps=200),
-    "c2_mixed_96": dict(n=96, h=0.3, n_atoms=40, n_occ=160, n_virt=80, seed=2,
-                        region=(0.2, 0.8), nl_rank=4, dt=0.05, n_steps=2000),
+    # seed 14: the first seed >= 2 whose self-consistent ground state (GPU solver,
+    # start block of N + 30 smooth random vectors of the same seed) converges with a
+    # HOMO-LUMO gap > 1e-3 Ha (1.03e-3; active-space edge gap 1.1e-3 Ha); the
+    # density loops of seeds 2-13 end with gaps of 2e-5 - 8.8e-4 Ha.
+    "c2_mixed_96": dict(n=96, h=0.3, n_atoms=40, n_occ=160, n_virt=80, seed=14,
+                        region=(0.2, 0.8), nl_rank=4, dt=0.05, n_steps=2000,
+                        gs=dict(n_guard=30, degree=24, max_scf=150, max_passes=20, tol_rho=1e-10, tol_res=1e-9,
+                                mix=0.15)),
     "c5_cluster_192": dict(n=192, h=0.3, n_atoms=600, n_occ=2400, n_virt=600, seed=5,
                            dt=0.05, n_steps=500),
 }
@@ -197,6 +203,13 @@ def config_run(name: str, **over) -> RunParams:
     for k, v in over.items():
         setattr(rp, k, v)
     return rp
+
+
+def ground_state_start(name: str) -> np.ndarray:
+    """Start block of the GPU ground-state solve of a configuration: N + n_guard
+    smooth random vectors of the configuration's seed."""
+    s = config_system(name)
+    return lowpass_orbitals(s.n, s.h, s.n_orb + CONFIGS[name]["gs"]["n_guard"], seed=s.seed)
 
 
 def batch_systems(n_mol=16, seed0=300, h=0.35) -> List[System]:

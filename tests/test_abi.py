@@ -182,3 +182,15 @@ def test_eigh_noalloc_rejects_sizes_beyond_its_static_array_without_a_gpu():
     with pytest.raises(rt.RTError) as e:
         rt.rt_eigh_noalloc(0, 8, 0, 8, 8)
     assert e.value.status == rt.RT_EINVAL and "NULL" in rt.rt_last_error(None)
+
+
+def test_checkpoint_calls_refuse_null_contexts_without_a_gpu():
+    import ctypes
+
+    from paper_2410_09189_amd import rt
+
+    n = ctypes.c_size_t(0)
+    assert rt.lib.rt_checkpoint_size(None, ctypes.byref(n)) == rt.RT_EINVAL
+    buf = (ctypes.c_char * 16)()
+    assert rt.lib.rt_checkpoint_save(None, buf, 16) == rt.RT_EINVAL
+    assert rt.lib.rt_checkpoint_load(None, buf, 16) == rt.RT_EINVAL

@@ -267,7 +267,30 @@ def test_mixed_eval_h_error_is_relative_to_the_perturbation(n, n_orb):
     ses.close()
 
 
+@functools.lru_cache(maxsize=None)
+def _c1_interaction_energy_change():
+    """max_t |E_int(t) - E_int(0)|, E_int = E_H + E_x, along the oracle's 200-step
+    trajectory: the energy that moves between the core and the interaction terms
+    while their sum stays constant."""
+    ref = oracle.run(c1_model(), synth.config_run("c1_parity_32", n_steps=200, h_thrs=1e-12), record_p=True)
+    e = []
+    for P in ref["Ps"]:
+        _, aux = c1_model().h_of_p(P)
+        e.append(aux["e_h"] + aux["e_x"])
+    e = np.array(e)
+    return float(np.max(np.abs(e - e[0])))
+
+
 def test_mixed_c1_trajectory_relative_dipole_error():
+    """Mixed mode against the oracle on the 32^3 molecule, 200 steps.  Dipole:
+    e_mu = max|dmu_mix - dmu_orc| / max|dmu_orc| <= 1e-5.  Energy: BF16x3
+    products (hi*hi' + hi*lo' + lo*hi', relative error ~2^-16 each, FP32 sums)
+    enter only the perturbation parts -- the density change and h^3 Psi^T dV Psi --
+    so the energy they can disturb is the interaction energy E_H + E_x that the
+    dynamics exchanges with the core term (1.03e-3 Ha over this run while the
+    total stays constant to 1e-13).  Bound: the energy-change error is at most
+    1e-5 of that exchange, over the whole run, and so is the drift (slope of a
+    linear fit times the run length)."""
     _say("C1 mixed 200 steps")
     from paper_2410_09189_amd import rt
 
@@ -284,9 +307,16 @@ def test_mixed_c1_trajectory_relative_dipole_error():
     dmu_ref = ref["mu"][:, 0] - ref["mu"][0, 0]
     dmu = mu[:, 0] - mu[0, 0]
     e_mu = np.max(np.abs(dmu - dmu_ref)) / np.max(np.abs(dmu_ref))
-    e_E = np.max(np.abs((E - E[0]) - (ref["E"] - ref["E"][0])))
-    print(f"mixed C1: e_mu {e_mu:.3e}, energy-change err {e_E:.3e}", flush=True)
+    dE = (E - E[0]) - (ref["E"] - ref["E"][0])
+    e_E = np.max(np.abs(dE))
+    t = rp.dt * np.arange(201)
+    drift = abs(np.polyfit(t, E - E[0], 1)[0]) * t[-1]
+    scale = _c1_interaction_energy_change()
+    print(f"mixed C1: e_mu {e_mu:.3e}, energy-change err {e_E:.3e} (drift over the run {drift:.3e}) "
+          f"of interaction-energy exchange {scale:.3e}", flush=True)
     assert e_mu < 1e-5
+    assert e_E <= 1e-5 * scale
+    assert drift <= 1e-5 * scale
     assert np.max(np.abs(tr - 16.0)) < 1e-12
     assert abs(mu[0, 0] - ref["mu"][0, 0]) < 1e-10
 
