@@ -194,6 +194,9 @@ def run_leg(rt, torch, sa, s, args, precision, hupdate, h_thrs, dp_thrs, profile
                     precision=precision, predictor=predictor)
     ses = rt.Session([sa], ra)
     ctx = ses.ctx
+    if not args.no_tune:
+        # launch shapes from the library's autotuner (timed once per shape, then cached)
+        rt.rt_autotune(ctx, TUNE_CACHE)
     rt.rt_step(ctx, args.warmup, n_traj=T, stats=False)
     torch.cuda.synchronize()
     if profile:
@@ -213,6 +216,8 @@ def run_leg(rt, torch, sa, s, args, precision, hupdate, h_thrs, dp_thrs, profile
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+# autotuner cache of this run (a fresh file per run: the choices are timed on this GPU)
+TUNE_CACHE = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"rt_tune_cache_{os.getpid()}.txt")
 
 
 def measured_traffic(key):
@@ -249,7 +254,7 @@ def roofline_of(prof, N, ng, mixed, full):
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes}
 
 
-def batched_molecules(rt, torch, steps, warmup):
+def batched_molecules(rt, torch, steps, warmup, tune=True):
     """Ragged batch: 16 synthetic molecules (grids 32^3..64^3, 10..60 orbitals) x the
     three kicks, mixed precision, stepped in one context (each molecule on its own
     stream, all advancing through the self-consistency rounds together), against the
@@ -272,6 +277,8 @@ def batched_molecules(rt, torch, steps, warmup):
 
     nm, nt = len(mols), len(AXES) * len(mols)
     ses = rt.Session([sa(m, p) for m, p in zip(mols, psis)], ra(nm))
+    if tune:
+        rt.rt_autotune(ses.ctx, TUNE_CACHE)
     rt.rt_step(ses.ctx, warmup, n_traj=nt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -280,6 +287,9 @@ def batched_molecules(rt, torch, steps, warmup):
     t_one = time.perf_counter() - t0
     ses.close()
     sess = [rt.Session([sa(m, p)], ra(1)) for m, p in zip(mols, psis)]
+    if tune:
+        for x in sess:
+            rt.rt_autotune(x.ctx, TUNE_CACHE)
     for x in sess:
         rt.rt_step(x.ctx, warmup, n_traj=len(AXES))
     torch.cuda.synchronize()
@@ -489,6 +499,34 @@ def learned_predictor(rt, torch, sa, s):
             "dipole_max_abs": float(np.max(np.abs(mu_l - mu_l[0])))}
 
 
+def ground_state_input(rt, torch, s, name):
+    """The input of the time loop: the molecule's stationary ground state, solved on
+    the GPU from a block of smooth random vectors (not part of the timed step)."""
+    import synth
+
+    N = s.n_orb
+    log(f"ground state of the {s.n[0]}^3 molecule on the GPU")
+    x0 = synth.ground_state_start(name)
+    gsp = synth.CONFIGS[name]["gs"]
+    sa0 = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
+                        n_virt=s.n_virt, psi0=x0, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
+                        nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images)
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter()
+    psi, eps_gs, _, st_gs = rt.ground_state(sa0, rt.gs_params(**gsp))
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter() - t_gs
+    gs_info = {"seconds": round(t_gs, 2), "density_iterations": st_gs["scf_iters"],
+               "homo_lumo_gap": float(eps_gs[s.n_occ] - eps_gs[s.n_occ - 1]),
+               "active_space_edge_gap": float(eps_gs[N] - eps_gs[N - 1]), "rho_err": st_gs["rho_err"],
+               "residual": st_gs["residual"], "params": gsp}
+    log(f"ground state: {t_gs:.1f} s, gap {gs_info['homo_lumo_gap']:.3e}")
+    sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
+                       n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
+                       nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images)
+    return psi, sa, gs_info
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -499,6 +537,13 @@ def main():
                     help="self-consistency thresholds of the equal-dipole-error sweep (must include --h-thrs)")
     ap.add_argument("--dp-thrs", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes instead of the autotuner's")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="run only the profiled mixed leg and print its roofline (for profiler runs of the "
+                         "launches the roofline times)")
+    ap.add_argument("--random-orbitals", action="store_true",
+                    help="smooth random orbitals made orthonormal at init instead of the ground state (for "
+                         "profiler runs: the kernels and their traffic do not depend on the orbitals' values)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-molecule batch leg")
     ap.add_argument("--no-ground-state", action="store_true", help="skip the GPU ground-state leg")
     ap.add_argument("--only-ground-state", action="store_true",
@@ -536,26 +581,17 @@ def main():
     N = s.n_orb
     # the input of the time loop: the molecule's stationary ground state, solved on
     # the GPU from a block of smooth random vectors (not part of the timed step)
-    log(f"ground state of the {s.n[0]}^3 molecule on the GPU")
-    x0 = synth.ground_state_start(name)
-    gsp = synth.CONFIGS[name]["gs"]
-    sa0 = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
-                        n_virt=s.n_virt, psi0=x0, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
-                        nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images)
-    torch.cuda.synchronize()
-    t_gs = time.perf_counter()
-    psi, eps_gs, _, st_gs = rt.ground_state(sa0, rt.gs_params(**gsp))
-    torch.cuda.synchronize()
-    t_gs = time.perf_counter() - t_gs
-    del x0, sa0
-    gs_info = {"seconds": round(t_gs, 2), "density_iterations": st_gs["scf_iters"],
-               "homo_lumo_gap": float(eps_gs[s.n_occ] - eps_gs[s.n_occ - 1]),
-               "active_space_edge_gap": float(eps_gs[N] - eps_gs[N - 1]), "rho_err": st_gs["rho_err"],
-               "residual": st_gs["residual"], "params": gsp}
-    log(f"ground state: {t_gs:.1f} s, gap {gs_info['homo_lumo_gap']:.3e}")
-    sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
-                       n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
-                       nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images)
+    if args.random_orbitals:
+        log("smooth random orbitals (profiling run)")
+        x = synth.lowpass_orbitals(s.n, s.h, N, seed=s.seed)
+        psi = torch.from_numpy(x.reshape(N, -1)).cuda()
+        del x
+        sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
+                           n_virt=s.n_virt, psi0=psi, nl_rank=s.nl_rank, nl_rcut=s.nl_rcut,
+                           nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images, orthonormalize=True)
+        gs_info = {"skipped": "random orbitals"}
+    else:
+        psi, sa, gs_info = ground_state_input(rt, torch, s, name)
     if args.only_variants:
         log("variants: non-orthogonal basis, fourth-order Magnus, pulses")
         print(json.dumps({"variants_96": variants(rt, torch, s, psi, args)}), flush=True)
@@ -563,6 +599,16 @@ def main():
     if args.only_learned:
         log("learned predictor: record, train, evaluate")
         print(json.dumps({"learned_predictor_96": learned_predictor(rt, torch, sa, s)}), flush=True)
+        return
+    if args.roofline_only:
+        log("profiled mixed leg only (quadratic first guess, paper threshold)")
+        prof = run_leg(rt, torch, sa, s, args, rt.RT_MIXED, rt.RT_HUPDATE_LOCAL, args.h_thrs, args.dp_thrs, True,
+                       predictor=rt.RT_PRED_QUADRATIC)
+        prof["ses"].close()
+        print(json.dumps({"roofline": roofline_of(prof["prof"], N, s.ng, True, False),
+                          "updates_per_step": sum(x[0] for x in prof["stats"]) / len(prof["stats"]),
+                          "phases_ms": {k: round(v[0], 3) for k, v in prof["prof"].items() if v[1]},
+                          "phases_launches": {k: v[1] for k, v in prof["prof"].items() if v[1]}}), flush=True)
         return
     log("reference: FP64, tight thresholds (1e-12, 1e-15)")
     ref = run_leg(rt, torch, sa, s, args, rt.RT_FP64, rt.RT_HUPDATE_FULL, 1e-12, 1e-15, False)
@@ -597,8 +643,16 @@ def main():
     prof_fp64_local = run_leg(rt, torch, sa, s, args, rt.RT_FP64, rt.RT_HUPDATE_LOCAL, args.h_thrs, args.dp_thrs,
                               True)
     prof_fp64_local["ses"].close()
-    prof_mixed = run_leg(rt, torch, sa, s, args, rt.RT_MIXED, rt.RT_HUPDATE_LOCAL, args.h_thrs, args.dp_thrs, True)
+    # the mixed profile runs the quadratic first guess: one Hamiltonian update per step
+    # at the paper's threshold, so every density and projection launch carries all
+    # three trajectories (the roofline's per-launch work)
+    prof_mixed = run_leg(rt, torch, sa, s, args, rt.RT_MIXED, rt.RT_HUPDATE_LOCAL, args.h_thrs, args.dp_thrs, True,
+                         predictor=rt.RT_PRED_QUADRATIC)
     ctx = prof_mixed["ses"].ctx
+    tuned = {} if args.no_tune else {
+        k: rt.rt_tune_get(ctx, 0, v) for k, v in (("stencil_fp64", rt.RT_TUNE_STENCIL_FP64),
+                                                   ("stencil_fp32", rt.RT_TUNE_STENCIL_FP32),
+                                                   ("projection_bf16x3", rt.RT_TUNE_PROJ_MIXED))}
 
     def dip_err(leg):
         d = leg["mu"] - leg["mu"][0]
@@ -636,7 +690,12 @@ def main():
             "hbm_frac": (2 * b * N * s.ng + b * s.ng) / t_apply / PEAK_HBM,
             "stencil_only": {"avg_launch_us": t_st * 1e6, "algorithmic_bytes_per_launch": st_bytes,
                              "achieved_GBps": st_bytes / t_st / 1e9, "frac": st_bytes / t_st / PEAK_HBM,
-                             "traffic": measured_traffic("stencil_fd8_fp32" if dt_ else "stencil_fd8_fp64")},
+                             # counted at the built-in tiling; another tiling re-reads other halo rows
+                             "traffic": measured_traffic("stencil_fd8_fp32" if dt_ else "stencil_fd8_fp64")
+                             if rt.rt_tune_get(ctx, 0, rt.RT_TUNE_STENCIL_FP32 if dt_ else
+                                               rt.RT_TUNE_STENCIL_FP64) == (0, 0) else None,
+                             "tiling": rt.rt_tune_get(ctx, 0, rt.RT_TUNE_STENCIL_FP32 if dt_ else
+                                                      rt.RT_TUNE_STENCIL_FP64)},
         }
     prof_mixed["ses"].close()
     del x64, y64, x32, y32
@@ -680,7 +739,7 @@ def main():
     plain_ok = [r for r in sweep if r["method"] == "plain_fp64" and r["dipole_rel_err"] <= max(
         e_ref, head.get("dipole_rel_err", e_ref))]
     plain_match = max(plain_ok, key=lambda r: r["steps_per_s"]) if plain_ok else None
-    best = sm_mixed_lin
+    best = sm_mixed_quad
     # Pareto view: for each mixed sweep point, the fastest plain point whose error is no
     # larger (10 % slack for equal errors), and the speedup over it
     pareto = []
@@ -714,13 +773,14 @@ def main():
         "fp64_local_update": sm_fp64_local,
         "fp64_tight_reference_steps_per_s": args.steps / ref["elapsed"],
         "apply_h_standalone": rates,
+        "autotuned_launch_shapes": tuned,
     }
     out["ground_state"] = gs_info
     log("no-kick control")
     out["no_kick_control"] = no_kick_control(rt, torch, sa)
     if not args.no_batch:
         log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")
-        out["batched_16_molecules"] = batched_molecules(rt, torch, args.steps, args.warmup)
+        out["batched_16_molecules"] = batched_molecules(rt, torch, args.steps, args.warmup, tune=not args.no_tune)
     if not args.no_variants:
         log("variants: non-orthogonal basis, fourth-order Magnus, pulses")
         out["variants_96"] = variants(rt, torch, s, psi, args)
