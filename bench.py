@@ -554,6 +554,7 @@ def main():
                     help="skip the non-orthogonal / fourth-order Magnus / pulse legs")
     ap.add_argument("--only-variants", action="store_true", help="run only those legs")
     ap.add_argument("--only-192", action="store_true", help="run only the 192^3 apply leg")
+    ap.add_argument("--only-batch", action="store_true", help="run only the 16-molecule batch leg")
     ap.add_argument("--only-learned", action="store_true", help="run only the learned-predictor leg")
     args = ap.parse_args()
     if args.h_thrs not in args.sweep:
@@ -571,6 +572,11 @@ def main():
     if args.only_192:
         log("FP32 H apply, 192^3 x 3000 orbitals")
         print(json.dumps({"apply_h_192": apply_h_192(rt, torch)}), flush=True)
+        return
+    if args.only_batch:
+        log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")
+        print(json.dumps({"batched_16_molecules": batched_molecules(rt, torch, args.steps, args.warmup,
+                                                                     tune=not args.no_tune)}), flush=True)
         return
     if args.only_ground_state:
         log("ground states of the 16 batch molecules on the GPU")
