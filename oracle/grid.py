@@ -79,14 +79,18 @@ def axis_coords(n: int, h: float) -> np.ndarray:
 
 
 def dipole_coordinate(sys, axis: int) -> np.ndarray:
-    """Centred sawtooth position operator on the periodic cell (Sec. Algorithm:
-    the field is a sawtooth-like potential; the vacuum dipole correction is not
-    applied).  q_i = (i - (n-1)/2) h, jump at the cell faces.  Returned on the
-    [nz, ny, nx] grid."""
+    """Sawtooth position operator on the periodic cell (Sec. Algorithm: the
+    field is a sawtooth-like potential whose jump lies in the vacuum).
+
+    Along the axis the coordinate rises by h per grid plane and drops by n h
+    once, between planes j0 - 1 and j0 (j0 = sys.saw_jump[axis], 0 = the cell
+    faces), centred so that it sums to zero over the cell:
+    q_i = (((i - j0) mod n) - (n-1)/2) h.  Returned on the [nz, ny, nx] grid."""
     nx, ny, nz = sys.n
     h = sys.h
     n_ax = sys.n[axis]
-    q = (np.arange(n_ax) - 0.5 * (n_ax - 1)) * h
+    j0 = int(getattr(sys, "saw_jump", (0, 0, 0))[axis])
+    q = (((np.arange(n_ax) - j0) % n_ax) - 0.5 * (n_ax - 1)) * h
     shape = [1, 1, 1]
     shape[2 - axis] = n_ax
     return np.broadcast_to(q.reshape(shape), (nz, ny, nx)).copy()

@@ -18,7 +18,7 @@ import numpy as np
 from scipy.sparse.linalg import LinearOperator, lobpcg
 
 from .grid import fd_coefficients_float, laplacian
-from .hamiltonian import hartree, lda_x
+from .hamiltonian import electrostatic, lda_x
 from .system import v_ion, projectors, apply_vnl
 
 
@@ -127,7 +127,7 @@ def ground_state(sys, n_extra: int = 4, tol_rho: float = 1e-11, tol_res: float =
     err = np.inf
     it = 0
     for it in range(1, max_scf + 1):
-        vh = hartree(rho, sys)
+        vh, _ = electrostatic(rho, sys)
         vx, _ = lda_x(rho)
         op = _Op(sys, vion + vh + vx)
         etol = max(tol_res * np.sqrt(dv) * 0.1, min(1e-4, 0.01 * err))
@@ -160,7 +160,7 @@ def ground_state(sys, n_extra: int = 4, tol_rho: float = 1e-11, tol_res: float =
         res_opt = sum(ci * r for ci, r in zip(c, hist_res))
         rho = rho_opt + 0.3 * res_opt
     # final orbitals: eigenvectors of H[rho] with the converged input density
-    vh = hartree(rho, sys)
+    vh, _ = electrostatic(rho, sys)
     vx, _ = lda_x(rho)
     op = _Op(sys, vion + vh + vx)
     w, X, res = eigensolve(op, X, nb, tol_res * np.sqrt(dv) * 0.1)
@@ -188,7 +188,7 @@ def dense_ground_state(sys, max_scf: int = 200, tol_rho: float = 1e-12):
     rho = 2.0 * np.sum(U[:, : sys.n_occ] ** 2, axis=1) / dv
     hist_in, hist_res = [], []
     for it in range(1, max_scf + 1):
-        vh = hartree(rho, sys)
+        vh, _ = electrostatic(rho, sys)
         vx, _ = lda_x(rho)
         Hm = H0 + np.diag(vion + vh + vx)
         w, U = np.linalg.eigh(0.5 * (Hm + Hm.T))
@@ -211,7 +211,7 @@ def dense_ground_state(sys, max_scf: int = 200, tol_rho: float = 1e-12):
         rhs[m] = 1.0
         c = np.linalg.solve(B, rhs)[:m]
         rho = sum(ci * r for ci, r in zip(c, hist_in)) + 0.3 * sum(ci * r for ci, r in zip(c, hist_res))
-    vh = hartree(rho, sys)
+    vh, _ = electrostatic(rho, sys)
     vx, _ = lda_x(rho)
     Hm = H0 + np.diag(vion + vh + vx)
     w, U = np.linalg.eigh(0.5 * (Hm + Hm.T))

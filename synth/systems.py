@@ -43,6 +43,10 @@ class System:
     nl_D: Optional[np.ndarray] = None  # (n_atoms, nl_rank) Ha
     n_images: int = 2  # periodic images summed per axis for the local wells
     seed: int = 0
+    # sawtooth jump plane per axis (grid index of the first plane after the jump; 0 = cell faces)
+    saw_jump: tuple = (0, 0, 0)
+    # bit q set: vacuum dipole correction along axis q
+    dipole_correction: int = 0
 
     @property
     def n_orb(self) -> int:
@@ -82,6 +86,10 @@ class System:
             "n_images": self.n_images,
             "seed": self.seed,
         }
+        if tuple(self.saw_jump) != (0, 0, 0):
+            d["saw_jump"] = [int(v) for v in self.saw_jump]
+        if self.dipole_correction:
+            d["dipole_correction"] = int(self.dipole_correction)
         return json.dumps(d, sort_keys=True)
 
     def digest(self) -> str:
