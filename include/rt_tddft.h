@@ -83,6 +83,23 @@ enum { RT_HUPDATE_FULL = 0, RT_HUPDATE_LOCAL = 1 };/* how H[P] is rebuilt, below
  *   combined with magnus_order 4 or the learned predictor (RT_EINVAL); a basis
  *   whose overlap is not positive definite gives RT_EINVAL at rt_init.
  * occ: occupations f_i (nullable: 2 for the first n_occ, 0 for the rest).
+ *
+ * Sawtooth field and vacuum dipole correction (Sec. Algorithm, time-dependent
+ * field: the constant field is a sawtooth potential with a dipole correction in
+ * the vacuum, after Bengtsson, Phys. Rev. B 59, 12301 (1999)).  The position
+ * operator along axis q is the sawtooth s_q(i) = (((i - j0) mod n_q) - (n_q-1)/2) h
+ * with j0 = saw_jump[q] in [0, n_q) (0: jump at the cell faces); it gives the
+ * dipole matrices M_q, the kick and the field.  Put j0 in the vacuum.  If bit q
+ * of dipole_correction is set, the cell's dipole written for electrons,
+ * d_q = h^3 sum rho s_q - sum_a Z_a s_q(R_a) (ions as point charges Z_a at
+ * their positions, s_q taken there in its continuous form), adds
+ * (4 pi / Omega) d_q s_q to V_loc (Omega = cell volume) and (2 pi / Omega) d_q^2
+ * to the electrostatic energy, at every Hamiltonian evaluation (time step and
+ * ground state).  This cancels the uniform field that periodic images of the
+ * dipole set up.  ion_charge: Z_a [n_atoms], nullable: the electron count
+ * sum_i f_i shared equally between the atoms (a neutral cell).  A zeroed tail
+ * is the plain sawtooth with its jump at the faces and no correction.
+ * RT_EINVAL: a jump outside [0, n_q) or a mask outside [0, 7].
  */
 typedef struct {
   int n[3];            /* nx, ny, nz; each in [8, 256]                           */
@@ -103,6 +120,9 @@ typedef struct {
   int psi0_on_device;
   int orthonormalize;
   int nonorthogonal;   /* propagate in the given basis with its overlap (above)  */
+  int saw_jump[3];     /* sawtooth jump plane per axis (above)                   */
+  int dipole_correction; /* bit q: vacuum dipole correction along axis q (above) */
+  const double* ion_charge; /* [n_atoms] point charges for the correction, or NULL */
 } rt_system;
 
 /*

@@ -16,11 +16,14 @@ Paper passages:
     potential with a dipole correction in the vacuum (Bengtsson, Phys. Rev. B
     59, 12301 (1999)).  Reading: along every axis q selected by the system's
     dipole_correction bit mask, the electrons' dipole d_q = h^3 sum rho s_q
-    (s_q the sawtooth coordinate, jump in the vacuum) adds the potential
-    (4 pi / Omega) d_q s_q and the energy (2 pi / Omega) d_q^2, Omega the cell
-    volume.  This cancels the spurious uniform field that the periodic images
-    of the dipole set up across the cell (exact for a density that varies along
-    q only), and H[P] stays the derivative of E[P].
+    (s_q the sawtooth coordinate, jump in the vacuum) minus that of the ions
+    taken as point charges adds the potential (4 pi / Omega) d_q s_q and the
+    energy (2 pi / Omega) d_q^2, Omega the cell volume.  This cancels the
+    spurious uniform field that the periodic images of the dipole set up across
+    the cell (exact for a charge that varies along q only), and H[P] stays the
+    derivative of E[P].  The synthetic ionic wells are not Coulombic, so their
+    point charges are an input of the system (default: the electron count
+    shared equally, a neutral cell).
 """
 
 import numpy as np
@@ -57,24 +60,49 @@ def hartree(rho: np.ndarray, sys) -> np.ndarray:
     return np.fft.ifftn(vg).real.ravel()
 
 
+def ion_charges(sys) -> np.ndarray:
+    """Point charges of the ions for the dipole correction: sys.ion_charge, or
+    the electron count sum_i f_i shared equally between the atoms (a neutral
+    cell)."""
+    q = getattr(sys, "ion_charge", None)
+    if q is not None:
+        return np.asarray(q, dtype=np.float64)
+    if sys.n_atoms == 0:
+        return np.zeros(0)
+    return np.full(sys.n_atoms, float(np.sum(sys.occupations())) / sys.n_atoms)
+
+
+def sawtooth_at(x: np.ndarray, sys, axis: int) -> np.ndarray:
+    """The sawtooth coordinate at arbitrary positions x along the axis: the
+    continuous form of the grid's (((x/h - j0) mod n) - (n-1)/2) h."""
+    h = sys.h
+    n = sys.n[axis]
+    j0 = int(getattr(sys, "saw_jump", (0, 0, 0))[axis])
+    return (np.mod(np.asarray(x) / h - j0, n) - 0.5 * (n - 1)) * h
+
+
 def dipole_correction(rho: np.ndarray, sys):
     """Vacuum dipole correction of a density: (v_dc on the grid, E_dc).
 
-    For each axis q in the bit mask sys.dipole_correction:
-    d_q = h^3 sum_r rho(r) s_q(r), v_dc += (4 pi / Omega) d_q s_q,
-    E_dc += (2 pi / Omega) d_q^2 (so that dE_dc / d rho(r) = v_dc(r) / h^3 per
-    point, i.e. E_dc = (1/2) h^3 sum rho v_dc).  No mask: (0, 0)."""
+    For each axis q in the bit mask sys.dipole_correction the dipole of the
+    cell's charge, written for electrons as d_q = h^3 sum_r rho(r) s_q(r) -
+    sum_a Z_a s_q(R_a) (electrons minus ion point charges), gives
+    v_dc += (4 pi / Omega) d_q s_q and E_dc += (2 pi / Omega) d_q^2, so that
+    dE_dc / d rho(r) = h^3 v_dc(r).  No mask: (0, 0)."""
     mask = int(getattr(sys, "dipole_correction", 0))
     if not mask:
         return 0.0, 0.0
     omega = float(np.prod(sys.cell))
     dv = sys.h ** 3
+    z = ion_charges(sys)
     v = np.zeros(sys.ng)
     e = 0.0
     for q in range(3):
         if (mask >> q) & 1:
             s = dipole_coordinate(sys, q).ravel()
             d = dv * float(np.sum(rho * s))
+            if sys.n_atoms:
+                d -= float(np.sum(z * sawtooth_at(sys.pos[:, q], sys, q)))
             v += (4.0 * np.pi / omega) * d * s
             e += (2.0 * np.pi / omega) * d * d
     return v, e

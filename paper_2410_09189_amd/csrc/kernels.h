@@ -30,7 +30,8 @@ inline Batch single() { return Batch{1, nullptr, 0, 0, 0, 0}; }
 // ---- grid fields -----------------------------------------------------------
 hipError_t vion(hipStream_t s, double* v, int nx, int ny, int nz, double h, int n_atoms,
                 const double* pos, const double* depth, const double* width, int n_images);
-hipError_t coord(hipStream_t s, double* q, int nx, int ny, int nz, double h, int axis);
+// sawtooth coordinate along one axis, jump between planes j0 - 1 and j0, centred
+hipError_t coord(hipStream_t s, double* q, int nx, int ny, int nz, double h, int axis, int j0);
 hipError_t fill(hipStream_t s, double* p, long n, double v);
 hipError_t fill_u64(hipStream_t s, unsigned long long* p, long n, unsigned long long v);
 hipError_t copy_d(hipStream_t s, double* dst, const double* src, long n);
@@ -86,10 +87,27 @@ hipError_t poisson_fft(hipStream_t s, const double* rho, double* vh, double2* z,
 hipError_t real_part(hipStream_t s, double* r, const double2* z, long n);
 
 // ---- exchange, local potential, energies -------------------------------------------
+// Grid shape, spacing and sawtooth jump planes (ng < 2^32 points); for the dipole
+// correction also the ions' part: gion[q] = (4 pi / Omega) d_ion,q (subtracted from the
+// electrons' field) and dion[q] = d_ion,q / h^3 (its energy term).
+struct SawGeom {
+  int nx = 0, ny = 0, nz = 0, jx = 0, jy = 0, jz = 0;
+  double h = 0.0;
+  double gion[3] = {0.0, 0.0, 0.0};
+  double dion[3] = {0.0, 0.0, 0.0};
+};
+// part3: [T][kRedBlocks][3] partial sums of rho s_q (s_q the sawtooth coordinates)
+hipError_t saw_dipole(hipStream_t s, const double* rho, const SawGeom& sg, long n, double* part3, int T,
+                      const int* active);
 // vx = -(3 rho/pi)^(1/3), vloc = vion + vh + vx; part[b] = (sum e_x, sum rho vh) per block.
+// With sg and gfield ([T][3], the electrons' (4 pi / Omega) h^3 sum rho s_q) both non-null,
+// g_q = gfield_q - sg.gion[q] and vh is taken as vh + sum_q g_q s_q (the vacuum dipole
+// correction) in vloc and in the energy sum; block 0 adds -sum_q g_q dion[q] to the latter,
+// so that 1/2 h^3 times it is E_H + (2 pi / Omega) sum_q d_q^2.
 // batched over T stacked fields (blockIdx.y), part2: [T][kRedBlocks][2]
 hipError_t lda_vloc(hipStream_t s, const double* rho, const double* vh, const double* vion,
-                    double* vx, double* vloc, long n, double* part2, int T, const int* active);
+                    double* vx, double* vloc, long n, double* part2, int T, const int* active,
+                    const SawGeom* sg = nullptr, const double* gfield = nullptr);
 // out[0..ncol) = scale[c] * sum_b part[b][c]   (single block, fixed order)
 hipError_t reduce_cols(hipStream_t s, const double* part, int nblk, int ncol, const double* scale3,
                        double* out, int T, const int* active);

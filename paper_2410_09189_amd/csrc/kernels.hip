@@ -93,8 +93,15 @@ hipError_t vion(hipStream_t s, double* v, int nx, int ny, int nz, double h, int 
   return hipGetLastError();
 }
 
-// Centred sawtooth coordinate q_i = (i - (n-1)/2) h along one axis.
-__global__ void k_coord(double* q, int nx, int ny, int nz, double h, int axis) {
+// Sawtooth coordinate along one axis: rises by h per plane, drops once between
+// planes j0 - 1 and j0, centred: q_i = (((i - j0) mod n) - (n-1)/2) h.
+__device__ __forceinline__ double saw(int i, int n, int j0, double h) {
+  int k = i - j0;
+  k += k < 0 ? n : 0;
+  return (k - 0.5 * (n - 1)) * h;
+}
+
+__global__ void k_coord(double* q, int nx, int ny, int nz, double h, int axis, int j0) {
   long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long ng = (long)nx * ny * nz;
   if (g >= ng) return;
@@ -102,12 +109,12 @@ __global__ void k_coord(double* q, int nx, int ny, int nz, double h, int axis) {
   if (axis == 0) { i = (int)(g % nx); n = nx; }
   else if (axis == 1) { i = (int)((g / nx) % ny); n = ny; }
   else { i = (int)(g / ((long)nx * ny)); n = nz; }
-  q[g] = (i - 0.5 * (n - 1)) * h;
+  q[g] = saw(i, n, j0, h);
 }
 
-hipError_t coord(hipStream_t s, double* q, int nx, int ny, int nz, double h, int axis) {
+hipError_t coord(hipStream_t s, double* q, int nx, int ny, int nz, double h, int axis, int j0) {
   long ng = (long)nx * ny * nz;
-  hipLaunchKernelGGL(k_coord, dim3(cdiv(ng, 256)), dim3(256), 0, s, q, nx, ny, nz, h, axis);
+  hipLaunchKernelGGL(k_coord, dim3(cdiv(ng, 256)), dim3(256), 0, s, q, nx, ny, nz, h, axis, j0);
   return hipGetLastError();
 }
 
@@ -1139,11 +1146,59 @@ hipError_t poisson_scale(hipStream_t s, double2* z, int nx, int ny, int nz, doub
 // ============================================================================
 // LDA exchange, local potential and energy partial sums
 // ============================================================================
+// Sawtooth values of one grid point, x fastest.
+struct SawPoint {
+  double x, y, z;
+};
+__device__ __forceinline__ SawPoint saw_point(unsigned g, const SawGeom& sg) {
+  const unsigned ix = g % (unsigned)sg.nx;
+  const unsigned r = g / (unsigned)sg.nx;
+  const unsigned iy = r % (unsigned)sg.ny;
+  const unsigned iz = r / (unsigned)sg.ny;
+  return SawPoint{saw((int)ix, sg.nx, sg.jx, sg.h), saw((int)iy, sg.ny, sg.jy, sg.h), saw((int)iz, sg.nz, sg.jz, sg.h)};
+}
+
+// Dipole partial sums of each trajectory's density about the sawtooth:
+// part3[t][blk][q] = sum over the block's points of rho s_q.
+__global__ __launch_bounds__(256) void k_saw_dipole(const double* __restrict__ rho, SawGeom sg, long n,
+                                                    double* part3, const int* active) {
+  __shared__ double sh[256];
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  rho += t * n;
+  part3 += (long)t * 3 * gridDim.x;
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double r = rho[i];
+    const SawPoint p = saw_point((unsigned)i, sg);
+    ax += r * p.x;
+    ay += r * p.y;
+    az += r * p.z;
+  }
+  ax = block_sum_256(ax, sh);
+  ay = block_sum_256(ay, sh);
+  az = block_sum_256(az, sh);
+  if (threadIdx.x == 0) {
+    part3[3 * blockIdx.x] = ax;
+    part3[3 * blockIdx.x + 1] = ay;
+    part3[3 * blockIdx.x + 2] = az;
+  }
+}
+hipError_t saw_dipole(hipStream_t s, const double* rho, const SawGeom& sg, long n, double* part3, int T,
+                      const int* active) {
+  hipLaunchKernelGGL(k_saw_dipole, dim3(kRedBlocks, T), dim3(256), 0, s, rho, sg, n, part3, active);
+  return hipGetLastError();
+}
+
+// vx, V_loc = V_ion + V_H (+ sum_q g_q s_q, the dipole correction, when DC) + v_x,
+// and the per-block exchange and electrostatic energy sums (the latter weighs
+// rho by V_H plus the correction, with the ions' energy term in block 0).
+template <bool DC>
 __global__ __launch_bounds__(256) void k_lda_vloc(const double* __restrict__ rho,
                                                   const double* __restrict__ vh,
                                                   const double* __restrict__ vion, double* __restrict__ vx,
                                                   double* __restrict__ vloc, long n, double* part2,
-                                                  const int* active) {
+                                                  const int* active, SawGeom sg, const double* gfield) {
   __shared__ double sh[256];
   const int t = blockIdx.y;
   if (active && !active[t]) return;
@@ -1152,6 +1207,12 @@ __global__ __launch_bounds__(256) void k_lda_vloc(const double* __restrict__ rho
   vx += t * n;
   vloc += t * n;
   part2 += (long)t * 2 * gridDim.x;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  if (DC) {
+    gx = gfield[3 * t] - sg.gion[0];
+    gy = gfield[3 * t + 1] - sg.gion[1];
+    gz = gfield[3 * t + 2] - sg.gion[2];
+  }
   const double cx = cbrt(3.0 / M_PI);
   double ex_sum = 0.0, eh_sum = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -1161,6 +1222,10 @@ __global__ __launch_bounds__(256) void k_lda_vloc(const double* __restrict__ rho
     double v = -cx * c;
     vx[i] = v;
     double h = vh[i];
+    if (DC) {
+      const SawPoint p = saw_point((unsigned)i, sg);
+      h += (gx * p.x + gy * p.y) + gz * p.z;
+    }
     vloc[i] = (vion[i] + h) + v;
     ex_sum += -0.75 * cx * rc * c;
     eh_sum += r * h;
@@ -1168,13 +1233,21 @@ __global__ __launch_bounds__(256) void k_lda_vloc(const double* __restrict__ rho
   double a = block_sum_256(ex_sum, sh);
   double b = block_sum_256(eh_sum, sh);
   if (threadIdx.x == 0) {
+    // E_dc = 1/2 sum_q g_q (d_el,q - d_ion,q): the ions' part once per trajectory
+    if (DC && blockIdx.x == 0) b -= (gx * sg.dion[0] + gy * sg.dion[1]) + gz * sg.dion[2];
     part2[2 * blockIdx.x] = a;
     part2[2 * blockIdx.x + 1] = b;
   }
 }
 hipError_t lda_vloc(hipStream_t s, const double* rho, const double* vh, const double* vion, double* vx,
-                    double* vloc, long n, double* part2, int T, const int* active) {
-  hipLaunchKernelGGL(k_lda_vloc, dim3(kRedBlocks, T), dim3(256), 0, s, rho, vh, vion, vx, vloc, n, part2, active);
+                    double* vloc, long n, double* part2, int T, const int* active, const SawGeom* sg,
+                    const double* gfield) {
+  if (sg && gfield)
+    hipLaunchKernelGGL(k_lda_vloc<true>, dim3(kRedBlocks, T), dim3(256), 0, s, rho, vh, vion, vx, vloc, n, part2,
+                       active, *sg, gfield);
+  else
+    hipLaunchKernelGGL(k_lda_vloc<false>, dim3(kRedBlocks, T), dim3(256), 0, s, rho, vh, vion, vx, vloc, n, part2,
+                       active, SawGeom{}, nullptr);
   return hipGetLastError();
 }
 

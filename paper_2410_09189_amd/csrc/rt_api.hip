@@ -143,6 +143,10 @@ struct SysDev {
   int n_split_cap = 1, n_split_x_cap = 1;  // partial buffers are sized for these
   bool mixed = false;
   bool nonorth = false;  // propagate in the given (non-orthogonal) basis with its overlap
+  int dcorr = 0;         // bit q: vacuum dipole correction along axis q
+  int jump[3] = {0, 0, 0};  // sawtooth jump plane per axis
+  double dion[3] = {0.0, 0.0, 0.0};  // ions' dipole sum_a Z_a s_q(R_a) on the corrected axes
+  double *dscale = nullptr, *dfield = nullptr, *dpart = nullptr;  // [3], [T][3], [T][kRedBlocks][3]
   double* tcur = nullptr;                  // device scalar: time t_j of the step being taken
   int box_off = 0;                         // this system's mailbox slot (words): seq, then payload
   unsigned long long box_seq = 0;          // publishes of this system the host has consumed
@@ -438,6 +442,9 @@ rt_status validate_system(const rt_system& s, std::string& why) {
   }
   if (s.n_occ < 0 || s.n_virt < 0 || s.n_occ + s.n_virt < 1) { why = "active space"; return RT_EINVAL; }
   if (!s.psi0) { why = "psi0 is NULL"; return RT_EINVAL; }
+  for (int q = 0; q < 3; ++q)
+    if (s.saw_jump[q] < 0 || s.saw_jump[q] >= s.n[q]) { why = "saw_jump outside [0, n)"; return RT_EINVAL; }
+  if (s.dipole_correction < 0 || s.dipole_correction > 7) { why = "dipole_correction mask outside [0, 7]"; return RT_EINVAL; }
   return RT_OK;
 }
 
@@ -592,6 +599,9 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.vloc = a.take<double>(T * ng);
     d.dv = a.take<double>(T * ng);
     d.eparts = a.take<double>(2 * T);
+    d.dscale = a.take<double>(3);
+    d.dfield = a.take<double>(3 * T);
+    d.dpart = a.take<double>(d.dcorr ? 3 * T * rtk::kRedBlocks : 1);
     d.W = a.take<double>(T * NN);
     d.part = a.take<double>(T * std::max(d.n_split, d.n_split_cap) * NN);
     if (d.mixed) {
@@ -659,6 +669,29 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
   }
 }
 
+// Ions' dipole about the sawtooth, sum_a Z_a s_q(R_a), on the corrected axes: Z_a
+// from ion_charge, else the electron count sum_i f_i shared equally; s_q in its
+// continuous form (((x / h - j0) mod n) - (n-1)/2) h.
+void ion_dipole(const rt_system& s, SysDev& d) {
+  for (int q = 0; q < 3; ++q) d.dion[q] = 0.0;
+  if (!s.dipole_correction || s.n_atoms < 1) return;
+  double ne = 0.0;
+  const int N = s.n_occ + s.n_virt;
+  for (int i = 0; i < N; ++i) ne += s.occ ? s.occ[i] : (i < s.n_occ ? 2.0 : 0.0);
+  for (int q = 0; q < 3; ++q) {
+    if (!((s.dipole_correction >> q) & 1)) continue;
+    const int n = s.n[q];
+    double acc = 0.0;
+    for (int a = 0; a < s.n_atoms; ++a) {
+      const double z = s.ion_charge ? s.ion_charge[a] : ne / s.n_atoms;
+      double u = s.pos[3 * a + q] / s.h - s.saw_jump[q];
+      u -= n * std::floor(u / n);
+      acc += z * ((u - 0.5 * (n - 1)) * s.h);
+    }
+    d.dion[q] = acc;
+  }
+}
+
 void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<SysDev>& S,
               std::vector<TrajDev>& T) {
   S.resize(n_sys);
@@ -681,6 +714,9 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
     d.n_union = (int)d.nl.u_idx.size();
     d.mixed = run->precision == RT_MIXED;
     d.nonorth = s.nonorthogonal != 0;
+    d.dcorr = s.dipole_correction;
+    for (int q = 0; q < 3; ++q) d.jump[q] = s.saw_jump[q];
+    ion_dipole(s, d);
     d.feat = d.nx % 16 == 0 && d.ny % 16 == 0 && d.nz % 16 == 0;
     d.mlp = run->predictor == RT_PRED_MLP;
     d.slot_traj.clear();
@@ -779,7 +815,22 @@ rt_status poisson_lda(rt_ctx* c, SysDev& d, int T, const int* act) {
     CK(rtk::poisson_fft(s, d.rho, d.vh, d.z, d.nx, d.ny, d.nz, d.h, d.twx, d.twy, d.twz, T));
   }
   Timed tl(c, PH_LDA);
-  CK(rtk::lda_vloc(s, d.rho, d.vh, d.vion, d.vx, d.vloc, d.ng, d.red2, T, act));
+  // vacuum dipole correction: g_q = (4 pi / Omega) h^3 sum rho s_q on the selected axes
+  rtk::SawGeom sg;
+  sg.nx = d.nx; sg.ny = d.ny; sg.nz = d.nz;
+  sg.jx = d.jump[0]; sg.jy = d.jump[1]; sg.jz = d.jump[2];
+  sg.h = d.h;
+  const double gscale = 4.0 * M_PI / ((double)d.ng * d.h3);
+  for (int q = 0; q < 3; ++q) {
+    sg.gion[q] = gscale * d.dion[q];
+    sg.dion[q] = d.dion[q] / d.h3;
+  }
+  if (d.dcorr) {
+    CK(rtk::saw_dipole(s, d.rho, sg, d.ng, d.dpart, T, act));
+    CK(rtk::reduce_cols(s, d.dpart, rtk::kRedBlocks, 3, d.dscale, d.dfield, T, act));
+  }
+  CK(rtk::lda_vloc(s, d.rho, d.vh, d.vion, d.vx, d.vloc, d.ng, d.red2, T, act, d.dcorr ? &sg : nullptr,
+                   d.dcorr ? d.dfield : nullptr));
   CK(rtk::reduce_cols(s, d.red2, rtk::kRedBlocks, 2, d.escale, d.eparts, T, act));
   return RT_OK;
 }
@@ -1047,6 +1098,16 @@ rt_status count_bad(rt_ctx* c, const double* v, long n, unsigned long long* scra
   return RT_OK;
 }
 
+// Scales of the dipole sums: (4 pi / Omega) h^3 on the corrected axes, 0 elsewhere.
+rt_status upload_dscale(rt_ctx* c, SysDev& d) {
+  const double omega = (double)d.nx * d.ny * d.nz * d.h3;
+  double sc[3];
+  for (int q = 0; q < 3; ++q) sc[q] = ((d.dcorr >> q) & 1) ? 4.0 * M_PI / omega * d.h3 : 0.0;
+  CK(hipMemcpyAsync(d.dscale, sc, sizeof(sc), hipMemcpyHostToDevice, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return RT_OK;
+}
+
 rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   hipStream_t st = c->stream;
   const long N = d.N, ng = d.ng, NN = N * N;
@@ -1063,6 +1124,7 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   double esc[2] = {d.h3, 0.5 * d.h3}, ez[2] = {0.0, 0.0};
   CK(hipMemcpyAsync(d.escale, esc, sizeof(esc), hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(d.ezero, ez, sizeof(ez), hipMemcpyHostToDevice, st));
+  RET(upload_dscale(c, d));
   if (d.n_atoms) {
     CK(hipMemcpyAsync(d.pos, s.pos, 3 * d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(d.depth, s.depth, d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1093,7 +1155,7 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
   }
   CK(rtk::vion(st, d.vion, d.nx, d.ny, d.nz, d.h, d.n_atoms, d.pos, d.depth, d.width, d.n_images));
   for (int q = 0; q < 3; ++q) {
-    CK(rtk::coord(st, d.dv, d.nx, d.ny, d.nz, d.h, q));
+    CK(rtk::coord(st, d.dv, d.nx, d.ny, d.nz, d.h, q, d.jump[q]));
     RET(project(c, d, d.psi, d.psi, d.dv, d.M3 + q * NN));
   }
   RET(apply_h64(c, d, d.psi, d.hpsi, d.vion, d.N));
@@ -1483,6 +1545,9 @@ void layout_gs(Arena& a, SysDev& d, GsDev& g) {
   d.red2 = a.take<double>(2 * rtk::kRedBlocks);
   d.escale = a.take<double>(2);
   d.eparts = a.take<double>(2);
+  d.dscale = a.take<double>(3);
+  d.dfield = a.take<double>(3);
+  d.dpart = a.take<double>(d.dcorr ? 3 * rtk::kRedBlocks : 1);
   d.rho = a.take<double>(ng);
   d.vh = a.take<double>(ng);
   d.vx = a.take<double>(ng);
@@ -1732,6 +1797,7 @@ rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs
   // static fields and tables
   double esc[2] = {d.h3, 0.5 * d.h3};
   CK(hipMemcpyAsync(d.escale, esc, sizeof(esc), hipMemcpyHostToDevice, st));
+  RET(upload_dscale(c, d));
   if (d.n_atoms) {
     CK(hipMemcpyAsync(d.pos, s.pos, 3 * d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(d.depth, s.depth, d.n_atoms * sizeof(double), hipMemcpyHostToDevice, st));

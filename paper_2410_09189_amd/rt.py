@@ -32,7 +32,8 @@ class rt_system(ctypes.Structure):
         ("nl_sigma", ctypes.c_double), ("nl_D", _dp), ("n_occ", ctypes.c_int),
         ("n_virt", ctypes.c_int), ("occ", _dp), ("psi0", ctypes.c_void_p),
         ("psi0_on_device", ctypes.c_int), ("orthonormalize", ctypes.c_int),
-        ("nonorthogonal", ctypes.c_int),
+        ("nonorthogonal", ctypes.c_int), ("saw_jump", ctypes.c_int * 3),
+        ("dipole_correction", ctypes.c_int), ("ion_charge", _dp),
     ]
 
 
@@ -148,12 +149,15 @@ class SystemArgs:
 
     def __init__(self, n, h, pos, depth, width, n_occ, n_virt, psi0, nl_rank=0, nl_rcut=2.0,
                  nl_sigma=0.6, nl_D=None, n_images=2, occ=None, orthonormalize=False,
-                 nonorthogonal=False):
+                 nonorthogonal=False, saw_jump=(0, 0, 0), dipole_correction=0, ion_charge=None):
         self.pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         self.depth = np.ascontiguousarray(depth, dtype=np.float64)
         self.width = np.ascontiguousarray(width, dtype=np.float64)
         self.nl_D = None if nl_D is None else np.ascontiguousarray(nl_D, dtype=np.float64)
         self.occ = None if occ is None else np.ascontiguousarray(occ, dtype=np.float64)
+        self.ion_charge = None if ion_charge is None else np.ascontiguousarray(ion_charge, dtype=np.float64)
+        if self.ion_charge is not None and self.ion_charge.shape != (self.pos.shape[0],):
+            raise ValueError("ion_charge needs one value per atom")
         self.psi0 = psi0  # numpy float64 array (host) or torch CUDA tensor (device)
         s = rt_system()
         s.n[:] = list(n)
@@ -174,6 +178,9 @@ class SystemArgs:
             s.psi0_on_device = 1
         s.orthonormalize = int(orthonormalize)
         s.nonorthogonal = int(nonorthogonal)
+        s.saw_jump[:] = [int(v) for v in saw_jump]
+        s.dipole_correction = int(dipole_correction)
+        s.ion_charge = _ptr(self.ion_charge)
         self.struct = s
 
 

@@ -47,6 +47,8 @@ class System:
     saw_jump: tuple = (0, 0, 0)
     # bit q set: vacuum dipole correction along axis q
     dipole_correction: int = 0
+    # ion point charges for the dipole correction (None: electrons shared equally)
+    ion_charge: Optional[np.ndarray] = None
 
     @property
     def n_orb(self) -> int:
@@ -90,6 +92,8 @@ class System:
             d["saw_jump"] = [int(v) for v in self.saw_jump]
         if self.dipole_correction:
             d["dipole_correction"] = int(self.dipole_correction)
+        if self.ion_charge is not None:
+            d["ion_charge"] = [float(v).hex() for v in self.ion_charge]
         return json.dumps(d, sort_keys=True)
 
     def digest(self) -> str:

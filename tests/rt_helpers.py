@@ -11,7 +11,10 @@ def system_args(s, psi, orthonormalize=False, device_psi=None, nonorthogonal=Fal
     return rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ,
                          n_virt=s.n_virt, psi0=psi if device_psi is None else device_psi,
                          nl_rank=s.nl_rank, nl_rcut=s.nl_rcut, nl_sigma=s.nl_sigma, nl_D=s.nl_D,
-                         n_images=s.n_images, orthonormalize=orthonormalize, nonorthogonal=nonorthogonal)
+                         n_images=s.n_images, orthonormalize=orthonormalize, nonorthogonal=nonorthogonal,
+                         saw_jump=tuple(getattr(s, "saw_jump", (0, 0, 0))),
+                         dipole_correction=int(getattr(s, "dipole_correction", 0)),
+                         ion_charge=getattr(s, "ion_charge", None))
 
 
 def run_args(rp, n_traj_axes=(0,), sys_index=None, kappas=None, **kw):

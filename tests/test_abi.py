@@ -101,6 +101,30 @@ def test_nonorthogonal_basis_exclusions_rejected(over):
     assert "nonorthogonal" in rt.rt_last_error() or "orthonormal basis" in rt.rt_last_error()
 
 
+@pytest.mark.parametrize("jump,mask", [((16, 0, 0), 0), ((0, -1, 0), 1), ((0, 0, 0), 8), ((0, 0, 0), -1)])
+def test_sawtooth_jump_and_dipole_mask_checked(jump, mask):
+    """The jump plane must lie on the grid and the correction mask select axes only."""
+    from paper_2410_09189_amd import rt
+
+    sa, ra = _args(dipole_correction=mask)
+    sa.struct.saw_jump[:] = list(jump)
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_workspace_size([sa], ra)
+    assert e.value.status == rt.RT_EINVAL
+    assert "saw_jump" in rt.rt_last_error() or "dipole_correction" in rt.rt_last_error()
+
+
+def test_dipole_correction_adds_its_partial_sums():
+    from paper_2410_09189_amd import rt
+
+    sa, ra = _args()
+    a = rt.rt_workspace_size([sa], ra)
+    sa, ra = _args(dipole_correction=5)
+    sa.struct.saw_jump[:] = [3, 15, 0]
+    b = rt.rt_workspace_size([sa], ra)
+    assert b > a
+
+
 def test_nonorthogonal_basis_takes_overlap_buffers():
     from paper_2410_09189_amd import rt
 

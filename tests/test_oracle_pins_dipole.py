@@ -21,7 +21,8 @@ def _slab_cell(axis, mask, jump):
     s = synth.make_system(tuple(n), 0.25, 1, 1, 1, seed=0)
     j = [0, 0, 0]
     j[axis] = jump
-    return dataclasses.replace(s, saw_jump=tuple(j), dipole_correction=mask)
+    # electrons only: the one synthetic atom carries no point charge here
+    return dataclasses.replace(s, saw_jump=tuple(j), dipole_correction=mask, ion_charge=np.zeros(1))
 
 
 def _sheets(s, axis, a, b, amp, w):
@@ -167,7 +168,48 @@ def test_blob_without_dipole_gets_no_correction():
     assert _symmetric_blob_field() < 1e-12
 
 
-@pytest.mark.parametrize("planted", ["sign", "factor_2pi", "energy_4pi", "uncentred"])
+def _blob_cell(jump_x, shift, charge=None):
+    """A 48 x 8 x 8 cell (h = 0.25) with one ion at x = 5 bohr of charge 2 and a
+    Gaussian electron blob of 2 electrons centred at 5 + shift."""
+    s = synth.make_system((48, 8, 8), 0.25, 1, 1, 1, seed=0)
+    pos = np.array([[5.0, 1.0, 1.0]])
+    s = dataclasses.replace(s, pos=pos, saw_jump=(jump_x, 0, 0), dipole_correction=1,
+                            ion_charge=charge)
+    x = np.arange(48) * s.h
+    prof = np.exp(-((x - 5.0 - shift) ** 2) / (2 * 0.5 ** 2))
+    prof *= 2.0 / (np.sum(prof) * s.h * (8 * s.h) ** 2)
+    rho = np.broadcast_to(prof.reshape(1, 1, 48), (8, 8, 48)).ravel().copy()
+    return s, rho
+
+
+def _ion_errors():
+    """(closed-form energy error of a displaced blob, jump dependence of a neutral cell's energy)."""
+    shift = 0.4
+    s, rho = _blob_cell(40, shift)  # default charge: 2 electrons on the one atom
+    _, e = hamiltonian.dipole_correction(rho, s)
+    omega = float(np.prod(s.cell))
+    closed = 2 * np.pi * (2.0 * shift) ** 2 / omega  # d = N_e * shift
+    err_closed = abs(e - closed) / closed
+    s2, rho2 = _blob_cell(38, shift)
+    _, e2 = hamiltonian.dipole_correction(rho2, s2)
+    return err_closed, abs(e2 - e) / closed
+
+
+def test_displaced_electrons_against_point_ions_closed_form_and_jump_invariance():
+    err_closed, err_jump = _ion_errors()
+    assert err_closed < 1e-9
+    assert err_jump < 1e-12
+
+
+def test_explicit_ion_charges_equal_the_default_share():
+    s, rho = _blob_cell(40, 0.3)
+    s2, _ = _blob_cell(40, 0.3, charge=np.array([2.0]))
+    a = hamiltonian.dipole_correction(rho, s)
+    b = hamiltonian.dipole_correction(rho, s2)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+@pytest.mark.parametrize("planted", ["sign", "factor_2pi", "energy_4pi", "uncentred", "ions_dropped", "ion_sign"])
 def test_dipole_pins_reject_planted_mistakes(monkeypatch, planted):
     orig_coord = grid.dipole_coordinate
 
@@ -184,6 +226,9 @@ def test_dipole_pins_reject_planted_mistakes(monkeypatch, planted):
                 if planted == "uncentred":  # measured from the jump plane, not the centre
                     c = c + 0.5 * (sys.n[q] - 1) * sys.h
                 d = sys.h ** 3 * float(np.sum(rho * c))
+                if planted != "ions_dropped" and sys.n_atoms:
+                    zi = hamiltonian.ion_charges(sys) * hamiltonian.sawtooth_at(sys.pos[:, q], sys, q)
+                    d += (1.0 if planted == "ion_sign" else -1.0) * float(np.sum(zi))
                 k = {"sign": -4.0, "factor_2pi": 2.0}.get(planted, 4.0)
                 v += (k * np.pi / omega) * d * c
                 e += ((4.0 if planted == "energy_4pi" else 2.0) * np.pi / omega) * d * d
@@ -193,4 +238,6 @@ def test_dipole_pins_reject_planted_mistakes(monkeypatch, planted):
     slope_err, step_err, _ = _slab_errors(2)
     d_err, _, _ = _energy_derivative_error()
     blob = _symmetric_blob_field()
-    assert slope_err > 1e-4 or step_err > 1e-4 or d_err > 1e-6 or blob > 1e-4
+    ion_closed, ion_jump = _ion_errors()
+    assert (slope_err > 1e-4 or step_err > 1e-4 or d_err > 1e-6 or blob > 1e-4 or ion_closed > 1e-4
+            or ion_jump > 1e-4)
