@@ -699,7 +699,7 @@ def main():
                              # counted at the built-in tiling; another tiling re-reads other halo rows
                              "traffic": measured_traffic("stencil_fd8_fp32" if dt_ else "stencil_fd8_fp64")
                              if rt.rt_tune_get(ctx, 0, rt.RT_TUNE_STENCIL_FP32 if dt_ else
-                                               rt.RT_TUNE_STENCIL_FP64) == (0, 0) else None,
+                                               rt.RT_TUNE_STENCIL_FP64) == (0, 0, 0) else None,
                              "tiling": rt.rt_tune_get(ctx, 0, rt.RT_TUNE_STENCIL_FP32 if dt_ else
                                                       rt.RT_TUNE_STENCIL_FP64)},
         }

@@ -262,12 +262,15 @@ rt_status rt_set_state(rt_ctx* ctx, int traj, const double* p_re, const double* 
  * Autotuner of the launch shapes (the paper tunes nothing; these are this
  * library's own kernels).  Tunables per system:
  *   RT_TUNE_STENCIL_FP64 / _FP32: y-tile rows p1 (a divisor of ny whose 16-byte
- *     strips fit one 256-thread block) and z chunks p2 (1..nz) of the FD8 + V
- *     stencil; the tiling changes no arithmetic (results bitwise equal);
+ *     strips fit one 256-thread block), z chunks p2 (1..nz) and halo look-ahead
+ *     p3 in {3, 4, 5, 6, 8} planes (how early the y-halo rows are requested) of
+ *     the FD8 + V stencil; the tiling changes no arithmetic (results bitwise
+ *     equal);
  *   RT_TUNE_PROJ_FP64: target block count p1 in {1024, 2048, 4096} of the FP64
  *     projection's K split (p2 reported: the resulting splits);
  *   RT_TUNE_PROJ_MIXED: splits p1 in {85, 128, 170, 255} of the BF16x3 projection
  *     for N <= 256 (p2 reported: the resulting splits).
+ * p3 is 0 for the projections.
  * The projection splits change the order of the FP64/FP32 partial sums, so
  * results move within rounding (and a trajectory's results then depend on the
  * splits its context uses).  0 selects the built-in choice.
@@ -275,7 +278,7 @@ rt_status rt_set_state(rt_ctx* ctx, int traj, const double* p_re, const double* 
  *   candidates on the context's own buffers (device time by hipEvents on the
  *   context's stream, one warm-up and three timed launches each) and the fastest
  *   kept.  cache_path (nullable): a text file of earlier choices, one line
- *   "arch|kernel|nx x ny x nz|N|T p1 p2" each; matching entries are applied
+ *   "arch|kernel|nx x ny x nz|N|T p1 p2 p3" each; matching entries are applied
  *   without timing and new ones appended.  Call after rt_init, before rt_step;
  *   it overwrites scratch buffers only (state and history unchanged).
  * rt_tune_set / rt_tune_get: pin or read one tunable (RT_EINVAL for shapes the
@@ -284,8 +287,8 @@ rt_status rt_set_state(rt_ctx* ctx, int traj, const double* p_re, const double* 
  */
 enum { RT_TUNE_STENCIL_FP64 = 0, RT_TUNE_STENCIL_FP32 = 1, RT_TUNE_PROJ_FP64 = 2, RT_TUNE_PROJ_MIXED = 3 };
 rt_status rt_autotune(rt_ctx* ctx, const char* cache_path);
-rt_status rt_tune_set(rt_ctx* ctx, int sys_index, int kernel, int p1, int p2);
-rt_status rt_tune_get(rt_ctx* ctx, int sys_index, int kernel, int* p1, int* p2);
+rt_status rt_tune_set(rt_ctx* ctx, int sys_index, int kernel, int p1, int p2, int p3);
+rt_status rt_tune_get(rt_ctx* ctx, int sys_index, int kernel, int* p1, int* p2, int* p3);
 const char* rt_tune_report(const rt_ctx* ctx);
 
 /*

@@ -41,11 +41,14 @@ hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, l
 
 // ---- Hamiltonian on the grid -------------------------------------------------
 // hpsi[j] = -1/2 L psi[j] + v psi[j] (8th-order FD, periodic), j < n_orb.  Tiling:
-// ty rows of y per block (a divisor of ny whose strips fit one block) and nzc z
-// chunks; 0 = the default choice.  The tiling changes no arithmetic.
+// ty rows of y per block (a divisor of ny whose strips fit one block), nzc z chunks
+// and hq planes of halo look-ahead (2 .. 8); 0 = the default choice.  The tiling
+// changes no arithmetic.
 template <typename T>
 hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
-                   int nz, double h, const double* coef5, int ty = 0, int nzc = 0);
+                   int nz, double h, const double* coef5, int ty = 0, int nzc = 0, int hq = 0);
+// halo look-ahead candidates of stencil<T>
+void stencil_halo_ahead(std::vector<int>& hq);
 // the tilings stencil<T> accepts on this grid (candidate ty values, nzc values)
 template <typename T>
 void stencil_tiles(int nx, int ny, int nz, int n_orb, std::vector<int>& ty, std::vector<int>& nzc);

@@ -172,16 +172,26 @@ hipError_t sub_d(hipStream_t s, double* dst, const double* a, const double* b, l
 // One block = one orbital, all x (nx <= 256), a tile of TY rows in y, a chunk of z
 // planes, blockDim = the tile's strips rounded up to whole waves.  A thread owns
 // COLS strips of V consecutive x points (V = 16 bytes / element size when nx
-// allows, else 1) and marches in z: the 9-plane window of its strips
-// sits in registers (z neighbours) with the next two planes' loads in flight.  The
-// current plane with a 4-row y halo is staged in one of two LDS buffers whose rows
-// carry 4 periodic copies on each side, so the x and y neighbours of a strip are
-// whole 16-byte LDS reads at fixed offsets (no wrap arithmetic); one barrier per
-// plane.  The next plane's halo rows and potential load while this plane computes.
-// Global traffic is whole x rows in 16-byte vectors; halo rows are the neighbouring
-// tiles' interiors, read from L2: blocks are ordered (tile, z chunk, orbital) with
-// the tile fastest and mapped XCD-aware, so the tiles of one orbital run together
-// on one XCD.
+// allows, else 1) and marches in z: the 9-plane window of its strips sits in
+// registers (z neighbours) with the next PD planes' loads in flight.  The current
+// plane with a 4-row y halo is staged in one of two LDS buffers whose rows carry 4
+// periodic copies on each side, so the x and y neighbours of a strip are whole
+// 16-byte LDS reads at fixed offsets (no wrap arithmetic); one barrier per plane.
+// Global traffic is whole x rows in 16-byte vectors.  Blocks are ordered (tile, z
+// chunk, orbital) with the tile fastest and mapped XCD-aware, so the tiles of one
+// orbital run together on one XCD and a tile's halo rows are its neighbours'
+// interior rows.
+// Latency: every value a plane waits for was requested at least two planes
+// earlier, and no register holding a load in flight is ever copied: the window
+// (9 + PD = KW planes), the potential (3 planes) and the staged halo (2 planes) are
+// rings whose slots are fixed by the plane's position modulo KW, with the z loop
+// unrolled KW times so that every slot index is a compile-time constant (a rotated
+// register would force a wait for every load in flight, exposing one full memory
+// latency per plane).  The halo rows are requested HQ planes ahead, close to when
+// the neighbouring tiles request the same rows for their windows (5 + PD planes
+// ahead), so the second request finds the line in L2; after their two planes in
+// registers they wait in an LDS ring of HQ - 1 planes (compact rows) and are
+// copied into the plane buffer when their plane comes up.
 struct StencilCoef {
   double c[5];  // -1/2 a_k / h^2
 };
@@ -213,18 +223,22 @@ __device__ __forceinline__ void sv_st_nt(T* p, const SVec<T, V>& x) {
   __builtin_nontemporal_store(w, reinterpret_cast<vt*>(p));
 }
 
-// Four waves per SIMD for latency hiding where the halo takes at most two strips per
-// thread (the register bound then costs at most a couple of spilled words).  PD planes
-// beyond the window are in flight (two measured best for both element types).
+// Up to 512 threads (8 waves) per block; three waves per SIMD leave 168 registers,
+// which the rings need with one halo strip per thread (two with more).
 template <typename T, int V, int COLS, int HS, int PD>
-__global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HS == 1 ? 3 : 2))) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
                                                  const T* __restrict__ v, int nx, int ny, int nz,
-                                                 int TY, int ZC, StencilCoef cf) {
+                                                 int TY, int ZC, int HQ, StencilCoef cf) {
   typedef SVec<T, V> Vec;
+  constexpr int KW = 9 + PD;  // window ring and unroll length; the potential's ring (3) and
+  static_assert(KW % 6 == 0, "the halo's (2) divide it");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T* const sp0 = reinterpret_cast<T*>(smem_raw);  // [2][TY + 8][nx + 8], x = 0 at column 4
   const int P = nx + 8;
   const int pln = (TY + 8) * P;
+  const int R = HQ - 1;           // LDS ring slots (HQ >= 3)
+  T* const ring = sp0 + 2 * pln;  // [R][8 nx]: halo rows of planes ahead, slot = plane % R
+  const int R8 = 8 * nx;
   const int tid = threadIdx.x, NT = blockDim.x;
   const long lid = xcd_logical(blockIdx.x, gridDim.x);
   const int tiles = ny / TY, nzc = (nz + ZC - 1) / ZC;
@@ -241,142 +255,152 @@ __global__ __launch_bounds__(256, (HS <= 2 ? 4 : 2)) void k_stencil(const T* __r
   const T c1 = (T)cf.c[1], c2 = (T)cf.c[2], c3 = (T)cf.c[3], c4 = (T)cf.c[4];
   const int spr = nx / V;  // strips per row
 
+  // window ring: plane z0 - 4 + k in slot k mod KW; potential: plane z0 + k in slot k mod 3.
+  // Loads are unconditional (threads past the tile read its first strip, planes past
+  // the chunk are clamped or wrapped into the grid): without divergent branches
+  // around them the compiler's waits cover exactly the loads a value needs.
   int cb[COLS], ls[COLS], pw[COLS];  // plane offset, LDS offset, LDS offset of the wrap copy (-1: none)
   bool ok[COLS];
-  Vec q[COLS][9], nq[COLS][PD], vv[COLS];
+  Vec wq[COLS][KW], vr[COLS][3];
 #pragma unroll
   for (int c = 0; c < COLS; ++c) {
     const int sidx = tid + c * NT;
     const int yl = sidx / spr, x = (sidx - yl * spr) * V;
     ok[c] = yl < rows;
-    cb[c] = (y0 + yl) * nx + x;
+    cb[c] = ok[c] ? (y0 + yl) * nx + x : y0 * nx;
     ls[c] = (yl + 4) * P + 4 + x;
     pw[c] = x < 4 ? ls[c] + nx : (x >= nx - 4 ? ls[c] - nx : -1);
-    if (ok[c]) {
 #pragma unroll
-      for (int d = 0; d < 9; ++d) q[c][d] = sv_ld<T, V>(f + (long)wrapi(z0 - 4 + d, nz) * plane + cb[c]);
-#pragma unroll
-      for (int k = 0; k < PD; ++k) nq[c][k] = sv_ld<T, V>(f + (long)wrapi(z0 + 5 + k, nz) * plane + cb[c]);
-      vv[c] = sv_ld<T, V>(v + (long)z0 * plane + cb[c]);
-    }
+    for (int d = 0; d < KW - 1; ++d) wq[c][d] = sv_ld<T, V>(f + (long)wrapi(z0 - 4 + d, nz) * plane + cb[c]);
+    vr[c][0] = sv_ld<T, V>(v + (long)z0 * plane + cb[c]);
+    vr[c][1] = sv_ld<T, V>(v + (long)min(z0 + 1, nz - 1) * plane + cb[c]);
   }
-  // y halo: 8 rows (4 below, 4 above the tile) of plane z, 8 spr <= NT HS strips
-  int hoff[HS], hl[HS], hw[HS];
-  Vec hv[HS];
+  // y halo: 8 rows (4 below, 4 above the tile), 8 spr <= NT HS strips; strip e sits
+  // at e V in an LDS ring slot.  Plane p enters the LDS ring at plane p - HQ + 2 (here
+  // for p < z0 + HQ - 2); plane z0 + HQ - 2 + k starts in register slot k (k = 0, 1).
+  int hoff[HS], hl[HS], hw[HS];  // hoff: global offset in the plane (0 for threads without a strip)
+  bool hok[HS];
+  Vec hr[HS][2];
 #pragma unroll
   for (int i = 0; i < HS; ++i) {
     const int e = tid + NT * i;
-    hoff[i] = -1;
-    if (e < 8 * spr) {
-      const int hr = e / spr, x = (e - hr * spr) * V;
-      const int yl = hr < 4 ? hr - 4 : rows + (hr - 4);
+    hok[i] = e < 8 * spr;
+    hoff[i] = 0;
+    hl[i] = hw[i] = -1;
+    if (hok[i]) {
+      const int hrow = e / spr, x = (e - hrow * spr) * V;
+      const int yl = hrow < 4 ? hrow - 4 : rows + (hrow - 4);
       hoff[i] = wrapi(y0 + yl, ny) * nx + x;
       hl[i] = (yl + 4) * P + 4 + x;
       hw[i] = x < 4 ? hl[i] + nx : (x >= nx - 4 ? hl[i] - nx : -1);
-      hv[i] = sv_ld<T, V>(f + (long)z0 * plane + hoff[i]);
+      for (int k = 0; k + 2 < HQ && z0 + k < z1; ++k)
+        sv_st<T, V>(ring + ((z0 + k) % R) * R8 + e * V, sv_ld<T, V>(f + (long)(z0 + k) * plane + hoff[i]));
     }
+    hr[i][0] = sv_ld<T, V>(f + (long)min(z0 + HQ - 2, nz - 1) * plane + hoff[i]);
+    hr[i][1] = sv_ld<T, V>(f + (long)min(z0 + HQ - 1, nz - 1) * plane + hoff[i]);
   }
-  for (int z = z0; z < z1; ++z) {
-    T* const sp = sp0 + ((z - z0) & 1) * pln;
+  __syncthreads();
+  for (int zb = z0; zb < z1; zb += KW) {
 #pragma unroll
-    for (int c = 0; c < COLS; ++c)
-      if (ok[c]) {
-        sv_st<T, V>(sp + ls[c], q[c][4]);
-        if (pw[c] >= 0) sv_st<T, V>(sp + pw[c], q[c][4]);
-      }
-#pragma unroll
-    for (int i = 0; i < HS; ++i)
-      if (hoff[i] >= 0) {
-        sv_st<T, V>(sp + hl[i], hv[i]);
-        if (hw[i] >= 0) sv_st<T, V>(sp + hw[i], hv[i]);
-      }
-    __syncthreads();
-    // next plane's halo and potential, and plane z + 5 + PD of the window, in flight
-    Vec vn[COLS], n3[COLS];
-    const bool more = z + 1 < z1;
-    if (more) {
-      const long zn = (long)(z + 1) * plane;
-#pragma unroll
-      for (int i = 0; i < HS; ++i)
-        if (hoff[i] >= 0) hv[i] = sv_ld<T, V>(f + zn + hoff[i]);
-      const long z7 = (long)wrapi(z + 5 + PD, nz) * plane;
+    for (int j = 0; j < KW; ++j) {
+      const int z = zb + j;  // plane z - 4 + d is window slot (j + d) % KW
+      if (z >= z1) break;
+      T* const sp = sp0 + ((z - z0) & 1) * pln;
 #pragma unroll
       for (int c = 0; c < COLS; ++c)
         if (ok[c]) {
-          vn[c] = sv_ld<T, V>(v + zn + cb[c]);
-          n3[c] = sv_ld<T, V>(f + z7 + cb[c]);
+          sv_st<T, V>(sp + ls[c], wq[c][(j + 4) % KW]);
+          if (pw[c] >= 0) sv_st<T, V>(sp + pw[c], wq[c][(j + 4) % KW]);
         }
-    }
-    const long zoff = (long)z * plane;
+      // halo of plane z: LDS ring -> plane buffer; plane z + HQ - 2 (register slot
+      // j % 2, loaded two planes ago) -> LDS slot (z - 1) mod R, whose last reader
+      // (plane z - 1) passed the previous barrier and which differs from z mod R
+      // (past the chunk the slot is never read)
 #pragma unroll
-    for (int c = 0; c < COLS; ++c) {
-      if (!ok[c]) continue;
-      const T* r0 = sp + ls[c];
-      T w[V + 8];  // x window x - 4 .. x + V + 3
+      for (int i = 0; i < HS; ++i)
+        if (hok[i]) {
+          const int e = tid + NT * i;
+          const Vec hz = sv_ld<T, V>(ring + (z % R) * R8 + e * V);
+          sv_st<T, V>(sp + hl[i], hz);
+          if (hw[i] >= 0) sv_st<T, V>(sp + hw[i], hz);
+          sv_st<T, V>(ring + ((z + HQ - 2) % R) * R8 + e * V, hr[i][j % 2]);
+        }
+      __syncthreads();
+      // in flight: halo of plane z + HQ (register slot j % 2, just freed), potential of
+      // plane z + 2 (slot of plane z - 1), window plane z + 4 + PD (slot of plane z - 5)
 #pragma unroll
-      for (int g = 0; g < (V + 8) / V; ++g) {
-        Vec t = sv_ld<T, V>(r0 - 4 + g * V);
-#pragma unroll
-        for (int u = 0; u < V; ++u) w[g * V + u] = t.e[u];
-      }
-      Vec ym[4], yp[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        ym[k] = sv_ld<T, V>(r0 - (k + 1) * P);
-        yp[k] = sv_ld<T, V>(r0 + (k + 1) * P);
-      }
-      Vec out;
-#pragma unroll
-      for (int u = 0; u < V; ++u) {
-        const T ctr = q[c][4].e[u];
-        T sx1 = w[u + 5] + w[u + 3], sx2 = w[u + 6] + w[u + 2];
-        T sx3 = w[u + 7] + w[u + 1], sx4 = w[u + 8] + w[u + 0];
-        T sy1 = yp[0].e[u] + ym[0].e[u], sy2 = yp[1].e[u] + ym[1].e[u];
-        T sy3 = yp[2].e[u] + ym[2].e[u], sy4 = yp[3].e[u] + ym[3].e[u];
-        T sz1 = q[c][5].e[u] + q[c][3].e[u], sz2 = q[c][6].e[u] + q[c][2].e[u];
-        T sz3 = q[c][7].e[u] + q[c][1].e[u], sz4 = q[c][8].e[u] + q[c][0].e[u];
-        T acc = c0 * ctr;
-        acc += c1 * ((sx1 + sy1) + sz1);
-        acc += c2 * ((sx2 + sy2) + sz2);
-        acc += c3 * ((sx3 + sy3) + sz3);
-        acc += c4 * ((sx4 + sy4) + sz4);
-        out.e[u] = acc + vv[c].e[u] * ctr;
-      }
-      sv_st_nt<T, V>(o + zoff + cb[c], out);
-    }
-    if (more) {
+      for (int i = 0; i < HS; ++i) hr[i][j % 2] = sv_ld<T, V>(f + (long)min(z + HQ, nz - 1) * plane + hoff[i]);
 #pragma unroll
       for (int c = 0; c < COLS; ++c) {
+        vr[c][(j + 2) % 3] = sv_ld<T, V>(v + (long)min(z + 2, nz - 1) * plane + cb[c]);
+        wq[c][(j + KW - 1) % KW] = sv_ld<T, V>(f + (long)wrapi(z + 4 + PD, nz) * plane + cb[c]);
+      }
+      const long zoff = (long)z * plane;
 #pragma unroll
-        for (int d = 0; d < 8; ++d) q[c][d] = q[c][d + 1];
-        q[c][8] = nq[c][0];
+      for (int c = 0; c < COLS; ++c) {
+        if (!ok[c]) continue;
+        const T* r0 = sp + ls[c];
+        T w[V + 8];  // x window x - 4 .. x + V + 3
 #pragma unroll
-        for (int k = 0; k + 1 < PD; ++k) nq[c][k] = nq[c][k + 1];
-        nq[c][PD - 1] = n3[c];
-        vv[c] = vn[c];
+        for (int g = 0; g < (V + 8) / V; ++g) {
+          Vec t = sv_ld<T, V>(r0 - 4 + g * V);
+#pragma unroll
+          for (int u = 0; u < V; ++u) w[g * V + u] = t.e[u];
+        }
+        Vec ym[4], yp[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          ym[k] = sv_ld<T, V>(r0 - (k + 1) * P);
+          yp[k] = sv_ld<T, V>(r0 + (k + 1) * P);
+        }
+        const Vec& zc0 = wq[c][(j + 4) % KW];
+        Vec out;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const T ctr = zc0.e[u];
+          T sx1 = w[u + 5] + w[u + 3], sx2 = w[u + 6] + w[u + 2];
+          T sx3 = w[u + 7] + w[u + 1], sx4 = w[u + 8] + w[u + 0];
+          T sy1 = yp[0].e[u] + ym[0].e[u], sy2 = yp[1].e[u] + ym[1].e[u];
+          T sy3 = yp[2].e[u] + ym[2].e[u], sy4 = yp[3].e[u] + ym[3].e[u];
+          T sz1 = wq[c][(j + 5) % KW].e[u] + wq[c][(j + 3) % KW].e[u];
+          T sz2 = wq[c][(j + 6) % KW].e[u] + wq[c][(j + 2) % KW].e[u];
+          T sz3 = wq[c][(j + 7) % KW].e[u] + wq[c][(j + 1) % KW].e[u];
+          T sz4 = wq[c][(j + 8) % KW].e[u] + wq[c][j % KW].e[u];
+          T acc = c0 * ctr;
+          acc += c1 * ((sx1 + sy1) + sz1);
+          acc += c2 * ((sx2 + sy2) + sz2);
+          acc += c3 * ((sx3 + sy3) + sz3);
+          acc += c4 * ((sx4 + sy4) + sz4);
+          out.e[u] = acc + vr[c][j % 3].e[u] * ctr;
+        }
+        sv_st_nt<T, V>(o + zoff + cb[c], out);
       }
     }
   }
 }
 
-// Default y tile: the largest divisor of ny whose strips fit one 256-thread block
-// (one strip per thread, registers for occupancy).
+// Default y tile: the smallest divisor of ny of at least 8 rows whose strips fit one
+// 512-thread block (one strip per thread): the tile's threads then cover its 8 halo
+// rows with one strip each; else the largest divisor that fits (measured on 96^3 and
+// 192^3: taller tiles than that were slower, lower ones re-read more halo).
 static int stencil_default_ty(int spr, int ny) {
-  for (int t = 64; t >= 1; --t)
-    if (t <= ny && ny % t == 0 && t * spr <= 256) return t;
+  for (int t = 8; t <= ny && t * spr <= 512; ++t)
+    if (ny % t == 0) return t;
+  for (int t = 7; t >= 1; --t)
+    if (t <= ny && ny % t == 0 && t * spr <= 512) return t;
   return 1;
 }
 
 template <typename T, int V>
 static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
-                                 int nz, const StencilCoef& cf, int ty, int nzc) {
+                                 int nz, const StencilCoef& cf, int ty, int nzc, int hq) {
   const int spr = nx / V;
   // y tile (ty > 0: as given; it must divide ny and its strips fit one block),
   // block = strips rounded up to whole waves
   const int TY = ty > 0 ? ty : stencil_default_ty(spr, ny);
-  if (ny % TY || TY * spr > 256) return hipErrorInvalidValue;
-  const int cols = (TY * spr + 255) / 256;
-  const int nt = cols > 1 ? 256 : (TY * spr + 63) / 64 * 64;
+  if (ny % TY || TY * spr > 512) return hipErrorInvalidValue;
+  const int cols = (TY * spr + 511) / 512;
+  const int nt = cols > 1 ? 512 : (TY * spr + 63) / 64 * 64;
   const int hs = (8 * spr + nt - 1) / nt;
   int tiles = ny / TY;
   // z chunks (nzc > 0: as given): by default doubled until the grid has 2048 blocks
@@ -389,13 +413,23 @@ static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* 
   if (nzc > nz) return hipErrorInvalidValue;
   int ZC = (nz + nzc - 1) / nzc;
   nzc = (nz + ZC - 1) / ZC;
-  size_t lds = 2 * (size_t)(TY + 8) * (nx + 8) * sizeof(T);
+  // halo look-ahead (hq > 0: as given, 3 .. 8): by default 6 planes in FP32 and 4 in
+  // FP64 (measured best at 96^3), fewer where the ring (hq - 1 planes of 8 halo rows)
+  // would take the block past 64 KB of LDS
+  const size_t lds_planes = 2 * (size_t)(TY + 8) * (nx + 8) * sizeof(T), lds_ring = (size_t)8 * nx * sizeof(T);
+  int HQ = hq;
+  if (HQ <= 0)
+    for (HQ = sizeof(T) == 4 ? 6 : 4; HQ > 3 && lds_planes + (HQ - 1) * lds_ring > 64 * 1024; --HQ) {
+    }
+  if (HQ < 3 || HQ > 8) return hipErrorInvalidValue;
+  const size_t lds = lds_planes + (HQ - 1) * lds_ring;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   dim3 grid((unsigned)((long)tiles * nzc * n_orb));
 #define RT_STENCIL(C, H) \
-  hipLaunchKernelGGL((k_stencil<T, V, C, H, 2>), grid, dim3(nt), lds, s, psi, hpsi, v, nx, \
-                     ny, nz, TY, ZC, cf)
-  // nx <= 256 gives spr <= 256, so one strip per thread always fits (cols == 1), and
-  // nt >= spr bounds the halo at 8 strips per thread
+  hipLaunchKernelGGL((k_stencil<T, V, C, H, 3>), grid, dim3(nt), lds, s, psi, hpsi, v, nx, \
+                     ny, nz, TY, ZC, HQ, cf)
+  // TY * spr <= 512 gives one strip per thread (cols == 1), and nt >= spr bounds the
+  // halo at 8 strips per thread
   if (cols != 1 || hs > 8) return hipErrorInvalidValue;
   if (hs <= 1) RT_STENCIL(1, 1);
   else if (hs <= 2) RT_STENCIL(1, 2);
@@ -407,13 +441,13 @@ static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* 
 
 template <typename T>
 hipError_t stencil(hipStream_t s, const T* psi, T* hpsi, const T* v, int n_orb, int nx, int ny,
-                   int nz, double h, const double* a, int ty, int nzc) {
+                   int nz, double h, const double* a, int ty, int nzc, int hq) {
   if (nx > 256 || ny > 256 || nz > 256) return hipErrorInvalidValue;
   StencilCoef cf;
   for (int k = 0; k < 5; ++k) cf.c[k] = -0.5 * a[k] / (h * h);
   constexpr int VV = 16 / sizeof(T);
-  if (nx % VV == 0) return stencil_launch<T, VV>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf, ty, nzc);
-  return stencil_launch<T, 1>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf, ty, nzc);
+  if (nx % VV == 0) return stencil_launch<T, VV>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf, ty, nzc, hq);
+  return stencil_launch<T, 1>(s, psi, hpsi, v, n_orb, nx, ny, nz, cf, ty, nzc, hq);
 }
 
 template <typename T>
@@ -422,17 +456,18 @@ void stencil_tiles(int nx, int ny, int nz, int n_orb, std::vector<int>& ty, std:
   const int spr = nx % VV == 0 ? nx / VV : nx;
   ty.clear();
   nzc.clear();
-  for (int t = 1; t <= ny && t * spr <= 256; ++t)
+  for (int t = 1; t <= ny && t * spr <= 512; ++t)
     if (ny % t == 0) ty.push_back(t);
   for (int z = 1; z <= 16 && z <= nz; z *= 2) nzc.push_back(z);
   (void)n_orb;
 }
+void stencil_halo_ahead(std::vector<int>& hq) { hq = {3, 4, 5, 6, 8}; }
 template void stencil_tiles<double>(int, int, int, int, std::vector<int>&, std::vector<int>&);
 template void stencil_tiles<float>(int, int, int, int, std::vector<int>&, std::vector<int>&);
 template hipError_t stencil<double>(hipStream_t, const double*, double*, const double*, int, int, int,
-                                    int, double, const double*, int, int);
+                                    int, double, const double*, int, int, int);
 template hipError_t stencil<float>(hipStream_t, const float*, float*, const float*, int, int, int, int,
-                                   double, const double*, int, int);
+                                   double, const double*, int, int, int);
 
 // ============================================================================
 // Separable nonlocal projectors

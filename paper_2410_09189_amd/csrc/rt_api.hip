@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <array>
 #include <mutex>
 #include <cmath>
 #include <cstdio>
@@ -138,7 +139,7 @@ struct SysDev {
   // tuned launch shapes (0 = the built-in choice): stencil y-tile rows and z chunks
   // per element type, target block count of the FP64 projection, splits of the
   // N <= 256 BF16x3 projection
-  int st_ty[2] = {0, 0}, st_nzc[2] = {0, 0};
+  int st_ty[2] = {0, 0}, st_nzc[2] = {0, 0}, st_hq[2] = {0, 0};
   int gemm_target = 0, tri_splits = 0;
   int n_split_cap = 1, n_split_x_cap = 1;  // partial buffers are sized for these
   bool mixed = false;
@@ -780,7 +781,8 @@ rt_status project(rt_ctx* c, SysDev& d, const double* A, const double* B, const 
 rt_status apply_h64(rt_ctx* c, SysDev& d, const double* psi, double* hpsi, const double* vloc, int n) {
   {
     Timed tm(c, PH_STENCIL);
-    CK(rtk::stencil<double>(c->stream, psi, hpsi, vloc, n, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[0], d.st_nzc[0]));
+    CK(rtk::stencil<double>(c->stream, psi, hpsi, vloc, n, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[0], d.st_nzc[0],
+                            d.st_hq[0]));
   }
   if (d.nl.rank) {
     Timed tm(c, PH_NONLOCAL);
@@ -795,7 +797,8 @@ rt_status apply_h64(rt_ctx* c, SysDev& d, const double* psi, double* hpsi, const
 rt_status apply_h32(rt_ctx* c, SysDev& d, const float* psi, float* hpsi, int n) {
   {
     Timed tm(c, PH_STENCIL);
-    CK(rtk::stencil<float>(c->stream, psi, hpsi, d.vloc32, n, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[1], d.st_nzc[1]));
+    CK(rtk::stencil<float>(c->stream, psi, hpsi, d.vloc32, n, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[1], d.st_nzc[1],
+                           d.st_hq[1]));
   }
   if (d.nl.rank) {
     Timed tm(c, PH_NONLOCAL);
@@ -1990,8 +1993,8 @@ void ckpt_walk(const rt_ctx* c, CkptWriter& w, F&& dev_copy) {
 // on the context's own buffers (hipEvents on the context's stream, one warm-up
 // and three timed launches each) and the fastest kept.  Choices are cached in a
 // text file, one line per (GPU architecture, kernel, grid, N, trajectories):
-// "key value1 value2"; a later context with the same key takes the cached value
-// without timing.  The stencil tiling changes no arithmetic; the projection
+// "key value1 value2 value3"; a later context with the same key takes the cached
+// value without timing.  The stencil tiling changes no arithmetic; the projection
 // splits change the order of the partial sums (results within rounding).
 // ---------------------------------------------------------------------------
 enum { TUNE_STENCIL64 = 0, TUNE_STENCIL32 = 1, TUNE_PROJ64 = 2, TUNE_PROJ_MIXED = 3 };
@@ -2020,8 +2023,8 @@ std::map<std::string, std::vector<int>> tune_cache_read(const char* path) {
   char line[512];
   while (std::fgets(line, sizeof(line), f)) {
     char key[256];
-    int v0 = 0, v1 = 0;
-    if (std::sscanf(line, "%255s %d %d", key, &v0, &v1) == 3) m[key] = {v0, v1};
+    int v0 = 0, v1 = 0, v2 = 0;
+    if (std::sscanf(line, "%255s %d %d %d", key, &v0, &v1, &v2) >= 3) m[key] = {v0, v1, v2};
   }
   std::fclose(f);
   return m;
@@ -2033,18 +2036,24 @@ void drop_graphs(SysDev& d) {
 }
 
 // applies a launch shape (validated); the projections re-split
-rt_status tune_apply(rt_ctx* c, SysDev& d, int kernel, int p1, int p2) {
+rt_status tune_apply(rt_ctx* c, SysDev& d, int kernel, int p1, int p2, int p3) {
+  if (p3 && kernel != TUNE_STENCIL64 && kernel != TUNE_STENCIL32)
+    return fail(c, RT_EINVAL, "the projections take no third launch parameter");
   switch (kernel) {
     case TUNE_STENCIL64:
     case TUNE_STENCIL32: {
-      std::vector<int> ty, nz;
+      std::vector<int> ty, nz, hq;
       if (kernel == TUNE_STENCIL64) rtk::stencil_tiles<double>(d.nx, d.ny, d.nz, d.N, ty, nz);
       else rtk::stencil_tiles<float>(d.nx, d.ny, d.nz, d.N, ty, nz);
-      if ((p1 && std::find(ty.begin(), ty.end(), p1) == ty.end()) || p2 < 0 || p2 > d.nz)
+      rtk::stencil_halo_ahead(hq);
+      if ((p1 && std::find(ty.begin(), ty.end(), p1) == ty.end()) || p2 < 0 || p2 > d.nz ||
+          (p3 && std::find(hq.begin(), hq.end(), p3) == hq.end()))
         return fail(c, RT_EINVAL, "stencil tiling (y rows " + std::to_string(p1) + ", z chunks " +
-                                      std::to_string(p2) + ") not available on this grid");
+                                      std::to_string(p2) + ", halo look-ahead " + std::to_string(p3) +
+                                      ") not available on this grid");
       d.st_ty[kernel] = p1;
       d.st_nzc[kernel] = p2;
+      d.st_hq[kernel] = p3;
       break;
     }
     case TUNE_PROJ64:
@@ -2096,12 +2105,12 @@ rt_status tune_run(rt_ctx* c, SysDev& d, int kernel) {
   switch (kernel) {
     case TUNE_STENCIL64:
       CK(rtk::stencil<double>(s, d.psi, d.hpsi, d.vloc_gs, d.N, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[0],
-                              d.st_nzc[0]));
+                              d.st_nzc[0], d.st_hq[0]));
       return RT_OK;
     case TUNE_STENCIL32: {
       float* in = reinterpret_cast<float*>(d.hpsi);  // FP32 copy of the orbitals, then the output
       CK(rtk::stencil<float>(s, in, in + (long)d.N * d.ng, d.vloc32, d.N, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[1],
-                             d.st_nzc[1]));
+                             d.st_nzc[1], d.st_hq[1]));
       return RT_OK;
     }
     case TUNE_PROJ64:
@@ -2137,41 +2146,61 @@ rt_status autotune_system(rt_ctx* c, SysDev& d, int si, const std::string& arch,
     auto it = cache.find(key);
     char line[320];
     if (it != cache.end()) {
-      RET(tune_apply(c, d, k, it->second[0], it->second[1]));
-      std::snprintf(line, sizeof(line), "system %d %s: %d %d (cached)\n", si, kTuneNames[k], it->second[0],
-                    it->second[1]);
+      RET(tune_apply(c, d, k, it->second[0], it->second[1], it->second[2]));
+      std::snprintf(line, sizeof(line), "system %d %s: %d %d %d (cached)\n", si, kTuneNames[k], it->second[0],
+                    it->second[1], it->second[2]);
       rep += line;
       continue;
     }
-    std::vector<std::pair<int, int>> cand;
-    if (k == TUNE_STENCIL64 || k == TUNE_STENCIL32) {
+    // candidates (p1, p2, p3); for the stencils the halo look-ahead is swept in a
+    // second round at the best tiling of the first
+    std::vector<std::array<int, 3>> cand;
+    std::vector<int> hq;
+    const bool stencil = k == TUNE_STENCIL64 || k == TUNE_STENCIL32;
+    if (stencil) {
       std::vector<int> ty, nz;
       if (k == TUNE_STENCIL64) rtk::stencil_tiles<double>(d.nx, d.ny, d.nz, d.N, ty, nz);
       else rtk::stencil_tiles<float>(d.nx, d.ny, d.nz, d.N, ty, nz);
-      cand.push_back({0, 0});
+      rtk::stencil_halo_ahead(hq);
+      cand.push_back({0, 0, 0});
       for (int a : ty)
-        for (int b : nz) cand.push_back({a, b});
+        for (int b : nz) cand.push_back({a, b, 0});
     } else if (k == TUNE_PROJ64) {
-      cand.push_back({0, 0});
-      for (int v : kGemmTargets) cand.push_back({v, 0});
+      cand.push_back({0, 0, 0});
+      for (int v : kGemmTargets) cand.push_back({v, 0, 0});
     } else {
-      cand.push_back({0, 0});
-      for (int v : kTriSplits) cand.push_back({v, 0});
+      cand.push_back({0, 0, 0});
+      for (int v : kTriSplits) cand.push_back({v, 0, 0});
     }
     double best = 1e300, t_def = 0.0;
-    std::pair<int, int> pick{0, 0};
-    for (auto& p : cand) {
-      RET(tune_apply(c, d, k, p.first, p.second));
-      double ms = 0.0;
-      RET(tune_time(c, [&] { return tune_run(c, d, k); }, ms));
-      if (p.first == 0 && p.second == 0) t_def = ms;
-      if (ms < best) { best = ms; pick = p; }
+    std::array<int, 3> pick{0, 0, 0};
+    size_t n_cand = 0;
+    for (int round = 0; round < (stencil ? 2 : 1); ++round) {
+      if (round == 1) {
+        cand.clear();
+        for (int v : hq) cand.push_back({pick[0], pick[1], v});
+      }
+      for (auto& p : cand) {
+        // a shape the kernel refuses (LDS) is skipped
+        if (tune_apply(c, d, k, p[0], p[1], p[2]) != RT_OK) continue;
+        double ms = 0.0;
+        rt_status st = tune_time(c, [&] { return tune_run(c, d, k); }, ms);
+        if (st != RT_OK) {
+          if (p[2] == 0) return st;  // the tilings of the first round all launch
+          (void)hipGetLastError();
+          continue;
+        }
+        ++n_cand;
+        if (p[0] == 0 && p[1] == 0 && p[2] == 0) t_def = ms;
+        if (ms < best) { best = ms; pick = p; }
+      }
     }
-    RET(tune_apply(c, d, k, pick.first, pick.second));
-    cache[key] = {pick.first, pick.second};
-    if (out) std::fprintf(out, "%s %d %d\n", key.c_str(), pick.first, pick.second);
-    std::snprintf(line, sizeof(line), "system %d %s: %d %d, %.1f us (built-in choice %.1f us, %zu candidates)\n",
-                  si, kTuneNames[k], pick.first, pick.second, 1e3 * best, 1e3 * t_def, cand.size());
+    c->err.clear();
+    RET(tune_apply(c, d, k, pick[0], pick[1], pick[2]));
+    cache[key] = {pick[0], pick[1], pick[2]};
+    if (out) std::fprintf(out, "%s %d %d %d\n", key.c_str(), pick[0], pick[1], pick[2]);
+    std::snprintf(line, sizeof(line), "system %d %s: %d %d %d, %.1f us (built-in choice %.1f us, %zu candidates)\n",
+                  si, kTuneNames[k], pick[0], pick[1], pick[2], 1e3 * best, 1e3 * t_def, n_cand);
     rep += line;
   }
   return RT_OK;
@@ -2420,18 +2449,20 @@ rt_status rt_autotune(rt_ctx* c, const char* cache_path) {
   return st;
 }
 
-rt_status rt_tune_set(rt_ctx* c, int si, int kernel, int p1, int p2) {
+rt_status rt_tune_set(rt_ctx* c, int si, int kernel, int p1, int p2, int p3) {
   if (!c) return RT_EINVAL;
   if (si < 0 || si >= (int)c->sys.size()) return fail(c, RT_EINVAL, "sys_index out of range");
-  return tune_apply(c, c->sys[si], kernel, p1, p2);
+  return tune_apply(c, c->sys[si], kernel, p1, p2, p3);
 }
 
-rt_status rt_tune_get(rt_ctx* c, int si, int kernel, int* p1, int* p2) {
-  if (!c || !p1 || !p2) return RT_EINVAL;
+rt_status rt_tune_get(rt_ctx* c, int si, int kernel, int* p1, int* p2, int* p3) {
+  if (!c || !p1 || !p2 || !p3) return RT_EINVAL;
   if (si < 0 || si >= (int)c->sys.size()) return fail(c, RT_EINVAL, "sys_index out of range");
   const SysDev& d = c->sys[si];
+  *p3 = 0;
   switch (kernel) {
-    case TUNE_STENCIL64: case TUNE_STENCIL32: *p1 = d.st_ty[kernel]; *p2 = d.st_nzc[kernel]; break;
+    case TUNE_STENCIL64: case TUNE_STENCIL32:
+      *p1 = d.st_ty[kernel]; *p2 = d.st_nzc[kernel]; *p3 = d.st_hq[kernel]; break;
     case TUNE_PROJ64: *p1 = d.gemm_target; *p2 = d.n_split; break;
     case TUNE_PROJ_MIXED: *p1 = d.tri_splits; *p2 = d.n_split_x; break;
     default: return fail(c, RT_EINVAL, "unknown tunable kernel");

@@ -92,8 +92,8 @@ def _load():
         "rt_get_matrix": ([vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
         "rt_set_state": ([vp, ctypes.c_int, _dp, _dp, _dp, _dp], ctypes.c_int),
         "rt_autotune": ([vp, ctypes.c_char_p], ctypes.c_int),
-        "rt_tune_set": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
-        "rt_tune_get": ([vp, ctypes.c_int, ctypes.c_int, _ip, _ip], ctypes.c_int),
+        "rt_tune_set": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "rt_tune_get": ([vp, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip], ctypes.c_int),
         "rt_tune_report": ([vp], ctypes.c_char_p),
         "rt_checkpoint_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "rt_checkpoint_save": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
@@ -394,14 +394,14 @@ def rt_autotune(ctx, cache_path=None) -> str:
     return lib.rt_tune_report(ctx).decode()
 
 
-def rt_tune_set(ctx, sys_index, kernel, p1, p2=0):
-    _check(lib.rt_tune_set(ctx, sys_index, kernel, p1, p2), ctx)
+def rt_tune_set(ctx, sys_index, kernel, p1, p2=0, p3=0):
+    _check(lib.rt_tune_set(ctx, sys_index, kernel, p1, p2, p3), ctx)
 
 
 def rt_tune_get(ctx, sys_index, kernel):
-    a, b = ctypes.c_int(0), ctypes.c_int(0)
-    _check(lib.rt_tune_get(ctx, sys_index, kernel, ctypes.byref(a), ctypes.byref(b)), ctx)
-    return a.value, b.value
+    a, b, c = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib.rt_tune_get(ctx, sys_index, kernel, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), ctx)
+    return a.value, b.value, c.value
 
 
 def rt_checkpoint_save(ctx) -> np.ndarray:

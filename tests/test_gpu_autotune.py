@@ -1,5 +1,6 @@
 """The autotuner of launch shapes, through the C ABI.  Every stencil tiling it
-may pick (y-tile rows x z chunks) gives the same H apply bit for bit in FP64 and
+may pick (y-tile rows x z chunks x halo look-ahead) gives the same H apply bit
+for bit in FP64 and
 FP32; tuned runs (stencil tiles and projection splits chosen by timing) agree
 with runs at the built-in shapes within rounding -- the FP64 parity bound and the
 mixed-precision bound; a second context reads every choice from the cache."""
@@ -38,16 +39,22 @@ def test_every_stencil_tiling_gives_the_same_apply_bitwise():
         ref = y.cpu().numpy()
         spr = 36 // (2 if dtype == 0 else 4)
         n = 0
-        for ty in [t for t in range(1, 41) if 40 % t == 0 and t * spr <= 256]:
-            for nzc in (1, 2, 4, 8, 16):
-                rt.rt_tune_set(ses.ctx, 0, kern, ty, nzc)
-                y.zero_()
-                rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), 20, dtype)
-                assert np.array_equal(y.cpu().numpy(), ref), (dtype, ty, nzc)
-                n += 1
-        assert n >= 25
+        tys = [t for t in range(1, 41) if 40 % t == 0 and t * spr <= 512]
+        # every tiling at the built-in halo look-ahead, then every look-ahead on a few
+        # tilings (z chunks of 2 planes have fewer planes than the look-ahead)
+        shapes = [(ty, nzc, 0) for ty in tys for nzc in (1, 2, 4, 8, 16)]
+        shapes += [(ty, nzc, hq) for ty in (tys[0], tys[-1]) for nzc in (1, 4, 16) for hq in (3, 4, 5, 6, 8)]
+        for ty, nzc, hq in shapes:
+            rt.rt_tune_set(ses.ctx, 0, kern, ty, nzc, hq)
+            y.zero_()
+            rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), 20, dtype)
+            assert np.array_equal(y.cpu().numpy(), ref), (dtype, ty, nzc, hq)
+            n += 1
+        assert n >= 55
         with pytest.raises(rt.RTError):
             rt.rt_tune_set(ses.ctx, 0, kern, 3, 1)  # 3 does not divide ny = 40
+        with pytest.raises(rt.RTError):
+            rt.rt_tune_set(ses.ctx, 0, kern, 0, 0, 2)  # not a look-ahead candidate
         rt.rt_tune_set(ses.ctx, 0, kern, 0, 0)
     ses.close()
 
