@@ -450,6 +450,100 @@ def apply_h_192(rt, torch, n_orb=3000, reps=3):
             "algorithmic_bytes": nbytes}
 
 
+def plane_wave_orbitals(torch, n, h, n_orb, chunk=96, device="cuda"):
+    """n_orb orthonormal orbitals of the periodic n^3 grid (h^3 inner product):
+    the constant and cos / sin(G . r) pairs of the lowest |G| (integer triplets m,
+    one of each +-m), exactly orthogonal under the grid sum.  Generated on the
+    device chunk by chunk and staged in a host array [n_orb][n^3] (float64)."""
+    omega = (n * h) ** 3
+    ms = []
+    r = 1
+    while len(ms) < n_orb:
+        ms = []
+        rng_ = range(-r, r + 1)
+        cand = sorted(((a * a + b * b + c * c, (a, b, c)) for a in rng_ for b in rng_ for c in rng_))
+        for _, m in cand:
+            first = next((v for v in m if v != 0), 0)
+            if m == (0, 0, 0):
+                ms.append((m, "c"))
+            elif first > 0:
+                ms.extend([(m, "c"), (m, "s")])
+        r += 1
+    ms = ms[:n_orb]
+    host = np.empty((n_orb, n ** 3), dtype=np.float64)
+    ax = torch.arange(n, dtype=torch.float64, device=device) * (2.0 * np.pi / n)
+    for j0 in range(0, n_orb, chunk):
+        blk = torch.empty((min(chunk, n_orb - j0), n, n, n), dtype=torch.float64, device=device)
+        for k, (m, kind) in enumerate(ms[j0:j0 + blk.shape[0]]):
+            ph = (m[2] * ax)[:, None, None] + (m[1] * ax)[None, :, None] + (m[0] * ax)[None, None, :]
+            if m == (0, 0, 0):
+                blk[k].fill_(1.0 / np.sqrt(omega))
+            else:
+                (torch.cos(ph, out=blk[k]) if kind == "c" else torch.sin(ph, out=blk[k])).mul_(np.sqrt(2.0 / omega))
+        torch.from_numpy(host[j0:j0 + blk.shape[0]]).copy_(blk.reshape(blk.shape[0], -1))
+        del blk
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return host
+
+
+def c5_time_step(rt, torch, steps=4, warmup=1, h_block=128):
+    """A whole time step at the nanoparticle shape: 192^3 grid, the 600-well fcc
+    cluster, 2400 occupied + 600 virtual orbitals, one x kick, mixed precision
+    with the local update and the quadratic first guess.  The FP64 orbitals
+    (170 GB) and their bf16 hi/lo pair (85 GB) are resident; the initial grid
+    Hamiltonian is applied 128 orbitals at a time (rt_run.h_block).  The orbitals
+    are orthonormal plane waves (the step's cost does not depend on their values;
+    they are not the cluster's ground state, so the state evolves from the start).
+    Reports steps/s, Hamiltonian updates per step and the phase times."""
+    import synth
+
+    s = synth.config_system("c5_cluster_192")
+    N, ng = s.n_orb, s.ng
+    t0 = time.perf_counter()
+    psi = plane_wave_orbitals(torch, s.n[0], s.h, N)
+    t_gen = time.perf_counter() - t0
+    sa = rt.SystemArgs(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ, n_virt=s.n_virt,
+                       psi0=psi, n_images=s.n_images)
+    n_steps = warmup + steps + 2
+    ra = rt.RunArgs(dt=0.05, n_steps_max=n_steps, h_thrs=1e-7, dp_thrs=1e-10, max_scf=30, max_terms=400,
+                    traj_sys=[0], traj_kappa=[1e-3], traj_axis=[0], precision=rt.RT_MIXED,
+                    hupdate=rt.RT_HUPDATE_LOCAL, predictor=rt.RT_PRED_QUADRATIC, h_block=h_block)
+    ws = rt.rt_workspace_size([sa], ra)
+    log(f"c5: orbitals generated in {t_gen:.1f} s; workspace {ws / 2**30:.1f} GiB")
+    t0 = time.perf_counter()
+    ses = rt.Session([sa], ra)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    del psi, sa
+    log(f"c5: rt_init {t_init:.1f} s")
+    rt.rt_step(ses.ctx, warmup, n_traj=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = rt.rt_step(ses.ctx, steps, n_traj=1, stats=True)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    rt.rt_profile(ses.ctx, enable=True, reset=True)
+    rt.rt_step(ses.ctx, 1, n_traj=1)
+    torch.cuda.synchronize()
+    ph = rt.rt_profile_read(ses.ctx)
+    rt.rt_profile(ses.ctx, enable=False, reset=True)
+    mu, E, tr = rt.rt_dipole(ses.ctx, 0, 0, warmup + steps + 2)
+    ses.close()
+    del ses
+    torch.cuda.empty_cache()
+    upd = [x[0] for x in st]
+    return {"workload": "c5_cluster_192: 192^3 h=0.3, 600-well fcc cluster (radius 25 bohr), N=3000 (2400 occ + "
+                        "600 virt), one x kick, mixed BF16x3 + local update + quadratic first guess, dt=0.05, "
+                        "H_thrs=1e-07; orthonormal plane-wave orbitals",
+            "steps_per_s": steps / t_run, "ms_per_step": 1e3 * t_run / steps,
+            "updates_per_step": float(np.mean(upd)), "workspace_GiB": ws / 2 ** 30,
+            "init_s": t_init, "orbital_generation_s": t_gen,
+            "phases_ms_one_step": {k: v[0] for k, v in ph.items() if v[1]},
+            "phase_launches_one_step": {k: v[1] for k, v in ph.items() if v[1]},
+            "trace_electrons": float(tr[-1]), "dipole_x_change": float(mu[-1][0] - mu[0][0])}
+
+
 def learned_predictor(rt, torch, sa, s):
     """The learned first guess on the 96^3 molecule (mixed precision): training
     samples recorded by the step itself on x and y kicks of two strengths, the
@@ -555,6 +649,7 @@ def main():
     ap.add_argument("--only-variants", action="store_true", help="run only those legs")
     ap.add_argument("--only-192", action="store_true", help="run only the 192^3 apply leg")
     ap.add_argument("--only-batch", action="store_true", help="run only the 16-molecule batch leg")
+    ap.add_argument("--only-c5", action="store_true", help="run only the 192^3 x 3000 time-step leg")
     ap.add_argument("--only-learned", action="store_true", help="run only the learned-predictor leg")
     args = ap.parse_args()
     if args.h_thrs not in args.sweep:
@@ -572,6 +667,10 @@ def main():
     if args.only_192:
         log("FP32 H apply, 192^3 x 3000 orbitals")
         print(json.dumps({"apply_h_192": apply_h_192(rt, torch)}), flush=True)
+        return
+    if args.only_c5:
+        log("time step, 192^3 x 3000 orbitals (mixed, blocked initialisation)")
+        print(json.dumps({"c5_time_step": c5_time_step(rt, torch)}), flush=True)
         return
     if args.only_batch:
         log("batched: 16 molecules x 3 kicks in one context vs 16 contexts")

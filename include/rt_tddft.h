@@ -183,6 +183,16 @@ typedef struct {
                                 (at most a few per system: the buffers rotate);
                                 0: eager launches.  Off while the phase timers of
                                 rt_profile are on.  Results are identical.        */
+  int h_block;               /* orbitals per block of the initial FP64 grid
+                                Hamiltonian application; 0: all at once.  With
+                                0 < h_block < N the orbital buffer beside Psi
+                                holds h_block orbitals instead of N (Psi^T H Psi
+                                is assembled block by block, H_gs as H_core +
+                                h^3 Psi^T diag(V_H + v_x) Psi), which is what lets
+                                a 192^3 x 3000-orbital system fit one device;
+                                needs hupdate RT_HUPDATE_LOCAL (or RT_MIXED) and
+                                no system with orthonormalize (RT_EINVAL).
+                                Results agree with h_block = 0 within rounding. */
 } rt_run;
 
 /* Per-trajectory, per-step counters written by rt_step when stats != NULL. */

@@ -144,6 +144,7 @@ struct SysDev {
   int n_split_cap = 1, n_split_x_cap = 1;  // partial buffers are sized for these
   bool mixed = false;
   bool nonorth = false;  // propagate in the given (non-orthogonal) basis with its overlap
+  int hb = 0;            // orbitals the buffer hpsi holds (N, or the run's h_block)
   int dcorr = 0;         // bit q: vacuum dipole correction along axis q
   int jump[3] = {0, 0, 0};  // sawtooth jump plane per axis
   double dion[3] = {0.0, 0.0, 0.0};  // ions' dipole sum_a Z_a s_q(R_a) on the corrected axes
@@ -480,6 +481,14 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
       }
   }
   if (run->hupdate != RT_HUPDATE_FULL && run->hupdate != RT_HUPDATE_LOCAL) { why = "hupdate"; return RT_EINVAL; }
+  if (run->h_block < 0) { why = "h_block < 0"; return RT_EINVAL; }
+  if (run->h_block > 0) {
+    if (run->precision != RT_MIXED && run->hupdate != RT_HUPDATE_LOCAL) {
+      why = "h_block needs RT_HUPDATE_LOCAL or RT_MIXED (the full update applies H to every orbital)"; return RT_EINVAL;
+    }
+    for (int i = 0; i < n_sys; ++i)
+      if (sys[i].orthonormalize) { why = "h_block excludes orthonormalize"; return RT_EINVAL; }
+  }
   if (run->magnus_order != 0 && run->magnus_order != 2 && run->magnus_order != 4) {
     why = "magnus_order must be 0, 2 or 4"; return RT_EINVAL;
   }
@@ -563,7 +572,7 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.tcur = a.take<double>(1);
     d.box_ctr = a.take<unsigned long long>(1);
     d.psi = a.take<double>(N * ng);
-    d.hpsi = a.take<double>(N * ng);
+    d.hpsi = a.take<double>((long)d.hb * ng);
     d.vion = a.take<double>(ng);
     d.vloc_gs = a.take<double>(ng);
     d.occ = a.take<double>(N);
@@ -715,6 +724,7 @@ void describe(const rt_system* sys, int n_sys, const rt_run* run, std::vector<Sy
     d.n_union = (int)d.nl.u_idx.size();
     d.mixed = run->precision == RT_MIXED;
     d.nonorth = s.nonorthogonal != 0;
+    d.hb = run->h_block > 0 && run->h_block < d.N ? run->h_block : d.N;
     d.dcorr = s.dipole_correction;
     for (int q = 0; q < 3; ++q) d.jump[q] = s.saw_jump[q];
     ion_dipole(s, d);
@@ -880,6 +890,19 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
     }
     Timed tr(c, PH_REDUCE);
     CK(rtk::reduce_parts_f32(s, d.part32, d.n_split_x, d.N, d.h3, d.Hgs, Hout, T, act, 0));
+    return RT_OK;
+  }
+  if (force_full && d.hb < d.N) {
+    // blocked systems: H[P] = H_core + h^3 Psi^T diag(V_loc - V_ion) Psi (no full apply)
+    CK(rtk::sub_d(s, d.dv, d.vloc, d.vion, d.ng, T, act));
+    const long sp = (long)d.n_split * NN;
+    {
+      Timed tm(c, PH_PROJECT);
+      CK(rtk::gemm_nt_f64(s, d.N, d.N, d.ng, d.psi, d.ng, d.psi, d.ng, d.dv, d.part, d.kps, d.n_split, 1, d.big,
+                          rtk::Batch{T, act, 0, 0, d.ng, sp}));
+    }
+    Timed tr(c, PH_REDUCE);
+    CK(rtk::reduce_parts(s, d.part, d.n_split, d.N, d.N, d.h3, Hout, 1, d.hcore, T, sp, 0, NN, act));
     return RT_OK;
   }
   if (r.hupdate == RT_HUPDATE_FULL || force_full) {
@@ -1161,8 +1184,26 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
     CK(rtk::coord(st, d.dv, d.nx, d.ny, d.nz, d.h, q, d.jump[q]));
     RET(project(c, d, d.psi, d.psi, d.dv, d.M3 + q * NN));
   }
-  RET(apply_h64(c, d, d.psi, d.hpsi, d.vion, d.N));
-  RET(project(c, d, d.psi, d.hpsi, nullptr, d.hcore));
+  if (d.hb == d.N) {
+    RET(apply_h64(c, d, d.psi, d.hpsi, d.vion, d.N));
+    RET(project(c, d, d.psi, d.hpsi, nullptr, d.hcore));
+  } else {
+    // H_core by blocks of hb orbitals J: rows J of X = h^3 (H Psi_J) Psi^T, then
+    // H_core = (X + X^T) / 2
+    for (int j0 = 0; j0 < d.N; j0 += d.hb) {
+      const int nb = std::min(d.hb, d.N - j0);
+      RET(apply_h64(c, d, d.psi + (long)j0 * ng, d.hpsi, d.vion, nb));
+      {
+        Timed tm(c, PH_PROJECT);
+        CK(rtk::gemm_nt_f64(st, nb, d.N, ng, d.hpsi, ng, d.psi, ng, nullptr, d.part, d.kps, d.n_split, 0, d.big,
+                            rtk::single()));
+      }
+      CK(rtk::reduce_parts(st, d.part, d.n_split, nb, d.N, d.h3, d.tmp2 + (long)j0 * N, 0, nullptr, 1, 0, 0, 0,
+                           nullptr));
+    }
+    CK(rtk::transpose(st, d.tmp2, d.tmp, d.N));
+    CK(rtk::lincomb(st, d.hcore, 0.5, d.tmp2, 0.5, d.tmp, NN));
+  }
   // ground-state Hamiltonian H_gs = H[P_gs] with the full FP64 apply (slot 0 fields);
   // P_gs = diag(f), or for a non-orthogonal basis with overlap S = h^3 Phi Phi^T = L L^T:
   // S^-1 = L^-T L^-1 and P_gs = L^-T diag(f) L^-1 (the occupations of the basis
@@ -2104,12 +2145,12 @@ rt_status tune_run(rt_ctx* c, SysDev& d, int kernel) {
   const long NN = nsq(d.N);
   switch (kernel) {
     case TUNE_STENCIL64:
-      CK(rtk::stencil<double>(s, d.psi, d.hpsi, d.vloc_gs, d.N, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[0],
+      CK(rtk::stencil<double>(s, d.psi, d.hpsi, d.vloc_gs, d.hb, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[0],
                               d.st_nzc[0], d.st_hq[0]));
       return RT_OK;
     case TUNE_STENCIL32: {
-      float* in = reinterpret_cast<float*>(d.hpsi);  // FP32 copy of the orbitals, then the output
-      CK(rtk::stencil<float>(s, in, in + (long)d.N * d.ng, d.vloc32, d.N, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[1],
+      float* in = reinterpret_cast<float*>(d.hpsi);  // FP32 copy of hb orbitals, then the output
+      CK(rtk::stencil<float>(s, in, in + (long)d.hb * d.ng, d.vloc32, d.hb, d.nx, d.ny, d.nz, d.h, d.coef, d.st_ty[1],
                              d.st_nzc[1], d.st_hq[1]));
       return RT_OK;
     }
@@ -2137,7 +2178,7 @@ rt_status autotune_system(rt_ctx* c, SysDev& d, int si, const std::string& arch,
   if (d.mixed && d.N <= rtk::proj_tri_max_n()) kernels.push_back(TUNE_PROJ_MIXED);
   // inputs of the timed launches: FP32 orbitals and potential, the ground-state
   // potential change (zero) as projection weights
-  CK(rtk::cast_d2f(s, reinterpret_cast<float*>(d.hpsi), d.psi, (long)d.N * d.ng));
+  CK(rtk::cast_d2f(s, reinterpret_cast<float*>(d.hpsi), d.psi, (long)d.hb * d.ng));
   CK(rtk::cast_d2f(s, d.vloc32, d.vloc_gs, d.ng));
   if (!d.mixed) CK(rtk::sub_d(s, d.dv, d.vloc, d.vloc_gs, d.ng, d.T, nullptr));
   else CK(rtk::delta_f32(s, d.dv32, d.vloc, d.vloc_gs, d.ng, d.T, nullptr));

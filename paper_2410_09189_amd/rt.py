@@ -45,6 +45,7 @@ class rt_run(ctypes.Structure):
         ("frozen_hxc", ctypes.c_int), ("n_traj", ctypes.c_int), ("traj_sys", _ip),
         ("traj_kappa", _dp), ("traj_axis", _ip), ("mlp_params", ctypes.POINTER(ctypes.c_float)),
         ("traj_field", _dp), ("magnus_order", ctypes.c_int), ("graph_capture", ctypes.c_int),
+        ("h_block", ctypes.c_int),
     ]
 
 
@@ -187,7 +188,8 @@ class SystemArgs:
 class RunArgs:
     def __init__(self, dt, n_steps_max, h_thrs, dp_thrs, max_scf, max_terms, traj_sys, traj_kappa,
                  traj_axis, precision=RT_FP64, predictor=RT_PRED_LINEAR, hupdate=RT_HUPDATE_FULL,
-                 frozen_hxc=False, mlp_params=None, traj_field=None, magnus_order=0, graph_capture=True):
+                 frozen_hxc=False, mlp_params=None, traj_field=None, magnus_order=0, graph_capture=True,
+                 h_block=0):
         self.traj_sys = np.ascontiguousarray(traj_sys, dtype=np.int32)
         self.traj_kappa = np.ascontiguousarray(traj_kappa, dtype=np.float64)
         self.traj_axis = np.ascontiguousarray(traj_axis, dtype=np.int32)
@@ -196,6 +198,7 @@ class RunArgs:
         r.max_scf, r.max_terms = max_scf, max_terms
         r.precision, r.predictor, r.hupdate, r.frozen_hxc = precision, predictor, hupdate, int(frozen_hxc)
         r.graph_capture = int(graph_capture)
+        r.h_block = int(h_block)
         r.n_traj = len(self.traj_sys)
         r.traj_sys = _ptr(self.traj_sys, ctypes.c_int)
         r.traj_kappa = _ptr(self.traj_kappa)

@@ -125,6 +125,29 @@ def test_dipole_correction_adds_its_partial_sums():
     assert b > a
 
 
+@pytest.mark.parametrize("over", [dict(h_block=4, hupdate=0), dict(h_block=4, hupdate=1, orthonormalize=1),
+                                  dict(h_block=-1, hupdate=1)])
+def test_h_block_needs_the_local_update_and_given_orthonormal_orbitals(over):
+    """Blocked initialisation never holds H applied to every orbital, which the full
+    update and the library's orthonormalisation need."""
+    from paper_2410_09189_amd import rt
+
+    sa, ra = _args(**over)
+    with pytest.raises(rt.RTError) as e:
+        rt.rt_workspace_size([sa], ra)
+    assert e.value.status == rt.RT_EINVAL and ("h_block" in rt.rt_last_error())
+
+
+def test_h_block_shrinks_the_workspace():
+    from paper_2410_09189_amd import rt
+
+    sa, ra = _args(hupdate=1)
+    a = rt.rt_workspace_size([sa], ra)
+    sa, ra = _args(hupdate=1, h_block=1)
+    b = rt.rt_workspace_size([sa], ra)
+    assert a - b == 3 * 16 ** 3 * 8  # N = 4: the H Psi buffer holds 1 orbital instead of 4
+
+
 def test_nonorthogonal_basis_takes_overlap_buffers():
     from paper_2410_09189_amd import rt
 
