@@ -593,6 +593,128 @@ def learned_predictor(rt, torch, sa, s):
             "dipole_max_abs": float(np.max(np.abs(mu_l - mu_l[0])))}
 
 
+def learned_predictor_c4(rt, torch, dts=(0.05, 0.2, 0.5, 1.0), train_seeds=range(400, 416),
+                         test_seeds=range(500, 504), n_rec=60, n_eval=60, h_thrs=1e-7):
+    """The learned first guess across molecules: 96^3 molecules of the N=240 mixed
+    workload's generator (40 wells + rank-4 projectors, 160 + 80 orbitals), ground
+    states on the GPU (a density loop stopped at 40 iterations is kept when
+    self-consistent to 1e-5; others are left out), samples recorded on x/y/z kicks
+    of the training seeds,
+    one network per time step trained on the GPU, then the held-out seeds stepped
+    with a z kick under the linear, quadratic and learned guesses.  Reports
+    Hamiltonian updates per step (after the 8 warm-up steps the features need),
+    time per step, the network's own time per step, and the dipole difference
+    to the linear run (same fixed point)."""
+    import synth
+    from paper_2410_09189_amd import predictor
+
+    c = synth.CONFIGS["c2_mixed_96"]
+    gsp = dict(n_guard=30, degree=24, max_scf=40, max_passes=20, tol_rho=1e-9, tol_res=1e-8, mix=0.15)
+
+    def molecule(seed):
+        s = synth.make_system(c["n"], c["h"], c["n_atoms"], c["n_occ"], c["n_virt"], seed, region=c["region"],
+                              nl_rank=c["nl_rank"])
+        x0 = synth.lowpass_orbitals(s.n, s.h, s.n_orb + gsp["n_guard"], seed)
+        kw = dict(n=s.n, h=s.h, pos=s.pos, depth=s.depth, width=s.width, n_occ=s.n_occ, n_virt=s.n_virt,
+                  nl_rank=s.nl_rank, nl_rcut=s.nl_rcut, nl_sigma=s.nl_sigma, nl_D=s.nl_D, n_images=s.n_images)
+        t0 = time.perf_counter()
+        try:
+            psi, eps, _, st = rt.ground_state(rt.SystemArgs(psi0=x0, **kw), rt.gs_params(**gsp))
+        except rt.RTError as e:
+            # most molecules of this generator have HOMO-LUMO gaps of 1e-5 - 1e-3 Ha and
+            # converge slowly; an iterate self-consistent to rho_err <= 1e-5 is kept
+            if not hasattr(e, "psi") or not (e.stats["rho_err"] <= 1e-5):
+                return None, time.perf_counter() - t0, e.stats.get("rho_err")
+            psi, eps, st = e.psi, e.eps, e.stats
+        return rt.SystemArgs(psi0=psi, **kw), time.perf_counter() - t0, st["rho_err"]
+
+    def ra(dt, axes, kappas, n, pred=0, params=None):
+        return rt.RunArgs(dt=dt, n_steps_max=n, h_thrs=h_thrs, dp_thrs=1e-12, max_scf=60, max_terms=400,
+                          traj_sys=[0] * len(axes), traj_kappa=list(kappas), traj_axis=list(axes),
+                          precision=rt.RT_MIXED, hupdate=rt.RT_HUPDATE_LOCAL, predictor=pred, mlp_params=params)
+
+    t_gs = 0.0
+    train, test, dropped = [], [], []
+    for seeds, dst in ((train_seeds, train), (test_seeds, test)):
+        for seed in seeds:
+            sa, t, rerr = molecule(seed)
+            t_gs += t
+            (dst.append((seed, sa)) if sa is not None else dropped.append(seed))
+            log(f"learned c4: molecule {seed} {'kept' if sa is not None else 'left out'} ({t:.1f} s, "
+                f"rho_err {rerr:.1e})")
+    # the network's forward pass alone, at the run's batch size (one trajectory)
+    n_in, n_h, n_out = rt.rt_mlp_dims()
+    out = {"workload": "96^3 molecules of the N=240 mixed workload's generator, mixed precision, local update, "
+                       f"H_thrs {h_thrs:g}; train seeds {list(train_seeds)[0]}..{list(train_seeds)[-1]} (x/y/z kicks "
+                       f"1e-3, {n_rec} recorded steps), held-out seeds {list(test_seeds)[0]}..{list(test_seeds)[-1]} "
+                       f"(z kick 1.5e-3, {n_eval} steps)",
+           "train_molecules": [x[0] for x in train], "test_molecules": [x[0] for x in test],
+           "left_out": dropped, "ground_state_s": round(t_gs, 1), "per_dt": {}}
+    if not train or not test:
+        out["note"] = "too few molecules with a usable ground state"
+        return out
+    for dt in dts:
+        Xs, Ys = [], []
+        for _, sa in train:
+            X, Y = predictor.record(lambda: rt.Session([sa], ra(dt, (0, 1, 2), (1e-3,) * 3, n_rec)), n_rec,
+                                    capacity=3 * n_rec)
+            Xs.append(X)
+            Ys.append(Y)
+        X, Y = torch.cat(Xs), torch.cat(Ys)
+        n_samples = X.shape[0]
+        params, hist = predictor.train(X, Y, epochs=30, batch=64, lr=1e-3, seed=0)
+        del Xs, Ys, X, Y
+        row = {"samples": int(n_samples), "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+        agg = {}
+        for name, pred in (("linear", rt.RT_PRED_LINEAR), ("quadratic", rt.RT_PRED_QUADRATIC),
+                           ("learned", rt.RT_PRED_MLP)):
+            ups, mss, dmu = [], [], []
+            for seed, sa in test:
+                ses = rt.Session([sa], ra(dt, (2,), (1.5e-3,), n_eval, pred=pred,
+                                          params=params if pred == rt.RT_PRED_MLP else None))
+                rt.rt_step(ses.ctx, 8, n_traj=1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = rt.rt_step(ses.ctx, n_eval - 8, n_traj=1, stats=True)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                mu = rt.rt_dipole(ses.ctx, 0, 0, n_eval + 1)[0][:, 2]
+                ses.close()
+                ups.append(float(np.mean([x[0] for x in st])))
+                mss.append(1e3 * el / (n_eval - 8))
+                dmu.append(mu)
+            agg[name] = {"updates_per_step": float(np.mean(ups)), "ms_per_step": float(np.mean(mss)),
+                         "updates_per_step_each": ups, "mu": dmu}
+        for name in ("quadratic", "learned"):
+            agg[name]["dipole_max_diff_vs_linear"] = float(max(np.max(np.abs(a - b)) for a, b in
+                                                               zip(agg[name]["mu"], agg["linear"]["mu"])))
+        scale = float(max(np.max(np.abs(m - m[0])) for m in agg["linear"]["mu"]))
+        for v in agg.values():
+            del v["mu"]
+        row.update(agg)
+        row["dipole_change_scale"] = scale
+        # the network's forward pass alone (one trajectory), to separate it from the step
+        x = torch.zeros((1, n_in), dtype=torch.float32, device="cuda")
+        y = torch.empty((1, n_out), dtype=torch.float32, device="cuda")
+        pd = torch.from_numpy(params).cuda()
+        wk = torch.empty(rt.rt_mlp_work_floats(n_in, n_h, n_out, 1), dtype=torch.float32, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        for _ in range(3):
+            rt.rt_mlp_forward(stream, (n_in, n_h, n_out), pd.data_ptr(), x.data_ptr(), y.data_ptr(), 1, wk.data_ptr())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            rt.rt_mlp_forward(stream, (n_in, n_h, n_out), pd.data_ptr(), x.data_ptr(), y.data_ptr(), 1, wk.data_ptr())
+        e1.record()
+        torch.cuda.synchronize()
+        row["network_forward_ms"] = e0.elapsed_time(e1) / 20
+        row["learned_ms_per_step_net_of_inference"] = row["learned"]["ms_per_step"] - row["network_forward_ms"]
+        out["per_dt"][str(dt)] = row
+        log(f"learned c4 dt {dt}: updates linear {agg['linear']['updates_per_step']:.2f}, quadratic "
+            f"{agg['quadratic']['updates_per_step']:.2f}, learned {agg['learned']['updates_per_step']:.2f}")
+    return out
+
+
 def ground_state_input(rt, torch, s, name):
     """The input of the time loop: the molecule's stationary ground state, solved on
     the GPU from a block of smooth random vectors (not part of the timed step)."""
@@ -650,6 +772,8 @@ def main():
     ap.add_argument("--only-192", action="store_true", help="run only the 192^3 apply leg")
     ap.add_argument("--only-batch", action="store_true", help="run only the 16-molecule batch leg")
     ap.add_argument("--only-c5", action="store_true", help="run only the 192^3 x 3000 time-step leg")
+    ap.add_argument("--only-learned-c4", action="store_true",
+                    help="run only the learned guess across molecules and time steps")
     ap.add_argument("--only-learned", action="store_true", help="run only the learned-predictor leg")
     args = ap.parse_args()
     if args.h_thrs not in args.sweep:
@@ -667,6 +791,10 @@ def main():
     if args.only_192:
         log("FP32 H apply, 192^3 x 3000 orbitals")
         print(json.dumps({"apply_h_192": apply_h_192(rt, torch)}), flush=True)
+        return
+    if args.only_learned_c4:
+        log("learned first guess: train on 16 molecules, test on 4 held out, dt 0.05 .. 1.0")
+        print(json.dumps({"learned_predictor_c4": learned_predictor_c4(rt, torch)}), flush=True)
         return
     if args.only_c5:
         log("time step, 192^3 x 3000 orbitals (mixed, blocked initialisation)")

@@ -438,7 +438,8 @@ rt_status rt_record_count(rt_ctx* ctx, int* rows);
  *   RT_ENOMEM for a short workspace, RT_ENOCONV when max_scf or max_passes is
  *   exhausted or the block loses rank; rt_last_error(NULL) names the cause.
  *   When the density loop hits max_scf, stats (rho_err: the last
- *   max|rho_out - rho_in|) and eps_out_host still describe the last iterate.
+ *   max|rho_out - rho_in|) and eps_out_host still describe the last iterate,
+ *   and psi_out_dev / rho_out_dev hold its orbitals and their density.
  */
 typedef struct {
   int n_guard;        /* extra block vectors (>= 2; N + n_guard <= 1024)        */

@@ -34,12 +34,16 @@ hipError_t proj_tri_bf16x3(hipStream_t s, int N, long ng, const unsigned short* 
 // C = base + alpha * sum_s part[s] (upper kept, mirrored)
 hipError_t reduce_parts_f32(hipStream_t s, const float* part, int n_split, int N, double alpha,
                             const double* base, double* C, int T, const int* active, long sbase);
-// rho = rho0 + sum_i psi_i sum_{j>=i} W_ij psi_j.  W: [T][ld][ld], ld = density_tile_ld(N).
-// N <= 256: resident-tile kernel on the point-major orbitals pthi/ptlo [ng][ld];
-// larger N: orbital-major phi/plo [N][ng].
+// rho = rho0 + sum_i psi_i sum_{j>=i} W_ij psi_j.  W: [T][ld][ld], ld = density_tile_ld(N)
+// (a multiple of 32, zero past N).  N <= 256: resident-tile kernel on the point-major
+// orbitals pthi/ptlo [ng][ld]; larger N: tiled product on the orbital-major phi/plo
+// [N][ng] with FP32 partial densities dpart [T][ceil(N / density_big_rows())][ng]
+// (scratch; ng % 8 == 0).
+int density_big_rows();
 hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* whi, const unsigned short* wlo,
                           const unsigned short* phi, const unsigned short* plo, const unsigned short* pthi,
-                          const unsigned short* ptlo, const double* rho0, double* rho, int T, const int* active);
+                          const unsigned short* ptlo, const double* rho0, double* rho, int T, const int* active,
+                          float* dpart);
 hipError_t delta_f32(hipStream_t s, float* d, const double* a, const double* b, long n, int T, const int* active);
 
 }  // namespace rtk

@@ -640,106 +640,6 @@ hipError_t reduce_parts_f32(hipStream_t s, const float* part, int n_split, int N
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Density change from the density-matrix change, fused:
-//   rho[r] = rho0[r] + sum_i psi_i(r) sum_{j >= i} W_ij psi_j(r)
-// with W (upper-weighted change, bf16 hi/lo) and Psi (bf16 hi/lo).  One block
-// owns 64 grid points and loops over 64-row blocks of W; Phi = W Psi is never
-// stored.  Psi columns are staged transposed in LDS (k = orbital contiguous).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_density_bf16x3(int N, long ng, const unsigned short* __restrict__ Whi,
-                                                        const unsigned short* __restrict__ Wlo,
-                                                        const unsigned short* __restrict__ Phi_,
-                                                        const unsigned short* __restrict__ Plo_,
-                                                        const double* __restrict__ rho0,
-                                                        double* __restrict__ rho, int T, const int* active,
-                                                        int ld) {
-  constexpr int BM = 64, BN = 64, BK = 32, PD = 8;
-  const int tb = blockIdx.x % T;
-  if (active && !active[tb]) return;
-  Whi += (long)tb * ld * ld;
-  Wlo += (long)tb * ld * ld;
-  rho += (long)tb * ng;
-  __shared__ unsigned short sWh[BM][BK + PD], sWl[BM][BK + PD];
-  __shared__ unsigned short sPh[BN][BK + PD], sPl[BN][BK + PD];
-  __shared__ float red[2][4][BN];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const long r0 = (long)(blockIdx.x / T) * BN;
-  float part[2] = {0.f, 0.f};
-  const int nI = cdivm(N, BM);
-  for (int I = 0; I < nI; ++I) {
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int jb = I * BM; jb < N; jb += BK) {
-      for (int e = tid; e < BM * BK; e += 256) {
-        int r = e / BK, c = e - r * BK;
-        int gi = I * BM + r, gj = jb + c;
-        bool ok = gi < N && gj < N;
-        sWh[r][c] = ok ? Whi[(long)gi * ld + gj] : (unsigned short)0;
-        sWl[r][c] = ok ? Wlo[(long)gi * ld + gj] : (unsigned short)0;
-      }
-      for (int e = tid; e < BK * BN; e += 256) {
-        int kj = e / BN, c = e - kj * BN;
-        int gj = jb + kj;
-        long gr = r0 + c;
-        bool ok = gj < N && gr < ng;
-        sPh[c][kj] = ok ? Phi_[(long)gj * ng + gr] : (unsigned short)0;
-        sPl[c][kj] = ok ? Plo_[(long)gj * ng + gr] : (unsigned short)0;
-      }
-      __syncthreads();
-      const int kc = 8 * (lane >> 4);
-      bf16x8 fwh[2], fwl[2], fph[2], fpl[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        int r = wm * 32 + i * 16 + (lane & 15);
-        fwh[i] = *reinterpret_cast<const bf16x8*>(&sWh[r][kc]);
-        fwl[i] = *reinterpret_cast<const bf16x8*>(&sWl[r][kc]);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        int c = wn * 32 + j * 16 + (lane & 15);
-        fph[j] = *reinterpret_cast<const bf16x8*>(&sPh[c][kc]);
-        fpl[j] = *reinterpret_cast<const bf16x8*>(&sPl[c][kc]);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fwl[i], fph[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fwh[i], fpl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fwh[i], fph[j], acc[i][j], 0, 0, 0);
-        }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int row = I * BM + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-          long col = r0 + wn * 32 + j * 16 + (lane & 15);
-          if (row < N && col < ng) {
-            float p = bf2f(Phi_[(long)row * ng + col]) + bf2f(Plo_[(long)row * ng + col]);
-            part[j] += p * acc[i][j][r];
-          }
-        }
-  }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) red[wm][lane >> 4][wn * 32 + j * 16 + (lane & 15)] = part[j];
-  __syncthreads();
-  if (tid < BN && r0 + tid < ng) {
-    double a = 0.0;
-    for (int x = 0; x < 2; ++x)
-      for (int y = 0; y < 4; ++y) a += (double)red[x][y][tid];
-    rho[r0 + tid] = rho0[r0 + tid] + a;
-  }
-}
-
 // Resident-tile density for N <= 256.  One block owns BN grid points and every
 // trajectory: the point-major hi/lo orbital tile [BN][NP] (NP = 32 NC, zero padded)
 // is loaded into LDS once; for each trajectory Z = W Psi_tile is accumulated with
@@ -899,11 +799,178 @@ __global__ __launch_bounds__(256 * WP, MINB) void k_density_tile32(long ng, cons
   }
 }
 
-int density_tile_ld(int N) { return N <= 256 ? (N + 31) / 32 * 32 : N; }
+// ---------------------------------------------------------------------------
+// Density for N > 256 (orbital-major hi/lo psi [N][ng], W row-major [ld][ld], ld a
+// multiple of 32, zero past N).  rho = rho0 + sum_i psi_i Z_i, Z = W Psi, as a tiled
+// product: one block per (128-row block I of W, trajectory, 128 grid points), I
+// fastest so the blocks sharing a tile of points run together and read its orbital
+// rows once from HBM, the rest from L2.  K runs over the orbitals j >= 128 I in
+// chunks of 32: the block stages W[I rows][chunk] and psi[chunk][points] into LDS
+// (the latter transposed to [point][j] by packing row pairs into 32-bit words,
+// 16-byte pieces XOR-swizzled by bits 2-3 of the row), double buffered, the next
+// chunk's loads in flight during the matrix instructions; four waves each own 64
+// rows x 64 points as 2 x 2 tiles of 32x32x16 BF16x3 products.  The epilogue
+// reads psi_i at the block's rows and points, reduces sum_i psi_i Z_i over the
+// rows, and writes one FP32 partial density per row block; k_density_sum adds
+// the partials in row-block order (deterministic).
+constexpr int DBM = 128, DBN = 128;
+__device__ __forceinline__ int dsw32(int r, int q) { return r * 32 + 8 * (q ^ ((r >> 2) & 3)); }
+
+__global__ __launch_bounds__(256, 2) void k_density_big(int N, long ng, int ld, const unsigned short* __restrict__ whi,
+                                                        const unsigned short* __restrict__ wlo,
+                                                        const unsigned short* __restrict__ phi,
+                                                        const unsigned short* __restrict__ plo,
+                                                        float* __restrict__ part, int nI, int T, const int* active) {
+  __shared__ __attribute__((aligned(16))) unsigned short sA[2][2][DBM * 32];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[2][2][DBN * 32];
+  __shared__ float red[2][DBN];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int I = (int)(lid % nI);
+  const long rest = lid / nI;
+  const int t = (int)(rest % T);
+  const long pt0 = (rest / T) * DBN;
+  if (active && !active[t]) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int i0 = I * DBM;
+  const int nk = (N - i0 + 31) / 32;
+  const long npt = min((long)DBN, ng - pt0);  // valid points of this tile (a multiple of 8)
+  const auto rWh = buf_rsrc(whi + (long)t * ld * ld, ld * ld * 2);
+  const auto rWl = buf_rsrc(wlo + (long)t * ld * ld, ld * ld * 2);
+  // staging roles: W pieces p = tid, tid + 256 (row p >> 2, piece p & 3); orbital rows
+  // 2 jp, 2 jp + 1 (jp = tid & 15) at points 8 pc .. 8 pc + 7 (pc = tid >> 4)
+  const int jp = tid & 15, pc = tid >> 4;
+  const int pv = 8 * pc < npt ? 16 * pc : (int)0x80000000;  // byte offset of the piece, or out of range
+  uint4 ah[2], al[2], bh[2], bl[2];
+  auto fetch = [&](int c) {
+    const int j0 = i0 + 32 * c;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int p = tid + 256 * u, row = p >> 2, q = p & 3;
+      const int off = ((i0 + row) * ld + j0 + 8 * q) * 2;
+      ah[u] = buf_ld16(rWh, off, 0);
+      al[u] = buf_ld16(rWl, off, 0);
+    }
+    const int rows = __builtin_amdgcn_readfirstlane(min(32, N - j0));
+    const int bytes = (int)(((long)(rows - 1) * ng + npt) * 2);
+    const auto rBh = buf_rsrc(phi + (long)j0 * ng + pt0, bytes);
+    const auto rBl = buf_rsrc(plo + (long)j0 * ng + pt0, bytes);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int o = pv < 0 ? pv : (int)((long)(2 * jp + u) * ng * 2) + pv;
+      bh[u] = buf_ld16(rBh, o, 0);
+      bl[u] = buf_ld16(rBl, o, 0);
+    }
+  };
+  auto stage = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int p = tid + 256 * u, row = p >> 2, q = p & 3;
+      *reinterpret_cast<uint4*>(&sA[b][0][dsw32(row, q)]) = ah[u];
+      *reinterpret_cast<uint4*>(&sA[b][1][dsw32(row, q)]) = al[u];
+    }
+    // transpose: word u of the point pair (rows 2 jp, 2 jp + 1) at point 8 pc + u
+    const unsigned int h0[4] = {bh[0].x, bh[0].y, bh[0].z, bh[0].w}, h1[4] = {bh[1].x, bh[1].y, bh[1].z, bh[1].w};
+    const unsigned int l0[4] = {bl[0].x, bl[0].y, bl[0].z, bl[0].w}, l1[4] = {bl[1].x, bl[1].y, bl[1].z, bl[1].w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int pt = 8 * pc + u, sh = 16 * (u & 1), w = u >> 1;
+      const unsigned int vh = ((h0[w] >> sh) & 0xFFFFu) | (((h1[w] >> sh) & 0xFFFFu) << 16);
+      const unsigned int vl = ((l0[w] >> sh) & 0xFFFFu) | (((l1[w] >> sh) & 0xFFFFu) << 16);
+      const int e = dsw32(pt, jp >> 2) + 2 * (jp & 3);
+      *reinterpret_cast<unsigned int*>(&sB[b][0][e]) = vh;
+      *reinterpret_cast<unsigned int*>(&sB[b][1][e]) = vl;
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+  const int l32 = lane & 31, k8 = lane >> 5;
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  for (int c = 0; c < nk; ++c) {
+    const int b = c & 1;
+    if (c + 1 < nk) fetch(c + 1);
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      bf16x8 fah[2], fal[2], fbh[2], fbl[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int ra = 64 * wr + 32 * x + l32, rb = 64 * wc + 32 * x + l32;
+        fah[x] = *reinterpret_cast<const bf16x8*>(&sA[b][0][dsw32(ra, 2 * s2 + k8)]);
+        fal[x] = *reinterpret_cast<const bf16x8*>(&sA[b][1][dsw32(ra, 2 * s2 + k8)]);
+        fbh[x] = *reinterpret_cast<const bf16x8*>(&sB[b][0][dsw32(rb, 2 * s2 + k8)]);
+        fbl[x] = *reinterpret_cast<const bf16x8*>(&sB[b][1][dsw32(rb, 2 * s2 + k8)]);
+      }
+      // the three BF16x3 terms outermost: consecutive products update different tiles
+#pragma unroll
+      for (int term = 0; term < 3; ++term)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            acc[x][y] = mfma32(term == 0 ? fal[x] : fah[x], term == 1 ? fbl[y] : fbh[y], acc[x][y]);
+    }
+    if (c + 1 < nk) stage(b ^ 1);
+    __syncthreads();
+  }
+  // epilogue: sum over the block's rows of psi_i Z_i at each point
+  const int rowsI = min(DBM, N - i0);
+  const int ebytes = (int)(((long)(rowsI - 1) * ng + npt) * 2);
+  const auto rEh = buf_rsrc(phi + (long)i0 * ng + pt0, ebytes);
+  const auto rEl = buf_rsrc(plo + (long)i0 * ng + pt0, ebytes);
+  float pr[2] = {0.f, 0.f};
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int col = 64 * wc + 32 * y + l32;
+    const bool cok = col < npt;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 64 * wr + 32 * x + 8 * (r >> 2) + 4 * k8 + (r & 3);
+        const int o = cok ? (int)(((long)row * ng + col) * 2) : (int)0x80000000;
+        const unsigned short vh = __builtin_amdgcn_raw_buffer_load_b16(rEh, o, 0, 0);
+        const unsigned short vl = __builtin_amdgcn_raw_buffer_load_b16(rEl, o, 0, 0);
+        pr[y] += (bf2f(vh) + bf2f(vl)) * acc[x][y][r];
+      }
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    pr[y] += __shfl_xor(pr[y], 32);
+    if (lane < 32) red[wr][64 * wc + 32 * y + lane] = pr[y];
+  }
+  __syncthreads();
+  if (tid < npt) part[((long)t * nI + I) * ng + pt0 + tid] = red[0][tid] + red[1][tid];
+}
+
+// rho_t = rho0 + sum_I part_t[I] (row-block order)
+__global__ void k_density_sum(const float* __restrict__ part, int nI, long ng, const double* __restrict__ rho0,
+                              double* __restrict__ rho, const int* active) {
+  const int t = blockIdx.y;
+  if (active && !active[t]) return;
+  part += (long)t * nI * ng;
+  for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < ng; p += (long)gridDim.x * blockDim.x) {
+    double a = rho0[p];
+    for (int I = 0; I < nI; ++I) a += (double)part[(long)I * ng + p];
+    rho[(long)t * ng + p] = a;
+  }
+}
+
+int density_big_rows() { return DBM; }
+
+int density_tile_ld(int N) { return (N + 31) / 32 * 32; }
 
 hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* whi, const unsigned short* wlo,
                           const unsigned short* phi, const unsigned short* plo, const unsigned short* pthi,
-                          const unsigned short* ptlo, const double* rho0, double* rho, int T, const int* active) {
+                          const unsigned short* ptlo, const double* rho0, double* rho, int T, const int* active,
+                          float* dpart) {
   if (N <= 256) {
     if (!pthi || !ptlo) return hipErrorInvalidValue;
     const dim3 grid(cdivm(ng, 64)), blk(256);
@@ -920,8 +987,16 @@ hipError_t density_bf16x3(hipStream_t s, int N, long ng, const unsigned short* w
     }
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_density_bf16x3, dim3(cdivm(ng, 64) * T), dim3(256), 0, s, N, ng, whi, wlo, phi, plo, rho0,
-                     rho, T, active, N);
+  if (!dpart || ng % 8) return hipErrorInvalidValue;
+  const int ld = density_tile_ld(N), nI = cdivm(N, DBM);
+  if ((long)ld * ld * 2 >= (1L << 31) || (long)DBM * ng * 2 >= (1L << 31) || 32L * ng * 2 >= (1L << 31))
+    return hipErrorInvalidValue;
+  const long blocks = (long)nI * T * cdivm(ng, DBN);
+  hipLaunchKernelGGL(k_density_big, dim3((unsigned)blocks), dim3(256), 0, s, N, ng, ld, whi, wlo, phi, plo, dpart, nI,
+                     T, active);
+  long b = (ng + 255) / 256;
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL(k_density_sum, dim3((unsigned)b, T), dim3(256), 0, s, dpart, nI, ng, rho0, rho, active);
   return hipGetLastError();
 }
 

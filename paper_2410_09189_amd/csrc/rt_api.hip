@@ -181,6 +181,7 @@ struct SysDev {
   int wld = 0;                                           // leading dimension of the W split
   double *rho_gs, *S_gs;
   float *dv32, *part32;
+  float* dpart32 = nullptr;                // N > 256: partial densities [T][row blocks][ng]
   // per-trajectory state [T][...]
   double *P0, *P1, *dP, *dPn, *C;          // stacked [S'; A'], 2 N^2 each
   double* gwork = nullptr;                 // Gershgorin rows [T][N][2] / observable partials [T][160]
@@ -626,6 +627,9 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
       if (d.N <= 256) {
         d.psiT_hi = a.take<unsigned short>(ng * d.wld);
         d.psiT_lo = a.take<unsigned short>(ng * d.wld);
+      } else {
+        const long nI = (d.N + rtk::density_big_rows() - 1) / rtk::density_big_rows();
+        d.dpart32 = a.take<float>(T * nI * ng);
       }
       d.rho_gs = a.take<double>(ng);
       d.S_gs = a.take<double>(NN);
@@ -874,7 +878,7 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
     if (mixed) {
       CK(rtk::upper_weighted_delta_bf16(s, S, d.S_gs, d.w_hi, d.w_lo, d.N, d.wld, sstride, T, act, d.N <= 256));
       CK(rtk::density_bf16x3(s, d.N, d.ng, d.w_hi, d.w_lo, d.psi_hi, d.psi_lo, d.psiT_hi, d.psiT_lo, d.rho_gs,
-                             d.rho, T, act));
+                             d.rho, T, act, d.dpart32));
     } else {
       CK(rtk::upper_weighted(s, S, d.W, d.N, sstride, T, act));
       CK(rtk::smalltall_f64(s, d.N, d.ng, d.W, d.psi, d.rho, 1, 1, T, act));
@@ -1921,7 +1925,17 @@ rt_status gs_run(rt_ctx* c, SysDev& d, GsDev& g, const rt_system& s, const rt_gs
     }
   };
   if (!conv) {
-    report(err, R.wanted_res());  // the last iterate, for diagnosis
+    // the last iterate, for diagnosis or as an approximate ground state: its Ritz
+    // vectors (signs fixed) and their density
+    double* X = g.blk[R.cur];
+    CK(rtk::fix_signs(st, X, N, ng));
+    CK(hipMemcpyAsync(psi_out, X, (size_t)N * ng * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (rho_out) {
+      CK(rtk::occ_density(st, X, g.occ, nb, ng, g.rho_out));
+      CK(hipMemcpyAsync(rho_out, g.rho_out, ng * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    CK(hipStreamSynchronize(st));
+    report(err, R.wanted_res());
     return fail(c, RT_ENOCONV, "ground state: density loop hit max_scf");
   }
   // final orbitals: eigenpairs of H[rho_in] at the converged input density

@@ -449,7 +449,9 @@ def rt_eigh_noalloc(stream_ptr, n, a_ptr, evals_ptr, vecs_ptr):
 
 def ground_state(system, params, device="cuda"):
     """Device workspace from torch, then rt_ground_state on torch's current stream.
-    Returns (psi [N][ng] torch tensor on the device, Ritz values, rho tensor, stats)."""
+    Returns (psi [N][ng] torch tensor on the device, Ritz values, rho tensor, stats).
+    When the density loop stops at max_scf the RTError also carries .psi and .rho
+    of the last iterate."""
     import torch
 
     s = system.struct
@@ -461,7 +463,12 @@ def ground_state(system, params, device="cuda"):
     psi = torch.empty((N, ng), dtype=torch.float64, device=device)
     rho = torch.empty(ng, dtype=torch.float64, device=device)
     stream = torch.cuda.current_stream(device).cuda_stream
-    eps, stats = rt_ground_state(system, params, ws.data_ptr(), ws_bytes, stream, psi.data_ptr(), rho.data_ptr())
+    try:
+        eps, stats = rt_ground_state(system, params, ws.data_ptr(), ws_bytes, stream, psi.data_ptr(), rho.data_ptr())
+    except RTError as e:
+        if e.status == RT_ENOCONV and e.stats.get("scf_iters", 0) >= params.max_scf:
+            e.psi, e.rho = psi, rho  # the last iterate of the density loop
+        raise
     del ws
     return psi, eps, rho, stats
 

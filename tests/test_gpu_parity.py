@@ -236,7 +236,7 @@ MIXED_REL = 1e-4
 @pytest.mark.parametrize("n,n_orb", [((36, 40, 32), 20), ((36, 40, 30), 100), ((36, 40, 30), 250),
                                      ((40, 36, 36), 300), ((36, 36, 30), 60), ((36, 30, 30), 70),
                                      ((36, 30, 30), 150), ((36, 40, 30), 190), ((36, 30, 30), 220),
-                                     ((36, 36, 30), 300)])
+                                     ((36, 36, 30), 300), ((36, 36, 30), 520)])
 def test_mixed_eval_h_error_is_relative_to_the_perturbation(n, n_orb):
     _say(f"mixed eval_h {n} N={n_orb}")
     torch = _torch()
