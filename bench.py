@@ -593,8 +593,8 @@ def learned_predictor(rt, torch, sa, s):
             "dipole_max_abs": float(np.max(np.abs(mu_l - mu_l[0])))}
 
 
-def learned_predictor_c4(rt, torch, dts=(0.05, 0.2, 0.5, 1.0), train_seeds=range(400, 416),
-                         test_seeds=range(500, 504), n_rec=60, n_eval=60, h_thrs=1e-7):
+def learned_predictor_c4(rt, torch, dts=(0.05, 0.2, 0.5, 1.0), train_seeds=(400, 404, 406, 410),
+                         test_seeds=(411, 413, 14), n_rec=60, n_eval=60, h_thrs=1e-7):
     """The learned first guess across molecules: 96^3 molecules of the N=240 mixed
     workload's generator (40 wells + rank-4 projectors, 160 + 80 orbitals), ground
     states on the GPU (a density loop stopped at 40 iterations is kept when
@@ -604,7 +604,11 @@ def learned_predictor_c4(rt, torch, dts=(0.05, 0.2, 0.5, 1.0), train_seeds=range
     with a z kick under the linear, quadratic and learned guesses.  Reports
     Hamiltonian updates per step (after the 8 warm-up steps the features need),
     time per step, the network's own time per step, and the dipole difference
-    to the linear run (same fixed point)."""
+    to the linear run (same fixed point).  The seeds are generator seeds whose
+    density loop settles within 40 iterations (of seeds 400-415 and 500-503 on the
+    box: 400, 404, 406, 410, 411, 413; the rest slosh at rho_err 1e-5 - 1e-3
+    between near-degenerate levels) plus the N=240 workload's own molecule (14);
+    training and test molecules are disjoint."""
     import synth
     from paper_2410_09189_amd import predictor
 
@@ -645,9 +649,8 @@ def learned_predictor_c4(rt, torch, dts=(0.05, 0.2, 0.5, 1.0), train_seeds=range
     # the network's forward pass alone, at the run's batch size (one trajectory)
     n_in, n_h, n_out = rt.rt_mlp_dims()
     out = {"workload": "96^3 molecules of the N=240 mixed workload's generator, mixed precision, local update, "
-                       f"H_thrs {h_thrs:g}; train seeds {list(train_seeds)[0]}..{list(train_seeds)[-1]} (x/y/z kicks "
-                       f"1e-3, {n_rec} recorded steps), held-out seeds {list(test_seeds)[0]}..{list(test_seeds)[-1]} "
-                       f"(z kick 1.5e-3, {n_eval} steps)",
+                       f"H_thrs {h_thrs:g}; train seeds {list(train_seeds)} (x/y/z kicks 1e-3, {n_rec} recorded "
+                       f"steps), held-out seeds {list(test_seeds)} (z kick 1.5e-3, {n_eval} steps)",
            "train_molecules": [x[0] for x in train], "test_molecules": [x[0] for x in test],
            "left_out": dropped, "ground_state_s": round(t_gs, 1), "per_dt": {}}
     if not train or not test:
@@ -793,7 +796,7 @@ def main():
         print(json.dumps({"apply_h_192": apply_h_192(rt, torch)}), flush=True)
         return
     if args.only_learned_c4:
-        log("learned first guess: train on 16 molecules, test on 4 held out, dt 0.05 .. 1.0")
+        log("learned first guess: train on 4 molecules, test on 3 held out, dt 0.05 .. 1.0")
         print(json.dumps({"learned_predictor_c4": learned_predictor_c4(rt, torch)}), flush=True)
         return
     if args.only_c5:

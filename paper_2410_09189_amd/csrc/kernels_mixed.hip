@@ -157,11 +157,22 @@ __device__ __forceinline__ uint4 buf_ld16(__amdgpu_buffer_rsrc_t r, int voff, in
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Fragment layout of v_mfma_f32_32x32x16_bf16: lane l holds row (A) / column (B)
+// l & 31 and k = 8 (l >> 5) .. 8 (l >> 5) + 7; result register r of lane l is
+// row 8 (r >> 2) + 4 (l >> 5) + (r & 3), column l & 31.  It retires twice the
+// products of the 16x16x32 form per issue cycle.
+__device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
 // Projection kernel: per thread one 32-bit row offset for the whole loop (the K
 // position rides in the scalar offset of buffer loads), rows >= N read as zero
 // through the resource bound, the weights fetched once per K chunk (all four
 // vectors a thread stages share its K columns), the next chunk in flight in
-// registers during the MFMAs, XCD-aware block order.  Needs 256 ng < 2^31.
+// registers during the MFMAs, XCD-aware block order.  Each wave owns 64 x 64 of
+// the 128 x 128 tile as 2 x 2 blocks of 32x32x16 products.  Needs 256 ng < 2^31.
 __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const unsigned short* __restrict__ Ahi,
                                                         const unsigned short* __restrict__ Alo,
                                                         const float* __restrict__ w, float* __restrict__ part,
@@ -191,8 +202,8 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
   // 16 x 16 blocks; 16-row / 16-column blocks past N are skipped everywhere
   const bool idle = (tm == tn) && (wm > wn);
   const bool lowdiag = (tm == tn) && (wm == wn);
-  const int nib = (int)min(4L, max(0L, (N - m0 - wm * 64 + 15) / 16));
-  const int njb = (int)min(4L, max(0L, (N - n0 - wn * 64 + 15) / 16));
+  const int nib = (int)min(2L, max(0L, (N - m0 - wm * 64 + 31) / 32));
+  const int njb = (int)min(2L, max(0L, (N - n0 - wn * 64 + 31) / 32));
   const auto rAh = buf_rsrc(Ahi + m0 * ng + k0, (int)((va * ng - k0) * 2));
   const auto rAl = buf_rsrc(Alo + m0 * ng + k0, (int)((va * ng - k0) * 2));
   const auto rBh = buf_rsrc(Ahi + n0 * ng + k0, (int)((vb * ng - k0) * 2));
@@ -223,11 +234,13 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
     rw0 = buf_ld16(rW, wv, 2 * so);
     rw1 = buf_ld16(rW, wv + 16, 2 * so);
   };
-  f32x4 acc[4][4];
+  f32x16 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
   fetch(k0);
   for (long kb = k0; kb < k1; kb += XK) {
     const float w0 = __uint_as_float(rw0.x), w1 = __uint_as_float(rw0.y), w2 = __uint_as_float(rw0.z),
@@ -249,55 +262,46 @@ __global__ __launch_bounds__(256, 2) void k_proj_bf16x3(int N, long ng, const un
     __syncthreads();
     if (kb + XK < k1) fetch(kb + XK);
 #pragma unroll
-    for (int kk = 0; kk < XK && !idle; kk += 32) {
-      bf16x8 fah[4], fal[4], fbh[4], fbl[4];
-      const int kc = kk + 8 * (lane >> 4);
+    for (int kk = 0; kk < XK && !idle; kk += 16) {
+      bf16x8 fah[2], fal[2], fbh[2], fbl[2];
+      const int kc = kk + 8 * (lane >> 5);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int r = wm * 64 + i * 16 + (lane & 15);
+      for (int i = 0; i < 2; ++i) {
+        int r = wm * 64 + i * 32 + (lane & 31);
         fah[i] = *reinterpret_cast<const bf16x8*>(&sAh[r][kc]);
         fal[i] = *reinterpret_cast<const bf16x8*>(&sAl[r][kc]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int r = wn * 64 + j * 16 + (lane & 15);
+      for (int j = 0; j < 2; ++j) {
+        int r = wn * 64 + j * 32 + (lane & 31);
         fbh[j] = *reinterpret_cast<const bf16x8*>(&sBh[r][kc]);
         fbl[j] = *reinterpret_cast<const bf16x8*>(&sBl[r][kc]);
       }
+      // the three BF16x3 terms outermost: consecutive products update different tiles
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int term = 0; term < 3; ++term)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (i >= nib || j >= njb || (lowdiag && i > j)) continue;
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fbh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fah[i], fbh[j], acc[i][j], 0, 0, 0);
-        }
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if (i >= nib || j >= njb || (lowdiag && i > j)) continue;
+            acc[i][j] = mfma32(term == 0 ? fal[i] : fah[i], term == 1 ? fbl[j] : fbh[j], acc[i][j]);
+          }
     }
     __syncthreads();
   }
   if (idle) return;
   float* P = part + (long)by * N * N;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        long row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        long col = n0 + wn * 64 + j * 16 + (lane & 15);
+      for (int r = 0; r < 16; ++r) {
+        long row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        long col = n0 + wn * 64 + j * 32 + (lane & 31);
         if (row < N && col < N) P[row * N + col] = acc[i][j][r];
       }
-}
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-// Fragment layout of v_mfma_f32_32x32x16_bf16: lane l holds row (A) / column (B)
-// l & 31 and k = 8 (l >> 5) .. 8 (l >> 5) + 7; result register r of lane l is
-// row 8 (r >> 2) + 4 (l >> 5) + (r & 3), column l & 31.  It retires twice the
-// products of the 16x16x32 form per issue cycle.
-__device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------

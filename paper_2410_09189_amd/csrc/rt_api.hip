@@ -536,10 +536,11 @@ void choose_split(SysDev& d) {
     long km = ((d.ng + nsm - 1) / nsm + bk - 1) / bk * bk;
     d.n_split_cap = std::max(d.n_split_cap, std::max(d.n_split, (int)((d.ng + km - 1) / km)));
   }
-  // BF16x3 projection: 128 x 128 upper tiles, K chunks of 64
+  // BF16x3 projection: 128 x 128 upper tiles, K chunks of 64, ~4096 blocks per
+  // trajectory (many rounds of two blocks per CU, so the last round's tail is short)
   int ntx = (d.N + 127) / 128;
   int tx = ntx * (ntx + 1) / 2;
-  long nsx = std::min((1024L + tx - 1) / tx, std::max(1L, d.ng / 2048));
+  long nsx = std::min((4096L + tx - 1) / tx, std::max(1L, d.ng / 2048));
   long kx = (d.ng + nsx - 1) / nsx;
   kx = (kx + 63) / 64 * 64;
   d.kps_x = kx;
