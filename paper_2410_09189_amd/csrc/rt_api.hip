@@ -1194,16 +1194,22 @@ rt_status init_system(rt_ctx* c, SysDev& d, const rt_system& s) {
     RET(project(c, d, d.psi, d.hpsi, nullptr, d.hcore));
   } else {
     // H_core by blocks of hb orbitals J: rows J of X = h^3 (H Psi_J) Psi^T, then
-    // H_core = (X + X^T) / 2
+    // H_core = (X + X^T) / 2.  A block's product has few 64 x 64 tiles, so K is split
+    // further (~2048 blocks), within the partial-sum buffer.
+    const long tiles = (long)((d.hb + 63) / 64) * ((d.N + 63) / 64);
+    const long room = (long)std::max(d.n_split, d.n_split_cap) * NN / ((long)d.hb * d.N);
+    const long nsb = std::max(1L, std::min({(2048 + tiles - 1) / tiles, room, std::max(1L, ng / 1024)}));
+    const long kpb = ((ng + nsb - 1) / nsb + 15) / 16 * 16;
+    const int nspb = (int)((ng + kpb - 1) / kpb);
     for (int j0 = 0; j0 < d.N; j0 += d.hb) {
       const int nb = std::min(d.hb, d.N - j0);
       RET(apply_h64(c, d, d.psi + (long)j0 * ng, d.hpsi, d.vion, nb));
       {
         Timed tm(c, PH_PROJECT);
-        CK(rtk::gemm_nt_f64(st, nb, d.N, ng, d.hpsi, ng, d.psi, ng, nullptr, d.part, d.kps, d.n_split, 0, d.big,
+        CK(rtk::gemm_nt_f64(st, nb, d.N, ng, d.hpsi, ng, d.psi, ng, nullptr, d.part, kpb, nspb, 0, d.big,
                             rtk::single()));
       }
-      CK(rtk::reduce_parts(st, d.part, d.n_split, nb, d.N, d.h3, d.tmp2 + (long)j0 * N, 0, nullptr, 1, 0, 0, 0,
+      CK(rtk::reduce_parts(st, d.part, nspb, nb, d.N, d.h3, d.tmp2 + (long)j0 * N, 0, nullptr, 1, 0, 0, 0,
                            nullptr));
     }
     CK(rtk::transpose(st, d.tmp2, d.tmp, d.N));
