@@ -136,16 +136,19 @@ constexpr int XB = 128, XK = 64, XPAD = 8;
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 // (hi + lo) * w of two packed bf16 pairs, re-split to packed bf16 hi/lo (round to
-// nearest even on the hardware converter).
+// nearest even on the hardware converter, both halves in one conversion).
 __device__ __forceinline__ void split_scaled2(unsigned int h, unsigned int l, float w0, float w1, unsigned int& oh,
                                               unsigned int& ol) {
-  float x0 = (__uint_as_float(h << 16) + __uint_as_float(l << 16)) * w0;
-  float x1 = (__uint_as_float(h & 0xFFFF0000u) + __uint_as_float(l & 0xFFFF0000u)) * w1;
-  bf16x2 hp = {(__bf16)x0, (__bf16)x1};
-  bf16x2 lp = {(__bf16)(x0 - (float)hp[0]), (__bf16)(x1 - (float)hp[1])};
-  oh = __builtin_bit_cast(unsigned int, hp);
-  ol = __builtin_bit_cast(unsigned int, lp);
+  const float x0 = (__uint_as_float(h << 16) + __uint_as_float(l << 16)) * w0;
+  const float x1 = (__uint_as_float(h & 0xFFFF0000u) + __uint_as_float(l & 0xFFFF0000u)) * w1;
+  const f32x2 x = {x0, x1};
+  const unsigned int hb = __builtin_bit_cast(unsigned int, __builtin_convertvector(x, bf16x2));
+  const f32x2 r = {x0 - __uint_as_float(hb << 16), x1 - __uint_as_float(hb & 0xFFFF0000u)};
+  oh = hb;
+  ol = __builtin_bit_cast(unsigned int, __builtin_convertvector(r, bf16x2));
 }
 
 // Raw buffer resource over [base, base + bytes): loads at offsets >= bytes return 0.
@@ -482,7 +485,7 @@ __device__ __forceinline__ void tri_stage(int N, const __amdgpu_buffer_rsrc_t& r
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = tid + NS * u;
-      if (e >= PIECES) break;
+      if (PIECES % NS != 0 && e >= PIECES) break;  // (no divergent branch when every thread has U)
       const int o = tri_off(e >> 2, q);
       *reinterpret_cast<uint4*>(s + o) = g.h[u];
       *reinterpret_cast<uint4*>(s + R + o) = g.l[u];
