@@ -978,7 +978,16 @@ __device__ __forceinline__ void fft_pass(const double2* src, double2* dst, const
   const int nb = n / R;
   const int tstep = n / (Ns * R);
   for (int e = threadIdx.x; e < nb * L; e += blockDim.x) {
-    const int j = e / L, c = e - j * L;
+    // neighbouring threads take neighbouring LDS elements: along the line for
+    // line-major data (LAYOUT 1), across lines for column-major data
+    int j, c;
+    if (LAYOUT == 1) {
+      c = e / nb;
+      j = e - c * nb;
+    } else {
+      j = e / L;
+      c = e - j * L;
+    }
     const int k = j % Ns;
     double2 v[R];
 #pragma unroll
@@ -1112,8 +1121,8 @@ static hipError_t fft_x_launch(hipStream_t s, double2* z, int nx, int ny, int nz
   FftPlan pl = fft_plan(n);
   if (pl.np < 0) return hipErrorInvalidValue;
   long n_lines = (long)ny * nz;
-  int lpb = n >= 256 ? 1 : 256 / n;
-  if (lpb > 16) lpb = 16;
+  // about 1536 elements per block (as the strided passes), at most 16 lines
+  int lpb = std::max(1, std::min(16, 1536 / n));
   size_t lds = (size_t)(n + 2 * lpb * n) * sizeof(double2);
   long ng = (long)nx * ny * nz;
   hipLaunchKernelGGL(k_fft_x, dim3(cdiv(n_lines, lpb), T), dim3(256), lds, s, z, n, n_lines, lpb, tw, inverse, pl, ng,
