@@ -1035,14 +1035,17 @@ __device__ double2* fft_lds(double2* A, double2* B, const double2* tws, int n, i
 // inverse); mode 1: forward transform, multiply by the Poisson kernel
 // 4 pi / (|G|^2 Ng) (G = 0 dropped), inverse transform -- used on z lines,
 // the last forward and first inverse axis, so the k-space field never leaves LDS.
+// px: row pitch of the k-space layout, nx for full rows, nx / 2 + 1 for the
+// half spectrum of real fields (kx = 0 .. nx / 2, all with mx = ix).
 struct PoissonGeom {
   int nx, ny, nz;
   double h;
+  int px;
 };
 
 __device__ __forceinline__ double poisson_factor(const PoissonGeom& g, long gidx) {
-  int ix = (int)(gidx % g.nx), iy = (int)((gidx / g.nx) % g.ny), iz = (int)(gidx / ((long)g.nx * g.ny));
-  int mx = ix < (g.nx + 1) / 2 ? ix : ix - g.nx;
+  int ix = (int)(gidx % g.px), iy = (int)((gidx / g.px) % g.ny), iz = (int)(gidx / ((long)g.px * g.ny));
+  int mx = ix < (g.nx + 1) / 2 || g.px != g.nx ? ix : ix - g.nx;
   int my = iy < (g.ny + 1) / 2 ? iy : iy - g.ny;
   int mz = iz < (g.nz + 1) / 2 ? iz : iz - g.nz;
   double gx = 2.0 * M_PI * mx / (g.nx * g.h), gy = 2.0 * M_PI * my / (g.ny * g.h), gz = 2.0 * M_PI * mz / (g.nz * g.h);
@@ -1115,6 +1118,90 @@ __global__ __launch_bounds__(256) void k_fft_x(double2* __restrict__ z, int n, l
   }
 }
 
+// Real fields along x (n even, M = n / 2): one complex transform of length M per
+// line on z_m = x_2m + i x_2m+1, then the half spectrum X_k, k = 0 .. M, from
+// X_k = E_k + e^(-2 pi i k / n) O_k, E_k = (Z_k + conj Z_(M-k)) / 2,
+// O_k = -i (Z_k - conj Z_(M-k)) / 2 (Z_M = Z_0), written with row pitch M + 1.
+// inverse: the reverse, Z'_k = (X_k + conj X_(M-k)) + i e^(2 pi i k / n) (X_k - conj X_(M-k)),
+// x_2m + i x_2m+1 = IDFT_M(Z')_m (unnormalised, as the full-row transform).  Each
+// line is a transform of its own (nothing mixes fields or lines).
+__global__ __launch_bounds__(256) void k_fft_x_half(double2* __restrict__ z, int n, long n_lines, int lpb,
+                                                    const double2* __restrict__ tw, int inverse, FftPlan pl,
+                                                    long fs, const double* __restrict__ rin,
+                                                    double* __restrict__ rout, long rs) {
+  extern __shared__ unsigned char smem_raw[];
+  const int M = n / 2, H = M + 1;
+  double2* tn = reinterpret_cast<double2*>(smem_raw);  // e^(2 pi i p / n), p < n
+  double2* tm = tn + n;                                // e^(2 pi i p / M), p < M
+  double2* A = tm + M;
+  double2* B = A + M * lpb;
+  const long l0 = (long)blockIdx.x * lpb;
+  const int t = blockIdx.y;
+  z += (long)t * fs;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) tn[p] = tw[p];
+  for (int p = threadIdx.x; p < M; p += blockDim.x) tm[p] = tw[2 * p];
+  const int nl = (int)min((long)lpb, n_lines - l0);
+  __syncthreads();
+  for (int e = threadIdx.x; e < lpb * M; e += blockDim.x) {
+    const int c = e / M, m = e - c * M;
+    double2 v = make_double2(0.0, 0.0);
+    if (c < nl) {
+      if (!inverse) {
+        const double* x = rin + t * rs + (l0 + c) * n;
+        v = make_double2(x[2 * m], x[2 * m + 1]);
+      } else {
+        const double2* X = z + (l0 + c) * H;
+        const double2 a = X[m], b = X[M - m];  // X_k, X_(M-k)
+        const double2 s = make_double2(a.x + b.x, a.y - b.y);   // X_k + conj X_(M-k)
+        const double2 d = make_double2(a.x - b.x, a.y + b.y);   // X_k - conj X_(M-k)
+        const double2 w = tn[m];
+        const double2 wd = make_double2(d.x * w.x - d.y * w.y, d.x * w.y + d.y * w.x);
+        v = make_double2(s.x - wd.y, s.y + wd.x);  // s + i wd
+      }
+    }
+    A[e] = v;
+  }
+  __syncthreads();
+  double2* out = fft_lds<1>(A, B, tm, M, lpb, pl, inverse ? 1.0 : -1.0);
+  if (!inverse) {
+    for (int e = threadIdx.x; e < nl * H; e += blockDim.x) {
+      const int c = e / H, k = e - c * H;
+      const double2 a = out[c * M + (k == M ? 0 : k)];
+      const double2 b = out[c * M + (k == 0 ? 0 : M - k)];
+      // E = (a + conj b) / 2, O = -i (a - conj b) / 2
+      const double2 E = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      const double2 O = make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x));
+      const double2 w = tn[k];  // conj is the forward twiddle
+      const double2 wo = make_double2(O.x * w.x + O.y * w.y, O.y * w.x - O.x * w.y);
+      z[(l0 + c) * H + k] = make_double2(E.x + wo.x, E.y + wo.y);
+    }
+  } else {
+    for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
+      const int c = e / M, m = e - c * M;
+      const double2 v = out[e];
+      double* x = rout + t * rs + (l0 + c) * n;
+      x[2 * m] = v.x;
+      x[2 * m + 1] = v.y;
+    }
+  }
+}
+
+// nr real fields (stride ng) to / from their half spectra in z (field stride ng).
+static hipError_t fft_x_half_launch(hipStream_t s, double2* z, int nx, int ny, int nz, const double2* tw,
+                                    int inverse, int T, const double* rin, double* rout) {
+  const int n = nx, M = nx / 2;
+  FftPlan pl = fft_plan(M);
+  if (nx % 2 || pl.np < 0) return hipErrorInvalidValue;
+  long n_lines = (long)ny * nz;
+  int lpb = std::max(1, std::min(16, 1536 / M));
+  lpb = std::max(1, std::min(lpb, (4096 - n - M) / (2 * M)));  // at most 64 KB of LDS
+  size_t lds = (size_t)(n + M + 2 * lpb * M) * sizeof(double2);
+  long ng = (long)nx * ny * nz;
+  hipLaunchKernelGGL(k_fft_x_half, dim3(cdiv(n_lines, lpb), T), dim3(256), lds, s, z, n, n_lines, lpb, tw, inverse,
+                     pl, ng, rin, rout, ng);
+  return hipGetLastError();
+}
+
 static hipError_t fft_x_launch(hipStream_t s, double2* z, int nx, int ny, int nz, const double2* tw, int inverse,
                                int T, const double* rin, double* rout) {
   const int n = nx;
@@ -1130,18 +1217,20 @@ static hipError_t fft_x_launch(hipStream_t s, double2* z, int nx, int ny, int nz
   return hipGetLastError();
 }
 
+// px: row pitch of z (nx, or nx / 2 + 1 for half spectra)
 static hipError_t fft_strided_launch(hipStream_t s, double2* z, int nx, int ny, int nz, int axis, const double2* tw,
-                                     int inverse, int T, int mode, double h) {
+                                     int inverse, int T, int mode, double h, int px = 0) {
+  if (px == 0) px = nx;
   const int n = axis == 1 ? ny : nz;
   FftPlan pl = fft_plan(n);
   if (pl.np < 0) return hipErrorInvalidValue;
   int TC = n <= 96 ? 16 : (n <= 192 ? 8 : 4);
-  long st = axis == 1 ? nx : (long)nx * ny;
-  int C = axis == 1 ? nx : nx * ny;
+  long st = axis == 1 ? px : (long)px * ny;
+  int C = axis == 1 ? px : px * ny;
   int n_outer = axis == 1 ? nz : 1;
-  long os = axis == 1 ? (long)nx * ny : 0;
+  long os = axis == 1 ? (long)px * ny : 0;
   size_t lds = (size_t)(n + 2 * n * TC) * sizeof(double2);
-  PoissonGeom pg{nx, ny, nz, h};
+  PoissonGeom pg{nx, ny, nz, h, px};
   long ng = (long)nx * ny * nz;
   hipLaunchKernelGGL(k_fft_strided, dim3(cdiv(C, TC), n_outer, T), dim3(256), lds, s, z, n, st, os, C, TC, tw, inverse,
                      pl, ng, mode, pg);
@@ -1155,10 +1244,20 @@ hipError_t dft_axis(hipStream_t s, double2* z, int nx, int ny, int nz, int axis,
 }
 
 // V_H,t = IFFT[4 pi FFT[rho_t] / |G|^2] for T stacked densities: five launches
-// (x fwd from the real field, y fwd, z fwd * kernel * z inv, y inv, x inv to the real field).
+// (x fwd from the real field, y fwd, z fwd * kernel * z inv, y inv, x inv to the real field);
+// for even nx the x passes are real-to-half-spectrum transforms.
 hipError_t poisson_fft(hipStream_t s, const double* rho, double* vh, double2* z, int nx, int ny, int nz, double h,
                        const double2* twx, const double2* twy, const double2* twz, int T) {
   hipError_t e;
+  if (nx % 2 == 0) {
+    // real fields: half spectra along x, so the y and z passes see nx / 2 + 1 columns
+    const int px = nx / 2 + 1;
+    if ((e = fft_x_half_launch(s, z, nx, ny, nz, twx, 0, T, rho, nullptr)) != hipSuccess) return e;
+    if ((e = fft_strided_launch(s, z, nx, ny, nz, 1, twy, 0, T, 0, h, px)) != hipSuccess) return e;
+    if ((e = fft_strided_launch(s, z, nx, ny, nz, 2, twz, 0, T, 1, h, px)) != hipSuccess) return e;
+    if ((e = fft_strided_launch(s, z, nx, ny, nz, 1, twy, 1, T, 0, h, px)) != hipSuccess) return e;
+    return fft_x_half_launch(s, z, nx, ny, nz, twx, 1, T, nullptr, vh);
+  }
   if ((e = fft_x_launch(s, z, nx, ny, nz, twx, 0, T, rho, nullptr)) != hipSuccess) return e;
   if ((e = fft_strided_launch(s, z, nx, ny, nz, 1, twy, 0, T, 0, h)) != hipSuccess) return e;
   if ((e = fft_strided_launch(s, z, nx, ny, nz, 2, twz, 0, T, 1, h)) != hipSuccess) return e;

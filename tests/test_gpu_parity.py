@@ -135,6 +135,34 @@ def test_eval_h_and_potentials_match_oracle(hupdate):
     ses.close()
 
 
+# x edges: 30 (half-spectrum transforms of odd length 15), 64 (length 32), 45 (odd:
+# full complex rows); y and z edges of 2-, 3- and 5-smooth lengths
+@pytest.mark.parametrize("shape", [(30, 24, 20), (64, 48, 40), (45, 32, 30)])
+def test_hartree_potential_on_grid_shapes_matches_oracle(shape):
+    _say(f"density and V_H through eval_h on a {shape} grid, N=12")
+    torch = _torch()
+    from paper_2410_09189_amd import rt
+
+    s, psi = _ragged_system(seed=12, n=shape, n_orb=12)
+    rp = synth.RunParams(dt=0.05, n_steps=2)
+    ses = _session([system_args(s, psi, orthonormalize=True)], run_args(rp, hupdate=1))
+    m = oracle.Model(s, orthonormalize_np(s, psi))
+    N = m.N
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((N, N))
+    S = np.diag(s.occupations()) + 0.1 * (A + A.T)
+    Sd = torch.from_numpy(S).cuda()
+    Hd = torch.empty_like(Sd)
+    rt.rt_eval_h(ses.ctx, 0, Sd.data_ptr(), Hd.data_ptr())
+    torch.cuda.synchronize()
+    ref, aux = m.h_of_p(S.astype(complex))
+    assert np.max(np.abs(Hd.cpu().numpy() - ref)) < 1e-11 * np.max(np.abs(ref))
+    for which, key in ((0, "rho"), (1, "vh")):
+        g = rt.rt_get_grid(ses.ctx, 0, which, s.ng)
+        assert np.max(np.abs(g - aux[key])) < 1e-12 * max(1.0, np.max(np.abs(aux[key]))), key
+    ses.close()
+
+
 @pytest.mark.parametrize("dt,n", [(0.05, 16), (0.3, 70), (-0.2, 33)])
 def test_series_propagation_matches_exact(dt, n):
     _say(f"rt_propagate dt={dt} N={n}")
