@@ -156,6 +156,13 @@ hipError_t gemm_nt_f64_series(hipStream_t s, int N, int T, const double* Hbar, c
 hipError_t series_update(hipStream_t s, const double* C, const double* C2, double* dPn, double* P1, int N,
                          double dt, int k, unsigned long long* slots, int stride, const double* kmin, double thrs,
                          int* done, int T, const int* active);
+// series term k for N <= series_small_max() in one launch (product and update fused,
+// one block per trajectory); same arguments and results as the two launches above
+// without Omega_2
+int series_small_max();
+hipError_t series_term_small(hipStream_t s, int N, int T, const double* G, const double* dP, double* dPn, double* P1,
+                             double dt, int k, unsigned long long* slots, int stride, const double* kmin,
+                             double thrs, int* done, const int* active);
 hipError_t series_finish(hipStream_t s, int kmax, const unsigned long long* slots, int stride,
                          const double* kmin, double thrs, int* done, int T, const int* active);
 // dst[t] = bit t of f (t < T <= 256), flags passed by value

@@ -1776,6 +1776,94 @@ hipError_t series_update(hipStream_t s, const double* C, const double* C2, doubl
   return hipGetLastError();
 }
 
+// One series term for N <= 64 in a single launch, one block per trajectory: the
+// product C = G . [S; A]^T (N x 2N) on v_mfma_f64_16x16x4f64 with G and dP staged in
+// LDS (zero padded to 64), C kept in LDS, then the same update as k_series_update
+// (dP_k from C and its transpose, P1 += dP_k, max |dP_k| to the slot).  Lane layout
+// of the matrix instruction: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16],
+// result register r is D[l / 16 + 4 r][l % 16].  Row pitches of 4 mod 32 doubles
+// keep each fragment read at two LDS passes.
+constexpr int SMALL_N = 64, SP = 68, CP = 132;
+__global__ __launch_bounds__(256) void k_series_term_small(const double* __restrict__ G,
+                                                           const double* __restrict__ dP, double* __restrict__ dPn,
+                                                           double* __restrict__ P1, int N, double dt, SeriesSkip sk,
+                                                           int* done, const int* active) {
+  __shared__ double sG[SMALL_N * SP];
+  __shared__ double sB[2 * SMALL_N * SP];  // rows 0..63: S, 64..127: A; later C [64][CP]
+  __shared__ double sh[256];
+  static_assert(SMALL_N * CP <= 2 * SMALL_N * SP, "C fits where the operands were");
+  const int t = blockIdx.x;
+  if (active && !active[t]) return;
+  if (series_stopped(sk, t)) {
+    if (threadIdx.x == 0 && done[2 * t] == 0) {
+      done[2 * t] = 1;
+      done[2 * t + 1] = sk.k - 1;
+    }
+    return;
+  }
+  const long NN = (long)N * N;
+  G += t * NN;
+  dP += t * 2 * NN;
+  dPn += t * 2 * NN;
+  P1 += t * 2 * NN;
+  for (int e = threadIdx.x; e < SMALL_N * SMALL_N; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const bool in = r < N && c < N;
+    sG[r * SP + c] = in ? G[r * N + c] : 0.0;
+    sB[r * SP + c] = in ? dP[r * N + c] : 0.0;
+    sB[(SMALL_N + r) * SP + c] = in ? dP[NN + r * N + c] : 0.0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+  f64x4 acc[8];
+#pragma unroll
+  for (int cb = 0; cb < 8; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int kp = (N + 3) & ~3;
+  for (int k0 = 0; k0 < kp; k0 += 4) {
+    const double a = sG[(16 * w + lr) * SP + k0 + lk];
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb) {
+      const double b = sB[(16 * cb + lr) * SP + k0 + lk];
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  double* Cs = sB;
+#pragma unroll
+  for (int cb = 0; cb < 8; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Cs[(16 * w + lk + 4 * r) * CP + 16 * cb + lr] = acc[cb][r];
+  __syncthreads();
+  const double f = dt / sk.k;
+  double m = 0.0;
+  for (int e = threadIdx.x; e < N * N; e += 256) {
+    const int i = e / N, j = e - i * N;
+    const double gS_ij = Cs[i * CP + j], gA_ij = Cs[i * CP + SMALL_N + j];
+    const double gS_ji = Cs[j * CP + i], gA_ji = Cs[j * CP + SMALL_N + i];
+    const double sv = -f * (gA_ij + gA_ji);
+    const double av = -f * (gS_ij - gS_ji);
+    dPn[e] = sv;
+    dPn[NN + e] = av;
+    P1[e] += sv;
+    P1[NN + e] += av;
+    m = fmax(m, sqrt(sv * sv + av * av));
+  }
+  m = block_max_256(m, sh);
+  if (threadIdx.x == 0)
+    atomic_max_nonneg(const_cast<unsigned long long*>(sk.slots) + (long)t * sk.stride + sk.k, m);
+}
+
+int series_small_max() { return SMALL_N; }
+
+hipError_t series_term_small(hipStream_t s, int N, int T, const double* G, const double* dP, double* dPn, double* P1,
+                             double dt, int k, unsigned long long* slots, int stride, const double* kmin,
+                             double thrs, int* done, const int* active) {
+  if (N < 1 || N > SMALL_N || T < 1) return hipErrorInvalidValue;
+  SeriesSkip sk{slots, kmin, done, thrs, k, stride};
+  hipLaunchKernelGGL(k_series_term_small, dim3(T), dim3(256), 0, s, G, dP, dPn, P1, N, dt, sk, done, active);
+  return hipGetLastError();
+}
+
 __global__ void k_series_finish(SeriesSkip sk, int* done, int T, const int* active) {
   int t = threadIdx.x;
   if (t >= T || (active && !active[t])) return;

@@ -986,6 +986,14 @@ struct Series {
     double* dP = dP0;
     double* dPn = dPn0;
     for (int k = k_from; k <= k_to; ++k) {
+      if (!B && d.N <= rtk::series_small_max()) {
+        // small N: product and update in one launch
+        Timed tm(c, PH_SERIES_GEMM);
+        CK(rtk::series_term_small(c->stream, d.N, T, Gs, dP, dPn, Pout, dt, k, slots, stride, kmin, thrs, done,
+                                  act));
+        std::swap(dP, dPn);
+        continue;
+      }
       {
         Timed tm(c, PH_SERIES_GEMM);
         CK(rtk::gemm_nt_f64_series(c->stream, d.N, T, Gs, dP, C, k, slots, stride, kmin, thrs, done, act));
