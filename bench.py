@@ -33,7 +33,7 @@ learned first guess on this molecule, the FP32 H apply at the
 192^3 x 3000-orbital nanoparticle shape, and the GPU ground-state solve of the
 16 batch molecules.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the benchmark runs on one GPU.
 """
 
 import argparse
@@ -787,7 +787,7 @@ def main():
     if args.h_thrs not in args.sweep:
         args.sweep = sorted(set(args.sweep) | {args.h_thrs}, reverse=True)
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1",
+        print("bench.py: the benchmark runs on exactly one GPU (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
