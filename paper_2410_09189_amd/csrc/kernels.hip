@@ -226,7 +226,7 @@ __device__ __forceinline__ void sv_st_nt(T* p, const SVec<T, V>& x) {
 // Up to 512 threads (8 waves) per block; three waves per SIMD leave 168 registers,
 // which the rings need with one halo strip per thread (two with more).
 template <typename T, int V, int COLS, int HS, int PD>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HS == 1 ? 3 : 2))) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(COLS == 1 && HS == 1 ? 3 : 2))) void k_stencil(const T* __restrict__ psi, T* __restrict__ hpsi,
                                                  const T* __restrict__ v, int nx, int ny, int nz,
                                                  int TY, int ZC, int HQ, StencilCoef cf) {
   typedef SVec<T, V> Vec;
@@ -379,6 +379,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HS == 1 ? 3
   }
 }
 
+// Threads per block and halo strips per thread of a tile of ty rows (spr strips a
+// row): one strip a thread up to 512 strips, else two; false where that does not
+// launch (more than 1024 strips, or two strips with more than two halo strips).
+static bool stencil_shape(int spr, int ty, int& cols, int& nt, int& hs) {
+  if (ty * spr > 1024) return false;
+  cols = ty * spr > 512 ? 2 : 1;
+  nt = ((ty * spr + cols - 1) / cols + 63) / 64 * 64;
+  hs = (8 * spr + nt - 1) / nt;
+  return hs <= 8 && (cols == 1 || hs <= 2);
+}
+
 // Default y tile: the smallest divisor of ny of at least 8 rows whose strips fit one
 // 512-thread block (one strip per thread): the tile's threads then cover its 8 halo
 // rows with one strip each; else the largest divisor that fits (measured on 96^3 and
@@ -398,10 +409,8 @@ static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* 
   // y tile (ty > 0: as given; it must divide ny and its strips fit one block),
   // block = strips rounded up to whole waves
   const int TY = ty > 0 ? ty : stencil_default_ty(spr, ny);
-  if (ny % TY || TY * spr > 512) return hipErrorInvalidValue;
-  const int cols = (TY * spr + 511) / 512;
-  const int nt = cols > 1 ? 512 : (TY * spr + 63) / 64 * 64;
-  const int hs = (8 * spr + nt - 1) / nt;
+  int cols, nt, hs;
+  if (ny % TY || !stencil_shape(spr, TY, cols, nt, hs)) return hipErrorInvalidValue;
   int tiles = ny / TY;
   // z chunks (nzc > 0: as given): by default doubled until the grid has 2048 blocks
   // or a chunk would drop below 16 planes
@@ -428,13 +437,16 @@ static hipError_t stencil_launch(hipStream_t s, const T* psi, T* hpsi, const T* 
 #define RT_STENCIL(C, H) \
   hipLaunchKernelGGL((k_stencil<T, V, C, H, 3>), grid, dim3(nt), lds, s, psi, hpsi, v, nx, \
                      ny, nz, TY, ZC, HQ, cf)
-  // TY * spr <= 512 gives one strip per thread (cols == 1), and nt >= spr bounds the
-  // halo at 8 strips per thread
-  if (cols != 1 || hs > 8) return hipErrorInvalidValue;
-  if (hs <= 1) RT_STENCIL(1, 1);
-  else if (hs <= 2) RT_STENCIL(1, 2);
-  else if (hs <= 4) RT_STENCIL(1, 4);
-  else RT_STENCIL(1, 8);
+  if (cols == 1) {
+    if (hs <= 1) RT_STENCIL(1, 1);
+    else if (hs <= 2) RT_STENCIL(1, 2);
+    else if (hs <= 4) RT_STENCIL(1, 4);
+    else RT_STENCIL(1, 8);
+  } else {
+    // (two strips and more than two halo strips a thread would not fit the registers)
+    if (hs <= 1) RT_STENCIL(2, 1);
+    else RT_STENCIL(2, 2);
+  }
 #undef RT_STENCIL
   return hipGetLastError();
 }
@@ -456,8 +468,9 @@ void stencil_tiles(int nx, int ny, int nz, int n_orb, std::vector<int>& ty, std:
   const int spr = nx % VV == 0 ? nx / VV : nx;
   ty.clear();
   nzc.clear();
-  for (int t = 1; t <= ny && t * spr <= 512; ++t)
-    if (ny % t == 0) ty.push_back(t);
+  int cols, nt, hs;
+  for (int t = 1; t <= ny && t * spr <= 1024; ++t)  // up to two strips per thread
+    if (ny % t == 0 && stencil_shape(spr, t, cols, nt, hs)) ty.push_back(t);
   for (int z = 1; z <= 16 && z <= nz; z *= 2) nzc.push_back(z);
   (void)n_orb;
 }

@@ -39,7 +39,7 @@ def test_every_stencil_tiling_gives_the_same_apply_bitwise():
         ref = y.cpu().numpy()
         spr = 36 // (2 if dtype == 0 else 4)
         n = 0
-        tys = [t for t in range(1, 41) if 40 % t == 0 and t * spr <= 512]
+        tys = [t for t in range(1, 41) if 40 % t == 0 and t * spr <= 1024]  # (two strips a thread past 512)
         # every tiling at the built-in halo look-ahead, then every look-ahead on a few
         # tilings (z chunks of 2 planes have fewer planes than the look-ahead)
         shapes = [(ty, nzc, 0) for ty in tys for nzc in (1, 2, 4, 8, 16)]
@@ -56,6 +56,35 @@ def test_every_stencil_tiling_gives_the_same_apply_bitwise():
         with pytest.raises(rt.RTError):
             rt.rt_tune_set(ses.ctx, 0, kern, 0, 0, 2)  # not a look-ahead candidate
         rt.rt_tune_set(ses.ctx, 0, kern, 0, 0)
+    ses.close()
+
+
+def test_two_strip_tilings_give_the_same_apply_bitwise():
+    """Tiles of more than 512 strips run with two strips a thread (and one or two
+    halo strips): on a 96-point x edge (48 FP64 / 24 FP32 strips a row) they give the
+    built-in tiling's apply bit for bit."""
+    _say("two-strip stencil tilings, 96x24x16 N=20, fp64 and fp32")
+    import torch
+
+    from paper_2410_09189_amd import rt
+
+    n = (96, 24, 16)
+    s = synth.make_system(n, 0.3, 4, 10, 10, seed=9, nl_rank=0, region=(0.3, 0.7))
+    psi = synth.lowpass_orbitals(n, 0.3, 20, 9)
+    ses = rt.Session([system_args(s, psi, orthonormalize=True)], run_args(synth.RunParams(dt=0.05, n_steps=2)))
+    x64 = torch.from_numpy(psi.reshape(20, -1)).cuda()
+    for dtype, kern, x, spr in ((0, rt.RT_TUNE_STENCIL_FP64, x64, 48), (1, rt.RT_TUNE_STENCIL_FP32, x64.float(), 24)):
+        y = torch.empty_like(x)
+        rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), 20, dtype)
+        ref = y.cpu().numpy()
+        two = [t for t in range(1, 25) if 24 % t == 0 and 512 < t * spr <= 1024]
+        assert two
+        for ty in two:
+            for nzc, hq in ((1, 0), (2, 0), (1, 3), (1, 8)):
+                rt.rt_tune_set(ses.ctx, 0, kern, ty, nzc, hq)
+                y.zero_()
+                rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), 20, dtype)
+                assert np.array_equal(y.cpu().numpy(), ref), (dtype, ty, nzc, hq)
     ses.close()
 
 

@@ -149,7 +149,8 @@ def test_full_size_step_matches_oracle(mode):
 def test_nanoparticle_shape_fp32_apply_sampled_against_oracle():
     """The 192^3 x 3000-orbital FP32 apply the benchmark times (85 GB in, 85 GB out,
     the chunking over the context's 64-orbital block included): three sampled
-    orbitals against the oracle's FD8 stencil + V_loc in FP64."""
+    orbitals against the oracle's FD8 stencil + V_loc in FP64, and the two-strip
+    tiling against the built-in one bit for bit."""
     import torch
 
     from paper_2410_09189_amd import rt
@@ -172,6 +173,14 @@ def test_nanoparticle_shape_fp32_apply_sampled_against_oracle():
     rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y.data_ptr(), n_orb, 1)
     torch.cuda.synchronize()
     vloc = rt.rt_get_grid(ses.ctx, 0, 4, ng)
+    # the tiling the autotuner takes at this shape (16-row tiles, two strips a
+    # thread) gives the built-in tiling's result bit for bit (first 200 orbitals)
+    rt.rt_tune_set(ses.ctx, 0, rt.RT_TUNE_STENCIL_FP32, 16, 1, 3)
+    y2 = torch.empty((200, ng), dtype=torch.float32, device="cuda")
+    rt.rt_apply_h(ses.ctx, 0, x.data_ptr(), y2.data_ptr(), 200, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(y2, y[:200])
+    del y2
     ses.close()
     coeffs = fd_coefficients_float(4)
     nx, ny, nz = s.n
