@@ -608,7 +608,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
                                                      int n_tn, Batch bt, SeriesSkip sk) {
   constexpr int BK = 16, PK = BK + 1, UA = BM * BK / 256, UB = BN * BK / 256;
   constexpr int WM = BM / 2, WN = BN / 2, FI = WM / 16, FJ = WN / 16;
-  const int tb = blockIdx.x % bt.T;
+  // XCD-aware order: consecutive logical blocks (the tiles of one K split, which
+  // share their rows of A and B) run on one XCD and read those rows through its L2
+  const long lid = xcd_logical(blockIdx.x + (long)gridDim.x * blockIdx.y, (long)gridDim.x * gridDim.y);
+  const int bx = (int)(lid % gridDim.x), by = (int)(lid / gridDim.x);
+  const int tb = bx % bt.T;
   if (bt.active && !bt.active[tb]) return;
   if (sk.k > 0 && series_stopped(sk, tb)) return;
   A += tb * bt.sa;
@@ -619,7 +623,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
   __shared__ double Bs[BN][PK];
   int tm, tn;
   {
-    int t = blockIdx.x / bt.T;
+    int t = bx / bt.T;
     if (upper) {
       tm = 0;
       int rowlen = n_tn;
@@ -630,7 +634,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
       tn = t - tm * n_tn;
     }
   }
-  const long k0 = (long)blockIdx.y * kps;
+  const long k0 = (long)by * kps;
   const long k1 = min(K, k0 + kps);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_f64(int M, int N, long K, const
     }
     __syncthreads();
   }
-  double* P = part + (long)blockIdx.y * M * N;
+  double* P = part + (long)by * M * N;
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
