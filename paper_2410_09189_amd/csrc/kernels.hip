@@ -786,13 +786,16 @@ __global__ __launch_bounds__(256) void k_smalltall_f64(int N, long ng, const dou
   __shared__ double Ws[BM][BK + 1];
   __shared__ double Ps[BK][BN + 2];
   __shared__ double red[2][BN];
-  const int tb = blockIdx.x % T;
+  // XCD-aware order: the T blocks of one column range (trajectory fastest) run on one
+  // XCD and read its Psi columns through one L2
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  const int tb = (int)(lid % T);
   if (active && !active[tb]) return;
   W += (long)tb * N * N;
   out += MODE == 0 ? (long)tb * N * ng : (long)tb * ng;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
-  const long r0 = (long)(blockIdx.x / T) * BN;
+  const long r0 = (lid / T) * BN;
   double rho_part[4] = {0.0, 0.0, 0.0, 0.0};
   const int nI = cdiv(N, BM);
   for (int I = 0; I < nI; ++I) {
