@@ -145,6 +145,7 @@ struct SysDev {
   bool mixed = false;
   bool nonorth = false;  // propagate in the given (non-orthogonal) basis with its overlap
   int hb = 0;            // orbitals the buffer hpsi holds (N, or the run's h_block)
+  int hpsi_sets = 0;     // FP64 full updates with T > 1: T buffers of H Psi in hpsiT (else 0)
   int dcorr = 0;         // bit q: vacuum dipole correction along axis q
   int jump[3] = {0, 0, 0};  // sawtooth jump plane per axis
   double dion[3] = {0.0, 0.0, 0.0};  // ions' dipole sum_a Z_a s_q(R_a) on the corrected axes
@@ -165,6 +166,7 @@ struct SysDev {
   std::vector<int> zeros2T;    // host zeros for the series flags
   // orbitals and static fields
   double *psi, *hpsi, *vion, *vloc_gs, *occ;
+  double* hpsiT = nullptr;  // [hpsi_sets][N][ng] (hpsi and psi trade places at init, so not hpsi)
   float* vloc32;
   double2* z;
   double2 *twx, *twy, *twz;
@@ -575,6 +577,10 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.box_ctr = a.take<unsigned long long>(1);
     d.psi = a.take<double>(N * ng);
     d.hpsi = a.take<double>((long)d.hb * ng);
+    // FP64 full updates hold every trajectory's H Psi, so that one projection launch
+    // covers the trajectories and they read Psi through a shared L2
+    d.hpsi_sets = (!d.mixed && run.hupdate == RT_HUPDATE_FULL && d.hb == d.N && T > 1) ? (int)T : 0;
+    d.hpsiT = d.hpsi_sets ? a.take<double>((long)d.hpsi_sets * N * ng) : nullptr;
     d.vion = a.take<double>(ng);
     d.vloc_gs = a.take<double>(ng);
     d.occ = a.take<double>(N);
@@ -908,6 +914,21 @@ rt_status eval_h(rt_ctx* c, SysDev& d, int T, const int* act, const std::vector<
     }
     Timed tr(c, PH_REDUCE);
     CK(rtk::reduce_parts(s, d.part, d.n_split, d.N, d.N, d.h3, Hout, 1, d.hcore, T, sp, 0, NN, act));
+    return RT_OK;
+  }
+  if ((r.hupdate == RT_HUPDATE_FULL || force_full) && T > 1 && d.hpsiT && d.hpsi_sets >= T) {
+    // every trajectory's H Psi, then one projection launch for all of them
+    const long nsz = (long)d.N * d.ng;
+    for (int t = 0; t < T; ++t)
+      if (act_host[t]) RET(apply_h64(c, d, d.psi, d.hpsiT + t * nsz, d.vloc + (long)t * d.ng, d.N));
+    const long sp = (long)d.n_split * NN;
+    {
+      Timed tm(c, PH_PROJECT);
+      CK(rtk::gemm_nt_f64(s, d.N, d.N, d.ng, d.psi, d.ng, d.hpsiT, d.ng, nullptr, d.part, d.kps, d.n_split, 1,
+                          d.big, rtk::Batch{T, act, 0, nsz, 0, sp}));
+    }
+    Timed tr(c, PH_REDUCE);
+    CK(rtk::reduce_parts(s, d.part, d.n_split, d.N, d.N, d.h3, Hout, 1, nullptr, T, sp, 0, NN, act));
     return RT_OK;
   }
   if (r.hupdate == RT_HUPDATE_FULL || force_full) {
