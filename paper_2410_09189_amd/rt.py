@@ -512,9 +512,16 @@ class Session:
         self.ctx = rt_init(systems, run, self.ws.data_ptr(), self.ws_bytes, self.stream)
 
     def close(self):
+        """Frees the context and lets torch reuse the workspace (after the stream's
+        work on it has finished)."""
         if self.ctx is not None:
             rt_free(self.ctx)
             self.ctx = None
+        if getattr(self, "ws", None) is not None:
+            import torch
+
+            torch.cuda.synchronize(self.ws.device)
+            self.ws = None
 
     def __del__(self):
         try:
