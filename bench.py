@@ -755,7 +755,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--h-thrs", type=float, default=1e-7)
     ap.add_argument("--sweep", type=float, nargs="+", default=[1e-6, 1e-7, 1e-8, 1e-9],
                     help="self-consistency thresholds of the equal-dipole-error sweep (must include --h-thrs)")

@@ -1384,7 +1384,11 @@ rt_status launch_update(rt_ctx* c, SysDev& d) {
     return enqueue_publish(c, d, d.resid, T * sizeof(unsigned long long));
   };
   std::vector<uintptr_t> key{2, (uintptr_t)T, (uintptr_t)d.P1, (uintptr_t)d.H1};
-  for (int t = 0; t < T; ++t) key.push_back((uintptr_t)d.active_host[t]);
+  // the captured sequence depends on the host's copy of the active flags only where
+  // launches are made per active trajectory (FP64 full updates, frozen potentials);
+  // elsewhere every kernel reads the device flags, so one graph serves every mask
+  if (c->run.frozen_hxc || (!d.mixed && c->run.hupdate == RT_HUPDATE_FULL))
+    for (int t = 0; t < T; ++t) key.push_back((uintptr_t)d.active_host[t]);
   return run_graph(c, d, key, update);
 }
 
