@@ -271,8 +271,10 @@ rt_status rt_set_state(rt_ctx* ctx, int traj, const double* p_re, const double* 
 /*
  * Autotuner of the launch shapes (the paper tunes nothing; these are this
  * library's own kernels).  Tunables per system:
- *   RT_TUNE_STENCIL_FP64 / _FP32: y-tile rows p1 (a divisor of ny whose 16-byte
- *     strips fit one 256-thread block), z chunks p2 (1..nz) and halo look-ahead
+ *   RT_TUNE_STENCIL_FP64 / _FP32: y-tile rows p1 (a divisor of ny whose tile has
+ *     at most 1024 16-byte strips: one strip a thread up to 512, two above, and
+ *     then only where each thread carries at most two of the 8 halo rows'
+ *     strips), z chunks p2 (1..nz) and halo look-ahead
  *     p3 in {3, 4, 5, 6, 8} planes (how early the y-halo rows are requested) of
  *     the FD8 + V stencil; the tiling changes no arithmetic (results bitwise
  *     equal);
