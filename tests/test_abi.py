@@ -148,6 +148,23 @@ def test_h_block_shrinks_the_workspace():
     assert a - b == 3 * 16 ** 3 * 8  # N = 4: the H Psi buffer holds 1 orbital instead of 4
 
 
+def test_fp64_full_updates_hold_one_h_psi_buffer_per_trajectory():
+    """FP64 full updates of several trajectories keep every trajectory's H Psi, so
+    that one projection launch covers them: the workspace grows by T N ng doubles
+    over the local update's, and not at all for a single trajectory."""
+    import synth
+    from rt_helpers import run_args
+
+    from paper_2410_09189_amd import rt
+
+    sa, _ = _args()
+    rp = synth.RunParams(dt=0.05, n_steps=10)
+    w = {(len(ax), h): rt.rt_workspace_size([sa], run_args(rp, n_traj_axes=ax, hupdate=h))
+         for ax in ((0,), (0, 1, 2)) for h in (0, 1)}
+    assert w[(1, 0)] == w[(1, 1)]
+    assert w[(3, 0)] - w[(3, 1)] == 3 * 4 * 16 ** 3 * 8  # T = 3, N = 4, 16^3 points
+
+
 def test_nonorthogonal_basis_takes_overlap_buffers():
     from paper_2410_09189_amd import rt
 
