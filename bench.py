@@ -68,8 +68,8 @@ def roof(phase, N, ng, mixed, T, full):
     if phase == "project_gemm":
         if mixed:
             return 4.0 * N * ng + 4.0 * T * ng, T * 3 * 2 * pairs * ng, PEAK_BF16
-        if full:  # one launch per trajectory: psi and H psi
-            return 16.0 * N * ng, 2 * pairs * ng, PEAK_FP64
+        if full:  # one launch for the T trajectories: psi once, every trajectory's H psi
+            return 8.0 * N * ng + 8.0 * T * N * ng, T * 2 * pairs * ng, PEAK_FP64
         return 8.0 * N * ng + 8.0 * T * ng, T * 2 * pairs * ng, PEAK_FP64
     if phase == "density":
         if mixed:
@@ -220,10 +220,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 TUNE_CACHE = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"rt_tune_cache_{os.getpid()}.txt")
 
 
-def measured_traffic(key):
+def measured_traffic(key, nbytes, tiling=None):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel's source file
-    has changed since the counters were taken."""
+    has changed since the counters were taken, when the counted launches had other
+    algorithmic bytes than this one (another launch shape), or, for the stencil, when
+    they ran another tiling (tile rows and z chunks set which halo rows and planes are
+    read again; the look-ahead only sets which plane's halo is in flight)."""
     import hashlib
 
     try:
@@ -232,6 +235,10 @@ def measured_traffic(key):
     except (OSError, KeyError, ValueError):
         return None
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    if abs(rec["algorithmic_bytes_per_launch"] - nbytes) > 0.5:
+        return None
+    if tiling is not None and list(rec.get("tiling", [0, 0]))[:2] != list(tiling)[:2]:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -244,7 +251,7 @@ def roofline_of(prof, N, ng, mixed, full):
     ms, launches = prof[dom]
     avg = ms / 1e3 / launches
     t_hbm, t_mfma = nbytes / PEAK_HBM, (flops / pk if flops else 0.0)
-    traffic = measured_traffic(dom if mixed else dom + "_fp64")
+    traffic = measured_traffic(dom if mixed else dom + "_fp64", nbytes)
     if t_hbm >= t_mfma:
         return {"bound": "hbm", "kernel": dom, "achieved": nbytes / avg / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": nbytes / avg / PEAK_HBM, "traffic": traffic, "avg_launch_us": avg * 1e6,
@@ -925,18 +932,17 @@ def main():
         st_ms, st_n = ph["stencil_fd8"]
         t_st = st_ms / 1e3 / st_n  # one stencil launch covers all N orbitals
         st_bytes = 2 * b * N * s.ng + b * s.ng  # psi in, H psi out, V once
+        tiling = rt.rt_tune_get(ctx, 0, rt.RT_TUNE_STENCIL_FP32 if dt_ else rt.RT_TUNE_STENCIL_FP64)
         rates["fp32" if dt_ else "fp64"] = {
             "orbital_gridpoints_per_s": N * s.ng / t_apply,
             "hbm_GBps_algorithmic": (2 * b * N * s.ng + b * s.ng) / t_apply / 1e9,
             "hbm_frac": (2 * b * N * s.ng + b * s.ng) / t_apply / PEAK_HBM,
             "stencil_only": {"avg_launch_us": t_st * 1e6, "algorithmic_bytes_per_launch": st_bytes,
                              "achieved_GBps": st_bytes / t_st / 1e9, "frac": st_bytes / t_st / PEAK_HBM,
-                             # counted at the built-in tiling; another tiling re-reads other halo rows
-                             "traffic": measured_traffic("stencil_fd8_fp32" if dt_ else "stencil_fd8_fp64")
-                             if rt.rt_tune_get(ctx, 0, rt.RT_TUNE_STENCIL_FP32 if dt_ else
-                                               rt.RT_TUNE_STENCIL_FP64) == (0, 0, 0) else None,
-                             "tiling": rt.rt_tune_get(ctx, 0, rt.RT_TUNE_STENCIL_FP32 if dt_ else
-                                                      rt.RT_TUNE_STENCIL_FP64)},
+                             # counted at one tiling; another one re-reads other halo rows
+                             "traffic": measured_traffic("stencil_fd8_fp32" if dt_ else "stencil_fd8_fp64",
+                                                         st_bytes, tiling),
+                             "tiling": tiling},
         }
     prof_mixed["ses"].close()
     del x64, y64, x32, y32
