@@ -363,6 +363,37 @@ def test_spectrum_sum_rule_on_analytic_signal():
         assert S[np.argmin(np.abs(om - w))] > 0
 
 
+def test_spectrum_integral_of_a_kicked_run_is_the_trk_sum():
+    """The dipole strength of a real self-consistent run integrates to the
+    Thomas-Reiche-Kuhn sum Tr(P0 [M, [H0, M]]) of the active space (the local
+    Hartree-exchange kernel adds nothing to the double commutator).  With damping
+    gamma the spectrum keeps a Lorentzian tail above the highest transition: for a
+    response with dmu(0) = 0 and dmu'(0) = -kappa TRK it decays as
+    4 gamma TRK / (pi w^2), so the integral up to w_max is
+    TRK (1 - 4 gamma / (pi w_max)).  A wrong time scale in the propagator, kick
+    strength or spectrum normalisation moves the integral by its own factor."""
+    import synth
+
+    s = c1_system()
+    _, eps = c1_ground_state()
+    m = c1_model()
+    M = m.M[0]
+    H0 = np.diag(eps[: m.N])
+    P0 = np.diag(s.occupations())
+    trk = np.trace(P0 @ (M @ (H0 @ M - M @ H0) - (H0 @ M - M @ H0) @ M))
+    # 30 a.u.: the damped response has fallen to e^-6 of its size by the end
+    rp = synth.config_run("c1_parity_32", n_steps=150, h_thrs=1e-9, dt=0.2)
+    out = oracle.run(m, rp)
+    mu = out["mu"][:, 0]
+    gamma, w_max = 0.2, 3.0
+    assert w_max > 3 * (eps[m.N - 1] - eps[0])  # above every transition of the active space
+    om = np.linspace(1e-4, w_max, 30000)
+    S = oracle.spectrum.spectrum(mu, mu[0], rp.dt, rp.kappa, om, gamma=gamma)
+    got = np.trapezoid(S, om)
+    want = trk * (1 - 4 * gamma / (np.pi * w_max))
+    assert abs(got - want) < 5e-3 * trk, (got, want, trk)
+
+
 # ---------------------------------------------------------------------------
 # External field V_j = sum_q E_q(t_j) M_q in the midpoint (Algorithm 1)
 # ---------------------------------------------------------------------------
