@@ -136,7 +136,11 @@ typedef struct {
  * rebuilt in the self-consistent loop:
  *   RT_HUPDATE_FULL  -- the grid Hamiltonian is applied to every orbital (FD
  *                       stencil + local + nonlocal) and projected, as in the
- *                       paper's Hamiltonian update.
+ *                       paper's Hamiltonian update.  In FP64 with several
+ *                       trajectories per system the workspace holds each
+ *                       trajectory's H Psi (n_traj N Ng doubles, if at most
+ *                       16 GiB) so one launch projects them all; otherwise
+ *                       they take turns in one buffer.  Same results.
  *   RT_HUPDATE_LOCAL -- the orbitals are fixed during propagation, so only the
  *                       Hartree-exchange part changes: H[P] = H_gs +
  *                       h^3 Psi^T diag(V_Hx[P] - V_Hx[P_gs]) Psi, with H_gs built

@@ -517,6 +517,9 @@ rt_status validate(const rt_system* sys, int n_sys, const rt_run* run, std::stri
 
 constexpr int kGemmTargets[3] = {1024, 2048, 4096};  // candidate block counts, FP64 projection
 constexpr int kTriSplits[4] = {85, 128, 170, 255};   // candidate splits, BF16x3 projection (N <= 256)
+// Largest extra workspace FP64 full updates take for per-trajectory H Psi buffers
+// (a few percent of one device's HBM; the batched projection gains ~10 %)
+constexpr long kHpsiSetsMaxBytes = 16L << 30;
 
 void choose_split(SysDev& d) {
   // FP64 projection: 64 x 64 upper tiles, K chunks of 16, ~2048 blocks (or the tuned count)
@@ -578,8 +581,10 @@ void layout(Arena& a, std::vector<SysDev>& S, const rt_run& run, int hist_cap) {
     d.psi = a.take<double>(N * ng);
     d.hpsi = a.take<double>((long)d.hb * ng);
     // FP64 full updates hold every trajectory's H Psi, so that one projection launch
-    // covers the trajectories and they read Psi through a shared L2
-    d.hpsi_sets = (!d.mixed && run.hupdate == RT_HUPDATE_FULL && d.hb == d.N && T > 1) ? (int)T : 0;
+    // covers the trajectories and they read Psi through a shared L2; past
+    // kHpsiSetsMaxBytes they share the one buffer and project one at a time
+    d.hpsi_sets = (!d.mixed && run.hupdate == RT_HUPDATE_FULL && d.hb == d.N && T > 1 &&
+                   T * N * ng * (long)sizeof(double) <= kHpsiSetsMaxBytes) ? (int)T : 0;
     d.hpsiT = d.hpsi_sets ? a.take<double>((long)d.hpsi_sets * N * ng) : nullptr;
     d.vion = a.take<double>(ng);
     d.vloc_gs = a.take<double>(ng);

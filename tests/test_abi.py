@@ -165,6 +165,26 @@ def test_fp64_full_updates_hold_one_h_psi_buffer_per_trajectory():
     assert w[(3, 0)] - w[(3, 1)] == 3 * 4 * 16 ** 3 * 8  # T = 3, N = 4, 16^3 points
 
 
+def test_fp64_full_update_h_psi_buffers_stop_at_16_gib():
+    """Past 16 GiB the trajectories' H Psi share one buffer (64 orbitals on 128^3:
+    16 trajectories take exactly 16 GiB, 17 would take more)."""
+    import synth
+    from rt_helpers import run_args
+
+    from paper_2410_09189_amd import rt
+
+    rp = synth.RunParams(dt=0.05, n_steps=10)
+    w = {}
+    for t in (16, 17):
+        for h in (0, 1):
+            sa, _ = _args(n_virt=62)
+            sa.struct.n[0] = sa.struct.n[1] = sa.struct.n[2] = 128
+            assert sa.struct.n_occ + sa.struct.n_virt == 64
+            w[(t, h)] = rt.rt_workspace_size([sa], run_args(rp, n_traj_axes=[q % 3 for q in range(t)], hupdate=h))
+    assert w[(16, 0)] - w[(16, 1)] == 16 << 30
+    assert w[(17, 0)] == w[(17, 1)]
+
+
 def test_nonorthogonal_basis_takes_overlap_buffers():
     from paper_2410_09189_amd import rt
 
