@@ -18,6 +18,8 @@ Modules
                delta kick, self-consistent time loop
   ground_state Kohn-Sham ground state used as the input active space
   spectrum     photoabsorption spectrum from the dipole history
+  predictor    learned first guess: features, network forward/backward, Adam
+               (imported by its tests as oracle.predictor)
 
 Functions whose result has no independent pin say "parity unpinned" here and
 in their docstring.  Currently: none.
