@@ -514,7 +514,7 @@ class Session:
     def close(self):
         """Frees the context and lets torch reuse the workspace (after the stream's
         work on it has finished)."""
-        if self.ctx is not None:
+        if getattr(self, "ctx", None) is not None:  # (absent when rt_init raised)
             rt_free(self.ctx)
             self.ctx = None
         if getattr(self, "ws", None) is not None:
